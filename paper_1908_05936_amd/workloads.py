@@ -1,0 +1,245 @@
+"""Seeded synthetic workloads for the batch container operations.
+
+This module only draws inputs: keys, values, query mixes and their order.  It holds none of the
+containers' arithmetic (no hashing, no probing, no batch semantics), so the CPU reference and the
+GPU library can both be fed from it without sharing any of the method.
+
+Every generator takes an explicit seed and uses numpy's PCG64 generator, so a run is reproducible
+on any machine with the same numpy.  Keys are returned as ``numpy.uint64`` arrays; all 2^64 key
+values are legal inputs (the containers mark slot occupancy without reserving key values,
+Section 5.1), so the draws are over the full 64-bit range.
+
+Workloads (sizes are parameters so tests can run scaled-down copies):
+
+* ``plain_table``   -- uniform distinct keys, values = batch index, a 50/50 present/absent find,
+                      an erase of a quarter of the keys and a final find of all keys.
+* ``large_table``   -- distinct uniform keys at load factor 0.8, Zipf(1.1) find popularity with a
+                      share of absent keys, then erase + re-insert of fresh keys.
+* ``voxel_blocks``  -- packed signed 21-bit int3 block coordinates sampled on spheres and planes in
+                      a 4096^3 grid, visited by a moving frustum (the reconstruction use case of
+                      Section 4.1).
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+U64 = np.uint64
+M21 = (1 << 21) - 1
+
+
+def rng_for(seed: int, stream: int = 0) -> np.random.Generator:
+    """Independent PCG64 stream ``stream`` of seed ``seed``."""
+    return np.random.Generator(np.random.PCG64(np.random.SeedSequence([int(seed), int(stream)])))
+
+
+def uniform_u64(rng: np.random.Generator, n: int) -> np.ndarray:
+    return rng.integers(0, 1 << 64, size=int(n), dtype=np.uint64, endpoint=False)
+
+
+def distinct_u64(rng: np.random.Generator, n: int, exclude: np.ndarray | None = None) -> np.ndarray:
+    """``n`` distinct uniform u64 keys in draw order; repeats (and members of ``exclude``) are redrawn."""
+    n = int(n)
+    out = np.empty(0, dtype=np.uint64)
+    excl = np.empty(0, dtype=np.uint64) if exclude is None else np.unique(np.asarray(exclude, np.uint64))
+    while out.size < n:
+        need = n - out.size
+        cand = np.concatenate([out, uniform_u64(rng, need + need // 64 + 16)])
+        _, first = np.unique(cand, return_index=True)
+        keep = np.zeros(cand.size, dtype=bool)
+        keep[first] = True
+        if excl.size:
+            keep &= ~np.isin(cand, excl)
+        out = cand[keep][:n] if keep.sum() >= n else cand[keep]
+    return out
+
+
+def zipf_ranks(rng: np.random.Generator, n: int, num_elements: int, exponent: float) -> np.ndarray:
+    """``n`` ranks in [1, num_elements] with P(k) proportional to k^-exponent.
+
+    Rejection-inversion sampling of Hoermann & Derflinger (1996), "Rejection-inversion to generate
+    variates from monotone discrete distributions", vectorised: propose by inverting the integral of
+    the continuous envelope x^-s, accept by the squeeze test or the exact integral bound.
+    """
+    s = float(exponent)
+    N = float(num_elements)
+
+    def h(x):
+        return np.exp(-s * np.log(x))
+
+    def helper1(x):  # log1p(x)/x, continuous at 0
+        return np.where(np.abs(x) > 1e-8, np.log1p(x) / np.where(x == 0, 1.0, x), 1.0 - x * (0.5 - x / 3.0))
+
+    def helper2(x):  # expm1(x)/x, continuous at 0
+        return np.where(np.abs(x) > 1e-8, np.expm1(x) / np.where(x == 0, 1.0, x), 1.0 + x * 0.5 * (1.0 + x / 3.0))
+
+    def H(x):
+        lx = np.log(x)
+        return helper2((1.0 - s) * lx) * lx
+
+    def Hinv(x):
+        t = np.maximum(x * (1.0 - s), -1.0)
+        return np.exp(helper1(t) * x)
+
+    h_x1 = H(np.float64(1.5)) - 1.0
+    h_n = H(np.float64(N + 0.5))
+    sq = 2.0 - Hinv(H(np.float64(2.5)) - h(np.float64(2.0)))
+    out = np.empty(int(n), dtype=np.int64)
+    todo = np.arange(int(n))
+    while todo.size:
+        u = h_n + rng.random(todo.size) * (h_x1 - h_n)
+        x = Hinv(u)
+        k = np.clip(np.floor(x + 0.5), 1, N)
+        ok = (k - x <= sq) | (u >= H(k + 0.5) - h(k))
+        out[todo[ok]] = k[ok].astype(np.int64)
+        todo = todo[~ok]
+    return out
+
+
+# --------------------------------------------------------------------------------------------
+# plain single table: u64 keys, u32 values = batch index
+# --------------------------------------------------------------------------------------------
+def plain_table(seed: int = 1, log2_keys: int = 16, log2_capacity: int = 17) -> dict:
+    rng = rng_for(seed)
+    n = 1 << log2_keys
+    keys = distinct_u64(rng, n)
+    vals = np.arange(n, dtype=np.uint32)
+    half = n // 2
+    present = keys[rng.integers(0, n, size=half)]
+    absent = distinct_u64(rng, n - half, exclude=keys)
+    q1 = np.concatenate([present, absent])
+    q1 = q1[rng.permutation(q1.size)]
+    erase = keys[rng.choice(n, size=n // 4, replace=False)]
+    q2 = keys[rng.permutation(n)]
+    return dict(capacity=1 << log2_capacity, insert_keys=keys, insert_vals=vals, find1=q1,
+                erase=erase, find2=q2)
+
+
+# --------------------------------------------------------------------------------------------
+# large table at load factor 0.8: u64 keys, u64 values = insertion ordinal
+# --------------------------------------------------------------------------------------------
+def large_table(seed: int = 3, log2_keys: int = 26, log2_queries: int = 27, log2_churn: int = 24,
+                absent_frac: float = 0.2, zipf_s: float = 1.1, load_factor: float = 0.8,
+                uniform: bool = False) -> dict:
+    """Fill to ``load_factor``, Zipf finds with ``absent_frac`` absent keys, erase + fresh re-insert.
+
+    ``capacity`` = live keys / load factor, the number of 16-byte slots (2^26 keys -> 83,886,080
+    slots, 1.342 GB).  The churn (erase 2^24 then insert 2^24 fresh keys) returns to the same load.
+    """
+    rng = rng_for(seed)
+    n = 1 << log2_keys
+    nq = 1 << log2_queries
+    nc = 1 << log2_churn
+    capacity = int(round(n / load_factor))
+    keys = distinct_u64(rng, n)
+    vals = np.arange(n, dtype=np.uint64)
+    n_abs = int(round(nq * absent_frac))
+    n_pre = nq - n_abs
+    if uniform:
+        pre = keys[rng.integers(0, n, size=n_pre)]
+    else:
+        perm = rng.permutation(n)                     # rank r (1-based) -> keys[perm[r-1]]
+        ranks = zipf_ranks(rng, n_pre, n, zipf_s)
+        pre = keys[perm[ranks - 1]]
+    fresh = distinct_u64(rng, n_abs + nc, exclude=keys)
+    absent = fresh[:n_abs]
+    q = np.concatenate([pre, absent])
+    q = q[rng.permutation(nq)]
+    erase = keys[rng.choice(n, size=nc, replace=False)]
+    reins = fresh[n_abs:]
+    reins_vals = np.arange(n, n + nc, dtype=np.uint64)
+    return dict(capacity=capacity, insert_keys=keys, insert_vals=vals, find=q, erase=erase,
+                reinsert_keys=reins, reinsert_vals=reins_vals)
+
+
+# --------------------------------------------------------------------------------------------
+# voxel-block coordinates
+# --------------------------------------------------------------------------------------------
+def pack_int3(x, y, z) -> np.ndarray:
+    """Pack signed 21-bit block coordinates into one u64: x in bits 0-20, y in 21-41, z in 42-62.
+
+    This is the key encoding of the voxel workload (an input format, not part of the method):
+    each component is taken modulo 2^21 (two's complement), bit 63 is zero.
+    """
+    x = np.asarray(x, dtype=np.int64).astype(np.uint64) & U64(M21)
+    y = np.asarray(y, dtype=np.int64).astype(np.uint64) & U64(M21)
+    z = np.asarray(z, dtype=np.int64).astype(np.uint64) & U64(M21)
+    return x | (y << U64(21)) | (z << U64(42))
+
+
+def _surface_points(rng, n_spheres, n_planes, grid_half, r_lo, r_hi, npts):
+    """Area-weighted uniform points on spheres and clipped planes inside [-grid_half, grid_half)^3."""
+    radii = rng.uniform(r_lo, r_hi, size=n_spheres)
+    centres = np.stack([rng.uniform(-grid_half + r, grid_half - r, size=3) for r in radii])
+    normals = rng.normal(size=(n_planes, 3))
+    normals /= np.linalg.norm(normals, axis=1, keepdims=True)
+    anchors = rng.uniform(-grid_half / 2, grid_half / 2, size=(n_planes, 3))
+    # plane area inside the cube: approximate by the square of side 2*grid_half spanned in the plane
+    sphere_area = 4.0 * math.pi * radii ** 2
+    plane_area = np.full(n_planes, (2.0 * grid_half) ** 2)
+    w = np.concatenate([sphere_area, plane_area])
+    w = w / w.sum()
+    which = rng.choice(w.size, size=npts, p=w)
+    pts = np.empty((npts, 3))
+    sph = which < n_spheres
+    ns = int(sph.sum())
+    d = rng.normal(size=(ns, 3))
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    idx = which[sph]
+    pts[sph] = centres[idx] + d * radii[idx, None]
+    pl = ~sph
+    pidx = which[pl] - n_spheres
+    nrm = normals[pidx]
+    # orthonormal basis (u, v) of each plane
+    a = np.where(np.abs(nrm[:, :1]) < 0.9, np.array([[1.0, 0, 0]]), np.array([[0, 1.0, 0]]))
+    u = np.cross(nrm, a)
+    u /= np.linalg.norm(u, axis=1, keepdims=True)
+    v = np.cross(nrm, u)
+    st = rng.uniform(-2.0 * grid_half, 2.0 * grid_half, size=(pl.sum(), 2))
+    pts[pl] = anchors[pidx] + u * st[:, :1] + v * st[:, 1:]
+    inside = np.all((pts >= -grid_half) & (pts < grid_half), axis=1)
+    return pts[inside]
+
+
+def voxel_blocks(seed: int = 2, n_distinct: int = 1 << 22, n_resident: int = 1 << 20,
+                 frames: int = 100, frame_queries: int = 1 << 18, hit_frac: float = 0.9,
+                 n_spheres: int = 64, n_planes: int = 8, grid: int = 4096,
+                 r_lo: float = 50.0, r_hi: float = 400.0) -> dict:
+    """Reconstruction-style block keys visited by a frustum that moves along a seeded direction.
+
+    The distinct surface blocks are sorted by their projection on a random unit direction; the
+    first ``n_resident`` are the initial residents.  Frame f queries ``frame_queries`` keys: the
+    next ``misses`` unseen blocks along the path plus ``hits`` blocks drawn without replacement from
+    the trailing resident window, shuffled.  The caller inserts the misses after each find.
+    """
+    rng = rng_for(seed)
+    half = grid // 2
+    blocks = np.empty((0, 3), dtype=np.int64)
+    while blocks.shape[0] < n_distinct:
+        need = n_distinct - blocks.shape[0]
+        pts = _surface_points(rng, n_spheres, n_planes, half, r_lo, r_hi, max(need * 2, 4096))
+        b = np.floor(pts).astype(np.int64)
+        b = np.concatenate([blocks, b])
+        _, first = np.unique(b, axis=0, return_index=True)
+        first.sort()
+        blocks = b[first][:n_distinct]
+    keys = pack_int3(blocks[:, 0], blocks[:, 1], blocks[:, 2])
+    d = rng.normal(size=3)
+    d /= np.linalg.norm(d)
+    proj = blocks.astype(np.float64) @ d
+    order = np.lexsort((keys, proj))
+    path = keys[order]
+    misses = int(round(frame_queries * (1.0 - hit_frac)))
+    hits = frame_queries - misses
+    window = n_resident // 2
+    frame_list = []
+    for f in range(frames):
+        end = n_resident + misses * f
+        new = path[end:end + misses]
+        lo = max(0, end - window)
+        hit = path[lo + rng.choice(end - lo, size=hits, replace=False)]
+        q = np.concatenate([hit, new])
+        frame_list.append(q[rng.permutation(q.size)])
+    return dict(path=path, residents=path[:n_resident], frames=frame_list,
+                pool_capacity=1 << 22, bucket_count=1 << 21)

@@ -1,0 +1,277 @@
+"""Pins of the CPU oracle against things other than itself (no GPU needed).
+
+* brute force (tests/bruteforce.py) on hypothesis-generated op sequences over a tiny key universe
+  that forces duplicates, reserved-looking bit patterns and capacity exhaustion;
+* Python's dict as the textbook map on larger random batches;
+* the paper's printed spatial-hash constants (tests/golden), the XOR decomposition of that hash,
+  and the independence of its bucket (mod 2^21) from the sign extension of the 21-bit fields;
+* closed forms of the pool order, capacity exhaustion and empty-table cases;
+* the invariants the chained layout must keep after every batch;
+* layout independence: results are identical under every bucket count and hash.
+"""
+import os
+
+import numpy as np
+import pytest
+from hypothesis import HealthCheck, given, settings
+from hypothesis import strategies as st
+
+import oracle
+from oracle import HASH_MIX64, HASH_VOXEL21, OraclePool, OracleTable
+from paper_1908_05936_amd.workloads import pack_int3
+from tests.bruteforce import BrutePool, BruteTable
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+U64MAX = (1 << 64) - 1
+UNIVERSE = list(range(16)) + [0, U64MAX, U64MAX - 1, 1 << 63]
+
+
+def _check(t, pool=None, from_pool=False):
+    bad, what = t.check(pool, from_pool)
+    assert bad == 0, f"invariant bits {what:#x}"
+
+
+# ------------------------------------------------------------------------------------------
+# brute force
+# ------------------------------------------------------------------------------------------
+keys_st = st.lists(st.sampled_from(UNIVERSE), min_size=0, max_size=24)
+map_op = st.tuples(st.sampled_from(["insert", "find", "erase", "clear"]), keys_st,
+                   st.lists(st.integers(0, U64MAX), min_size=24, max_size=24))
+
+
+@settings(max_examples=300, deadline=None, suppress_health_check=[HealthCheck.too_slow])
+@given(cap=st.integers(0, 12), bits=st.sampled_from([32, 64]), nb=st.sampled_from([1, 3, 8, 64]),
+       hk=st.sampled_from([HASH_MIX64, HASH_VOXEL21]), ops=st.lists(map_op, max_size=12))
+def test_map_ops_match_bruteforce(cap, bits, nb, hk, ops):
+    t = OracleTable(cap, bits, hk, nb)
+    b = BruteTable(cap, bits)
+    mask = (1 << bits) - 1
+    for kind, keys, vals in ops:
+        vals = [v & mask for v in vals[:len(keys)]]
+        k = np.array(keys, dtype=np.uint64)
+        if kind == "insert":
+            got = t.insert(k, np.array(vals, dtype=np.uint64))
+            assert got.tolist() == b.insert(keys, vals)
+        elif kind == "find":
+            out, fd = t.find(k)
+            eo, ef = b.find(keys)
+            assert [int(x) for x in out] == eo and fd.tolist() == ef
+        elif kind == "erase":
+            assert t.erase(k).tolist() == b.erase(keys)
+        else:
+            t.clear()
+            b.pairs = []
+        assert t.size() == len(b.pairs)
+        ks, vs = t.dump()
+        assert list(zip(ks.tolist(), [int(v) for v in vs])) == b.dump()
+        _check(t)
+
+
+alloc_op = st.tuples(st.sampled_from(["insert_alloc", "erase_release", "find"]), keys_st)
+
+
+@settings(max_examples=300, deadline=None, suppress_health_check=[HealthCheck.too_slow])
+@given(cap=st.integers(0, 12), pcap=st.integers(0, 12), nb=st.sampled_from([1, 5, 32]),
+       ops=st.lists(alloc_op, max_size=12))
+def test_pool_ops_match_bruteforce(cap, pcap, nb, ops):
+    t = OracleTable(cap, 32, HASH_MIX64, nb)
+    p = OraclePool(pcap)
+    b = BruteTable(cap, 32)
+    bp = BrutePool(pcap)
+    for kind, keys in ops:
+        k = np.array(keys, dtype=np.uint64)
+        if kind == "insert_alloc":
+            out, stt = t.insert_alloc(p, k)
+            eo, es = b.insert_alloc(bp, keys)
+            assert out.tolist() == eo and stt.tolist() == es
+        elif kind == "erase_release":
+            assert t.erase_release(p, k).tolist() == b.erase_release(bp, keys)
+        else:
+            out, fd = t.find(k)
+            eo, ef = b.find(keys)
+            assert [int(x) for x in out] == eo and fd.tolist() == ef
+        assert p.dump().tolist() == bp.stack
+        _check(t, p, from_pool=True)
+
+
+@settings(max_examples=200, deadline=None)
+@given(pcap=st.integers(0, 10),
+       ops=st.lists(st.tuples(st.sampled_from(["pop", "push"]), st.integers(0, 8),
+                              st.lists(st.integers(-5, 20), min_size=8, max_size=8)), max_size=10))
+def test_pool_stack_matches_bruteforce(pcap, ops):
+    p = OraclePool(pcap)
+    bp = BrutePool(pcap)
+    for kind, n, vals in ops:
+        if kind == "pop":
+            out, stt = p.pop(n)
+            eo, es = bp.pop(n)
+            assert out.tolist() == eo and stt.tolist() == es
+        else:
+            assert p.push(np.array(vals[:n], dtype=np.int32)).tolist() == bp.push(vals[:n])
+        assert p.dump().tolist() == bp.stack
+
+
+# ------------------------------------------------------------------------------------------
+# Python dict as the textbook map, at a size brute force cannot reach
+# ------------------------------------------------------------------------------------------
+@pytest.mark.parametrize("seed", [0, 1])
+def test_dict_replay(seed):
+    rng = np.random.default_rng(seed)
+    universe = rng.integers(0, 1 << 64, size=3000, dtype=np.uint64)
+    cap = 2000
+    t = OracleTable(cap, 64, HASH_MIX64, 997)
+    d = {}
+    for step in range(12):
+        kind = ["insert", "find", "erase"][step % 3]
+        k = universe[rng.integers(0, universe.size, size=4000)]
+        if kind == "insert":
+            v = rng.integers(0, 1 << 64, size=k.size, dtype=np.uint64)
+            got = t.insert(k, v)
+            exp = []
+            for kk, vv in zip(k.tolist(), v.tolist()):
+                if kk in d:
+                    exp.append(0)
+                elif len(d) == cap:
+                    exp.append(2)
+                else:
+                    d[kk] = vv
+                    exp.append(1)
+            assert got.tolist() == exp
+        elif kind == "find":
+            out, fd = t.find(k)
+            assert fd.tolist() == [int(kk in d) for kk in k.tolist()]
+            assert out.tolist() == [d.get(kk, U64MAX) for kk in k.tolist()]
+        else:
+            got = t.erase(k)
+            exp = []
+            for kk in k.tolist():
+                exp.append(int(d.pop(kk, None) is not None))
+            assert got.tolist() == exp
+        assert t.size() == len(d)
+        _check(t)
+
+
+# ------------------------------------------------------------------------------------------
+# spatial hash of Section 4.1
+# ------------------------------------------------------------------------------------------
+def _golden_constants():
+    out = {}
+    with open(os.path.join(GOLDEN, "voxel21_constants.txt")) as f:
+        for line in f:
+            if line.strip() and not line.startswith("#"):
+                axis, m = line.split()
+                out[axis] = int(m)
+    return out
+
+
+def test_voxel_hash_unit_vectors_are_the_printed_constants():
+    c = _golden_constants()
+    assert oracle.voxel21_hash(int(pack_int3(1, 0, 0))) == c["x"]
+    assert oracle.voxel21_hash(int(pack_int3(0, 1, 0))) == c["y"]
+    assert oracle.voxel21_hash(int(pack_int3(0, 0, 1))) == c["z"]
+    assert oracle.voxel21_hash(0) == 0
+    # a negative int converts to size_t by adding 2^64
+    assert oracle.voxel21_hash(int(pack_int3(-1, 0, 0))) == (1 << 64) - c["x"]
+    assert oracle.voxel21_hash(int(pack_int3(0, 0, -1))) == (1 << 64) - c["z"]
+    # 2 * the x constant still fits in an int; 30 * it wraps past 2^31
+    assert oracle.voxel21_hash(int(pack_int3(2, 0, 0))) == 2 * c["x"]
+    wrapped = (30 * c["x"]) % (1 << 32)
+    assert wrapped >= 1 << 31
+    assert oracle.voxel21_hash(int(pack_int3(30, 0, 0))) == (1 << 64) - ((1 << 32) - wrapped)
+
+
+def test_voxel_hash_xor_decomposition_and_21bit_buckets():
+    c = _golden_constants()
+    rng = np.random.default_rng(7)
+    xyz = rng.integers(-(1 << 20), 1 << 20, size=(2000, 3))
+    M = (1 << 21) - 1
+    for x, y, z in xyz.tolist():
+        h = oracle.voxel21_hash(int(pack_int3(x, y, z)))
+        hx = oracle.voxel21_hash(int(pack_int3(x, 0, 0)))
+        hy = oracle.voxel21_hash(int(pack_int3(0, y, 0)))
+        hz = oracle.voxel21_hash(int(pack_int3(0, 0, z)))
+        assert h == hx ^ hy ^ hz
+        # bucket mod 2^21 depends only on the unsigned 21-bit fields, exact integer arithmetic
+        ux, uy, uz = x & M, y & M, z & M
+        assert h & M == ((ux * c["x"]) ^ (uy * c["y"]) ^ (uz * c["z"])) & M
+
+
+def test_voxel_bucket_reduction():
+    c = _golden_constants()
+    t21 = OracleTable(8, 32, HASH_VOXEL21, 1 << 21)
+    t1000 = OracleTable(8, 32, HASH_VOXEL21, 1000)
+    k = int(pack_int3(-1, 0, 0))
+    assert t21.bucket_of(k) == ((1 << 64) - c["x"]) % (1 << 21)
+    assert t1000.bucket_of(k) == ((1 << 64) - c["x"]) % 1000
+    assert t21.bucket_of(int(pack_int3(0, 1, 0))) == c["y"] % (1 << 21)
+
+
+# ------------------------------------------------------------------------------------------
+# closed forms and special cases
+# ------------------------------------------------------------------------------------------
+def test_fresh_pool_order_and_lifo_reuse():
+    p = OraclePool(10)
+    out, stt = p.pop(4)
+    assert out.tolist() == [0, 1, 2, 3] and stt.tolist() == [1] * 4
+    t = OracleTable(100, 32, HASH_MIX64, 17)
+    p2 = OraclePool(50)
+    keys = np.array([5, 9, 5, 7, 11, 9], dtype=np.uint64)
+    out, stt = t.insert_alloc(p2, keys)
+    # first occurrences take 0, 1, 2, 3 in order; repeats report the existing value
+    assert out.tolist() == [0, 1, 0, 2, 3, 1]
+    assert stt.tolist() == [1, 1, 0, 1, 1, 0]
+    er = t.erase_release(p2, np.array([9, 11, 9, 5], dtype=np.uint64))
+    assert er.tolist() == [1, 1, 0, 1]
+    out, stt = t.insert_alloc(p2, np.array([100, 101, 102, 103], dtype=np.uint64))
+    # pushed 1, 3, 0 (in batch order) -> popped in reverse, then the fresh index 4
+    assert out.tolist() == [0, 3, 1, 4]
+
+
+def test_capacity_exhaustion():
+    C = 37
+    t = OracleTable(C, 64, HASH_MIX64, 8)
+    keys = np.arange(1000, 1000 + C + 5, dtype=np.uint64)
+    st_ = t.insert(keys, keys)
+    assert st_.tolist() == [1] * C + [2] * 5
+    assert t.size() == C and t.error() & 1
+    # present keys still report PRESENT at capacity; repeats of a FULL key stay FULL
+    st2 = t.insert(np.array([1000, 5000, 5000], dtype=np.uint64), np.zeros(3, np.uint64))
+    assert st2.tolist() == [0, 2, 2]
+    t0 = OracleTable(0, 64, HASH_MIX64, 1)
+    assert t0.insert(np.array([1], dtype=np.uint64), np.array([1], np.uint64)).tolist() == [2]
+
+
+def test_empty_table_and_reserved_patterns():
+    t = OracleTable(16, 64, HASH_MIX64, 4)
+    ks = np.array([0, U64MAX, U64MAX - 1, 1 << 63], dtype=np.uint64)
+    out, fd = t.find(ks)
+    assert fd.tolist() == [0] * 4 and out.tolist() == [U64MAX] * 4
+    assert t.erase(ks).tolist() == [0] * 4
+    assert t.insert(ks, ks).tolist() == [1] * 4
+    out, fd = t.find(ks)
+    assert fd.tolist() == [1] * 4 and out.tolist() == ks.tolist()
+    t32 = OracleTable(4, 32, HASH_MIX64, 4)
+    out, fd = t32.find(ks[:1])
+    assert out.dtype == np.uint32 and int(out[0]) == (1 << 32) - 1
+
+
+def test_results_do_not_depend_on_layout():
+    rng = np.random.default_rng(3)
+    base = rng.integers(0, 1 << 64, size=300, dtype=np.uint64)
+    batches = [base[rng.integers(0, 300, size=500)] for _ in range(6)]
+    ref = None
+    for hk, nb in [(HASH_MIX64, 1), (HASH_MIX64, 7), (HASH_MIX64, 4096), (HASH_VOXEL21, 1 << 21),
+                   (HASH_VOXEL21, 13)]:
+        t = OracleTable(250, 64, hk, nb)
+        res = []
+        for j, b in enumerate(batches):
+            if j % 3 == 0:
+                res.append(t.insert(b, b ^ np.uint64(0xABCDEF)).tolist())
+            elif j % 3 == 1:
+                res.append([x.tolist() for x in t.find(b)])
+            else:
+                res.append(t.erase(b).tolist())
+            _check(t)
+        if ref is None:
+            ref = res
+        assert res == ref
