@@ -1,0 +1,201 @@
+/*
+ * ct.h -- C ABI of the batch hash containers and index pool for AMD MI355X (gfx950).
+ *
+ * The containers follow the paper's STL-like containers: unordered_map / unordered_set
+ * (Section 4.1) and the vector / deque back operations (Sections 4.2 and 4.3), whose design
+ * decisions are given at the start of Section 4 (fixed capacity; insert and erase as the central
+ * operations; lock-free, non-blocking lookups; inserting beyond capacity as the only failure).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  * Counts are int64_t (the paper's signed index type, Section 3.2).  A negative count is an
+ *    argument error; a zero count is a no-op that returns CT_OK.
+ *  * Key, value, status and index arrays are DEVICE pointers owned by the caller.  Inputs must not
+ *    alias outputs.  Output pointers documented as nullable may be NULL to skip that output.
+ *  * `stream` is a hipStream_t passed as void* (NULL = the default stream).  Batch calls only
+ *    enqueue work and return; calls documented as "synchronises" wait for `stream`.
+ *  * Calls on one table (or pool) must be ordered on one stream by the caller; different tables
+ *    are independent and may run concurrently on different streams.
+ *  * Argument errors are detected on the host before anything is enqueued and return
+ *    CT_E_INVALID; a failed HIP launch returns CT_E_HIP.  Per-element outcomes (FULL, pool empty)
+ *    are reported in the status arrays and OR-ed into a sticky device error word (ct_get_error).
+ *  * Every 2^64 key value is a legal key: occupancy is kept without reserving key values
+ *    (the indicator principle of Section 5.1).
+ *
+ * Batch semantics
+ * ---------------
+ * A batch of n elements gives exactly the results of n single-element calls made one after the
+ * other in index order.  So among equal keys in one batch the lowest index acts first and later
+ * copies see the state it left; a key that is already present is never modified by insert.
+ *
+ * Memory
+ * ------
+ * A table or pool lives in one caller-provided device buffer of the size reported by
+ * ct_table_bytes / ct_pool_bytes, at least 256-byte aligned.  The buffer holds the slots, the
+ * counters and the per-batch scratch; the library allocates no device memory.  The handle returned
+ * by the init call is host memory owned by the library until the matching destroy call.
+ */
+#ifndef CT_H
+#define CT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum ct_status {
+    CT_OK = 0,
+    CT_E_INVALID = 1, /* bad argument; nothing was enqueued */
+    CT_E_FULL = 2,    /* reserved for callers mapping the sticky error word */
+    CT_E_EMPTY = 3,   /* reserved for callers mapping the sticky error word */
+    CT_E_NOMEM = 4,   /* host allocation of a handle failed */
+    CT_E_HIP = 5      /* a HIP runtime call or kernel launch failed */
+} ct_status;
+
+/* Per-element insert status (status arrays of ct_insert_batch / ct_insert_alloc_batch). */
+#define CT_PRESENT 0u  /* key was already present; nothing modified (Section 4.1, insert) */
+#define CT_INSERTED 1u /* key stored */
+#define CT_FULL 2u     /* capacity (or the pool) exhausted: the only failure case (Section 4) */
+
+/* Bits of the sticky device error word. */
+#define CT_ERR_FULL 1u      /* an insert met a full table */
+#define CT_ERR_POOL 2u      /* a pool ran empty (pop) or over capacity (push) */
+#define CT_ERR_INTERNAL 0x80000000u /* an internal consistency check failed (a library bug) */
+
+typedef enum ct_val_kind {
+    CT_VAL_NONE = 0, /* unordered_set: keys only */
+    CT_VAL_U32 = 1,  /* unordered_map with 32-bit mapped values */
+    CT_VAL_U64 = 2   /* unordered_map with 64-bit mapped values */
+} ct_val_kind;
+
+typedef enum ct_hash_kind {
+    CT_HASH_MIX64 = 0,  /* MurmurHash3 64-bit finaliser, multiply-high reduction: generic keys */
+    CT_HASH_VOXEL21 = 1 /* spatial hash of Section 4.1 on packed signed 21-bit int3 keys:
+                           (x*73856093 ^ y*19349669 ^ z*83492791) in 32-bit wrapping int
+                           arithmetic, sign-extended to 64 bits, modulo bucket_count.
+                           Packing: x bits 0-20, y bits 21-41, z bits 42-62. */
+} ct_hash_kind;
+
+/* Table description. */
+typedef struct ct_table_desc {
+    int64_t capacity;     /* C: number of distinct keys guaranteed storable whatever their hashes
+                             (the fixed capacity of Section 4).  C >= 0. */
+    int32_t val_kind;     /* ct_val_kind */
+    int32_t hash_kind;    /* ct_hash_kind */
+    int64_t bucket_count; /* home buckets, 8 slots each (one 128-byte line); 0 = ceil(C / 8).
+                             Must satisfy 8 * bucket_count >= C and bucket_count >= 1. */
+    int64_t chunk;        /* keys handled per internal insert/erase chunk; a power of two in
+                             [1024, 2^24]; 0 = min(2^20, max(1024, pow2ceil(C))).  Batches larger
+                             than a chunk run as consecutive chunks (same results). */
+} ct_table_desc;
+
+typedef struct ct_table ct_table;
+typedef struct ct_pool ct_pool;
+
+/* --- tables ------------------------------------------------------------------------------- */
+
+/* Bytes of device memory a table with description `d` needs.  Host only. */
+ct_status ct_table_bytes(const ct_table_desc *d, int64_t *bytes);
+
+/* Create an empty table in `d_buf` (device, `bytes` >= ct_table_bytes, 256-byte aligned) and
+   return its handle in *out.  Enqueues the initialisation on `stream` (createDeviceObject,
+   Section 3.7). */
+ct_status ct_table_init(void *d_buf, int64_t bytes, const ct_table_desc *d, void *stream,
+                        ct_table **out);
+
+/* Release the host handle (destroyDeviceObject, Section 3.7).  The device buffer stays owned by
+   the caller; work already enqueued must have finished before the buffer is reused. */
+ct_status ct_table_destroy(ct_table *t);
+
+/* Geometry of a table: home buckets and chunk size (host only, either pointer nullable). */
+ct_status ct_table_info(const ct_table *t, int64_t *bucket_count, int64_t *chunk);
+
+/* Iterator-based insert of an array (Section 4.1, insert).  keys[n] u64; vals[n] u32 or u64 by the
+   table's value kind (ignored and nullable for sets, required otherwise).  status[n] (nullable):
+   CT_PRESENT, CT_INSERTED or CT_FULL per element. */
+ct_status ct_insert_batch(ct_table *t, const uint64_t *keys, const void *vals, int64_t n,
+                          uint8_t *status, void *stream);
+
+/* find / contains (Section 4.1) for an array.  vals_out[n] (nullable; u32 or u64 by value kind;
+   not allowed for sets) receives the mapped value, or all-ones of the value width when the key is
+   absent; found[n] (nullable) receives 1 when present, else 0.  Read-only and lock-free. */
+ct_status ct_find_batch(ct_table *t, const uint64_t *keys, int64_t n, void *vals_out,
+                        uint8_t *found, void *stream);
+
+/* erase (Section 4.1) for an array.  erased[n] (nullable): 1 if the key was present before this
+   element, else 0. */
+ct_status ct_erase_batch(ct_table *t, const uint64_t *keys, int64_t n, uint8_t *erased,
+                         void *stream);
+
+/* Number of live keys.  Synchronises `stream`. */
+ct_status ct_size(ct_table *t, int64_t *h_size, void *stream);
+
+/* Remove every key (capacity unchanged; Section 4 "Capacity").  The pool, if any, is untouched. */
+ct_status ct_clear(ct_table *t, void *stream);
+
+/* Copy the live (key, value) pairs in unspecified order into keys_out/vals_out (device,
+   `cap` entries; vals_out nullable, ignored for sets; values written as u64) and return the live
+   count in *h_count (which may exceed `cap`; only `cap` pairs are written).  Synchronises.  The
+   range-to-vector selection of Section 3.6. */
+ct_status ct_dump(ct_table *t, uint64_t *keys_out, uint64_t *vals_out, int64_t cap,
+                  int64_t *h_count, void *stream);
+
+/* Check the layout invariants on the device: every live key is reachable from its home bucket,
+   the live count equals the size counter.  *h_violations = number of failures.  Synchronises. */
+ct_status ct_check_invariants(ct_table *t, int64_t *h_violations, void *stream);
+
+/* Read and clear the sticky error word (CT_ERR_* bits).  Synchronises. */
+ct_status ct_get_error(ct_table *t, uint32_t *h_err, void *stream);
+
+/* --- index pool: vector/deque of int32 used as a LIFO free list (Sections 4.2, 4.3) -------- */
+
+/* Bytes of device memory a pool of `capacity` int32 entries needs.  Host only. */
+ct_status ct_pool_bytes(int64_t capacity, int64_t *bytes);
+
+/* Create a full pool in `d_buf`: it holds 0 .. capacity-1 and pops return 0, 1, 2, ... */
+ct_status ct_pool_init(void *d_buf, int64_t bytes, int64_t capacity, void *stream, ct_pool **out);
+
+ct_status ct_pool_destroy(ct_pool *p);
+
+/* pop_back n times (Section 4.2: pop_back returns the removed value).  out[n] (nullable) gets the
+   value or -1 once the pool is empty; status[n] (nullable) 1 = popped, 2 = empty. */
+ct_status ct_pool_pop_batch(ct_pool *p, int64_t n, int32_t *out, uint8_t *status, void *stream);
+
+/* push_back in[0..n) in order (Section 4.2).  status[n] (nullable) 1 = stored, 2 = the pool was
+   at capacity (value dropped, CT_ERR_POOL set). */
+ct_status ct_pool_push_batch(ct_pool *p, const int32_t *in, int64_t n, uint8_t *status,
+                             void *stream);
+
+/* Number of entries in the pool.  Synchronises. */
+ct_status ct_pool_size(ct_pool *p, int64_t *h_size, void *stream);
+
+/* Copy the stack bottom-first into out (device, `cap` entries) and return the entry count in
+   *h_count.  Synchronises. */
+ct_status ct_pool_dump(ct_pool *p, int32_t *out, int64_t cap, int64_t *h_count, void *stream);
+
+/* Read and clear the pool's sticky error word.  Synchronises. */
+ct_status ct_pool_get_error(ct_pool *p, uint32_t *h_err, void *stream);
+
+/* --- tables whose values come from a pool (block map of Section 4.1: key -> block index) --- */
+
+/* Insert of an array into a CT_VAL_U32 table where every new key takes pop_back() of `p` as its
+   value, new keys taking pool entries in batch order.  vals_out[n] (nullable, int32): the new or
+   existing value, -1 on FULL.  status[n] (nullable): CT_PRESENT / CT_INSERTED / CT_FULL, FULL
+   when the table is at capacity or the pool is empty. */
+ct_status ct_insert_alloc_batch(ct_table *t, ct_pool *p, const uint64_t *keys, int64_t n,
+                                int32_t *vals_out, uint8_t *status, void *stream);
+
+/* Erase of an array where each removed key's value is pushed back to `p`, in batch order.
+   erased[n] nullable as for ct_erase_batch. */
+ct_status ct_erase_release_batch(ct_table *t, ct_pool *p, const uint64_t *keys, int64_t n,
+                                 uint8_t *erased, void *stream);
+
+/* Static description of a status code. */
+const char *ct_status_str(ct_status s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CT_H */

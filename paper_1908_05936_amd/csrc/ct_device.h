@@ -1,0 +1,188 @@
+// ct_device.h -- device-side layout and wave64 helpers of the batch hash containers (gfx950).
+//
+// Layout of a table buffer (one caller-owned device allocation):
+//   [Header, 256 B][home buckets: nb x 128 B][dedup buckets][dup list][flags][refs][tile sums]
+//
+// Home buckets.  A bucket is one 128-byte line of 8 slots {u64 key, u64 value}.  A key's home
+// bucket is h(key) mod nb; a key that does not fit overflows into the following buckets
+// (cyclically), so every one of the 8*nb slots can hold any key and the fixed capacity of
+// Section 4 is a hard guarantee.  Occupancy is kept in the key word with two reserved bit
+// patterns, kEmpty and kTomb; the two keys that share those patterns are stored out of band in
+// the header (spec_*), so every 2^64 key value stays legal (the indicator principle of
+// Section 5.1 without a separate bitset).
+//
+// Probe rule.  A lookup scans buckets from home and stops at the first bucket holding the key or
+// holding a kEmpty slot.  Inserts claim the first free (kEmpty or kTomb) slot at or before the
+// first bucket that holds a kEmpty slot, so every live key is reachable.  Erase writes kEmpty
+// when its bucket already holds a kEmpty slot (no probe sequence passes such a bucket) and kTomb
+// otherwise.
+//
+// Cooperation.  Eight lanes of a wave64 probe one key: lane j loads slot j of the bucket (one
+// 16-byte load per lane, one 128-byte line per group), a ballot answers "which slot matches /
+// is empty", and a shuffle broadcasts the matching value.  A wave therefore has eight keys in
+// flight per step.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ct {
+
+constexpr uint64_t kEmpty = ~0ull;      // slot never held a key since the last clear
+constexpr uint64_t kTomb = ~0ull - 1;   // slot held a key that was erased
+constexpr int kSlots = 8;               // slots per bucket (one 128-byte line)
+constexpr uint32_t kNone = 0xFFFFFFFFu;
+constexpr uint64_t kNoPos = ~0ull;
+constexpr uint64_t kSpecRef = ~0ull - 3;  // refs kSpecRef+0/+1 name the out-of-band keys
+constexpr int kTile = 1024;             // elements per tile of the rank scan
+constexpr int kBlock = 256;             // threads per block of every group kernel
+
+enum : uint8_t { kPresent = 0, kInserted = 1, kFull = 2, kNoStatus = 0xFF };
+enum : uint32_t { kErrFull = 1u, kErrPool = 2u, kErrInternal = 0x80000000u };
+
+struct alignas(16) Slot {
+  uint64_t key;
+  uint64_t val;
+};
+struct alignas(128) Bucket {
+  Slot s[kSlots];
+};
+
+// dedup scratch: key -> lowest chunk index holding it
+struct alignas(16) DSlot {
+  uint64_t key;
+  uint32_t idx;
+  uint32_t pad;
+};
+struct alignas(128) DBucket {
+  DSlot s[kSlots];
+};
+
+struct alignas(256) Header {
+  uint64_t size;           // live keys, out-of-band keys included
+  uint64_t size0;          // size when the current chunk started
+  uint64_t spec_val[2];    // values of the keys kTomb (index 0) and kEmpty (index 1)
+  uint32_t spec_live[2];
+  uint32_t spec_first[2];  // lowest chunk index of each out-of-band key in the current chunk
+  uint32_t err;            // sticky CT_ERR_* bits
+  uint32_t fast;           // 1 when the current chunk cannot reach capacity or empty the pool
+  uint32_t ndup;           // duplicate elements listed for the current chunk
+  uint32_t nnew;           // flagged elements of the current chunk (set by the rank scan)
+  uint64_t dump_count;
+  uint64_t live_count;
+  uint64_t violations;
+};
+
+struct alignas(256) PoolHeader {
+  int64_t top;   // entries on the stack
+  int64_t top0;  // top when the current batch started
+  int64_t cap;
+  uint32_t err;
+};
+
+// Everything a kernel needs to reach a table; passed by value (a shallow copy, Section 3.7).
+struct TableView {
+  Bucket* bk;
+  uint64_t nb;
+  uint64_t cap;
+  Header* hdr;
+  DBucket* dd;
+  uint2* dup;       // (chunk index, index of its first occurrence)
+  uint8_t* flag;    // per chunk element: 1 = takes part in the rank scan
+  uint64_t* ref;    // per chunk element: claimed slot, or the value an erase releases
+  uint32_t* tsum;   // per tile: flagged count, then its exclusive prefix
+  int hash;         // 0 mix64, 1 voxel21
+  int nb_pow2;
+};
+
+// ---------------------------------------------------------------------------------------------
+// hashes
+// ---------------------------------------------------------------------------------------------
+__device__ __forceinline__ uint64_t fmix64(uint64_t k) {  // MurmurHash3 finaliser (Appleby)
+  k ^= k >> 33;
+  k *= 0xff51afd7ed558ccdull;
+  k ^= k >> 33;
+  k *= 0xc4ceb9fe1a85ec53ull;
+  k ^= k >> 33;
+  return k;
+}
+
+__device__ __forceinline__ int32_t sfield21(uint64_t v) {  // low 21 bits, sign-extended
+  return ((int32_t)((uint32_t)v << 11)) >> 11;
+}
+
+// Spatial hash of Section 4.1 on a packed int3 key, as the 64-bit size_t the listing returns.
+__device__ __forceinline__ uint64_t voxel21(uint64_t key) {
+  const uint32_t x = (uint32_t)sfield21(key);
+  const uint32_t y = (uint32_t)sfield21(key >> 21);
+  const uint32_t z = (uint32_t)sfield21(key >> 42);
+  const uint32_t h = (x * 73856093u) ^ (y * 19349669u) ^ (z * 83492791u);
+  return (uint64_t)(int64_t)(int32_t)h;
+}
+
+__device__ __forceinline__ uint64_t home_of(const TableView& t, uint64_t key) {
+  if (t.hash == 1) {
+    const uint64_t h = voxel21(key);
+    return t.nb_pow2 ? (h & (t.nb - 1)) : (h % t.nb);
+  }
+  return __umul64hi(fmix64(key), t.nb);
+}
+
+__device__ __forceinline__ uint32_t dedup_home(uint64_t key, uint32_t dmask) {
+  return (uint32_t)(fmix64(key ^ 0x9E3779B97F4A7C15ull) >> 32) & dmask;
+}
+
+__device__ __forceinline__ uint64_t next_bucket(const TableView& t, uint64_t b) {
+  return (b + 1 == t.nb) ? 0 : b + 1;
+}
+
+// ---------------------------------------------------------------------------------------------
+// wave64 group helpers: 8 groups of 8 lanes per wave
+// ---------------------------------------------------------------------------------------------
+__device__ __forceinline__ int wave_lane() { return (int)(threadIdx.x & 63); }
+__device__ __forceinline__ int group_base() { return wave_lane() & ~7; }
+__device__ __forceinline__ uint32_t group_bits(uint64_t ballot) {
+  return (uint32_t)(ballot >> group_base()) & 0xFFu;
+}
+__device__ __forceinline__ int lowest(uint32_t m) { return __builtin_ctz(m); }
+
+// ---------------------------------------------------------------------------------------------
+// atomics with explicit order and scope.  Claims are relaxed at agent scope: a claim only has to
+// be unique, and the results of a batch are read after the kernel boundary that ends it.
+// ---------------------------------------------------------------------------------------------
+__device__ __forceinline__ bool cas64(uint64_t* p, uint64_t& expected, uint64_t desired) {
+  return __hip_atomic_compare_exchange_strong(p, &expected, desired, __ATOMIC_RELAXED,
+                                              __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint32_t amin32(uint32_t* p, uint32_t v) {
+  return __hip_atomic_fetch_min(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint32_t aadd32(uint32_t* p, uint32_t v) {
+  return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint64_t aadd64(uint64_t* p, uint64_t v) {
+  return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint32_t aor32(uint32_t* p, uint32_t v) {
+  return __hip_atomic_fetch_or(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Reserve a position in an append-only list for every active lane with `pred`, one atomic per wave.
+__device__ __forceinline__ uint32_t wave_append(bool pred, uint32_t* counter) {
+  const uint64_t m = __ballot(pred);
+  uint32_t base = 0;
+  if (m) {
+    const int leader = __builtin_ctzll(m);
+    if (wave_lane() == leader) base = aadd32(counter, (uint32_t)__builtin_popcountll(m));
+    base = __shfl(base, leader, 64);
+  }
+  return base + (uint32_t)__builtin_popcountll(m & ((1ull << wave_lane()) - 1ull));
+}
+
+// Sum of `v` over the wave; call with every lane of the wave active.
+__device__ __forceinline__ uint64_t wave_sum(uint64_t v) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+}  // namespace ct

@@ -1,0 +1,1147 @@
+// ct_table.hip -- gfx950 kernels and the C ABI of the batch hash containers and index pool.
+//
+// Operation pipelines (every kernel on the caller's stream, in this order):
+//   find           : k_find                                    one launch, read-only, lock-free
+//   insert (chunk) : k_prologue -> k_dedup -> k_insert [-> k_tile_count -> k_tile_scan -> k_final]
+//                    -> k_fix
+//   insert_alloc   : k_prologue -> k_dedup -> k_insert -> k_tile_count -> k_tile_scan -> k_final
+//                    -> k_fix
+//   erase          : k_prologue -> k_dedup -> k_erase
+//   erase_release  : k_prologue -> k_dedup -> k_erase -> k_tile_count -> k_tile_scan -> k_final
+//
+// Index-order semantics.  k_dedup records, per distinct key of the chunk, the lowest chunk index
+// holding it (an atomic min in a cache-resident scratch table).  Only that element (the "actor")
+// touches the table; later copies are resolved afterwards from its outcome (k_fix), which gives
+// exactly the results of a sequential replay.  Distinct actors never race on one key, so a claim
+// CAS can only fail because another key took the slot.  When a chunk might reach capacity or
+// empty the pool, or when values come from a pool, the new actors are ranked by an exclusive scan
+// in index order (k_tile_count / k_tile_scan) and k_final hands out capacity and pool entries by
+// rank, so the k-th new key of the chunk is the k-th to be stored, as in the sequential replay.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdint>
+#include <cstdlib>
+#include <new>
+
+#include "ct.h"
+#include "ct_device.h"
+
+using namespace ct;
+
+namespace {
+
+// ---------------------------------------------------------------------------------------------
+// value I/O by value kind (0 none, 1 u32, 2 u64); table slots always hold 64-bit values
+// ---------------------------------------------------------------------------------------------
+template <int VK>
+__device__ __forceinline__ uint64_t load_val(const void* vals, int64_t i) {
+  if constexpr (VK == 1) return (uint64_t)static_cast<const uint32_t*>(vals)[i];
+  else if constexpr (VK == 2) return static_cast<const uint64_t*>(vals)[i];
+  else return 0;
+}
+template <int VK>
+__device__ __forceinline__ void store_val(void* out, int64_t i, uint64_t v) {
+  if constexpr (VK == 1) static_cast<uint32_t*>(out)[i] = (uint32_t)v;
+  else if constexpr (VK == 2) static_cast<uint64_t*>(out)[i] = v;
+}
+template <int VK>
+__device__ __forceinline__ uint64_t sentinel() {
+  return VK == 1 ? 0xFFFFFFFFull : ~0ull;
+}
+
+// ---------------------------------------------------------------------------------------------
+// group-cooperative probes of the home table (8 lanes, converged within the group)
+// ---------------------------------------------------------------------------------------------
+struct Probe {
+  bool found;
+  bool had_empty;    // the bucket where the key was found holds a kEmpty slot
+  uint64_t val;
+  uint64_t pos;      // slot index b*8+c of the key when found
+  uint64_t free_b;   // first bucket with a free slot on the probe path (when !found)
+  bool has_free;
+};
+
+__device__ __forceinline__ Probe probe(const TableView& t, uint64_t key, int sub, bool want_free) {
+  Probe r;
+  r.found = false;
+  r.had_empty = false;
+  r.val = 0;
+  r.pos = kNoPos;
+  r.free_b = 0;
+  r.has_free = false;
+  uint64_t b = home_of(t, key);
+  for (uint64_t step = 0; step < t.nb; ++step) {
+    const Slot s = t.bk[b].s[sub];
+    const uint32_t m = group_bits(__ballot(s.key == key));
+    const uint32_t e = group_bits(__ballot(s.key == kEmpty));
+    if (m) {
+      const int c = lowest(m);
+      r.found = true;
+      r.had_empty = e != 0;
+      r.val = __shfl(s.val, group_base() + c, 64);
+      r.pos = b * kSlots + (uint64_t)c;
+      return r;
+    }
+    if (want_free && !r.has_free) {
+      const uint32_t f = e | group_bits(__ballot(s.key == kTomb));
+      if (f) {
+        r.has_free = true;
+        r.free_b = b;
+      }
+    }
+    if (e) return r;
+    b = next_bucket(t, b);
+  }
+  return r;
+}
+
+// Claim a free slot for an absent `key`, scanning forward from bucket `b`.  Returns the slot
+// index, or kNoPos when every bucket was tried (only possible when the table is physically full).
+// A stale view can only show a slot as free when it is not: the CAS then fails and reports the
+// truth, so the scan always makes progress.
+__device__ __forceinline__ uint64_t claim(const TableView& t, uint64_t key, uint64_t b, int sub) {
+  for (uint64_t step = 0; step < t.nb; ++step) {
+    const uint64_t cur = t.bk[b].s[sub].key;
+    uint32_t f = group_bits(__ballot(cur == kEmpty || cur == kTomb));
+    while (f) {
+      const int c = lowest(f);
+      int won = 0;
+      if (sub == c) {
+        uint64_t expected = cur;
+        won = cas64(&t.bk[b].s[c].key, expected, key) ? 1 : 0;
+      }
+      if (group_bits(__ballot(won))) return b * kSlots + (uint64_t)c;
+      f &= f - 1;
+    }
+    b = next_bucket(t, b);
+  }
+  return kNoPos;
+}
+
+// Lowest chunk index of `key` recorded by k_dedup.  The key is always there; the scan is bounded
+// anyway, and a miss makes the element act for itself and raises kErrInternal.
+__device__ __forceinline__ uint32_t first_index(const TableView& t, uint64_t key, uint32_t dmask,
+                                                int sub, uint32_t self) {
+  if (key >= kTomb) return t.hdr->spec_first[key - kTomb];
+  uint32_t b = dedup_home(key, dmask);
+  for (uint32_t step = 0; step <= dmask; ++step) {
+    const DSlot s = t.dd[b].s[sub];
+    const uint32_t m = group_bits(__ballot(s.key == key));
+    if (m) return __shfl(s.idx, group_base() + lowest(m), 64);
+    b = (b + 1) & dmask;
+  }
+  if (sub == 0) aor32(&t.hdr->err, kErrInternal);
+  return self;
+}
+
+// ---------------------------------------------------------------------------------------------
+// kernels
+// ---------------------------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_table_reset(TableView t, int zero_header) {
+  const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t nt = (int64_t)gridDim.x * blockDim.x;
+  const int64_t nslots = (int64_t)t.nb * kSlots;
+  uint4 empty = make_uint4(0xFFFFFFFFu, 0xFFFFFFFFu, 0u, 0u);
+  for (int64_t j = tid; j < nslots; j += nt)
+    *reinterpret_cast<uint4*>(&t.bk[j >> 3].s[j & 7]) = empty;
+  if (tid == 0) {
+    Header* h = t.hdr;
+    h->size = 0;
+    h->size0 = 0;
+    h->spec_val[0] = h->spec_val[1] = 0;
+    h->spec_live[0] = h->spec_live[1] = 0;
+    h->spec_first[0] = h->spec_first[1] = kNone;
+    if (zero_header) h->err = 0;
+    h->fast = 0;
+    h->ndup = 0;
+    h->nnew = 0;
+    h->dump_count = 0;
+    h->live_count = 0;
+    h->violations = 0;
+  }
+}
+
+// Per chunk: clear the dedup scratch, snapshot the counters, decide whether the chunk can reach
+// capacity (or empty the pool).
+__global__ __launch_bounds__(kBlock) void k_prologue(TableView t, PoolHeader* pool,
+                                                     uint32_t dbuckets, int64_t q) {
+  const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t nt = (int64_t)gridDim.x * blockDim.x;
+  const uint4 empty = make_uint4(0xFFFFFFFFu, 0xFFFFFFFFu, kNone, 0u);
+  for (int64_t j = tid; j < (int64_t)dbuckets * kSlots; j += nt)
+    *reinterpret_cast<uint4*>(&t.dd[j >> 3].s[j & 7]) = empty;
+  if (tid == 0) {
+    Header* h = t.hdr;
+    h->size0 = h->size;
+    h->spec_first[0] = h->spec_first[1] = kNone;
+    h->ndup = 0;
+    h->nnew = 0;
+    bool fast = h->size + (uint64_t)q <= t.cap;
+    if (pool) {
+      pool->top0 = pool->top;
+      fast = fast && pool->top >= q;
+    }
+    h->fast = fast ? 1u : 0u;
+  }
+}
+
+// Lowest index per distinct key of the chunk.
+__global__ __launch_bounds__(kBlock) void k_dedup(TableView t, const uint64_t* __restrict__ keys,
+                                                  int64_t q, uint32_t dmask) {
+  const int sub = threadIdx.x & 7;
+  const int64_t ng = (int64_t)gridDim.x * (kBlock / 8);
+  for (int64_t i = (int64_t)blockIdx.x * (kBlock / 8) + (threadIdx.x >> 3); i < q; i += ng) {
+    const uint64_t key = keys[i];
+    if (key >= kTomb) {
+      if (sub == 0) amin32(&t.hdr->spec_first[key - kTomb], (uint32_t)i);
+      continue;
+    }
+    uint32_t b = dedup_home(key, dmask);
+    for (;;) {
+      const DSlot s = t.dd[b].s[sub];
+      const uint32_t m = group_bits(__ballot(s.key == key));
+      if (m) {
+        if (sub == lowest(m)) amin32(&t.dd[b].s[sub].idx, (uint32_t)i);
+        break;
+      }
+      uint32_t e = group_bits(__ballot(s.key == kEmpty));
+      bool placed = false;
+      while (e) {
+        const int c = lowest(e);
+        int ok = 0;
+        if (sub == c) {
+          uint64_t expected = kEmpty;
+          if (cas64(&t.dd[b].s[c].key, expected, key) || expected == key) {
+            amin32(&t.dd[b].s[c].idx, (uint32_t)i);
+            ok = 1;
+          }
+        }
+        if (group_bits(__ballot(ok))) {
+          placed = true;
+          break;
+        }
+        e &= e - 1;
+      }
+      if (placed) break;
+      b = (b + 1) & dmask;
+    }
+  }
+}
+
+// Insert actors.  fast: claim directly.  Otherwise (or with a pool) flag new keys for ranking.
+template <int VK, bool ALLOC>
+__global__ __launch_bounds__(kBlock) void k_insert(TableView t, const uint64_t* __restrict__ keys,
+                                                   const void* __restrict__ vals, int64_t q,
+                                                   uint32_t dmask, uint8_t* __restrict__ status,
+                                                   int32_t* __restrict__ vout) {
+  const int sub = threadIdx.x & 7;
+  const bool fast = t.hdr->fast != 0;
+  const bool flags = ALLOC || !fast;
+  const int64_t ng = (int64_t)gridDim.x * (kBlock / 8);
+  uint64_t ins = 0;
+  for (int64_t i = (int64_t)blockIdx.x * (kBlock / 8) + (threadIdx.x >> 3); i < q; i += ng) {
+    const uint64_t key = keys[i];
+    const uint32_t first = first_index(t, key, dmask, sub, (uint32_t)i);
+    if (first != (uint32_t)i) {
+      const uint32_t slot = wave_append(sub == 0, &t.hdr->ndup);
+      if (sub == 0) {
+        t.dup[slot] = make_uint2((uint32_t)i, first);
+        if (flags) t.flag[i] = 0;
+      }
+      continue;
+    }
+    uint8_t st = kNoStatus;
+    uint8_t newf = 0;
+    if (key >= kTomb) {
+      if (sub == 0) {
+        const int s = (int)(key - kTomb);
+        if (t.hdr->spec_live[s]) {
+          st = kPresent;
+          if (ALLOC && vout) vout[i] = (int32_t)(uint32_t)t.hdr->spec_val[s];
+        } else if (!fast) {
+          newf = 1;
+        } else if (ALLOC) {
+          t.hdr->spec_live[s] = 1;
+          t.ref[i] = kSpecRef + (uint64_t)s;
+          newf = 1;
+        } else {
+          t.hdr->spec_live[s] = 1;
+          t.hdr->spec_val[s] = load_val<VK>(vals, i);
+          st = kInserted;
+          ++ins;
+        }
+      }
+    } else {
+      const Probe p = probe(t, key, sub, fast);
+      if (p.found) {
+        st = kPresent;
+        if (ALLOC && vout && sub == 0) vout[i] = (int32_t)(uint32_t)p.val;
+      } else if (!fast) {
+        newf = 1;
+      } else {
+        const uint64_t pos = p.has_free ? claim(t, key, p.free_b, sub) : kNoPos;
+        if (pos == kNoPos) {  // cannot happen while size + chunk <= capacity <= 8 * nb
+          st = kFull;
+          if (sub == 0) aor32(&t.hdr->err, kErrFull);
+        } else if (ALLOC) {
+          if (sub == 0) t.ref[i] = pos;
+          newf = 1;
+        } else {
+          if (sub == (int)(pos & 7)) t.bk[pos >> 3].s[pos & 7].val = load_val<VK>(vals, i);
+          st = kInserted;
+          if (sub == 0) ++ins;
+        }
+      }
+    }
+    if (sub == 0) {
+      if (flags) t.flag[i] = newf;
+      if (status && st != kNoStatus) status[i] = st;
+    }
+  }
+  if (!ALLOC && fast) {
+    const uint64_t tot = wave_sum(ins);
+    if (wave_lane() == 0 && tot) aadd64(&t.hdr->size, tot);
+  }
+}
+
+// Erase actors.  RELEASE: the removed value is kept for the ordered push to the pool.
+template <bool RELEASE>
+__global__ __launch_bounds__(kBlock) void k_erase(TableView t, const uint64_t* __restrict__ keys,
+                                                  int64_t q, uint32_t dmask,
+                                                  uint8_t* __restrict__ erased) {
+  const int sub = threadIdx.x & 7;
+  const int64_t ng = (int64_t)gridDim.x * (kBlock / 8);
+  uint64_t del = 0;
+  for (int64_t i = (int64_t)blockIdx.x * (kBlock / 8) + (threadIdx.x >> 3); i < q; i += ng) {
+    const uint64_t key = keys[i];
+    const uint32_t first = first_index(t, key, dmask, sub, (uint32_t)i);
+    uint8_t hit = 0;
+    uint64_t val = 0;
+    if (first == (uint32_t)i) {
+      if (key >= kTomb) {
+        if (sub == 0) {
+          const int s = (int)(key - kTomb);
+          if (t.hdr->spec_live[s]) {
+            t.hdr->spec_live[s] = 0;
+            val = t.hdr->spec_val[s];
+            hit = 1;
+          }
+        }
+      } else {
+        const Probe p = probe(t, key, sub, false);
+        if (p.found) {
+          if (sub == (int)(p.pos & 7)) t.bk[p.pos >> 3].s[p.pos & 7].key = p.had_empty ? kEmpty : kTomb;
+          val = p.val;
+          hit = 1;
+        }
+      }
+    }
+    if (sub == 0) {
+      if (erased) erased[i] = hit;
+      if (RELEASE) {
+        t.flag[i] = hit;
+        t.ref[i] = val;
+      }
+      del += hit;
+    }
+  }
+  const uint64_t tot = wave_sum(del);
+  if (wave_lane() == 0 && tot) aadd64(&t.hdr->size, (uint64_t)0 - tot);
+}
+
+// Flagged count per tile of kTile elements.
+__global__ __launch_bounds__(kBlock) void k_tile_count(TableView t, int64_t q, int only_slow) {
+  if (only_slow && t.hdr->fast) return;
+  __shared__ uint32_t part[kBlock / 64];
+  const int64_t t0 = (int64_t)blockIdx.x * kTile;
+  uint64_t c = 0;
+  for (int j = threadIdx.x; j < kTile; j += kBlock) {
+    const int64_t i = t0 + j;
+    if (i < q) c += t.flag[i];
+  }
+  c = wave_sum(c);
+  if (wave_lane() == 0) part[threadIdx.x >> 6] = (uint32_t)c;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t s = 0;
+    for (int w = 0; w < kBlock / 64; ++w) s += part[w];
+    t.tsum[blockIdx.x] = s;
+  }
+}
+
+// Exclusive block-wide scan of one value per thread (kBlock threads); returns the prefix and
+// writes the block total to *total.
+__device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* total) {
+  __shared__ uint32_t wsum[kBlock / 64];
+  const int lane = wave_lane();
+  uint32_t x = v;
+  for (int off = 1; off < 64; off <<= 1) {
+    const uint32_t y = __shfl_up(x, off, 64);
+    if (lane >= off) x += y;
+  }
+  if (lane == 63) wsum[threadIdx.x >> 6] = x;
+  __syncthreads();
+  uint32_t before = 0, all = 0;
+  for (int w = 0; w < kBlock / 64; ++w) {
+    if (w < (int)(threadIdx.x >> 6)) before += wsum[w];
+    all += wsum[w];
+  }
+  *total = all;
+  __syncthreads();
+  return before + x - v;
+}
+
+// Single block: exclusive scan of the tile counts, then the counter updates the ranks imply.
+// mode 0: insert near capacity; 1: insert with pool values; 2: erase releasing to the pool.
+__global__ __launch_bounds__(1024) void k_tile_scan(TableView t, PoolHeader* pool, int ntiles,
+                                                    int mode) {
+  const bool fast = t.hdr->fast != 0;
+  if (mode == 0 && fast) return;
+  __shared__ uint32_t carry;
+  if (threadIdx.x == 0) carry = 0;
+  __syncthreads();
+  for (int base = 0; base < ntiles; base += 1024) {
+    const int j = base + (int)threadIdx.x;
+    const uint32_t v = j < ntiles ? t.tsum[j] : 0u;
+    // 1024-thread exclusive scan via 16 waves
+    __shared__ uint32_t ws[16];
+    const int lane = wave_lane();
+    uint32_t x = v;
+    for (int off = 1; off < 64; off <<= 1) {
+      const uint32_t y = __shfl_up(x, off, 64);
+      if (lane >= off) x += y;
+    }
+    if (lane == 63) ws[threadIdx.x >> 6] = x;
+    __syncthreads();
+    uint32_t before = 0, all = 0;
+    for (int w = 0; w < 16; ++w) {
+      if (w < (int)(threadIdx.x >> 6)) before += ws[w];
+      all += ws[w];
+    }
+    if (j < ntiles) t.tsum[j] = carry + before + x - v;
+    __syncthreads();
+    if (threadIdx.x == 0) carry += all;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    Header* h = t.hdr;
+    const uint64_t nnew = carry;
+    h->nnew = carry;
+    const uint64_t room = t.cap - h->size0;
+    if (mode == 0) {
+      const uint64_t ins = nnew < room ? nnew : room;
+      h->size = h->size0 + ins;
+      if (nnew > room) h->err |= kErrFull;
+    } else if (mode == 1) {
+      const uint64_t avail = (uint64_t)pool->top0;
+      const uint64_t lim = room < avail ? room : avail;
+      const uint64_t ins = nnew < lim ? nnew : lim;
+      h->size = h->size0 + ins;
+      pool->top = pool->top0 - (int64_t)ins;
+      if (nnew > lim) {
+        if (room <= avail) h->err |= kErrFull;
+        else h->err |= kErrPool;
+      }
+    } else {
+      const uint64_t room_p = (uint64_t)(pool->cap - pool->top0);
+      const uint64_t pushed = nnew < room_p ? nnew : room_p;
+      pool->top = pool->top0 + (int64_t)pushed;
+      if (nnew > room_p) pool->err |= kErrPool;
+    }
+  }
+}
+
+// Ranked completion of flagged elements, one tile per block.
+// MODE 0: insert near capacity (rank < room -> claim, else FULL)
+// MODE 1: insert with pool values (rank < min(room, pool) -> value = stack[top0-1-rank])
+// MODE 2: erase releasing to the pool (stack[top0+rank] = value)
+template <int VK, int MODE>
+__global__ __launch_bounds__(kBlock) void k_final(TableView t, PoolHeader* pool,
+                                                  int32_t* __restrict__ pstack,
+                                                  const uint64_t* __restrict__ keys,
+                                                  const void* __restrict__ vals, int64_t q,
+                                                  uint8_t* __restrict__ status,
+                                                  int32_t* __restrict__ vout) {
+  const bool fast = t.hdr->fast != 0;
+  if (MODE == 0 && fast) return;
+  __shared__ uint16_t list[kTile];
+  const int64_t t0 = (int64_t)blockIdx.x * kTile;
+  uint32_t f[kTile / kBlock];
+  uint32_t cnt = 0;
+#pragma unroll
+  for (int k = 0; k < kTile / kBlock; ++k) {
+    const int64_t i = t0 + (int64_t)threadIdx.x * (kTile / kBlock) + k;
+    f[k] = i < q ? t.flag[i] : 0u;
+    cnt += f[k];
+  }
+  uint32_t total;
+  uint32_t o = block_exclusive_scan(cnt, &total);
+#pragma unroll
+  for (int k = 0; k < kTile / kBlock; ++k)
+    if (f[k]) list[o++] = (uint16_t)(threadIdx.x * (kTile / kBlock) + k);
+  __syncthreads();
+  const uint64_t rbase = t.tsum[blockIdx.x];
+  const Header* h = t.hdr;
+  const uint64_t room = t.cap - h->size0;
+  const int sub = threadIdx.x & 7;
+  for (uint32_t j = threadIdx.x >> 3; j < total; j += kBlock / 8) {
+    const int64_t i = t0 + list[j];
+    const uint64_t rank = rbase + j;
+    if constexpr (MODE == 2) {
+      if (sub == 0) {
+        const int64_t pos = pool->top0 + (int64_t)rank;
+        if (pos < pool->cap) pstack[pos] = (int32_t)(uint32_t)t.ref[i];
+      }
+      continue;
+    } else {
+      uint64_t lim = room;
+      if constexpr (MODE == 1) {
+        const uint64_t avail = (uint64_t)pool->top0;
+        lim = room < avail ? room : avail;
+      }
+      if (rank >= lim) {
+        if (sub == 0) {
+          if (status) status[i] = kFull;
+          if (MODE == 1 && vout) vout[i] = -1;
+        }
+        continue;
+      }
+      const uint64_t key = keys[i];
+      uint64_t v = 0;
+      if constexpr (MODE == 1) v = (uint64_t)(uint32_t)pstack[pool->top0 - 1 - (int64_t)rank];
+      else v = load_val<VK>(vals, i);
+      uint64_t pos;
+      if (MODE == 1 && fast) {
+        pos = t.ref[i];
+      } else if (key >= kTomb) {
+        pos = kSpecRef + (key - kTomb);
+        if (sub == 0) t.hdr->spec_live[key - kTomb] = 1;
+      } else {
+        const Probe p = probe(t, key, sub, true);
+        pos = p.has_free ? claim(t, key, p.free_b, sub) : kNoPos;
+      }
+      if (pos >= kSpecRef && pos != kNoPos) {
+        if (sub == 0) t.hdr->spec_val[pos - kSpecRef] = v;
+      } else if (pos != kNoPos) {
+        if (sub == (int)(pos & 7)) t.bk[pos >> 3].s[pos & 7].val = v;
+      }
+      if (sub == 0) {
+        if (status) status[i] = pos == kNoPos ? kFull : kInserted;
+        if (MODE == 1 && vout) vout[i] = pos == kNoPos ? -1 : (int32_t)(uint32_t)v;
+      }
+    }
+  }
+}
+
+// Later copies of a key take the outcome of its first occurrence: PRESENT (or its value), unless
+// the first occurrence met FULL, which a later copy meets again.
+__global__ __launch_bounds__(kBlock) void k_fix(TableView t, uint8_t* __restrict__ status,
+                                                int32_t* __restrict__ vout) {
+  const uint32_t nd = t.hdr->ndup;
+  const uint32_t tid = blockIdx.x * blockDim.x + threadIdx.x;
+  const uint32_t nt = gridDim.x * blockDim.x;
+  for (uint32_t j = tid; j < nd; j += nt) {
+    const uint2 d = t.dup[j];
+    if (vout) vout[d.x] = vout[d.y];
+    if (status) status[d.x] = status[d.y] == kFull ? kFull : kPresent;
+  }
+}
+
+template <int VK>
+__global__ __launch_bounds__(kBlock) void k_find(TableView t, const uint64_t* __restrict__ keys,
+                                                 int64_t n, void* __restrict__ out,
+                                                 uint8_t* __restrict__ found) {
+  const int sub = threadIdx.x & 7;
+  const int64_t ng = (int64_t)gridDim.x * (kBlock / 8);
+  for (int64_t i = (int64_t)blockIdx.x * (kBlock / 8) + (threadIdx.x >> 3); i < n; i += ng) {
+    const uint64_t key = keys[i];
+    bool hit = false;
+    uint64_t v = 0;
+    if (key >= kTomb) {
+      hit = t.hdr->spec_live[key - kTomb] != 0;
+      v = t.hdr->spec_val[key - kTomb];
+    } else {
+      uint64_t b = home_of(t, key);
+      for (uint64_t step = 0; step < t.nb; ++step) {
+        const Slot s = t.bk[b].s[sub];
+        const uint32_t m = group_bits(__ballot(s.key == key));
+        if (m) {
+          v = __shfl(s.val, group_base() + lowest(m), 64);
+          hit = true;
+          break;
+        }
+        if (group_bits(__ballot(s.key == kEmpty))) break;
+        b = next_bucket(t, b);
+      }
+    }
+    if (sub == 0) {
+      if (out) store_val<VK>(out, i, hit ? v : sentinel<VK>());
+      if (found) found[i] = hit ? 1 : 0;
+    }
+  }
+}
+
+__global__ void k_dump_begin(TableView t) { t.hdr->dump_count = 0; }
+
+__global__ __launch_bounds__(kBlock) void k_dump(TableView t, uint64_t* __restrict__ kout,
+                                                 uint64_t* __restrict__ vout, int64_t cap) {
+  const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t nt = (int64_t)gridDim.x * blockDim.x;
+  const int64_t nslots = (int64_t)t.nb * kSlots;
+  // trip count equal for all lanes of a wave so the wave-wide append stays converged
+  const int64_t span = ((nslots + nt - 1) / nt) * nt;
+  uint32_t* cnt32 = reinterpret_cast<uint32_t*>(&t.hdr->dump_count);
+  for (int64_t j = tid; j < span; j += nt) {
+    Slot s;
+    bool live = false;
+    if (j < nslots) {
+      s = t.bk[j >> 3].s[j & 7];
+      live = s.key != kEmpty && s.key != kTomb;
+    }
+    const uint32_t p = wave_append(live, cnt32);
+    if (live && (int64_t)p < cap) {
+      kout[p] = s.key;
+      if (vout) vout[p] = s.val;
+    }
+  }
+  if (tid == 0) {
+    for (int s = 0; s < 2; ++s) {
+      if (!t.hdr->spec_live[s]) continue;
+      const uint32_t p = aadd32(cnt32, 1u);
+      if ((int64_t)p < cap) {
+        kout[p] = kTomb + (uint64_t)s;
+        if (vout) vout[p] = t.hdr->spec_val[s];
+      }
+    }
+  }
+}
+
+__global__ void k_check_begin(TableView t) {
+  t.hdr->live_count = 0;
+  t.hdr->violations = 0;
+}
+
+// Every live key must be reachable: no bucket between its home and its bucket holds a kEmpty slot.
+__global__ __launch_bounds__(kBlock) void k_check(TableView t) {
+  const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t nt = (int64_t)gridDim.x * blockDim.x;
+  const int64_t nslots = (int64_t)t.nb * kSlots;
+  uint64_t live = 0, bad = 0;
+  for (int64_t j = tid; j < nslots; j += nt) {
+    const uint64_t key = t.bk[j >> 3].s[j & 7].key;
+    if (key == kEmpty || key == kTomb) continue;
+    ++live;
+    const uint64_t at = (uint64_t)(j >> 3);
+    uint64_t b = home_of(t, key);
+    for (uint64_t step = 0; b != at; ++step) {
+      if (step >= t.nb) { ++bad; break; }
+      bool has_empty = false;
+      for (int c = 0; c < kSlots; ++c) has_empty |= t.bk[b].s[c].key == kEmpty;
+      if (has_empty) { ++bad; break; }
+      b = next_bucket(t, b);
+    }
+  }
+  live = wave_sum(live);
+  bad = wave_sum(bad);
+  if (wave_lane() == 0) {
+    if (live) aadd64(&t.hdr->live_count, live);
+    if (bad) aadd64(&t.hdr->violations, bad);
+  }
+}
+
+// ---------------------------------------------------------------------------------------------
+// pool kernels
+// ---------------------------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_pool_init(PoolHeader* ph, int32_t* stack, int64_t cap) {
+  const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t nt = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t j = tid; j < cap; j += nt) stack[j] = (int32_t)(cap - 1 - j);
+  if (tid == 0) {
+    ph->top = cap;
+    ph->top0 = cap;
+    ph->cap = cap;
+    ph->err = 0;
+  }
+}
+
+__global__ void k_pool_snapshot(PoolHeader* ph) { ph->top0 = ph->top; }
+
+__global__ __launch_bounds__(kBlock) void k_pool_pop(PoolHeader* ph, const int32_t* __restrict__ stack,
+                                                     int64_t n, int32_t* __restrict__ out,
+                                                     uint8_t* __restrict__ status) {
+  const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t nt = (int64_t)gridDim.x * blockDim.x;
+  const int64_t top0 = ph->top0;
+  for (int64_t i = tid; i < n; i += nt) {
+    const bool ok = i < top0;
+    if (out) out[i] = ok ? stack[top0 - 1 - i] : -1;
+    if (status) status[i] = ok ? 1 : 2;
+  }
+  if (tid == 0) {
+    ph->top = n < top0 ? top0 - n : 0;
+    if (n > top0) ph->err |= kErrPool;
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_pool_push(PoolHeader* ph, int32_t* __restrict__ stack,
+                                                      const int32_t* __restrict__ in, int64_t n,
+                                                      uint8_t* __restrict__ status) {
+  const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t nt = (int64_t)gridDim.x * blockDim.x;
+  const int64_t top0 = ph->top0, cap = ph->cap;
+  for (int64_t i = tid; i < n; i += nt) {
+    const bool ok = top0 + i < cap;
+    if (ok) stack[top0 + i] = in[i];
+    if (status) status[i] = ok ? 1 : 2;
+  }
+  if (tid == 0) {
+    ph->top = (top0 + n < cap) ? top0 + n : cap;
+    if (top0 + n > cap) ph->err |= kErrPool;
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_pool_copy(const PoolHeader* ph, const int32_t* __restrict__ stack,
+                                                      int32_t* __restrict__ out, int64_t cap) {
+  const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t nt = (int64_t)gridDim.x * blockDim.x;
+  const int64_t m = ph->top < cap ? ph->top : cap;
+  for (int64_t j = tid; j < m; j += nt) out[j] = stack[j];
+}
+
+}  // namespace
+
+// =============================================================================================
+// host side
+// =============================================================================================
+struct ct_table {
+  ct_table_desc desc;
+  uint8_t* base;
+  int64_t bytes;
+  TableView v;
+  int64_t chunk;      // Q: elements per chunk (power of two)
+  uint64_t size_ub;   // upper bound of the live count known to the host
+};
+
+struct ct_pool {
+  uint8_t* base;
+  int64_t cap;
+  PoolHeader* hdr;
+  int32_t* stack;
+};
+
+namespace {
+
+constexpr int64_t kAlign = 256;
+constexpr int kMaxGroupBlocks = 16384;
+
+int64_t align_up(int64_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+int64_t pow2ceil(int64_t x) {
+  int64_t p = 1;
+  while (p < x) p <<= 1;
+  return p;
+}
+
+struct Layout {
+  int64_t nb, chunk, dbuckets, ntiles;
+  int64_t off_bk, off_dd, off_dup, off_flag, off_ref, off_tsum, total;
+};
+
+bool make_layout(const ct_table_desc* d, Layout* L) {
+  if (!d || d->capacity < 0) return false;
+  if (d->val_kind < 0 || d->val_kind > 2 || d->hash_kind < 0 || d->hash_kind > 1) return false;
+  int64_t nb = d->bucket_count ? d->bucket_count : (d->capacity + kSlots - 1) / kSlots;
+  if (nb < 1) nb = 1;
+  if (nb > ((int64_t)1 << 40)) return false;
+  if (nb * kSlots < d->capacity) return false;
+  int64_t q = d->chunk;
+  if (q == 0) q = std::min<int64_t>((int64_t)1 << 20, std::max<int64_t>(1024, pow2ceil(d->capacity)));
+  if (q < 1024 || q > ((int64_t)1 << 24) || (q & (q - 1))) return false;
+  L->nb = nb;
+  L->chunk = q;
+  L->dbuckets = (2 * q) / kSlots;
+  L->ntiles = (q + kTile - 1) / kTile;
+  int64_t off = align_up((int64_t)sizeof(Header));
+  L->off_bk = off;
+  off = align_up(off + nb * (int64_t)sizeof(Bucket));
+  L->off_dd = off;
+  off = align_up(off + L->dbuckets * (int64_t)sizeof(DBucket));
+  L->off_dup = off;
+  off = align_up(off + q * (int64_t)sizeof(uint2));
+  L->off_flag = off;
+  off = align_up(off + q);
+  L->off_ref = off;
+  off = align_up(off + q * 8);
+  L->off_tsum = off;
+  off = align_up(off + L->ntiles * 4);
+  L->total = off;
+  return true;
+}
+
+inline hipStream_t S(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+int group_blocks(int64_t n) {
+  const int64_t b = (n + (kBlock / 8) - 1) / (kBlock / 8);
+  return (int)std::max<int64_t>(1, std::min<int64_t>(b, kMaxGroupBlocks));
+}
+
+int flat_blocks(int64_t n) {
+  const int64_t b = (n + kBlock - 1) / kBlock;
+  return (int)std::max<int64_t>(1, std::min<int64_t>(b, 8192));
+}
+
+ct_status launched() { return hipGetLastError() == hipSuccess ? CT_OK : CT_E_HIP; }
+
+uint32_t dedup_buckets_for(int64_t q) {
+  const int64_t b = pow2ceil(2 * q) / kSlots;
+  return (uint32_t)std::max<int64_t>(1, b);
+}
+
+template <typename T>
+ct_status read_back(const T* dev, T* host, hipStream_t s) {
+  if (hipMemcpyAsync(host, dev, sizeof(T), hipMemcpyDeviceToHost, s) != hipSuccess) return CT_E_HIP;
+  return hipStreamSynchronize(s) == hipSuccess ? CT_OK : CT_E_HIP;
+}
+
+// ---------------------------------------------------------------------------------------------
+// insert / erase drivers
+// ---------------------------------------------------------------------------------------------
+template <int VK>
+ct_status insert_chunks(ct_table* t, const uint64_t* keys, const void* vals, int64_t n,
+                        uint8_t* status, hipStream_t s) {
+  const int vb = VK == 1 ? 4 : 8;
+  for (int64_t c0 = 0; c0 < n; c0 += t->chunk) {
+    const int64_t q = std::min<int64_t>(t->chunk, n - c0);
+    const uint32_t db = dedup_buckets_for(q);
+    const uint64_t* kc = keys + c0;
+    const void* vc = VK ? static_cast<const void*>(static_cast<const uint8_t*>(vals) + c0 * vb) : nullptr;
+    uint8_t* sc = status ? status + c0 : nullptr;
+    const int gb = group_blocks(q);
+    const int ntiles = (int)((q + kTile - 1) / kTile);
+    k_prologue<<<flat_blocks(db * (int64_t)kSlots), kBlock, 0, s>>>(t->v, nullptr, db, q);
+    k_dedup<<<gb, kBlock, 0, s>>>(t->v, kc, q, db - 1);
+    k_insert<VK, false><<<gb, kBlock, 0, s>>>(t->v, kc, vc, q, db - 1, sc, nullptr);
+    // the host bound proves that no element can meet FULL: the rank pass is not needed
+    const bool surely_fast = t->size_ub + (uint64_t)q <= (uint64_t)t->desc.capacity;
+    if (!surely_fast) {
+      k_tile_count<<<ntiles, kBlock, 0, s>>>(t->v, q, 1);
+      k_tile_scan<<<1, 1024, 0, s>>>(t->v, nullptr, ntiles, 0);
+      k_final<VK, 0><<<ntiles, kBlock, 0, s>>>(t->v, nullptr, nullptr, kc, vc, q, sc, nullptr);
+    }
+    if (sc) k_fix<<<flat_blocks(q), kBlock, 0, s>>>(t->v, sc, nullptr);
+    t->size_ub = std::min<uint64_t>(t->size_ub + (uint64_t)q, (uint64_t)t->desc.capacity);
+    ct_status r = launched();
+    if (r != CT_OK) return r;
+  }
+  return CT_OK;
+}
+
+template <bool RELEASE>
+ct_status erase_chunks(ct_table* t, ct_pool* p, const uint64_t* keys, int64_t n, uint8_t* erased,
+                       hipStream_t s) {
+  for (int64_t c0 = 0; c0 < n; c0 += t->chunk) {
+    const int64_t q = std::min<int64_t>(t->chunk, n - c0);
+    const uint32_t db = dedup_buckets_for(q);
+    const uint64_t* kc = keys + c0;
+    uint8_t* ec = erased ? erased + c0 : nullptr;
+    const int gb = group_blocks(q);
+    const int ntiles = (int)((q + kTile - 1) / kTile);
+    k_prologue<<<flat_blocks(db * (int64_t)kSlots), kBlock, 0, s>>>(t->v, RELEASE ? p->hdr : nullptr, db, q);
+    k_dedup<<<gb, kBlock, 0, s>>>(t->v, kc, q, db - 1);
+    k_erase<RELEASE><<<gb, kBlock, 0, s>>>(t->v, kc, q, db - 1, ec);
+    if (RELEASE) {
+      k_tile_count<<<ntiles, kBlock, 0, s>>>(t->v, q, 0);
+      k_tile_scan<<<1, 1024, 0, s>>>(t->v, p->hdr, ntiles, 2);
+      k_final<0, 2><<<ntiles, kBlock, 0, s>>>(t->v, p->hdr, p->stack, kc, nullptr, q, nullptr, nullptr);
+    }
+    ct_status r = launched();
+    if (r != CT_OK) return r;
+  }
+  return CT_OK;
+}
+
+ct_status check_batch(const ct_table* t, const void* keys, int64_t n) {
+  if (!t || n < 0) return CT_E_INVALID;
+  if (n > 0 && !keys) return CT_E_INVALID;
+  return CT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* ct_status_str(ct_status s) {
+  switch (s) {
+    case CT_OK: return "ok";
+    case CT_E_INVALID: return "invalid argument";
+    case CT_E_FULL: return "capacity exhausted";
+    case CT_E_EMPTY: return "pool empty";
+    case CT_E_NOMEM: return "host allocation failed";
+    case CT_E_HIP: return "HIP runtime error";
+  }
+  return "unknown status";
+}
+
+ct_status ct_table_bytes(const ct_table_desc* d, int64_t* bytes) {
+  Layout L;
+  if (!bytes || !make_layout(d, &L)) return CT_E_INVALID;
+  *bytes = L.total;
+  return CT_OK;
+}
+
+ct_status ct_table_init(void* d_buf, int64_t bytes, const ct_table_desc* d, void* stream,
+                        ct_table** out) {
+  Layout L;
+  if (!out || !d_buf || !make_layout(d, &L) || bytes < L.total) return CT_E_INVALID;
+  if (reinterpret_cast<uintptr_t>(d_buf) % kAlign) return CT_E_INVALID;
+  ct_table* t = new (std::nothrow) ct_table;
+  if (!t) return CT_E_NOMEM;
+  uint8_t* base = static_cast<uint8_t*>(d_buf);
+  t->desc = *d;
+  t->desc.bucket_count = L.nb;
+  t->desc.chunk = L.chunk;
+  t->base = base;
+  t->bytes = bytes;
+  t->chunk = L.chunk;
+  t->size_ub = 0;
+  TableView& v = t->v;
+  v.hdr = reinterpret_cast<Header*>(base);
+  v.bk = reinterpret_cast<Bucket*>(base + L.off_bk);
+  v.nb = (uint64_t)L.nb;
+  v.cap = (uint64_t)d->capacity;
+  v.dd = reinterpret_cast<DBucket*>(base + L.off_dd);
+  v.dup = reinterpret_cast<uint2*>(base + L.off_dup);
+  v.flag = base + L.off_flag;
+  v.ref = reinterpret_cast<uint64_t*>(base + L.off_ref);
+  v.tsum = reinterpret_cast<uint32_t*>(base + L.off_tsum);
+  v.hash = d->hash_kind;
+  v.nb_pow2 = (L.nb & (L.nb - 1)) == 0;
+  k_table_reset<<<flat_blocks(L.nb * kSlots), kBlock, 0, S(stream)>>>(v, 1);
+  if (launched() != CT_OK) {
+    delete t;
+    return CT_E_HIP;
+  }
+  *out = t;
+  return CT_OK;
+}
+
+ct_status ct_table_destroy(ct_table* t) {
+  if (!t) return CT_E_INVALID;
+  delete t;
+  return CT_OK;
+}
+
+ct_status ct_table_info(const ct_table* t, int64_t* bucket_count, int64_t* chunk) {
+  if (!t) return CT_E_INVALID;
+  if (bucket_count) *bucket_count = (int64_t)t->v.nb;
+  if (chunk) *chunk = t->chunk;
+  return CT_OK;
+}
+
+ct_status ct_insert_batch(ct_table* t, const uint64_t* keys, const void* vals, int64_t n,
+                          uint8_t* status, void* stream) {
+  ct_status r = check_batch(t, keys, n);
+  if (r != CT_OK) return r;
+  if (n == 0) return CT_OK;
+  const int vk = t->desc.val_kind;
+  if (vk != CT_VAL_NONE && !vals) return CT_E_INVALID;
+  if (vk == CT_VAL_U32) return insert_chunks<1>(t, keys, vals, n, status, S(stream));
+  if (vk == CT_VAL_U64) return insert_chunks<2>(t, keys, vals, n, status, S(stream));
+  return insert_chunks<0>(t, keys, nullptr, n, status, S(stream));
+}
+
+ct_status ct_find_batch(ct_table* t, const uint64_t* keys, int64_t n, void* vals_out,
+                        uint8_t* found, void* stream) {
+  ct_status r = check_batch(t, keys, n);
+  if (r != CT_OK) return r;
+  const int vk = t->desc.val_kind;
+  if (vk == CT_VAL_NONE && vals_out) return CT_E_INVALID;
+  if (n == 0) return CT_OK;
+  const int gb = group_blocks(n);
+  if (vk == CT_VAL_U32) k_find<1><<<gb, kBlock, 0, S(stream)>>>(t->v, keys, n, vals_out, found);
+  else if (vk == CT_VAL_U64) k_find<2><<<gb, kBlock, 0, S(stream)>>>(t->v, keys, n, vals_out, found);
+  else k_find<0><<<gb, kBlock, 0, S(stream)>>>(t->v, keys, n, nullptr, found);
+  return launched();
+}
+
+ct_status ct_erase_batch(ct_table* t, const uint64_t* keys, int64_t n, uint8_t* erased,
+                         void* stream) {
+  ct_status r = check_batch(t, keys, n);
+  if (r != CT_OK) return r;
+  if (n == 0) return CT_OK;
+  return erase_chunks<false>(t, nullptr, keys, n, erased, S(stream));
+}
+
+ct_status ct_size(ct_table* t, int64_t* h_size, void* stream) {
+  if (!t || !h_size) return CT_E_INVALID;
+  uint64_t v = 0;
+  ct_status r = read_back(&t->v.hdr->size, &v, S(stream));
+  if (r != CT_OK) return r;
+  *h_size = (int64_t)v;
+  t->size_ub = v;
+  return CT_OK;
+}
+
+ct_status ct_clear(ct_table* t, void* stream) {
+  if (!t) return CT_E_INVALID;
+  k_table_reset<<<flat_blocks((int64_t)t->v.nb * kSlots), kBlock, 0, S(stream)>>>(t->v, 0);
+  t->size_ub = 0;
+  return launched();
+}
+
+ct_status ct_dump(ct_table* t, uint64_t* keys_out, uint64_t* vals_out, int64_t cap,
+                  int64_t* h_count, void* stream) {
+  if (!t || !h_count || cap < 0 || (cap > 0 && !keys_out)) return CT_E_INVALID;
+  if (t->desc.val_kind == CT_VAL_NONE) vals_out = nullptr;
+  k_dump_begin<<<1, 1, 0, S(stream)>>>(t->v);
+  k_dump<<<flat_blocks((int64_t)t->v.nb * kSlots), kBlock, 0, S(stream)>>>(t->v, keys_out, vals_out, cap);
+  if (launched() != CT_OK) return CT_E_HIP;
+  uint64_t c = 0;
+  ct_status r = read_back(&t->v.hdr->dump_count, &c, S(stream));
+  if (r != CT_OK) return r;
+  *h_count = (int64_t)(c & 0xFFFFFFFFull);
+  return CT_OK;
+}
+
+ct_status ct_check_invariants(ct_table* t, int64_t* h_violations, void* stream) {
+  if (!t || !h_violations) return CT_E_INVALID;
+  k_check_begin<<<1, 1, 0, S(stream)>>>(t->v);
+  k_check<<<flat_blocks((int64_t)t->v.nb * kSlots), kBlock, 0, S(stream)>>>(t->v);
+  if (launched() != CT_OK) return CT_E_HIP;
+  Header h;
+  if (hipMemcpyAsync(&h, t->v.hdr, sizeof(Header), hipMemcpyDeviceToHost, S(stream)) != hipSuccess)
+    return CT_E_HIP;
+  if (hipStreamSynchronize(S(stream)) != hipSuccess) return CT_E_HIP;
+  const uint64_t specs = (uint64_t)(h.spec_live[0] != 0) + (uint64_t)(h.spec_live[1] != 0);
+  int64_t bad = (int64_t)h.violations;
+  if (h.live_count + specs != h.size) ++bad;
+  if (h.size > t->v.cap) ++bad;
+  *h_violations = bad;
+  return CT_OK;
+}
+
+ct_status ct_get_error(ct_table* t, uint32_t* h_err, void* stream) {
+  if (!t || !h_err) return CT_E_INVALID;
+  uint32_t e = 0;
+  ct_status r = read_back(&t->v.hdr->err, &e, S(stream));
+  if (r != CT_OK) return r;
+  *h_err = e;
+  const uint32_t zero = 0;
+  if (hipMemcpyAsync(&t->v.hdr->err, &zero, sizeof(zero), hipMemcpyHostToDevice, S(stream)) != hipSuccess)
+    return CT_E_HIP;
+  return hipStreamSynchronize(S(stream)) == hipSuccess ? CT_OK : CT_E_HIP;
+}
+
+// --- pools -------------------------------------------------------------------------------------
+ct_status ct_pool_bytes(int64_t capacity, int64_t* bytes) {
+  if (!bytes || capacity < 0 || capacity > 0x7FFFFFFFll) return CT_E_INVALID;
+  *bytes = align_up((int64_t)sizeof(PoolHeader)) + align_up(capacity * 4);
+  return CT_OK;
+}
+
+ct_status ct_pool_init(void* d_buf, int64_t bytes, int64_t capacity, void* stream, ct_pool** out) {
+  int64_t need = 0;
+  if (!out || !d_buf || ct_pool_bytes(capacity, &need) != CT_OK || bytes < need) return CT_E_INVALID;
+  if (reinterpret_cast<uintptr_t>(d_buf) % kAlign) return CT_E_INVALID;
+  ct_pool* p = new (std::nothrow) ct_pool;
+  if (!p) return CT_E_NOMEM;
+  p->base = static_cast<uint8_t*>(d_buf);
+  p->cap = capacity;
+  p->hdr = reinterpret_cast<PoolHeader*>(p->base);
+  p->stack = reinterpret_cast<int32_t*>(p->base + align_up((int64_t)sizeof(PoolHeader)));
+  k_pool_init<<<flat_blocks(capacity), kBlock, 0, S(stream)>>>(p->hdr, p->stack, capacity);
+  if (launched() != CT_OK) {
+    delete p;
+    return CT_E_HIP;
+  }
+  *out = p;
+  return CT_OK;
+}
+
+ct_status ct_pool_destroy(ct_pool* p) {
+  if (!p) return CT_E_INVALID;
+  delete p;
+  return CT_OK;
+}
+
+ct_status ct_pool_pop_batch(ct_pool* p, int64_t n, int32_t* out, uint8_t* status, void* stream) {
+  if (!p || n < 0) return CT_E_INVALID;
+  if (n == 0) return CT_OK;
+  k_pool_snapshot<<<1, 1, 0, S(stream)>>>(p->hdr);
+  k_pool_pop<<<flat_blocks(n), kBlock, 0, S(stream)>>>(p->hdr, p->stack, n, out, status);
+  return launched();
+}
+
+ct_status ct_pool_push_batch(ct_pool* p, const int32_t* in, int64_t n, uint8_t* status,
+                             void* stream) {
+  if (!p || n < 0 || (n > 0 && !in)) return CT_E_INVALID;
+  if (n == 0) return CT_OK;
+  k_pool_snapshot<<<1, 1, 0, S(stream)>>>(p->hdr);
+  k_pool_push<<<flat_blocks(n), kBlock, 0, S(stream)>>>(p->hdr, p->stack, in, n, status);
+  return launched();
+}
+
+ct_status ct_pool_size(ct_pool* p, int64_t* h_size, void* stream) {
+  if (!p || !h_size) return CT_E_INVALID;
+  return read_back(&p->hdr->top, h_size, S(stream));
+}
+
+ct_status ct_pool_dump(ct_pool* p, int32_t* out, int64_t cap, int64_t* h_count, void* stream) {
+  if (!p || !h_count || cap < 0 || (cap > 0 && !out)) return CT_E_INVALID;
+  if (cap > 0) k_pool_copy<<<flat_blocks(cap), kBlock, 0, S(stream)>>>(p->hdr, p->stack, out, cap);
+  if (launched() != CT_OK) return CT_E_HIP;
+  return read_back(&p->hdr->top, h_count, S(stream));
+}
+
+ct_status ct_pool_get_error(ct_pool* p, uint32_t* h_err, void* stream) {
+  if (!p || !h_err) return CT_E_INVALID;
+  uint32_t e = 0;
+  ct_status r = read_back(&p->hdr->err, &e, S(stream));
+  if (r != CT_OK) return r;
+  *h_err = e;
+  const uint32_t zero = 0;
+  if (hipMemcpyAsync(&p->hdr->err, &zero, sizeof(zero), hipMemcpyHostToDevice, S(stream)) != hipSuccess)
+    return CT_E_HIP;
+  return hipStreamSynchronize(S(stream)) == hipSuccess ? CT_OK : CT_E_HIP;
+}
+
+ct_status ct_insert_alloc_batch(ct_table* t, ct_pool* p, const uint64_t* keys, int64_t n,
+                                int32_t* vals_out, uint8_t* status, void* stream) {
+  ct_status r = check_batch(t, keys, n);
+  if (r != CT_OK || !p) return CT_E_INVALID;
+  if (t->desc.val_kind != CT_VAL_U32) return CT_E_INVALID;
+  if (n == 0) return CT_OK;
+  hipStream_t s = S(stream);
+  for (int64_t c0 = 0; c0 < n; c0 += t->chunk) {
+    const int64_t q = std::min<int64_t>(t->chunk, n - c0);
+    const uint32_t db = dedup_buckets_for(q);
+    const uint64_t* kc = keys + c0;
+    uint8_t* sc = status ? status + c0 : nullptr;
+    int32_t* vc = vals_out ? vals_out + c0 : nullptr;
+    const int gb = group_blocks(q);
+    const int ntiles = (int)((q + kTile - 1) / kTile);
+    k_prologue<<<flat_blocks(db * (int64_t)kSlots), kBlock, 0, s>>>(t->v, p->hdr, db, q);
+    k_dedup<<<gb, kBlock, 0, s>>>(t->v, kc, q, db - 1);
+    k_insert<1, true><<<gb, kBlock, 0, s>>>(t->v, kc, nullptr, q, db - 1, sc, vc);
+    k_tile_count<<<ntiles, kBlock, 0, s>>>(t->v, q, 0);
+    k_tile_scan<<<1, 1024, 0, s>>>(t->v, p->hdr, ntiles, 1);
+    k_final<1, 1><<<ntiles, kBlock, 0, s>>>(t->v, p->hdr, p->stack, kc, nullptr, q, sc, vc);
+    if (sc || vc) k_fix<<<flat_blocks(q), kBlock, 0, s>>>(t->v, sc, vc);
+    t->size_ub = std::min<uint64_t>(t->size_ub + (uint64_t)q, (uint64_t)t->desc.capacity);
+    r = launched();
+    if (r != CT_OK) return r;
+  }
+  return CT_OK;
+}
+
+ct_status ct_erase_release_batch(ct_table* t, ct_pool* p, const uint64_t* keys, int64_t n,
+                                 uint8_t* erased, void* stream) {
+  ct_status r = check_batch(t, keys, n);
+  if (r != CT_OK || !p) return CT_E_INVALID;
+  if (t->desc.val_kind != CT_VAL_U32) return CT_E_INVALID;
+  if (n == 0) return CT_OK;
+  return erase_chunks<true>(t, p, keys, n, erased, S(stream));
+}
+
+}  // extern "C"

@@ -1,0 +1,300 @@
+"""Python binding of the C ABI in ``include/ct.h`` (argument marshalling only).
+
+Every operation runs in the HIP library ``libct.so``; this module only turns torch tensors into
+device pointers and the current torch stream into the ``hipStream_t`` the library enqueues on.
+If the library is missing the import of a table or pool fails loudly: there is no fallback.
+
+Keys are ``torch.int64`` tensors holding the u64 bit patterns.  32-bit values travel as
+``torch.int32`` holding u32 bits, 64-bit values as ``torch.int64`` holding u64 bits.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import torch
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libct.so")
+
+CT_OK, CT_E_INVALID, CT_E_FULL, CT_E_EMPTY, CT_E_NOMEM, CT_E_HIP = range(6)
+PRESENT, INSERTED, FULL = 0, 1, 2
+ERR_FULL, ERR_POOL = 1, 2
+VAL_NONE, VAL_U32, VAL_U64 = 0, 1, 2
+HASH_MIX64, HASH_VOXEL21 = 0, 1
+
+
+class CtError(RuntimeError):
+    pass
+
+
+class TableDesc(C.Structure):
+    _fields_ = [("capacity", C.c_int64), ("val_kind", C.c_int32), ("hash_kind", C.c_int32),
+                ("bucket_count", C.c_int64), ("chunk", C.c_int64)]
+
+
+_lib = None
+
+# name -> (restype, argtypes)
+_P, _I64, _I32 = C.c_void_p, C.c_int64, C.c_int32
+_PI64 = C.POINTER(C.c_int64)
+SIGNATURES = {
+    "ct_status_str": (C.c_char_p, [C.c_int]),
+    "ct_table_bytes": (C.c_int, [C.POINTER(TableDesc), _PI64]),
+    "ct_table_init": (C.c_int, [_P, _I64, C.POINTER(TableDesc), _P, C.POINTER(_P)]),
+    "ct_table_destroy": (C.c_int, [_P]),
+    "ct_table_info": (C.c_int, [_P, _PI64, _PI64]),
+    "ct_insert_batch": (C.c_int, [_P, _P, _P, _I64, _P, _P]),
+    "ct_find_batch": (C.c_int, [_P, _P, _I64, _P, _P, _P]),
+    "ct_erase_batch": (C.c_int, [_P, _P, _I64, _P, _P]),
+    "ct_size": (C.c_int, [_P, _PI64, _P]),
+    "ct_clear": (C.c_int, [_P, _P]),
+    "ct_dump": (C.c_int, [_P, _P, _P, _I64, _PI64, _P]),
+    "ct_check_invariants": (C.c_int, [_P, _PI64, _P]),
+    "ct_get_error": (C.c_int, [_P, C.POINTER(C.c_uint32), _P]),
+    "ct_pool_bytes": (C.c_int, [_I64, _PI64]),
+    "ct_pool_init": (C.c_int, [_P, _I64, _I64, _P, C.POINTER(_P)]),
+    "ct_pool_destroy": (C.c_int, [_P]),
+    "ct_pool_pop_batch": (C.c_int, [_P, _I64, _P, _P, _P]),
+    "ct_pool_push_batch": (C.c_int, [_P, _P, _I64, _P, _P]),
+    "ct_pool_size": (C.c_int, [_P, _PI64, _P]),
+    "ct_pool_dump": (C.c_int, [_P, _P, _I64, _PI64, _P]),
+    "ct_pool_get_error": (C.c_int, [_P, C.POINTER(C.c_uint32), _P]),
+    "ct_insert_alloc_batch": (C.c_int, [_P, _P, _P, _I64, _P, _P, _P]),
+    "ct_erase_release_batch": (C.c_int, [_P, _P, _P, _I64, _P, _P]),
+    "ctr_gather": (C.c_int, [_P, _I64, _I32, _P, _I64, _P, _P]),
+    "ctr_gather_cas": (C.c_int, [_P, _I64, _I32, _P, _I64, _P, _P]),
+    "ctr_cas": (C.c_int, [_P, _I64, _P, _I64, _P]),
+    "ctr_copy": (C.c_int, [_P, _P, _I64, _P]),
+}
+
+
+def lib():
+    """The loaded HIP library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise CtError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+        L = C.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(rc: int, what: str):
+    if rc != CT_OK:
+        msg = lib().ct_status_str(rc).decode()
+        raise CtError(f"{what}: {msg} ({rc})")
+
+
+def _stream(device) -> int:
+    return torch.cuda.current_stream(device).cuda_stream
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _need(t, dtype, n, name, device):
+    if t.dtype != dtype:
+        raise CtError(f"{name} must be {dtype}, got {t.dtype}")
+    if t.device != device:
+        raise CtError(f"{name} must be on {device}")
+    if not t.is_contiguous():
+        raise CtError(f"{name} must be contiguous")
+    if n is not None and t.numel() != n:
+        raise CtError(f"{name} must have {n} elements")
+
+
+_VAL_DTYPE = {VAL_U32: torch.int32, VAL_U64: torch.int64}
+
+
+class Pool:
+    """Device index pool: a fixed-capacity int32 stack (vector/deque back operations)."""
+
+    def __init__(self, capacity: int, device="cuda"):
+        self.device = torch.device(device)
+        if self.device.index is None:
+            self.device = torch.device("cuda", torch.cuda.current_device())
+        self.capacity = int(capacity)
+        nb = C.c_int64(0)
+        _check(lib().ct_pool_bytes(self.capacity, C.byref(nb)), "ct_pool_bytes")
+        self.buf = torch.empty(nb.value, dtype=torch.uint8, device=self.device)
+        h = C.c_void_p()
+        _check(lib().ct_pool_init(_ptr(self.buf), nb.value, self.capacity, _stream(self.device),
+                                  C.byref(h)), "ct_pool_init")
+        self._h = h
+
+    def __del__(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.ct_pool_destroy(self._h)
+            self._h = None
+
+    def pop(self, n: int):
+        out = torch.empty(int(n), dtype=torch.int32, device=self.device)
+        st = torch.empty(int(n), dtype=torch.uint8, device=self.device)
+        _check(lib().ct_pool_pop_batch(self._h, int(n), _ptr(out), _ptr(st), _stream(self.device)),
+               "ct_pool_pop_batch")
+        return out, st
+
+    def push(self, values: torch.Tensor):
+        _need(values, torch.int32, None, "values", self.device)
+        st = torch.empty(values.numel(), dtype=torch.uint8, device=self.device)
+        _check(lib().ct_pool_push_batch(self._h, _ptr(values), values.numel(), _ptr(st),
+                                        _stream(self.device)), "ct_pool_push_batch")
+        return st
+
+    def size(self) -> int:
+        v = C.c_int64(0)
+        _check(lib().ct_pool_size(self._h, C.byref(v), _stream(self.device)), "ct_pool_size")
+        return v.value
+
+    def dump(self) -> torch.Tensor:
+        n = self.size()
+        out = torch.empty(max(n, 1), dtype=torch.int32, device=self.device)
+        cnt = C.c_int64(0)
+        _check(lib().ct_pool_dump(self._h, _ptr(out), n, C.byref(cnt), _stream(self.device)),
+               "ct_pool_dump")
+        return out[:cnt.value]
+
+    def error(self) -> int:
+        e = C.c_uint32(0)
+        _check(lib().ct_pool_get_error(self._h, C.byref(e), _stream(self.device)), "ct_pool_get_error")
+        return e.value
+
+
+class Table:
+    """unordered_map (value_kind VAL_U32 / VAL_U64) or unordered_set (VAL_NONE) on one GPU."""
+
+    def __init__(self, capacity: int, value_kind: int = VAL_U64, hash_kind: int = HASH_MIX64,
+                 bucket_count: int = 0, chunk: int = 0, device="cuda"):
+        self.device = torch.device(device)
+        if self.device.index is None:
+            self.device = torch.device("cuda", torch.cuda.current_device())
+        self.desc = TableDesc(int(capacity), int(value_kind), int(hash_kind), int(bucket_count),
+                              int(chunk))
+        nb = C.c_int64(0)
+        _check(lib().ct_table_bytes(C.byref(self.desc), C.byref(nb)), "ct_table_bytes")
+        self.nbytes = nb.value
+        self.buf = torch.empty(self.nbytes, dtype=torch.uint8, device=self.device)
+        h = C.c_void_p()
+        _check(lib().ct_table_init(_ptr(self.buf), self.nbytes, C.byref(self.desc),
+                                   _stream(self.device), C.byref(h)), "ct_table_init")
+        self._h = h
+        b = C.c_int64(0)
+        c = C.c_int64(0)
+        _check(lib().ct_table_info(self._h, C.byref(b), C.byref(c)), "ct_table_info")
+        self.bucket_count = b.value
+        self.chunk = c.value
+        self.capacity = int(capacity)
+        self.value_kind = int(value_kind)
+
+    def __del__(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.ct_table_destroy(self._h)
+            self._h = None
+
+    @property
+    def value_dtype(self):
+        return _VAL_DTYPE.get(self.value_kind)
+
+    def insert(self, keys: torch.Tensor, vals: torch.Tensor | None = None, status: bool = True):
+        n = keys.numel()
+        _need(keys, torch.int64, None, "keys", self.device)
+        if self.value_kind != VAL_NONE:
+            if vals is None:
+                raise CtError("values are required for a map")
+            _need(vals, self.value_dtype, n, "vals", self.device)
+        st = torch.empty(n, dtype=torch.uint8, device=self.device) if status else None
+        _check(lib().ct_insert_batch(self._h, _ptr(keys), _ptr(vals) if self.value_kind else None,
+                                     n, _ptr(st), _stream(self.device)), "ct_insert_batch")
+        return st
+
+    def find(self, keys: torch.Tensor, values: bool = True, found: bool = True, out=None):
+        n = keys.numel()
+        _need(keys, torch.int64, None, "keys", self.device)
+        v = None
+        if values and self.value_kind != VAL_NONE:
+            v = out if out is not None else torch.empty(n, dtype=self.value_dtype, device=self.device)
+        f = torch.empty(n, dtype=torch.uint8, device=self.device) if found else None
+        _check(lib().ct_find_batch(self._h, _ptr(keys), n, _ptr(v), _ptr(f), _stream(self.device)),
+               "ct_find_batch")
+        return v, f
+
+    def erase(self, keys: torch.Tensor, status: bool = True):
+        n = keys.numel()
+        _need(keys, torch.int64, None, "keys", self.device)
+        er = torch.empty(n, dtype=torch.uint8, device=self.device) if status else None
+        _check(lib().ct_erase_batch(self._h, _ptr(keys), n, _ptr(er), _stream(self.device)),
+               "ct_erase_batch")
+        return er
+
+    def insert_alloc(self, pool: Pool, keys: torch.Tensor):
+        n = keys.numel()
+        _need(keys, torch.int64, None, "keys", self.device)
+        out = torch.empty(n, dtype=torch.int32, device=self.device)
+        st = torch.empty(n, dtype=torch.uint8, device=self.device)
+        _check(lib().ct_insert_alloc_batch(self._h, pool._h, _ptr(keys), n, _ptr(out), _ptr(st),
+                                           _stream(self.device)), "ct_insert_alloc_batch")
+        return out, st
+
+    def erase_release(self, pool: Pool, keys: torch.Tensor):
+        n = keys.numel()
+        _need(keys, torch.int64, None, "keys", self.device)
+        er = torch.empty(n, dtype=torch.uint8, device=self.device)
+        _check(lib().ct_erase_release_batch(self._h, pool._h, _ptr(keys), n, _ptr(er),
+                                            _stream(self.device)), "ct_erase_release_batch")
+        return er
+
+    def size(self) -> int:
+        v = C.c_int64(0)
+        _check(lib().ct_size(self._h, C.byref(v), _stream(self.device)), "ct_size")
+        return v.value
+
+    def __len__(self):
+        return self.size()
+
+    def clear(self):
+        _check(lib().ct_clear(self._h, _stream(self.device)), "ct_clear")
+
+    def dump(self):
+        """Live (keys, values) in unspecified order; values as int64 holding the slot's u64."""
+        n = self.size()
+        k = torch.empty(max(n, 1), dtype=torch.int64, device=self.device)
+        v = torch.empty(max(n, 1), dtype=torch.int64, device=self.device)
+        cnt = C.c_int64(0)
+        _check(lib().ct_dump(self._h, _ptr(k), _ptr(v), n, C.byref(cnt), _stream(self.device)),
+               "ct_dump")
+        m = cnt.value
+        return k[:m], v[:m]
+
+    def check(self) -> int:
+        v = C.c_int64(0)
+        _check(lib().ct_check_invariants(self._h, C.byref(v), _stream(self.device)),
+               "ct_check_invariants")
+        return v.value
+
+    def error(self) -> int:
+        e = C.c_uint32(0)
+        _check(lib().ct_get_error(self._h, C.byref(e), _stream(self.device)), "ct_get_error")
+        return e.value
+
+
+# --- measured ceilings (include/ct_roofline.h) ------------------------------------------------
+def gather(lines: torch.Tensor, nlines: int, line_bytes: int, keys: torch.Tensor, out: torch.Tensor,
+           cas: bool = False):
+    f = lib().ctr_gather_cas if cas else lib().ctr_gather
+    _check(f(_ptr(lines), int(nlines), int(line_bytes), _ptr(keys), keys.numel(), _ptr(out),
+             _stream(keys.device)), "ctr_gather")
+
+
+def cas_words(words: torch.Tensor, nwords: int, keys: torch.Tensor):
+    _check(lib().ctr_cas(_ptr(words), int(nwords), _ptr(keys), keys.numel(), _stream(keys.device)),
+           "ctr_cas")
+
+
+def copy(src: torch.Tensor, dst: torch.Tensor, nbytes: int):
+    _check(lib().ctr_copy(_ptr(src), _ptr(dst), int(nbytes), _stream(src.device)), "ctr_copy")

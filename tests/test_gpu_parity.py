@@ -1,0 +1,236 @@
+"""GPU parity: every output of the HIP library equals the CPU oracle's, element by element.
+
+All cases call through the C ABI (the ctypes binding in paper_1908_05936_amd.ct).  Integer
+results, so the bar is bit-exact.  Sizes span many 128-byte buckets, several dedup chunks and
+rank tiles, and ragged tails.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1908_05936_amd import ct
+from paper_1908_05936_amd.workloads import distinct_u64, plain_table, rng_for
+
+pytestmark = pytest.mark.gpu
+
+U64MAX = (1 << 64) - 1
+RESERVED = np.array([0, U64MAX, U64MAX - 1, 1 << 63, U64MAX - 2], dtype=np.uint64)
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    ct.lib()
+    return torch.device("cuda", 0)
+
+
+def g64(a, dev):
+    return torch.from_numpy(np.ascontiguousarray(np.asarray(a, dtype=np.uint64)).view(np.int64)).to(dev)
+
+
+def g32(a, dev):
+    return torch.from_numpy(np.ascontiguousarray(np.asarray(a).astype(np.uint32)).view(np.int32)).to(dev)
+
+
+def npu(t, bits=64):
+    a = t.cpu().numpy()
+    return a.view(np.uint64) if bits == 64 else a.view(np.uint32)
+
+
+class Pair:
+    """A GPU table and an oracle table driven with the same batches; every output is compared."""
+
+    def __init__(self, dev, capacity, bits=64, hash_kind=ct.HASH_MIX64, bucket_count=0, chunk=0,
+                 pool=None):
+        vk = {0: ct.VAL_NONE, 32: ct.VAL_U32, 64: ct.VAL_U64}[bits]
+        self.dev, self.bits = dev, bits
+        self.g = ct.Table(capacity, vk, hash_kind, bucket_count, chunk, device=dev)
+        self.o = oracle.OracleTable(capacity, bits, hash_kind, bucket_count or max(1, capacity))
+        self.gp = ct.Pool(pool, device=dev) if pool is not None else None
+        self.op = oracle.OraclePool(pool) if pool is not None else None
+
+    def insert(self, keys, vals=None):
+        keys = np.asarray(keys, dtype=np.uint64)
+        if self.bits == 0:
+            st = self.g.insert(g64(keys, self.dev))
+        elif self.bits == 32:
+            st = self.g.insert(g64(keys, self.dev), g32(vals, self.dev))
+        else:
+            st = self.g.insert(g64(keys, self.dev), g64(vals, self.dev))
+        exp = self.o.insert(keys, vals)
+        np.testing.assert_array_equal(st.cpu().numpy(), exp)
+        return exp
+
+    def find(self, keys):
+        keys = np.asarray(keys, dtype=np.uint64)
+        v, f = self.g.find(g64(keys, self.dev))
+        ev, ef = self.o.find(keys)
+        np.testing.assert_array_equal(f.cpu().numpy(), ef)
+        if self.bits:
+            np.testing.assert_array_equal(npu(v, self.bits), ev)
+        return ev, ef
+
+    def erase(self, keys):
+        keys = np.asarray(keys, dtype=np.uint64)
+        er = self.g.erase(g64(keys, self.dev))
+        exp = self.o.erase(keys)
+        np.testing.assert_array_equal(er.cpu().numpy(), exp)
+        return exp
+
+    def insert_alloc(self, keys):
+        keys = np.asarray(keys, dtype=np.uint64)
+        v, st = self.g.insert_alloc(self.gp, g64(keys, self.dev))
+        ev, es = self.o.insert_alloc(self.op, keys)
+        np.testing.assert_array_equal(st.cpu().numpy(), es)
+        np.testing.assert_array_equal(v.cpu().numpy(), ev)
+
+    def erase_release(self, keys):
+        keys = np.asarray(keys, dtype=np.uint64)
+        er = self.g.erase_release(self.gp, g64(keys, self.dev))
+        np.testing.assert_array_equal(er.cpu().numpy(), self.o.erase_release(self.op, keys))
+
+    def same_state(self):
+        assert self.g.size() == self.o.size()
+        k, v = self.g.dump()
+        k = npu(k)
+        v = npu(v)
+        order = np.argsort(k, kind="stable")
+        ek, ev = self.o.dump()
+        np.testing.assert_array_equal(k[order], ek)
+        if self.bits:
+            np.testing.assert_array_equal(v[order], ev.astype(np.uint64))
+        assert self.g.check() == 0
+        if self.gp is not None:
+            np.testing.assert_array_equal(self.gp.dump().cpu().numpy(), self.op.dump())
+
+
+def test_plain_table_workload(dev):
+    """u64 keys / u32 values: 2^16 inserts at capacity 2^17, 50/50 find, 25 % erase, final find."""
+    w = plain_table(seed=1)
+    p = Pair(dev, w["capacity"], 32)
+    assert (p.insert(w["insert_keys"], w["insert_vals"]) == 1).all()
+    p.same_state()
+    p.find(w["find1"])
+    p.erase(w["erase"])
+    _, f = p.find(w["find2"])
+    assert int(f.sum()) == 49152
+    p.same_state()
+
+
+@pytest.mark.parametrize("bits", [0, 32, 64])
+@pytest.mark.parametrize("chunk", [0, 1024])
+def test_duplicates_and_reserved_keys(dev, bits, chunk):
+    rng = rng_for(11, bits + chunk)
+    universe = np.concatenate([distinct_u64(rng, 3000), RESERVED])
+    p = Pair(dev, 8000, bits, chunk=chunk)
+    for step in range(9):
+        n = [1, 7, 1023, 1025, 4099, 20000, 3, 12345, 2048][step]
+        keys = universe[rng.integers(0, universe.size, size=n)]
+        vals = rng.integers(0, 1 << 63, size=n, dtype=np.uint64)
+        kind = step % 3
+        if kind == 0:
+            p.insert(keys, vals & np.uint64(0xFFFFFFFF) if bits == 32 else vals)
+        elif kind == 1:
+            p.find(keys)
+        else:
+            p.erase(keys[: n // 2])
+        p.same_state()
+
+
+@pytest.mark.parametrize("chunk", [0, 1024])
+def test_capacity_exhaustion(dev, chunk):
+    rng = rng_for(12, chunk)
+    C = 3000
+    p = Pair(dev, C, 64, chunk=chunk)
+    keys = distinct_u64(rng, 5000)
+    batch = np.concatenate([keys[:2000], keys[:500], keys[2000:5000], RESERVED])
+    batch = batch[rng.permutation(batch.size)]
+    st = p.insert(batch, rng.integers(0, 1 << 63, size=batch.size, dtype=np.uint64))
+    assert (st == 2).any()
+    p.same_state()
+    assert p.g.error() & ct.ERR_FULL
+    p.erase(keys[:1000])
+    p.insert(keys[3000:4500], np.arange(1500, dtype=np.uint64))
+    p.same_state()
+
+
+def test_empty_and_degenerate(dev):
+    p = Pair(dev, 100, 64)
+    empty = np.zeros(0, dtype=np.uint64)
+    p.insert(empty, empty)
+    p.find(empty)
+    p.erase(empty)
+    p.find(RESERVED)       # empty table: sentinels
+    p.erase(RESERVED)
+    p.same_state()
+    same = np.full(5000, 12345, dtype=np.uint64)   # one key, maximum contention
+    p.insert(same, np.arange(5000, dtype=np.uint64))
+    p.find(same[:10])
+    p.erase(same)
+    p.same_state()
+    z = Pair(dev, 0, 32)  # capacity 0: every insert is FULL
+    z.insert(np.array([1, 2, 1], dtype=np.uint64), np.array([1, 2, 3]))
+    z.same_state()
+
+
+@pytest.mark.parametrize("nb", [1, 37, 1 << 10])
+def test_full_physical_table_and_wraparound(dev, nb):
+    """Capacity equal to every physical slot: probes wrap around the bucket array."""
+    rng = rng_for(13, nb)
+    C = 8 * nb
+    p = Pair(dev, C, 64, bucket_count=nb)
+    keys = distinct_u64(rng, C + 10)
+    p.insert(keys, np.arange(keys.size, dtype=np.uint64))
+    p.find(keys)
+    p.erase(keys[::3])
+    p.insert(keys[::3][::-1], np.arange(keys[::3].size, dtype=np.uint64))
+    p.same_state()
+
+
+@pytest.mark.parametrize("nb", [1 << 12, 1000])
+def test_voxel_hash_table(dev, nb):
+    rng = rng_for(14, nb)
+    xyz = rng.integers(-50, 50, size=(20000, 3))
+    from paper_1908_05936_amd.workloads import pack_int3
+
+    keys = pack_int3(xyz[:, 0], xyz[:, 1], xyz[:, 2])
+    p = Pair(dev, 8 * nb, 32, hash_kind=ct.HASH_VOXEL21, bucket_count=nb)
+    p.insert(keys, np.arange(keys.size) % 1000)
+    p.find(keys[::-1])
+    p.erase(keys[:5000])
+    p.same_state()
+
+
+@pytest.mark.parametrize("pool_cap", [50000, 2000])
+def test_alloc_and_release(dev, pool_cap):
+    rng = rng_for(15, pool_cap)
+    universe = np.concatenate([distinct_u64(rng, 8000), RESERVED])
+    p = Pair(dev, 6000, 32, pool=pool_cap)
+    for step in range(10):
+        keys = universe[rng.integers(0, universe.size, size=int(rng.integers(1, 6000)))]
+        if step % 2 == 0:
+            p.insert_alloc(keys)
+        else:
+            p.erase_release(keys[: keys.size // 2])
+        p.find(keys[:100])
+        p.same_state()
+
+
+def test_pool_stack(dev):
+    gp = ct.Pool(1000, device=dev)
+    op = oracle.OraclePool(1000)
+    out, st = gp.pop(300)
+    eo, es = op.pop(300)
+    np.testing.assert_array_equal(out.cpu().numpy(), eo)
+    np.testing.assert_array_equal(st.cpu().numpy(), es)
+    vals = np.arange(5000, 5500, dtype=np.int32)
+    st = gp.push(torch.from_numpy(vals).to(dev))
+    np.testing.assert_array_equal(st.cpu().numpy(), op.push(vals))
+    out, st = gp.pop(1500)
+    eo, es = op.pop(1500)
+    np.testing.assert_array_equal(out.cpu().numpy(), eo)
+    np.testing.assert_array_equal(st.cpu().numpy(), es)
+    assert gp.size() == op.size() == 0
+    assert gp.error() & ct.ERR_POOL
