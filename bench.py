@@ -1,0 +1,281 @@
+"""Benchmark of the batch hash-container hot path on one MI355X.
+
+One step is one pass of the whole path over the large-table workload, on a table already resident
+in HBM: clear, fill 2^26 distinct u64 keys with u64 values (load factor 0 -> 0.8 of 83,886,080
+slots, 1.342 GB), find 2^27 queries (Zipf(1.1) popularity over the live keys, 20 % absent), erase
+2^24 live keys, re-insert 2^24 fresh keys (load 0.6 -> 0.8).  Inputs are generated once and kept
+on the GPU; only the container calls are timed.
+
+The printed JSON line carries:
+  value        whole-step throughput, container operations per second (Mops/s)
+  breakdown    per-operation Mops/s from HIP events on the library's stream
+  roofline     the dominant kernel's algorithmic bytes per launch / its mean duration vs 8 TB/s
+  random_access the same kernels against ceilings measured in this run on this chip
+  cpu_baseline the CPU oracle timed on a bounded sample of the same workload
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import platform
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+FIND_BYTES = 8 + 8 + 1 + 128      # key in, value out, found flag, one 128-byte bucket line
+INSERT_BYTES = 8 + 8 + 1 + 2 * 128  # key, value, status in/out; bucket line read + written back
+METRIC = "find & insert Mops/s at load 0.8 (1 GPU); served p50/p99 batch latency"
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--log2-keys", type=int, default=26)
+    ap.add_argument("--log2-queries", type=int, default=27)
+    ap.add_argument("--log2-churn", type=int, default=24)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-ceilings", action="store_true")
+    ap.add_argument("--cpu-sample-shift", type=int, default=1,
+                    help="oracle sample = the workload with every size divided by 2^shift")
+    return ap.parse_args()
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def to_dev(a, dev):
+    import torch
+
+    return torch.from_numpy(np.ascontiguousarray(a).view(np.int64)).to(dev)
+
+
+def measure_ceilings(ct, torch, dev, nlines, find_keys, uniform_keys):
+    """Random 128-byte line gathers (R1), gather + CAS (R2), bare CAS (R3), stream copy (R4) at
+    the table's footprint; R5 replays the find's own key stream through the R1 kernel."""
+    buf = torch.zeros(nlines * 128, dtype=torch.uint8, device=dev)
+    out = torch.empty(uniform_keys.numel(), dtype=torch.int64, device=dev)
+    res = {}
+
+    def timed(fn, reps=5):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps * 1e-3
+
+    n = uniform_keys.numel()
+    t = timed(lambda: ct.gather(buf, nlines, 128, uniform_keys, out))
+    res["R1_gather128_Mlines_s"] = n / t / 1e6
+    t = timed(lambda: ct.gather(buf, nlines * 2, 64, uniform_keys, out))
+    res["R1_gather64_Mlines_s"] = n / t / 1e6
+    t = timed(lambda: ct.gather(buf, nlines, 128, uniform_keys, out, cas=True))
+    res["R2_gather128_cas_Mops_s"] = n / t / 1e6
+    t = timed(lambda: ct.cas_words(buf, nlines * 16, uniform_keys))
+    res["R3_cas_Mops_s"] = n / t / 1e6
+    nb = min(buf.numel(), 1 << 30)
+    dst = torch.empty(nb, dtype=torch.uint8, device=dev)
+    t = timed(lambda: ct.copy(buf, dst, nb))
+    res["R4_copy_GB_s"] = 2 * nb / t / 1e9
+    del dst
+    out2 = torch.empty(find_keys.numel(), dtype=torch.int64, device=dev)
+    t = timed(lambda: ct.gather(buf, nlines, 128, find_keys, out2))
+    res["R5_find_stream_Mlines_s"] = find_keys.numel() / t / 1e6
+    del buf, out, out2
+    torch.cuda.empty_cache()
+    return res
+
+
+def cpu_baseline(shift, seed=3):
+    """The oracle as it stands, single-threaded, on the workload scaled down by 2^shift."""
+    import oracle
+    from paper_1908_05936_amd.workloads import large_table
+
+    w = large_table(seed=seed, log2_keys=26 - shift, log2_queries=27 - shift, log2_churn=24 - shift)
+    o = oracle.OracleTable(w["capacity"], 64)
+    ops = w["insert_keys"].size + w["find"].size + w["erase"].size + w["reinsert_keys"].size
+    t0 = time.perf_counter()
+    o.insert(w["insert_keys"], w["insert_vals"])
+    o.find(w["find"])
+    o.erase(w["erase"])
+    o.insert(w["reinsert_keys"], w["reinsert_vals"])
+    dt = time.perf_counter() - t0
+    return {
+        "value": ops / dt / 1e6,
+        "unit": "Mops/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": (f"large_table scaled by 1/{1 << shift}: fill 2^{26 - shift}, "
+                   f"2^{27 - shift} Zipf(1.1) finds (20% absent), erase 2^{24 - shift}, "
+                   f"re-insert 2^{24 - shift}; {ops} ops in {dt:.2f} s, single thread"),
+        "host_cpu": platform.processor() or platform.machine(),
+        "host_threads_available": os.cpu_count(),
+    }
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(f"bench.py runs on one GPU only; --gpus {a.gpus} is not supported "
+              "(the container path is single-GPU; sharding is described in DESIGN.md)",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    from paper_1908_05936_amd import ct
+    from paper_1908_05936_amd.workloads import large_table
+
+    dev = torch.device("cuda", 0)
+    ct.lib()
+    t0 = time.perf_counter()
+    w = large_table(seed=3, log2_keys=a.log2_keys, log2_queries=a.log2_queries, log2_churn=a.log2_churn)
+    log(f"generated workload in {time.perf_counter() - t0:.1f} s")
+    n_fill = w["insert_keys"].size
+    n_find = w["find"].size
+    n_er = w["erase"].size
+    n_re = w["reinsert_keys"].size
+    cap = w["capacity"]
+    K_fill, V_fill = to_dev(w["insert_keys"], dev), to_dev(w["insert_vals"], dev)
+    Q = to_dev(w["find"], dev)
+    E = to_dev(w["erase"], dev)
+    K_re, V_re = to_dev(w["reinsert_keys"], dev), to_dev(w["reinsert_vals"], dev)
+    n_present_expected = int(round(n_find * 0.8))
+    del w
+
+    table = ct.Table(cap, ct.VAL_U64, ct.HASH_MIX64, device=dev)
+    st_fill = torch.empty(n_fill, dtype=torch.uint8, device=dev)
+    vals_out = torch.empty(n_find, dtype=torch.int64, device=dev)
+    found = torch.empty(n_find, dtype=torch.uint8, device=dev)
+    erased = torch.empty(n_er, dtype=torch.uint8, device=dev)
+    st_re = torch.empty(n_re, dtype=torch.uint8, device=dev)
+    L = ct.lib()
+    h = table._h
+    s = ct._stream(dev)
+    P = ct._ptr
+
+    def op_clear():
+        ct._check(L.ct_clear(h, s), "clear")
+
+    def op_fill():
+        ct._check(L.ct_insert_batch(h, P(K_fill), P(V_fill), n_fill, P(st_fill), s), "fill")
+
+    def op_find():
+        ct._check(L.ct_find_batch(h, P(Q), n_find, P(vals_out), P(found), s), "find")
+
+    def op_erase():
+        ct._check(L.ct_erase_batch(h, P(E), n_er, P(erased), s), "erase")
+
+    def op_reins():
+        ct._check(L.ct_insert_batch(h, P(K_re), P(V_re), n_re, P(st_re), s), "reinsert")
+
+    ops = [("clear", op_clear), ("insert_fill", op_fill), ("find", op_find), ("erase", op_erase),
+           ("insert_churn", op_reins)]
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(len(ops) + 1)]
+
+    def step(timing):
+        if timing:
+            ev[0].record()
+        for j, (_, fn) in enumerate(ops):
+            fn()
+            if timing:
+                ev[j + 1].record()
+
+    for _ in range(a.warmup):
+        step(False)
+    torch.cuda.synchronize()
+    # sanity of the last warm-up step: sizes and hit counts the workload fixes
+    if a.warmup:
+        assert int((st_fill == 1).sum()) == n_fill
+        assert int(found.sum()) == n_present_expected, int(found.sum())
+        assert int(erased.sum()) == n_er and int((st_re == 1).sum()) == n_re
+        assert table.size() == n_fill
+    per = {name: 0.0 for name, _ in ops}
+    torch.cuda.synchronize()
+    w0 = time.perf_counter()
+    for _ in range(a.steps):
+        step(True)
+        torch.cuda.synchronize()
+        for j, (name, _) in enumerate(ops):
+            per[name] += ev[j].elapsed_time(ev[j + 1]) * 1e-3
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - w0
+    total_ops = n_fill + n_find + n_er + n_re
+    dev_time = sum(per.values())
+    ms_step = wall / a.steps * 1e3
+    counts = {"clear": 0, "insert_fill": n_fill, "find": n_find, "erase": n_er, "insert_churn": n_re}
+    breakdown = {name: {"ms": per[name] / a.steps * 1e3,
+                        "Mops_s": (counts[name] * a.steps / per[name] / 1e6) if counts[name] else None}
+                 for name, _ in ops}
+    find_t = per["find"] / a.steps
+    fill_t = per["insert_fill"] / a.steps
+    find_gbs = FIND_BYTES * n_find / find_t / 1e9
+    fill_gbs = INSERT_BYTES * n_fill / fill_t / 1e9
+    dominant = "find" if find_t >= fill_t else "insert_fill"
+    roof = {
+        "kernel": "k_find<u64>" if dominant == "find" else "insert pipeline (fill)",
+        "bound": "hbm",
+        "achieved": find_gbs if dominant == "find" else fill_gbs,
+        "peak": HBM_PEAK_GBS,
+        "unit": "GB/s",
+        "frac": (find_gbs if dominant == "find" else fill_gbs) / HBM_PEAK_GBS,
+        "traffic": None,
+        "bytes_per_op": FIND_BYTES if dominant == "find" else INSERT_BYTES,
+        "ops_per_launch": n_find if dominant == "find" else n_fill,
+    }
+    line = {
+        "metric": METRIC,
+        "value": total_ops * a.steps / dev_time / 1e6,
+        "unit": "Mops/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u64",
+        "data": "synthetic",
+        "config": {
+            "workload": (f"large_table: 2^{a.log2_keys} distinct u64 keys -> u64 values at load factor 0.8 "
+                         f"({cap} slots, {cap * 16 / 1e9:.3f} GB), 2^{a.log2_queries} finds Zipf(1.1) "
+                         f"with 20% absent, erase 2^{a.log2_churn}, re-insert 2^{a.log2_churn} fresh"),
+            "capacity": cap,
+            "bucket_count": table.bucket_count,
+            "ops_per_step": total_ops,
+            "wall_Mops_s": total_ops * a.steps / wall / 1e6,
+        },
+        "breakdown": breakdown,
+        "roofline": roof,
+    }
+    if not a.no_ceilings:
+        rng = np.random.default_rng(99)
+        uni = torch.from_numpy(rng.integers(0, 1 << 63, size=n_find, dtype=np.int64)).to(dev)
+        del vals_out, found
+        torch.cuda.empty_cache()
+        ceil = measure_ceilings(ct, torch, dev, cap // 8, Q, uni)
+        f_mops = breakdown["find"]["Mops_s"]
+        i_mops = breakdown["insert_fill"]["Mops_s"]
+        ceil["find_frac_of_R1"] = f_mops / ceil["R1_gather128_Mlines_s"]
+        ceil["find_frac_of_R5"] = f_mops / ceil["R5_find_stream_Mlines_s"]
+        ceil["insert_frac_of_R2"] = i_mops / ceil["R2_gather128_cas_Mops_s"]
+        line["random_access"] = ceil
+    if not a.no_cpu_baseline:
+        log("timing the CPU oracle sample")
+        line["cpu_baseline"] = cpu_baseline(a.cpu_sample_shift)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -48,16 +48,6 @@ struct alignas(128) Bucket {
   Slot s[kSlots];
 };
 
-// dedup scratch: key -> lowest chunk index holding it
-struct alignas(16) DSlot {
-  uint64_t key;
-  uint32_t idx;
-  uint32_t pad;
-};
-struct alignas(128) DBucket {
-  DSlot s[kSlots];
-};
-
 struct alignas(256) Header {
   uint64_t size;           // live keys, out-of-band keys included
   uint64_t size0;          // size when the current chunk started
@@ -86,11 +76,13 @@ struct TableView {
   uint64_t nb;
   uint64_t cap;
   Header* hdr;
-  DBucket* dd;
+  uint64_t* dd;      // dedup scratch: (fingerprint << 32 | lowest chunk index), kEmpty = free
+  uint8_t* dmark;   // per chunk element: 1 = its key occurs more than once in the chunk
   uint2* dup;       // (chunk index, index of its first occurrence)
   uint8_t* flag;    // per chunk element: 1 = takes part in the rank scan
   uint64_t* ref;    // per chunk element: claimed slot, or the value an erase releases
   uint32_t* tsum;   // per tile: flagged count, then its exclusive prefix
+  int64_t* bcnt;    // per block of the last insert/erase kernel: change of the live count
   int hash;         // 0 mix64, 1 voxel21
   int nb_pow2;
 };
@@ -128,8 +120,8 @@ __device__ __forceinline__ uint64_t home_of(const TableView& t, uint64_t key) {
   return __umul64hi(fmix64(key), t.nb);
 }
 
-__device__ __forceinline__ uint32_t dedup_home(uint64_t key, uint32_t dmask) {
-  return (uint32_t)(fmix64(key ^ 0x9E3779B97F4A7C15ull) >> 32) & dmask;
+__device__ __forceinline__ uint64_t dedup_mix(uint64_t key) {
+  return fmix64(key ^ 0x9E3779B97F4A7C15ull);
 }
 
 __device__ __forceinline__ uint64_t next_bucket(const TableView& t, uint64_t b) {
@@ -155,6 +147,9 @@ __device__ __forceinline__ bool cas64(uint64_t* p, uint64_t& expected, uint64_t 
                                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 __device__ __forceinline__ uint32_t amin32(uint32_t* p, uint32_t v) {
+  return __hip_atomic_fetch_min(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint64_t amin64(uint64_t* p, uint64_t v) {
   return __hip_atomic_fetch_min(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 __device__ __forceinline__ uint32_t aadd32(uint32_t* p, uint32_t v) {
@@ -183,6 +178,18 @@ __device__ __forceinline__ uint32_t wave_append(bool pred, uint32_t* counter) {
 __device__ __forceinline__ uint64_t wave_sum(uint64_t v) {
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
   return v;
+}
+
+// Sum of `v` over a block of kBlock threads, returned to thread 0; call with every thread active.
+__device__ __forceinline__ int64_t block_sum(int64_t v) {
+  __shared__ int64_t part[kBlock / 64];
+  v = (int64_t)wave_sum((uint64_t)v);
+  if (wave_lane() == 0) part[threadIdx.x >> 6] = v;
+  __syncthreads();
+  int64_t s = 0;
+  if (threadIdx.x == 0)
+    for (int w = 0; w < kBlock / 64; ++w) s += part[w];
+  return s;
 }
 
 }  // namespace ct

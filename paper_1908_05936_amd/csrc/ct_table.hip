@@ -119,19 +119,21 @@ __device__ __forceinline__ uint64_t claim(const TableView& t, uint64_t key, uint
   return kNoPos;
 }
 
-// Lowest chunk index of `key` recorded by k_dedup.  The key is always there; the scan is bounded
-// anyway, and a miss makes the element act for itself and raises kErrInternal.
-__device__ __forceinline__ uint32_t first_index(const TableView& t, uint64_t key, uint32_t dmask,
-                                                int sub, uint32_t self) {
-  if (key >= kTomb) return t.hdr->spec_first[key - kTomb];
-  uint32_t b = dedup_home(key, dmask);
+// Per lane: lowest chunk index of a key that k_dedup marked as repeated.  The entry is always
+// there; the scan is bounded anyway, and a miss makes the element act for itself and raises
+// kErrInternal.
+__device__ __forceinline__ uint32_t dedup_lookup(const TableView& t, const uint64_t* keys,
+                                                 uint64_t key, uint32_t dmask, uint32_t self) {
+  const uint64_t mix = dedup_mix(key);
+  const uint64_t tag = mix & 0xFFFFFFFF00000000ull;
+  uint32_t h = (uint32_t)mix & dmask;
   for (uint32_t step = 0; step <= dmask; ++step) {
-    const DSlot s = t.dd[b].s[sub];
-    const uint32_t m = group_bits(__ballot(s.key == key));
-    if (m) return __shfl(s.idx, group_base() + lowest(m), 64);
-    b = (b + 1) & dmask;
+    const uint64_t e = t.dd[h];
+    if (e == kEmpty) break;
+    if ((e & 0xFFFFFFFF00000000ull) == tag && keys[(uint32_t)e] == key) return (uint32_t)e;
+    h = (h + 1) & dmask;
   }
-  if (sub == 0) aor32(&t.hdr->err, kErrInternal);
+  aor32(&t.hdr->err, kErrInternal);
   return self;
 }
 
@@ -165,12 +167,12 @@ __global__ __launch_bounds__(kBlock) void k_table_reset(TableView t, int zero_he
 // Per chunk: clear the dedup scratch, snapshot the counters, decide whether the chunk can reach
 // capacity (or empty the pool).
 __global__ __launch_bounds__(kBlock) void k_prologue(TableView t, PoolHeader* pool,
-                                                     uint32_t dbuckets, int64_t q) {
+                                                     uint32_t dslots, int64_t q) {
   const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t nt = (int64_t)gridDim.x * blockDim.x;
-  const uint4 empty = make_uint4(0xFFFFFFFFu, 0xFFFFFFFFu, kNone, 0u);
-  for (int64_t j = tid; j < (int64_t)dbuckets * kSlots; j += nt)
-    *reinterpret_cast<uint4*>(&t.dd[j >> 3].s[j & 7]) = empty;
+  const uint4 empty = make_uint4(0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu);
+  for (int64_t j = tid; j < (int64_t)dslots / 2; j += nt) reinterpret_cast<uint4*>(t.dd)[j] = empty;
+  for (int64_t j = tid; j < (q + 15) / 16; j += nt) reinterpret_cast<uint4*>(t.dmark)[j] = make_uint4(0, 0, 0, 0);
   if (tid == 0) {
     Header* h = t.hdr;
     h->size0 = h->size;
@@ -186,50 +188,118 @@ __global__ __launch_bounds__(kBlock) void k_prologue(TableView t, PoolHeader* po
   }
 }
 
-// Lowest index per distinct key of the chunk.
+// Lowest index per distinct key of the chunk, one thread per element.  The first copy of a key
+// to arrive claims an empty entry with one CAS; a later copy lowers the entry's index with an
+// atomic min and marks both itself and the previous holder as repeated, so every element of a key
+// that occurs more than once ends up marked and elements of unique keys stay unmarked.  All
+// indices held by one entry belong to one key, so the fingerprint plus one look at that element's
+// key identifies the entry exactly.
 __global__ __launch_bounds__(kBlock) void k_dedup(TableView t, const uint64_t* __restrict__ keys,
                                                   int64_t q, uint32_t dmask) {
-  const int sub = threadIdx.x & 7;
-  const int64_t ng = (int64_t)gridDim.x * (kBlock / 8);
-  for (int64_t i = (int64_t)blockIdx.x * (kBlock / 8) + (threadIdx.x >> 3); i < q; i += ng) {
+  const int64_t nt = (int64_t)gridDim.x * kBlock;
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < q; i += nt) {
     const uint64_t key = keys[i];
     if (key >= kTomb) {
-      if (sub == 0) amin32(&t.hdr->spec_first[key - kTomb], (uint32_t)i);
+      amin32(&t.hdr->spec_first[key - kTomb], (uint32_t)i);
       continue;
     }
-    uint32_t b = dedup_home(key, dmask);
-    for (;;) {
-      const DSlot s = t.dd[b].s[sub];
-      const uint32_t m = group_bits(__ballot(s.key == key));
-      if (m) {
-        if (sub == lowest(m)) amin32(&t.dd[b].s[sub].idx, (uint32_t)i);
+    const uint64_t mix = dedup_mix(key);
+    const uint64_t tag = mix & 0xFFFFFFFF00000000ull;
+    const uint64_t mine = tag | (uint64_t)i;
+    uint32_t h = (uint32_t)mix & dmask;
+    for (uint32_t step = 0; step <= dmask; ++step) {
+      uint64_t e = t.dd[h];
+      if (e == kEmpty) {
+        uint64_t expected = kEmpty;
+        if (cas64(&t.dd[h], expected, mine)) break;
+        e = expected;
+      }
+      if ((e & 0xFFFFFFFF00000000ull) == tag && keys[(uint32_t)e] == key) {
+        const uint64_t old = amin64(&t.dd[h], mine);
+        t.dmark[i] = 1;
+        t.dmark[(uint32_t)old] = 1;
         break;
       }
-      uint32_t e = group_bits(__ballot(s.key == kEmpty));
-      bool placed = false;
-      while (e) {
-        const int c = lowest(e);
-        int ok = 0;
-        if (sub == c) {
-          uint64_t expected = kEmpty;
-          if (cas64(&t.dd[b].s[c].key, expected, key) || expected == key) {
-            amin32(&t.dd[b].s[c].idx, (uint32_t)i);
-            ok = 1;
-          }
-        }
-        if (group_bits(__ballot(ok))) {
-          placed = true;
-          break;
-        }
-        e &= e - 1;
-      }
-      if (placed) break;
-      b = (b + 1) & dmask;
+      h = (h + 1) & dmask;
     }
   }
 }
 
-// Insert actors.  fast: claim directly.  Otherwise (or with a pool) flag new keys for ranking.
+// Index-order role of this lane's element: its own index when it is the first copy of its key in
+// the chunk, else the index of that first copy.
+__device__ __forceinline__ uint32_t first_copy(const TableView& t, const uint64_t* keys,
+                                               uint64_t key, int64_t i, uint32_t dmask) {
+  if (key >= kTomb) return t.hdr->spec_first[key - kTomb];
+  if (t.dmark[i]) return dedup_lookup(t, keys, key, dmask, (uint32_t)i);
+  return (uint32_t)i;
+}
+
+// Group probe of up to 8 keys at once.  Key u of the group (held by lane u, broadcast here) is
+// probed when bit u of `A` is set.  All bucket loads of a round are issued before any is
+// resolved.  Results: bit u of *found / *hadE / *freeb, and on lane u for its own key: the slot
+// and value when found; with WANT_FREE, the first free slot on the probe path (bucket *myfb, slot
+// *myc) and the key word seen there (*myexp, the expected value of a claim).
+template <bool WANT_FREE>
+__device__ __forceinline__ void group_probe(const TableView& t, uint64_t key, uint32_t A, int sub,
+                                            uint32_t* found, uint32_t* hadE, uint32_t* freeb,
+                                            uint64_t* mypos, uint64_t* myval, uint64_t* myfb,
+                                            int* myc, uint64_t* myexp) {
+  const int gb = group_base();
+  uint64_t kk[kSlots], b[kSlots];
+  Slot sl[kSlots];
+#pragma unroll
+  for (int u = 0; u < kSlots; ++u) {
+    kk[u] = __shfl(key, gb + u, 64);
+    b[u] = ((A >> u) & 1) ? home_of(t, kk[u]) : 0;
+  }
+  uint32_t live = A, fnd = 0, he = 0, frb = 0;
+  for (uint64_t round = 0; live && round < t.nb; ++round) {
+    // unconditional: a branch around each load would make the compiler drain the load queue
+    // before the next one; a finished key re-reads its last bucket (an L1 hit)
+#pragma unroll
+    for (int u = 0; u < kSlots; ++u) sl[u] = t.bk[b[u]].s[sub];
+#pragma unroll
+    for (int u = 0; u < kSlots; ++u) {
+      if (!((live >> u) & 1)) continue;
+      const uint32_t m = group_bits(__ballot(sl[u].key == kk[u]));
+      const uint32_t e = group_bits(__ballot(sl[u].key == kEmpty));
+      if (m) {
+        const int c = lowest(m);
+        const uint64_t v = __shfl(sl[u].val, gb + c, 64);
+        if (sub == u) {
+          *mypos = b[u] * kSlots + (uint64_t)c;
+          *myval = v;
+        }
+        fnd |= 1u << u;
+        if (e) he |= 1u << u;
+        live &= ~(1u << u);
+        continue;
+      }
+      if (WANT_FREE && !((frb >> u) & 1)) {
+        const uint32_t f = e | group_bits(__ballot(sl[u].key == kTomb));
+        if (f) {
+          const int c = lowest(f);
+          const uint64_t seen = __shfl(sl[u].key, gb + c, 64);
+          frb |= 1u << u;
+          if (sub == u) {
+            *myfb = b[u];
+            *myc = c;
+            *myexp = seen;
+          }
+        }
+      }
+      if (e) live &= ~(1u << u);
+      else b[u] = next_bucket(t, b[u]);
+    }
+  }
+  *found = fnd;
+  *hadE = he;
+  *freeb = frb;
+}
+
+// Insert actors, 8 elements per group and one per lane.  fast: claim directly with one CAS per
+// new key (all CASes of the group in flight together; a lost race retries one key at a time).
+// Otherwise (or with a pool) flag new keys for the ranked completion.
 template <int VK, bool ALLOC>
 __global__ __launch_bounds__(kBlock) void k_insert(TableView t, const uint64_t* __restrict__ keys,
                                                    const void* __restrict__ vals, int64_t q,
@@ -239,105 +309,135 @@ __global__ __launch_bounds__(kBlock) void k_insert(TableView t, const uint64_t* 
   const bool fast = t.hdr->fast != 0;
   const bool flags = ALLOC || !fast;
   const int64_t ng = (int64_t)gridDim.x * (kBlock / 8);
-  uint64_t ins = 0;
-  for (int64_t i = (int64_t)blockIdx.x * (kBlock / 8) + (threadIdx.x >> 3); i < q; i += ng) {
-    const uint64_t key = keys[i];
-    const uint32_t first = first_index(t, key, dmask, sub, (uint32_t)i);
-    if (first != (uint32_t)i) {
-      const uint32_t slot = wave_append(sub == 0, &t.hdr->ndup);
-      if (sub == 0) {
-        t.dup[slot] = make_uint2((uint32_t)i, first);
-        if (flags) t.flag[i] = 0;
-      }
-      continue;
-    }
+  int64_t ins = 0;
+  for (int64_t g0 = ((int64_t)blockIdx.x * (kBlock / 8) + (threadIdx.x >> 3)) * kSlots; g0 < q;
+       g0 += ng * kSlots) {
+    const int64_t i = g0 + sub;
+    const bool valid = i < q;
+    const uint64_t key = valid ? keys[i] : kEmpty;
+    const uint32_t first = valid ? first_copy(t, keys, key, i, dmask) : 0u;
+    const bool actor = valid && first == (uint32_t)i;
+    const bool dup = valid && !actor;
+    const uint32_t slot = wave_append(dup, &t.hdr->ndup);
+    if (dup) t.dup[slot] = make_uint2((uint32_t)i, first);
+
     uint8_t st = kNoStatus;
     uint8_t newf = 0;
-    if (key >= kTomb) {
-      if (sub == 0) {
-        const int s = (int)(key - kTomb);
-        if (t.hdr->spec_live[s]) {
+    uint64_t ref = 0;
+    if (actor && key >= kTomb) {  // out-of-band key: this lane alone
+      const int s = (int)(key - kTomb);
+      if (t.hdr->spec_live[s]) {
+        st = kPresent;
+        if (ALLOC && vout) vout[i] = (int32_t)(uint32_t)t.hdr->spec_val[s];
+      } else if (!fast) {
+        newf = 1;
+      } else if (ALLOC) {
+        t.hdr->spec_live[s] = 1;
+        ref = kSpecRef + (uint64_t)s;
+        newf = 1;
+      } else {
+        t.hdr->spec_live[s] = 1;
+        t.hdr->spec_val[s] = load_val<VK>(vals, i);
+        st = kInserted;
+        ++ins;
+      }
+    }
+    const uint32_t A = group_bits(__ballot(actor && key < kTomb));
+    if (A) {
+      uint32_t found, hadE, freeb;
+      uint64_t mypos = kNoPos, myval = 0, myfb = 0, myexp = 0;
+      int myc = 0;
+      group_probe<true>(t, key, A, sub, &found, &hadE, &freeb, &mypos, &myval, &myfb, &myc, &myexp);
+      const uint32_t want = fast ? (A & ~found & freeb) : 0u;
+      if (want) {
+        // every lane claims for its own key: one CAS instruction for the whole group
+        int won = 0;
+        if ((want >> sub) & 1) {
+          uint64_t expected = myexp;
+          won = cas64(&t.bk[myfb].s[myc].key, expected, key) ? 1 : 0;
+        }
+        if (won) mypos = myfb * kSlots + (uint64_t)myc;
+        const uint32_t retry = want & ~group_bits(__ballot(won));
+        if (retry) {  // lost a race for the slot to another key: scan on, one key at a time
+          const int gb = group_base();
+#pragma unroll
+          for (int u = 0; u < kSlots; ++u) {
+            if (!((retry >> u) & 1)) continue;
+            const uint64_t ku = __shfl(key, gb + u, 64);
+            const uint64_t fbu = __shfl(myfb, gb + u, 64);
+            const uint64_t pos = claim(t, ku, fbu, sub);
+            if (sub == u) mypos = pos;
+          }
+        }
+      }
+      if ((A >> sub) & 1) {
+        if ((found >> sub) & 1) {
           st = kPresent;
-          if (ALLOC && vout) vout[i] = (int32_t)(uint32_t)t.hdr->spec_val[s];
+          if (ALLOC && vout) vout[i] = (int32_t)(uint32_t)myval;
         } else if (!fast) {
           newf = 1;
+        } else if (!((want >> sub) & 1) || mypos == kNoPos) {
+          st = kFull;  // no free slot anywhere: cannot happen while size + chunk <= capacity
+          aor32(&t.hdr->err, kErrFull);
         } else if (ALLOC) {
-          t.hdr->spec_live[s] = 1;
-          t.ref[i] = kSpecRef + (uint64_t)s;
+          ref = mypos;
           newf = 1;
         } else {
-          t.hdr->spec_live[s] = 1;
-          t.hdr->spec_val[s] = load_val<VK>(vals, i);
+          t.bk[mypos >> 3].s[mypos & 7].val = load_val<VK>(vals, i);
           st = kInserted;
           ++ins;
         }
       }
-    } else {
-      const Probe p = probe(t, key, sub, fast);
-      if (p.found) {
-        st = kPresent;
-        if (ALLOC && vout && sub == 0) vout[i] = (int32_t)(uint32_t)p.val;
-      } else if (!fast) {
-        newf = 1;
-      } else {
-        const uint64_t pos = p.has_free ? claim(t, key, p.free_b, sub) : kNoPos;
-        if (pos == kNoPos) {  // cannot happen while size + chunk <= capacity <= 8 * nb
-          st = kFull;
-          if (sub == 0) aor32(&t.hdr->err, kErrFull);
-        } else if (ALLOC) {
-          if (sub == 0) t.ref[i] = pos;
-          newf = 1;
-        } else {
-          if (sub == (int)(pos & 7)) t.bk[pos >> 3].s[pos & 7].val = load_val<VK>(vals, i);
-          st = kInserted;
-          if (sub == 0) ++ins;
-        }
-      }
     }
-    if (sub == 0) {
+    if (valid) {
       if (flags) t.flag[i] = newf;
+      if (ALLOC && newf) t.ref[i] = ref;
       if (status && st != kNoStatus) status[i] = st;
     }
   }
-  if (!ALLOC && fast) {
-    const uint64_t tot = wave_sum(ins);
-    if (wave_lane() == 0 && tot) aadd64(&t.hdr->size, tot);
-  }
+  // one partial per block, summed by k_apply_count: no same-address atomics across the grid
+  const int64_t tot = block_sum(ins);
+  if (threadIdx.x == 0) t.bcnt[blockIdx.x] = tot;
 }
 
-// Erase actors.  RELEASE: the removed value is kept for the ordered push to the pool.
+// Erase actors, 8 elements per group.  RELEASE: the removed value is kept for the ordered push.
 template <bool RELEASE>
 __global__ __launch_bounds__(kBlock) void k_erase(TableView t, const uint64_t* __restrict__ keys,
                                                   int64_t q, uint32_t dmask,
                                                   uint8_t* __restrict__ erased) {
   const int sub = threadIdx.x & 7;
   const int64_t ng = (int64_t)gridDim.x * (kBlock / 8);
-  uint64_t del = 0;
-  for (int64_t i = (int64_t)blockIdx.x * (kBlock / 8) + (threadIdx.x >> 3); i < q; i += ng) {
-    const uint64_t key = keys[i];
-    const uint32_t first = first_index(t, key, dmask, sub, (uint32_t)i);
+  int64_t del = 0;
+  for (int64_t g0 = ((int64_t)blockIdx.x * (kBlock / 8) + (threadIdx.x >> 3)) * kSlots; g0 < q;
+       g0 += ng * kSlots) {
+    const int64_t i = g0 + sub;
+    const bool valid = i < q;
+    const uint64_t key = valid ? keys[i] : kEmpty;
+    const bool actor = valid && first_copy(t, keys, key, i, dmask) == (uint32_t)i;
     uint8_t hit = 0;
     uint64_t val = 0;
-    if (first == (uint32_t)i) {
-      if (key >= kTomb) {
-        if (sub == 0) {
-          const int s = (int)(key - kTomb);
-          if (t.hdr->spec_live[s]) {
-            t.hdr->spec_live[s] = 0;
-            val = t.hdr->spec_val[s];
-            hit = 1;
-          }
-        }
-      } else {
-        const Probe p = probe(t, key, sub, false);
-        if (p.found) {
-          if (sub == (int)(p.pos & 7)) t.bk[p.pos >> 3].s[p.pos & 7].key = p.had_empty ? kEmpty : kTomb;
-          val = p.val;
-          hit = 1;
-        }
+    if (actor && key >= kTomb) {
+      const int s = (int)(key - kTomb);
+      if (t.hdr->spec_live[s]) {
+        t.hdr->spec_live[s] = 0;
+        val = t.hdr->spec_val[s];
+        hit = 1;
       }
     }
-    if (sub == 0) {
+    const uint32_t A = group_bits(__ballot(actor && key < kTomb));
+    if (A) {
+      uint32_t found, hadE, freeb;
+      uint64_t mypos = kNoPos, myval = 0, myfb = 0, myexp = 0;
+      int myc = 0;
+      group_probe<false>(t, key, A, sub, &found, &hadE, &freeb, &mypos, &myval, &myfb, &myc, &myexp);
+      if ((found >> sub) & 1) {
+        // kEmpty only where the bucket already holds one: no probe sequence runs through it
+        t.bk[mypos >> 3].s[mypos & 7].key = ((hadE >> sub) & 1) ? kEmpty : kTomb;
+        val = myval;
+        hit = 1;
+      }
+    }
+    if (valid) {
       if (erased) erased[i] = hit;
       if (RELEASE) {
         t.flag[i] = hit;
@@ -346,8 +446,23 @@ __global__ __launch_bounds__(kBlock) void k_erase(TableView t, const uint64_t* _
       del += hit;
     }
   }
-  const uint64_t tot = wave_sum(del);
-  if (wave_lane() == 0 && tot) aadd64(&t.hdr->size, (uint64_t)0 - tot);
+  const int64_t tot = block_sum(del);
+  if (threadIdx.x == 0) t.bcnt[blockIdx.x] = -tot;
+}
+
+// Add the per-block partials of the preceding insert/erase kernel to the live count.
+__global__ __launch_bounds__(1024) void k_apply_count(TableView t, int nblocks) {
+  int64_t v = 0;
+  for (int j = threadIdx.x; j < nblocks; j += 1024) v += t.bcnt[j];
+  v = (int64_t)wave_sum((uint64_t)v);
+  __shared__ int64_t part[16];
+  if (wave_lane() == 0) part[threadIdx.x >> 6] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int64_t s = 0;
+    for (int w = 0; w < 16; ++w) s += part[w];
+    if (s) t.hdr->size = (uint64_t)((int64_t)t.hdr->size + s);
+  }
 }
 
 // Flagged count per tile of kTile elements.
@@ -548,36 +663,40 @@ __global__ __launch_bounds__(kBlock) void k_fix(TableView t, uint8_t* __restrict
   }
 }
 
+// find / contains, 8 keys per group and one per lane for loading and storing (coalesced).  The
+// group probes its keys together in rounds: every pending bucket load of a round is issued before
+// the first ballot, so a lane has up to 8 independent 16-byte loads in flight.
 template <int VK>
 __global__ __launch_bounds__(kBlock) void k_find(TableView t, const uint64_t* __restrict__ keys,
                                                  int64_t n, void* __restrict__ out,
-                                                 uint8_t* __restrict__ found) {
+                                                 uint8_t* __restrict__ found_out) {
   const int sub = threadIdx.x & 7;
   const int64_t ng = (int64_t)gridDim.x * (kBlock / 8);
-  for (int64_t i = (int64_t)blockIdx.x * (kBlock / 8) + (threadIdx.x >> 3); i < n; i += ng) {
-    const uint64_t key = keys[i];
+  for (int64_t g0 = ((int64_t)blockIdx.x * (kBlock / 8) + (threadIdx.x >> 3)) * kSlots; g0 < n;
+       g0 += ng * kSlots) {
+    const int64_t i = g0 + sub;
+    const bool valid = i < n;
+    const uint64_t key = valid ? keys[i] : kEmpty;
     bool hit = false;
     uint64_t v = 0;
-    if (key >= kTomb) {
+    if (valid && key >= kTomb) {
       hit = t.hdr->spec_live[key - kTomb] != 0;
       v = t.hdr->spec_val[key - kTomb];
-    } else {
-      uint64_t b = home_of(t, key);
-      for (uint64_t step = 0; step < t.nb; ++step) {
-        const Slot s = t.bk[b].s[sub];
-        const uint32_t m = group_bits(__ballot(s.key == key));
-        if (m) {
-          v = __shfl(s.val, group_base() + lowest(m), 64);
-          hit = true;
-          break;
-        }
-        if (group_bits(__ballot(s.key == kEmpty))) break;
-        b = next_bucket(t, b);
+    }
+    const uint32_t A = group_bits(__ballot(valid && key < kTomb));
+    if (A) {
+      uint32_t found, hadE, freeb;
+      uint64_t mypos = kNoPos, myval = 0, myfb = 0, myexp = 0;
+      int myc = 0;
+      group_probe<false>(t, key, A, sub, &found, &hadE, &freeb, &mypos, &myval, &myfb, &myc, &myexp);
+      if ((A >> sub) & 1) {
+        hit = (found >> sub) & 1;
+        v = myval;
       }
     }
-    if (sub == 0) {
+    if (valid) {
       if (out) store_val<VK>(out, i, hit ? v : sentinel<VK>());
-      if (found) found[i] = hit ? 1 : 0;
+      if (found_out) found_out[i] = hit ? 1 : 0;
     }
   }
 }
@@ -744,8 +863,8 @@ int64_t pow2ceil(int64_t x) {
 }
 
 struct Layout {
-  int64_t nb, chunk, dbuckets, ntiles;
-  int64_t off_bk, off_dd, off_dup, off_flag, off_ref, off_tsum, total;
+  int64_t nb, chunk, dslots, ntiles;
+  int64_t off_bk, off_dd, off_dmark, off_dup, off_flag, off_ref, off_tsum, off_bcnt, total;
 };
 
 bool make_layout(const ct_table_desc* d, Layout* L) {
@@ -760,13 +879,15 @@ bool make_layout(const ct_table_desc* d, Layout* L) {
   if (q < 1024 || q > ((int64_t)1 << 24) || (q & (q - 1))) return false;
   L->nb = nb;
   L->chunk = q;
-  L->dbuckets = (2 * q) / kSlots;
+  L->dslots = 2 * q;
   L->ntiles = (q + kTile - 1) / kTile;
   int64_t off = align_up((int64_t)sizeof(Header));
   L->off_bk = off;
   off = align_up(off + nb * (int64_t)sizeof(Bucket));
   L->off_dd = off;
-  off = align_up(off + L->dbuckets * (int64_t)sizeof(DBucket));
+  off = align_up(off + L->dslots * 8);
+  L->off_dmark = off;
+  off = align_up(off + q);
   L->off_dup = off;
   off = align_up(off + q * (int64_t)sizeof(uint2));
   L->off_flag = off;
@@ -775,6 +896,8 @@ bool make_layout(const ct_table_desc* d, Layout* L) {
   off = align_up(off + q * 8);
   L->off_tsum = off;
   off = align_up(off + L->ntiles * 4);
+  L->off_bcnt = off;
+  off = align_up(off + kMaxGroupBlocks * 8);
   L->total = off;
   return true;
 }
@@ -793,10 +916,8 @@ int flat_blocks(int64_t n) {
 
 ct_status launched() { return hipGetLastError() == hipSuccess ? CT_OK : CT_E_HIP; }
 
-uint32_t dedup_buckets_for(int64_t q) {
-  const int64_t b = pow2ceil(2 * q) / kSlots;
-  return (uint32_t)std::max<int64_t>(1, b);
-}
+// dedup entries for a chunk of q elements: a power of two >= 2q (load at most one half)
+uint32_t dedup_slots_for(int64_t q) { return (uint32_t)std::max<int64_t>(2, pow2ceil(2 * q)); }
 
 template <typename T>
 ct_status read_back(const T* dev, T* host, hipStream_t s) {
@@ -813,15 +934,16 @@ ct_status insert_chunks(ct_table* t, const uint64_t* keys, const void* vals, int
   const int vb = VK == 1 ? 4 : 8;
   for (int64_t c0 = 0; c0 < n; c0 += t->chunk) {
     const int64_t q = std::min<int64_t>(t->chunk, n - c0);
-    const uint32_t db = dedup_buckets_for(q);
+    const uint32_t db = dedup_slots_for(q);
     const uint64_t* kc = keys + c0;
     const void* vc = VK ? static_cast<const void*>(static_cast<const uint8_t*>(vals) + c0 * vb) : nullptr;
     uint8_t* sc = status ? status + c0 : nullptr;
-    const int gb = group_blocks(q);
+    const int gb = group_blocks((q + kSlots - 1) / kSlots);
     const int ntiles = (int)((q + kTile - 1) / kTile);
-    k_prologue<<<flat_blocks(db * (int64_t)kSlots), kBlock, 0, s>>>(t->v, nullptr, db, q);
-    k_dedup<<<gb, kBlock, 0, s>>>(t->v, kc, q, db - 1);
+    k_prologue<<<flat_blocks(db / 2), kBlock, 0, s>>>(t->v, nullptr, db, q);
+    k_dedup<<<flat_blocks(q), kBlock, 0, s>>>(t->v, kc, q, db - 1);
     k_insert<VK, false><<<gb, kBlock, 0, s>>>(t->v, kc, vc, q, db - 1, sc, nullptr);
+    k_apply_count<<<1, 1024, 0, s>>>(t->v, gb);
     // the host bound proves that no element can meet FULL: the rank pass is not needed
     const bool surely_fast = t->size_ub + (uint64_t)q <= (uint64_t)t->desc.capacity;
     if (!surely_fast) {
@@ -842,14 +964,15 @@ ct_status erase_chunks(ct_table* t, ct_pool* p, const uint64_t* keys, int64_t n,
                        hipStream_t s) {
   for (int64_t c0 = 0; c0 < n; c0 += t->chunk) {
     const int64_t q = std::min<int64_t>(t->chunk, n - c0);
-    const uint32_t db = dedup_buckets_for(q);
+    const uint32_t db = dedup_slots_for(q);
     const uint64_t* kc = keys + c0;
     uint8_t* ec = erased ? erased + c0 : nullptr;
-    const int gb = group_blocks(q);
+    const int gb = group_blocks((q + kSlots - 1) / kSlots);
     const int ntiles = (int)((q + kTile - 1) / kTile);
-    k_prologue<<<flat_blocks(db * (int64_t)kSlots), kBlock, 0, s>>>(t->v, RELEASE ? p->hdr : nullptr, db, q);
-    k_dedup<<<gb, kBlock, 0, s>>>(t->v, kc, q, db - 1);
+    k_prologue<<<flat_blocks(db / 2), kBlock, 0, s>>>(t->v, RELEASE ? p->hdr : nullptr, db, q);
+    k_dedup<<<flat_blocks(q), kBlock, 0, s>>>(t->v, kc, q, db - 1);
     k_erase<RELEASE><<<gb, kBlock, 0, s>>>(t->v, kc, q, db - 1, ec);
+    k_apply_count<<<1, 1024, 0, s>>>(t->v, gb);
     if (RELEASE) {
       k_tile_count<<<ntiles, kBlock, 0, s>>>(t->v, q, 0);
       k_tile_scan<<<1, 1024, 0, s>>>(t->v, p->hdr, ntiles, 2);
@@ -910,11 +1033,13 @@ ct_status ct_table_init(void* d_buf, int64_t bytes, const ct_table_desc* d, void
   v.bk = reinterpret_cast<Bucket*>(base + L.off_bk);
   v.nb = (uint64_t)L.nb;
   v.cap = (uint64_t)d->capacity;
-  v.dd = reinterpret_cast<DBucket*>(base + L.off_dd);
+  v.dd = reinterpret_cast<uint64_t*>(base + L.off_dd);
+  v.dmark = base + L.off_dmark;
   v.dup = reinterpret_cast<uint2*>(base + L.off_dup);
   v.flag = base + L.off_flag;
   v.ref = reinterpret_cast<uint64_t*>(base + L.off_ref);
   v.tsum = reinterpret_cast<uint32_t*>(base + L.off_tsum);
+  v.bcnt = reinterpret_cast<int64_t*>(base + L.off_bcnt);
   v.hash = d->hash_kind;
   v.nb_pow2 = (L.nb & (L.nb - 1)) == 0;
   k_table_reset<<<flat_blocks(L.nb * kSlots), kBlock, 0, S(stream)>>>(v, 1);
@@ -958,7 +1083,7 @@ ct_status ct_find_batch(ct_table* t, const uint64_t* keys, int64_t n, void* vals
   const int vk = t->desc.val_kind;
   if (vk == CT_VAL_NONE && vals_out) return CT_E_INVALID;
   if (n == 0) return CT_OK;
-  const int gb = group_blocks(n);
+  const int gb = group_blocks((n + kSlots - 1) / kSlots);
   if (vk == CT_VAL_U32) k_find<1><<<gb, kBlock, 0, S(stream)>>>(t->v, keys, n, vals_out, found);
   else if (vk == CT_VAL_U64) k_find<2><<<gb, kBlock, 0, S(stream)>>>(t->v, keys, n, vals_out, found);
   else k_find<0><<<gb, kBlock, 0, S(stream)>>>(t->v, keys, n, nullptr, found);
@@ -1115,14 +1240,14 @@ ct_status ct_insert_alloc_batch(ct_table* t, ct_pool* p, const uint64_t* keys, i
   hipStream_t s = S(stream);
   for (int64_t c0 = 0; c0 < n; c0 += t->chunk) {
     const int64_t q = std::min<int64_t>(t->chunk, n - c0);
-    const uint32_t db = dedup_buckets_for(q);
+    const uint32_t db = dedup_slots_for(q);
     const uint64_t* kc = keys + c0;
     uint8_t* sc = status ? status + c0 : nullptr;
     int32_t* vc = vals_out ? vals_out + c0 : nullptr;
-    const int gb = group_blocks(q);
+    const int gb = group_blocks((q + kSlots - 1) / kSlots);
     const int ntiles = (int)((q + kTile - 1) / kTile);
-    k_prologue<<<flat_blocks(db * (int64_t)kSlots), kBlock, 0, s>>>(t->v, p->hdr, db, q);
-    k_dedup<<<gb, kBlock, 0, s>>>(t->v, kc, q, db - 1);
+    k_prologue<<<flat_blocks(db / 2), kBlock, 0, s>>>(t->v, p->hdr, db, q);
+    k_dedup<<<flat_blocks(q), kBlock, 0, s>>>(t->v, kc, q, db - 1);
     k_insert<1, true><<<gb, kBlock, 0, s>>>(t->v, kc, nullptr, q, db - 1, sc, vc);
     k_tile_count<<<ntiles, kBlock, 0, s>>>(t->v, q, 0);
     k_tile_scan<<<1, 1024, 0, s>>>(t->v, p->hdr, ntiles, 1);

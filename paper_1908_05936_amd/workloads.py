@@ -55,6 +55,20 @@ def distinct_u64(rng: np.random.Generator, n: int, exclude: np.ndarray | None = 
     return out
 
 
+def splitmix64(seed: int, start: int, n: int) -> np.ndarray:
+    """Outputs ``start .. start+n-1`` of the splitmix64 generator seeded with ``seed``
+    (Steele, Lea & Flood 2014).  Its output function is a bijection of the 64-bit state and the
+    states of distinct counters differ, so outputs of distinct counters are distinct keys: disjoint
+    counter ranges give disjoint key sets without any de-duplication pass.
+    """
+    gamma = np.uint64(0x9E3779B97F4A7C15)
+    i = np.arange(int(start) + 1, int(start) + int(n) + 1, dtype=np.uint64)
+    z = np.uint64(int(seed) & ((1 << 64) - 1)) + i * gamma
+    z = (z ^ (z >> np.uint64(30))) * np.uint64(0xBF58476D1CE4E5B9)
+    z = (z ^ (z >> np.uint64(27))) * np.uint64(0x94D049BB133111EB)
+    return z ^ (z >> np.uint64(31))
+
+
 def zipf_ranks(rng: np.random.Generator, n: int, num_elements: int, exponent: float) -> np.ndarray:
     """``n`` ranks in [1, num_elements] with P(k) proportional to k^-exponent.
 
@@ -132,7 +146,7 @@ def large_table(seed: int = 3, log2_keys: int = 26, log2_queries: int = 27, log2
     nq = 1 << log2_queries
     nc = 1 << log2_churn
     capacity = int(round(n / load_factor))
-    keys = distinct_u64(rng, n)
+    keys = splitmix64(seed, 0, n)
     vals = np.arange(n, dtype=np.uint64)
     n_abs = int(round(nq * absent_frac))
     n_pre = nq - n_abs
@@ -142,7 +156,7 @@ def large_table(seed: int = 3, log2_keys: int = 26, log2_queries: int = 27, log2
         perm = rng.permutation(n)                     # rank r (1-based) -> keys[perm[r-1]]
         ranks = zipf_ranks(rng, n_pre, n, zipf_s)
         pre = keys[perm[ranks - 1]]
-    fresh = distinct_u64(rng, n_abs + nc, exclude=keys)
+    fresh = splitmix64(seed, n, n_abs + nc)          # disjoint from the live keys
     absent = fresh[:n_abs]
     q = np.concatenate([pre, absent])
     q = q[rng.permutation(nq)]

@@ -1,0 +1,51 @@
+"""The seeded input generators produce what they promise (no GPU, no container arithmetic)."""
+import numpy as np
+
+from paper_1908_05936_amd.workloads import large_table, pack_int3, plain_table, splitmix64, zipf_ranks, rng_for
+
+
+def test_splitmix64_published_vector():
+    # reference output of splitmix64 seeded with 1234567 (Vigna's reference implementation)
+    assert splitmix64(1234567, 0, 3).tolist() == [6457827717110365317, 3203168211198807973,
+                                                   9817491932198370423]
+    assert splitmix64(1234567, 2, 1).tolist() == [9817491932198370423]
+
+
+def test_zipf_rank_frequencies():
+    rng = rng_for(5)
+    N, s = 1000, 1.1
+    r = zipf_ranks(rng, 400000, N, s)
+    assert r.min() >= 1 and r.max() <= N
+    p = np.arange(1, N + 1, dtype=np.float64) ** -s
+    p /= p.sum()
+    freq = np.bincount(r, minlength=N + 1)[1:] / r.size
+    for k in (1, 2, 3, 10, 100):
+        assert abs(freq[k - 1] - p[k - 1]) < 5 * np.sqrt(p[k - 1] / r.size) + 1e-4, k
+
+
+def test_plain_table_shape():
+    w = plain_table(seed=1, log2_keys=10, log2_capacity=11)
+    k = w["insert_keys"]
+    assert np.unique(k).size == k.size == 1024
+    assert np.isin(w["find1"], k).sum() == 512
+    assert np.isin(w["erase"], k).all() and np.unique(w["erase"]).size == 256
+    assert np.array_equal(np.sort(w["find2"]), np.sort(k))
+
+
+def test_large_table_shape():
+    w = large_table(seed=3, log2_keys=14, log2_queries=15, log2_churn=12)
+    k = w["insert_keys"]
+    assert np.unique(k).size == k.size
+    assert w["capacity"] == round((1 << 14) / 0.8)
+    present = np.isin(w["find"], k)
+    assert present.sum() == (1 << 15) - round((1 << 15) * 0.2)
+    assert not np.isin(w["reinsert_keys"], k).any()
+    assert not np.isin(w["find"][~present], w["reinsert_keys"]).any()
+
+
+def test_pack_int3_fields():
+    assert int(pack_int3(1, 0, 0)) == 1
+    assert int(pack_int3(0, 1, 0)) == 1 << 21
+    assert int(pack_int3(0, 0, 1)) == 1 << 42
+    assert int(pack_int3(-1, 0, 0)) == (1 << 21) - 1
+    assert int(pack_int3(0, 0, -1)) == ((1 << 21) - 1) << 42
