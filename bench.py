@@ -41,6 +41,7 @@ def parse():
     ap.add_argument("--log2-keys", type=int, default=26)
     ap.add_argument("--log2-queries", type=int, default=27)
     ap.add_argument("--log2-churn", type=int, default=24)
+    ap.add_argument("--chunk", type=int, default=0, help="table chunk (0 = library default)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-ceilings", action="store_true")
     ap.add_argument("--cpu-sample-shift", type=int, default=1,
@@ -154,7 +155,7 @@ def main():
     n_present_expected = int(round(n_find * 0.8))
     del w
 
-    table = ct.Table(cap, ct.VAL_U64, ct.HASH_MIX64, device=dev)
+    table = ct.Table(cap, ct.VAL_U64, ct.HASH_MIX64, chunk=a.chunk, device=dev)
     st_fill = torch.empty(n_fill, dtype=torch.uint8, device=dev)
     vals_out = torch.empty(n_find, dtype=torch.int64, device=dev)
     found = torch.empty(n_find, dtype=torch.uint8, device=dev)
@@ -253,6 +254,7 @@ def main():
                          f"with 20% absent, erase 2^{a.log2_churn}, re-insert 2^{a.log2_churn} fresh"),
             "capacity": cap,
             "bucket_count": table.bucket_count,
+            "chunk": table.chunk,
             "ops_per_step": total_ops,
             "wall_Mops_s": total_ops * a.steps / wall / 1e6,
         },

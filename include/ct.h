@@ -83,11 +83,16 @@ typedef struct ct_table_desc {
                              (the fixed capacity of Section 4).  C >= 0. */
     int32_t val_kind;     /* ct_val_kind */
     int32_t hash_kind;    /* ct_hash_kind */
-    int64_t bucket_count; /* home buckets, 8 slots each (one 128-byte line); 0 = ceil(C / 8).
-                             Must satisfy 8 * bucket_count >= C and bucket_count >= 1. */
+    int64_t bucket_count; /* buckets of 8 slots each (one 128-byte line); 0 = the smallest prime
+                             >= ceil(C / 8).  Must satisfy 8 * bucket_count >= C and
+                             bucket_count >= 1.  Probing steps between buckets by a per-key
+                             stride (double hashing) when the count is prime or a power of two,
+                             and by 1 otherwise. */
     int64_t chunk;        /* keys handled per internal insert/erase chunk; a power of two in
-                             [1024, 2^24]; 0 = min(2^20, max(1024, pow2ceil(C))).  Batches larger
-                             than a chunk run as consecutive chunks (same results). */
+                             [1024, 2^24]; 0 = the largest power of two <= C/8, clamped to
+                             [1024, 2^23].  Batches larger than a chunk run as consecutive chunks
+                             (same results).  The table buffer holds 34 bytes of scratch per
+                             chunk element. */
 } ct_table_desc;
 
 typedef struct ct_table ct_table;

@@ -85,6 +85,8 @@ struct TableView {
   int64_t* bcnt;    // per block of the last insert/erase kernel: change of the live count
   int hash;         // 0 mix64, 1 voxel21
   int nb_pow2;
+  int step_mode;    // probe step between buckets: 0 linear (1), 1 odd (nb a power of two),
+                    // 2 any in [1, nb) (nb prime); every mode visits all nb buckets
 };
 
 // ---------------------------------------------------------------------------------------------
@@ -112,20 +114,38 @@ __device__ __forceinline__ uint64_t voxel21(uint64_t key) {
   return (uint64_t)(int64_t)(int32_t)h;
 }
 
-__device__ __forceinline__ uint64_t home_of(const TableView& t, uint64_t key) {
+// Home bucket and probe step of a key.  The probe sequence is home, home+step, home+2*step, ...
+// (mod nb): double hashing, so displaced keys of neighbouring homes do not pile up into long
+// runs, and a step coprime with nb visits every bucket (the capacity guarantee).
+struct Seq {
+  uint64_t home;
+  uint64_t step;
+};
+
+__device__ __forceinline__ Seq probe_seq(const TableView& t, uint64_t key) {
+  const uint64_t mix = fmix64(key);
+  Seq r;
   if (t.hash == 1) {
     const uint64_t h = voxel21(key);
-    return t.nb_pow2 ? (h & (t.nb - 1)) : (h % t.nb);
+    r.home = t.nb_pow2 ? (h & (t.nb - 1)) : (h % t.nb);
+  } else {
+    r.home = __umul64hi(mix, t.nb);
   }
-  return __umul64hi(fmix64(key), t.nb);
+  const uint64_t rot = (mix << 32) | (mix >> 32);
+  if (t.step_mode == 1) r.step = (rot | 1ull) & (t.nb - 1);
+  else if (t.step_mode == 2) r.step = 1 + __umul64hi(rot, t.nb - 1);
+  else r.step = 1;
+  if (t.nb == 1) r.step = 0;
+  return r;
 }
 
 __device__ __forceinline__ uint64_t dedup_mix(uint64_t key) {
   return fmix64(key ^ 0x9E3779B97F4A7C15ull);
 }
 
-__device__ __forceinline__ uint64_t next_bucket(const TableView& t, uint64_t b) {
-  return (b + 1 == t.nb) ? 0 : b + 1;
+__device__ __forceinline__ uint64_t next_bucket(const TableView& t, uint64_t b, uint64_t step) {
+  b += step;
+  return b >= t.nb ? b - t.nb : b;
 }
 
 // ---------------------------------------------------------------------------------------------

@@ -50,6 +50,17 @@ __global__ __launch_bounds__(kB) void k_cas(uint64_t* __restrict__ words, uint64
   }
 }
 
+// Fire-and-forget 64-bit atomic min (no returned value) on a random word per key.
+__global__ __launch_bounds__(kB) void k_amin(uint64_t* __restrict__ words, uint64_t nwords,
+                                             const uint64_t* __restrict__ keys, int64_t n) {
+  const int64_t nt = (int64_t)gridDim.x * kB;
+  for (int64_t i = (int64_t)blockIdx.x * kB + threadIdx.x; i < n; i += nt) {
+    const uint64_t key = keys[i];
+    __hip_atomic_fetch_min(words + __umul64hi(fmix64(key), nwords), key, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
 __global__ __launch_bounds__(kB) void k_copy(const uint4* __restrict__ src, uint4* __restrict__ dst,
                                              int64_t n16) {
   const int64_t nt = (int64_t)gridDim.x * kB;
@@ -98,6 +109,15 @@ ct_status ctr_cas(void* words, int64_t nwords, const uint64_t* keys, int64_t n, 
   if (reinterpret_cast<uintptr_t>(words) % 8) return CT_E_INVALID;
   if (n == 0) return CT_OK;
   k_cas<<<blocks_for(n, kB, 16384), kB, 0, reinterpret_cast<hipStream_t>(stream)>>>(
+      static_cast<uint64_t*>(words), (uint64_t)nwords, keys, n);
+  return done();
+}
+
+ct_status ctr_amin(void* words, int64_t nwords, const uint64_t* keys, int64_t n, void* stream) {
+  if (!words || nwords <= 0 || n < 0 || (n > 0 && !keys)) return CT_E_INVALID;
+  if (reinterpret_cast<uintptr_t>(words) % 8) return CT_E_INVALID;
+  if (n == 0) return CT_OK;
+  k_amin<<<blocks_for(n, kB, 16384), kB, 0, reinterpret_cast<hipStream_t>(stream)>>>(
       static_cast<uint64_t*>(words), (uint64_t)nwords, keys, n);
   return done();
 }

@@ -70,7 +70,8 @@ __device__ __forceinline__ Probe probe(const TableView& t, uint64_t key, int sub
   r.pos = kNoPos;
   r.free_b = 0;
   r.has_free = false;
-  uint64_t b = home_of(t, key);
+  const Seq q = probe_seq(t, key);
+  uint64_t b = q.home;
   for (uint64_t step = 0; step < t.nb; ++step) {
     const Slot s = t.bk[b].s[sub];
     const uint32_t m = group_bits(__ballot(s.key == key));
@@ -91,7 +92,7 @@ __device__ __forceinline__ Probe probe(const TableView& t, uint64_t key, int sub
       }
     }
     if (e) return r;
-    b = next_bucket(t, b);
+    b = next_bucket(t, b, q.step);
   }
   return r;
 }
@@ -100,7 +101,8 @@ __device__ __forceinline__ Probe probe(const TableView& t, uint64_t key, int sub
 // index, or kNoPos when every bucket was tried (only possible when the table is physically full).
 // A stale view can only show a slot as free when it is not: the CAS then fails and reports the
 // truth, so the scan always makes progress.
-__device__ __forceinline__ uint64_t claim(const TableView& t, uint64_t key, uint64_t b, int sub) {
+__device__ __forceinline__ uint64_t claim(const TableView& t, uint64_t key, uint64_t b,
+                                          uint64_t stride, int sub) {
   for (uint64_t step = 0; step < t.nb; ++step) {
     const uint64_t cur = t.bk[b].s[sub].key;
     uint32_t f = group_bits(__ballot(cur == kEmpty || cur == kTomb));
@@ -114,7 +116,7 @@ __device__ __forceinline__ uint64_t claim(const TableView& t, uint64_t key, uint
       if (group_bits(__ballot(won))) return b * kSlots + (uint64_t)c;
       f &= f - 1;
     }
-    b = next_bucket(t, b);
+    b = next_bucket(t, b, stride);
   }
   return kNoPos;
 }
@@ -243,14 +245,17 @@ template <bool WANT_FREE>
 __device__ __forceinline__ void group_probe(const TableView& t, uint64_t key, uint32_t A, int sub,
                                             uint32_t* found, uint32_t* hadE, uint32_t* freeb,
                                             uint64_t* mypos, uint64_t* myval, uint64_t* myfb,
-                                            int* myc, uint64_t* myexp) {
+                                            int* myc, uint64_t* myexp, uint64_t* mystep) {
   const int gb = group_base();
-  uint64_t kk[kSlots], b[kSlots];
+  uint64_t kk[kSlots], b[kSlots], st[kSlots];
   Slot sl[kSlots];
+  Seq mine = {0, 0};
+  if ((A >> sub) & 1) mine = probe_seq(t, key);  // each lane hashes its own key once
 #pragma unroll
   for (int u = 0; u < kSlots; ++u) {
     kk[u] = __shfl(key, gb + u, 64);
-    b[u] = ((A >> u) & 1) ? home_of(t, kk[u]) : 0;
+    b[u] = __shfl(mine.home, gb + u, 64);
+    st[u] = __shfl(mine.step, gb + u, 64);
   }
   uint32_t live = A, fnd = 0, he = 0, frb = 0;
   for (uint64_t round = 0; live && round < t.nb; ++round) {
@@ -289,12 +294,13 @@ __device__ __forceinline__ void group_probe(const TableView& t, uint64_t key, ui
         }
       }
       if (e) live &= ~(1u << u);
-      else b[u] = next_bucket(t, b[u]);
+      else b[u] = next_bucket(t, b[u], st[u]);
     }
   }
   *found = fnd;
   *hadE = he;
   *freeb = frb;
+  *mystep = mine.step;
 }
 
 // Insert actors, 8 elements per group and one per lane.  fast: claim directly with one CAS per
@@ -347,7 +353,9 @@ __global__ __launch_bounds__(kBlock) void k_insert(TableView t, const uint64_t* 
       uint32_t found, hadE, freeb;
       uint64_t mypos = kNoPos, myval = 0, myfb = 0, myexp = 0;
       int myc = 0;
-      group_probe<true>(t, key, A, sub, &found, &hadE, &freeb, &mypos, &myval, &myfb, &myc, &myexp);
+      uint64_t mystep = 0;
+      group_probe<true>(t, key, A, sub, &found, &hadE, &freeb, &mypos, &myval, &myfb, &myc, &myexp,
+                        &mystep);
       const uint32_t want = fast ? (A & ~found & freeb) : 0u;
       if (want) {
         // every lane claims for its own key: one CAS instruction for the whole group
@@ -365,7 +373,8 @@ __global__ __launch_bounds__(kBlock) void k_insert(TableView t, const uint64_t* 
             if (!((retry >> u) & 1)) continue;
             const uint64_t ku = __shfl(key, gb + u, 64);
             const uint64_t fbu = __shfl(myfb, gb + u, 64);
-            const uint64_t pos = claim(t, ku, fbu, sub);
+            const uint64_t stu = __shfl(mystep, gb + u, 64);
+            const uint64_t pos = claim(t, ku, fbu, stu, sub);
             if (sub == u) mypos = pos;
           }
         }
@@ -429,7 +438,9 @@ __global__ __launch_bounds__(kBlock) void k_erase(TableView t, const uint64_t* _
       uint32_t found, hadE, freeb;
       uint64_t mypos = kNoPos, myval = 0, myfb = 0, myexp = 0;
       int myc = 0;
-      group_probe<false>(t, key, A, sub, &found, &hadE, &freeb, &mypos, &myval, &myfb, &myc, &myexp);
+      uint64_t mystep = 0;
+      group_probe<false>(t, key, A, sub, &found, &hadE, &freeb, &mypos, &myval, &myfb, &myc, &myexp,
+                         &mystep);
       if ((found >> sub) & 1) {
         // kEmpty only where the bucket already holds one: no probe sequence runs through it
         t.bk[mypos >> 3].s[mypos & 7].key = ((hadE >> sub) & 1) ? kEmpty : kTomb;
@@ -634,7 +645,7 @@ __global__ __launch_bounds__(kBlock) void k_final(TableView t, PoolHeader* pool,
         if (sub == 0) t.hdr->spec_live[key - kTomb] = 1;
       } else {
         const Probe p = probe(t, key, sub, true);
-        pos = p.has_free ? claim(t, key, p.free_b, sub) : kNoPos;
+        pos = p.has_free ? claim(t, key, p.free_b, probe_seq(t, key).step, sub) : kNoPos;
       }
       if (pos >= kSpecRef && pos != kNoPos) {
         if (sub == 0) t.hdr->spec_val[pos - kSpecRef] = v;
@@ -688,7 +699,9 @@ __global__ __launch_bounds__(kBlock) void k_find(TableView t, const uint64_t* __
       uint32_t found, hadE, freeb;
       uint64_t mypos = kNoPos, myval = 0, myfb = 0, myexp = 0;
       int myc = 0;
-      group_probe<false>(t, key, A, sub, &found, &hadE, &freeb, &mypos, &myval, &myfb, &myc, &myexp);
+      uint64_t mystep = 0;
+      group_probe<false>(t, key, A, sub, &found, &hadE, &freeb, &mypos, &myval, &myfb, &myc, &myexp,
+                         &mystep);
       if ((A >> sub) & 1) {
         hit = (found >> sub) & 1;
         v = myval;
@@ -752,13 +765,14 @@ __global__ __launch_bounds__(kBlock) void k_check(TableView t) {
     if (key == kEmpty || key == kTomb) continue;
     ++live;
     const uint64_t at = (uint64_t)(j >> 3);
-    uint64_t b = home_of(t, key);
+    const Seq q = probe_seq(t, key);
+    uint64_t b = q.home;
     for (uint64_t step = 0; b != at; ++step) {
       if (step >= t.nb) { ++bad; break; }
       bool has_empty = false;
       for (int c = 0; c < kSlots; ++c) has_empty |= t.bk[b].s[c].key == kEmpty;
       if (has_empty) { ++bad; break; }
-      b = next_bucket(t, b);
+      b = next_bucket(t, b, q.step);
     }
   }
   live = wave_sum(live);
@@ -856,6 +870,21 @@ constexpr int kMaxGroupBlocks = 16384;
 
 int64_t align_up(int64_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
+bool is_prime(int64_t x) {
+  if (x < 2) return false;
+  if (x % 2 == 0) return x == 2;
+  for (int64_t d = 3; d * d <= x; d += 2)
+    if (x % d == 0) return false;
+  return true;
+}
+
+// Smallest prime >= x (x >= 1); a prime bucket count lets every probe step visit all buckets.
+int64_t next_prime(int64_t x) {
+  if (x <= 2) return 2;
+  while (!is_prime(x)) ++x;
+  return x;
+}
+
 int64_t pow2ceil(int64_t x) {
   int64_t p = 1;
   while (p < x) p <<= 1;
@@ -870,12 +899,19 @@ struct Layout {
 bool make_layout(const ct_table_desc* d, Layout* L) {
   if (!d || d->capacity < 0) return false;
   if (d->val_kind < 0 || d->val_kind > 2 || d->hash_kind < 0 || d->hash_kind > 1) return false;
-  int64_t nb = d->bucket_count ? d->bucket_count : (d->capacity + kSlots - 1) / kSlots;
+  int64_t nb = d->bucket_count;
+  if (nb == 0) nb = next_prime(std::max<int64_t>(1, (d->capacity + kSlots - 1) / kSlots));
   if (nb < 1) nb = 1;
   if (nb > ((int64_t)1 << 40)) return false;
   if (nb * kSlots < d->capacity) return false;
   int64_t q = d->chunk;
-  if (q == 0) q = std::min<int64_t>((int64_t)1 << 20, std::max<int64_t>(1024, pow2ceil(d->capacity)));
+  if (q == 0) {
+    // one chunk per ~capacity/8 keys: long kernels amortise launch and drain, and the scratch
+    // (34 bytes per chunk element) stays near a quarter of the 128 bytes per 8 slots
+    int64_t f = 1024;
+    while (f * 2 <= d->capacity / 8 && f < ((int64_t)1 << 23)) f *= 2;
+    q = f;
+  }
   if (q < 1024 || q > ((int64_t)1 << 24) || (q & (q - 1))) return false;
   L->nb = nb;
   L->chunk = q;
@@ -1042,6 +1078,7 @@ ct_status ct_table_init(void* d_buf, int64_t bytes, const ct_table_desc* d, void
   v.bcnt = reinterpret_cast<int64_t*>(base + L.off_bcnt);
   v.hash = d->hash_kind;
   v.nb_pow2 = (L.nb & (L.nb - 1)) == 0;
+  v.step_mode = v.nb_pow2 ? 1 : (is_prime(L.nb) ? 2 : 0);
   k_table_reset<<<flat_blocks(L.nb * kSlots), kBlock, 0, S(stream)>>>(v, 1);
   if (launched() != CT_OK) {
     delete t;

@@ -65,6 +65,7 @@ SIGNATURES = {
     "ctr_gather": (C.c_int, [_P, _I64, _I32, _P, _I64, _P, _P]),
     "ctr_gather_cas": (C.c_int, [_P, _I64, _I32, _P, _I64, _P, _P]),
     "ctr_cas": (C.c_int, [_P, _I64, _P, _I64, _P]),
+    "ctr_amin": (C.c_int, [_P, _I64, _P, _I64, _P]),
     "ctr_copy": (C.c_int, [_P, _P, _I64, _P]),
 }
 
@@ -294,6 +295,11 @@ def gather(lines: torch.Tensor, nlines: int, line_bytes: int, keys: torch.Tensor
 def cas_words(words: torch.Tensor, nwords: int, keys: torch.Tensor):
     _check(lib().ctr_cas(_ptr(words), int(nwords), _ptr(keys), keys.numel(), _stream(keys.device)),
            "ctr_cas")
+
+
+def amin_words(words: torch.Tensor, nwords: int, keys: torch.Tensor):
+    _check(lib().ctr_amin(_ptr(words), int(nwords), _ptr(keys), keys.numel(), _stream(keys.device)),
+           "ctr_amin")
 
 
 def copy(src: torch.Tensor, dst: torch.Tensor, nbytes: int):

@@ -230,15 +230,18 @@ def voxel_blocks(seed: int = 2, n_distinct: int = 1 << 22, n_resident: int = 1 <
     rng = rng_for(seed)
     half = grid // 2
     blocks = np.empty((0, 3), dtype=np.int64)
+    keys = np.empty(0, dtype=np.uint64)
     while blocks.shape[0] < n_distinct:
         need = n_distinct - blocks.shape[0]
         pts = _surface_points(rng, n_spheres, n_planes, half, r_lo, r_hi, max(need * 2, 4096))
         b = np.floor(pts).astype(np.int64)
         b = np.concatenate([blocks, b])
-        _, first = np.unique(b, axis=0, return_index=True)
+        k = np.concatenate([keys, pack_int3(b[blocks.shape[0]:, 0], b[blocks.shape[0]:, 1],
+                                            b[blocks.shape[0]:, 2])])
+        _, first = np.unique(k, return_index=True)   # the packing is injective on the grid
         first.sort()
-        blocks = b[first][:n_distinct]
-    keys = pack_int3(blocks[:, 0], blocks[:, 1], blocks[:, 2])
+        first = first[:n_distinct]
+        blocks, keys = b[first], k[first]
     d = rng.normal(size=3)
     d /= np.linalg.norm(d)
     proj = blocks.astype(np.float64) @ d
