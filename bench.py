@@ -28,9 +28,44 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-FIND_BYTES = 8 + 8 + 1 + 128      # key in, value out, found flag, one 128-byte bucket line
-INSERT_BYTES = 8 + 8 + 1 + 2 * 128  # key, value, status in/out; bucket line read + written back
+# algorithmic bytes per operation (what the method itself must move)
+FIND_BYTES = 8 + 8 + 1 + 128        # key in, value out, found flag; one 128-byte bucket line read
+INSERT_BYTES = 8 + 8 + 1 + 2 * 128  # key, value in, status out; bucket line read and written back
+ERASE_BYTES = 8 + 1 + 2 * 128       # key in, flag out; bucket line read and written back
 METRIC = "find & insert Mops/s at load 0.8 (1 GPU); served p50/p99 batch latency"
+PMC_SUMMARY = os.path.join(ROOT, "profiles", "pmc_large_table.md")
+KERNEL_SOURCES = ["include/ct.h", "paper_1908_05936_amd/csrc/ct_device.h",
+                  "paper_1908_05936_amd/csrc/ct_table.hip"]
+
+
+def kernel_source_hash() -> str:
+    import hashlib
+
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def recorded_traffic():
+    """Per-launch HBM bytes of each kernel from the committed counter summary, if it was taken
+    from the kernels as they are now (same source hash); else None."""
+    try:
+        text = open(PMC_SUMMARY).read()
+    except OSError:
+        return None
+    start = text.find("```json")
+    if start < 0:
+        return None
+    end = text.find("```", start + 7)
+    try:
+        data = json.loads(text[start + 7:end])
+    except ValueError:
+        return None
+    if data.get("source_sha256") != kernel_source_hash():
+        return None
+    return data
 
 
 def parse():
@@ -203,6 +238,8 @@ def main():
         assert int(erased.sum()) == n_er and int((st_re == 1).sum()) == n_re
         assert table.size() == n_fill
     per = {name: 0.0 for name, _ in ops}
+    table.profiling(True)
+    table.profile_reset()
     torch.cuda.synchronize()
     w0 = time.perf_counter()
     for _ in range(a.steps):
@@ -219,21 +256,39 @@ def main():
     breakdown = {name: {"ms": per[name] / a.steps * 1e3,
                         "Mops_s": (counts[name] * a.steps / per[name] / 1e6) if counts[name] else None}
                  for name, _ in ops}
-    find_t = per["find"] / a.steps
-    fill_t = per["insert_fill"] / a.steps
-    find_gbs = FIND_BYTES * n_find / find_t / 1e9
-    fill_gbs = INSERT_BYTES * n_fill / fill_t / 1e9
-    dominant = "find" if find_t >= fill_t else "insert_fill"
+    prof = table.profile()
+    table.profiling(False)
+    n_ins = (n_fill + n_re) * a.steps
+    kern = {
+        "k_find": (prof["find"], FIND_BYTES * n_find * a.steps),
+        "k_insert": (prof["insert"], INSERT_BYTES * n_ins),
+        "k_erase": (prof["erase"], ERASE_BYTES * n_er * a.steps),
+        "k_dedup": (prof["dedup"], None),
+    }
+    kernels = {}
+    for name, ((ms, launches), alg) in kern.items():
+        kernels[name] = {"ms_per_step": ms / a.steps, "launches_per_step": launches / a.steps,
+                         "share_of_step": ms / (dev_time * 1e3) if dev_time else None}
+        if alg is not None and ms:
+            kernels[name]["achieved_GB_s"] = alg / (ms * 1e-3) / 1e9
+            kernels[name]["algorithmic_bytes_per_launch"] = alg / launches
+    dominant = max(("k_find", "k_insert", "k_erase"), key=lambda k: kernels[k]["ms_per_step"])
+    traffic = recorded_traffic()
+    tr = None
+    if traffic and dominant in traffic.get("kernels", {}):
+        tk = traffic["kernels"][dominant]
+        tr = tk["fetch_bytes_per_launch"] + tk["write_bytes_per_launch"]
+    dk = kernels[dominant]
     roof = {
-        "kernel": "k_find<u64>" if dominant == "find" else "insert pipeline (fill)",
+        "kernel": dominant,
         "bound": "hbm",
-        "achieved": find_gbs if dominant == "find" else fill_gbs,
+        "achieved": dk["achieved_GB_s"],
         "peak": HBM_PEAK_GBS,
         "unit": "GB/s",
-        "frac": (find_gbs if dominant == "find" else fill_gbs) / HBM_PEAK_GBS,
-        "traffic": None,
-        "bytes_per_op": FIND_BYTES if dominant == "find" else INSERT_BYTES,
-        "ops_per_launch": n_find if dominant == "find" else n_fill,
+        "frac": dk["achieved_GB_s"] / HBM_PEAK_GBS,
+        "traffic": tr,
+        "algorithmic_bytes_per_launch": dk["algorithmic_bytes_per_launch"],
+        "mean_launch_ms": dk["ms_per_step"] / dk["launches_per_step"],
     }
     line = {
         "metric": METRIC,
@@ -259,6 +314,7 @@ def main():
             "wall_Mops_s": total_ops * a.steps / wall / 1e6,
         },
         "breakdown": breakdown,
+        "kernels": kernels,
         "roofline": roof,
     }
     if not a.no_ceilings:

@@ -196,6 +196,32 @@ ct_status ct_insert_alloc_batch(ct_table *t, ct_pool *p, const uint64_t *keys, i
 ct_status ct_erase_release_batch(ct_table *t, ct_pool *p, const uint64_t *keys, int64_t n,
                                  uint8_t *erased, void *stream);
 
+/* --- kernel timing (tracing) ---------------------------------------------------------------- */
+
+/* Kernel kinds the library launches for a table. */
+#define CT_KERNEL_CLEAR 0    /* table reset */
+#define CT_KERNEL_PROLOGUE 1 /* per-chunk scratch clear and counter snapshot */
+#define CT_KERNEL_DEDUP 2    /* lowest index per distinct key of a chunk */
+#define CT_KERNEL_INSERT 3   /* insert probe and claim */
+#define CT_KERNEL_ERASE 4    /* erase probe and release */
+#define CT_KERNEL_APPLY 5    /* live-count update */
+#define CT_KERNEL_RANK 6     /* index-order rank scan (capacity or pool limits) */
+#define CT_KERNEL_FINAL 7    /* ranked completion */
+#define CT_KERNEL_FIX 8      /* outcomes of repeated keys */
+#define CT_KERNEL_FIND 9     /* find / contains */
+#define CT_KERNEL_KINDS 10
+
+/* While enabled, every kernel launched for `t` is bracketed by two HIP events recorded on the
+   stream of the call that launched it.  Disabling folds the pending records into the totals. */
+ct_status ct_table_set_profiling(ct_table *t, int enable);
+
+/* Total device time (ms) and launch count of kernel kind `kind` recorded for `t` since profiling
+   was first enabled or last reset.  Waits for the recorded events.  Either output nullable. */
+ct_status ct_table_profile(ct_table *t, int32_t kind, double *total_ms, int64_t *launches);
+
+/* Zero the per-kind totals (after waiting for pending records). */
+ct_status ct_table_profile_reset(ct_table *t);
+
 /* Static description of a status code. */
 const char *ct_status_str(ct_status s);
 

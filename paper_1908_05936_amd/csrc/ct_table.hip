@@ -23,6 +23,7 @@
 #include <cstdint>
 #include <cstdlib>
 #include <new>
+#include <vector>
 
 #include "ct.h"
 #include "ct_device.h"
@@ -847,7 +848,19 @@ __global__ __launch_bounds__(kBlock) void k_pool_copy(const PoolHeader* ph, cons
 // =============================================================================================
 // host side
 // =============================================================================================
+// Per-table kernel timing: while enabled, each kernel launched for the table is bracketed by two
+// HIP events recorded on the caller's stream; read-out waits for them and sums per kernel kind.
+struct Profiler {
+  bool on = false;
+  std::vector<hipEvent_t> events;  // pairs (start, end)
+  std::vector<int> kinds;          // kind of each recorded pair
+  size_t used = 0;
+  double total_ms[CT_KERNEL_KINDS] = {};
+  int64_t launches[CT_KERNEL_KINDS] = {};
+};
+
 struct ct_table {
+  Profiler prof;
   ct_table_desc desc;
   uint8_t* base;
   int64_t bytes;
@@ -940,6 +953,40 @@ bool make_layout(const ct_table_desc* d, Layout* L) {
 
 inline hipStream_t S(void* s) { return reinterpret_cast<hipStream_t>(s); }
 
+// Sum the recorded pairs into the per-kind totals (waits for the last recorded event).
+ct_status prof_drain(Profiler& P) {
+  ct_status r = CT_OK;
+  for (size_t j = 0; j < P.kinds.size(); ++j) {
+    float ms = 0.f;
+    if (hipEventSynchronize(P.events[2 * j + 1]) != hipSuccess ||
+        hipEventElapsedTime(&ms, P.events[2 * j], P.events[2 * j + 1]) != hipSuccess) {
+      r = CT_E_HIP;
+      continue;
+    }
+    P.total_ms[P.kinds[j]] += ms;
+    P.launches[P.kinds[j]] += 1;
+  }
+  P.kinds.clear();
+  P.used = 0;
+  return r;
+}
+
+// Launch `f` (a kernel launch on stream s) for table t, timed when profiling is on.
+template <typename F>
+void launch(ct_table* t, int kind, hipStream_t s, F&& f) {
+  hipEvent_t end = nullptr;
+  if (t && t->prof.on) {
+    Profiler& P = t->prof;
+    if (P.used + 2 > P.events.size()) prof_drain(P);
+    hipEventRecord(P.events[P.used], s);
+    end = P.events[P.used + 1];
+    P.kinds.push_back(kind);
+    P.used += 2;
+  }
+  f();
+  if (end) hipEventRecord(end, s);
+}
+
 int group_blocks(int64_t n) {
   const int64_t b = (n + (kBlock / 8) - 1) / (kBlock / 8);
   return (int)std::max<int64_t>(1, std::min<int64_t>(b, kMaxGroupBlocks));
@@ -976,18 +1023,18 @@ ct_status insert_chunks(ct_table* t, const uint64_t* keys, const void* vals, int
     uint8_t* sc = status ? status + c0 : nullptr;
     const int gb = group_blocks((q + kSlots - 1) / kSlots);
     const int ntiles = (int)((q + kTile - 1) / kTile);
-    k_prologue<<<flat_blocks(db / 2), kBlock, 0, s>>>(t->v, nullptr, db, q);
-    k_dedup<<<flat_blocks(q), kBlock, 0, s>>>(t->v, kc, q, db - 1);
-    k_insert<VK, false><<<gb, kBlock, 0, s>>>(t->v, kc, vc, q, db - 1, sc, nullptr);
-    k_apply_count<<<1, 1024, 0, s>>>(t->v, gb);
+    launch(t, CT_KERNEL_PROLOGUE, s, [&] { k_prologue<<<flat_blocks(db / 2), kBlock, 0, s>>>(t->v, nullptr, db, q); });
+    launch(t, CT_KERNEL_DEDUP, s, [&] { k_dedup<<<flat_blocks(q), kBlock, 0, s>>>(t->v, kc, q, db - 1); });
+    launch(t, CT_KERNEL_INSERT, s, [&] { k_insert<VK, false><<<gb, kBlock, 0, s>>>(t->v, kc, vc, q, db - 1, sc, nullptr); });
+    launch(t, CT_KERNEL_APPLY, s, [&] { k_apply_count<<<1, 1024, 0, s>>>(t->v, gb); });
     // the host bound proves that no element can meet FULL: the rank pass is not needed
     const bool surely_fast = t->size_ub + (uint64_t)q <= (uint64_t)t->desc.capacity;
     if (!surely_fast) {
-      k_tile_count<<<ntiles, kBlock, 0, s>>>(t->v, q, 1);
-      k_tile_scan<<<1, 1024, 0, s>>>(t->v, nullptr, ntiles, 0);
-      k_final<VK, 0><<<ntiles, kBlock, 0, s>>>(t->v, nullptr, nullptr, kc, vc, q, sc, nullptr);
+      launch(t, CT_KERNEL_RANK, s, [&] { k_tile_count<<<ntiles, kBlock, 0, s>>>(t->v, q, 1); });
+      launch(t, CT_KERNEL_RANK, s, [&] { k_tile_scan<<<1, 1024, 0, s>>>(t->v, nullptr, ntiles, 0); });
+      launch(t, CT_KERNEL_FINAL, s, [&] { k_final<VK, 0><<<ntiles, kBlock, 0, s>>>(t->v, nullptr, nullptr, kc, vc, q, sc, nullptr); });
     }
-    if (sc) k_fix<<<flat_blocks(q), kBlock, 0, s>>>(t->v, sc, nullptr);
+    if (sc) launch(t, CT_KERNEL_FIX, s, [&] { k_fix<<<flat_blocks(q), kBlock, 0, s>>>(t->v, sc, nullptr); });
     t->size_ub = std::min<uint64_t>(t->size_ub + (uint64_t)q, (uint64_t)t->desc.capacity);
     ct_status r = launched();
     if (r != CT_OK) return r;
@@ -1005,14 +1052,14 @@ ct_status erase_chunks(ct_table* t, ct_pool* p, const uint64_t* keys, int64_t n,
     uint8_t* ec = erased ? erased + c0 : nullptr;
     const int gb = group_blocks((q + kSlots - 1) / kSlots);
     const int ntiles = (int)((q + kTile - 1) / kTile);
-    k_prologue<<<flat_blocks(db / 2), kBlock, 0, s>>>(t->v, RELEASE ? p->hdr : nullptr, db, q);
-    k_dedup<<<flat_blocks(q), kBlock, 0, s>>>(t->v, kc, q, db - 1);
-    k_erase<RELEASE><<<gb, kBlock, 0, s>>>(t->v, kc, q, db - 1, ec);
-    k_apply_count<<<1, 1024, 0, s>>>(t->v, gb);
+    launch(t, CT_KERNEL_PROLOGUE, s, [&] { k_prologue<<<flat_blocks(db / 2), kBlock, 0, s>>>(t->v, RELEASE ? p->hdr : nullptr, db, q); });
+    launch(t, CT_KERNEL_DEDUP, s, [&] { k_dedup<<<flat_blocks(q), kBlock, 0, s>>>(t->v, kc, q, db - 1); });
+    launch(t, CT_KERNEL_ERASE, s, [&] { k_erase<RELEASE><<<gb, kBlock, 0, s>>>(t->v, kc, q, db - 1, ec); });
+    launch(t, CT_KERNEL_APPLY, s, [&] { k_apply_count<<<1, 1024, 0, s>>>(t->v, gb); });
     if (RELEASE) {
-      k_tile_count<<<ntiles, kBlock, 0, s>>>(t->v, q, 0);
-      k_tile_scan<<<1, 1024, 0, s>>>(t->v, p->hdr, ntiles, 2);
-      k_final<0, 2><<<ntiles, kBlock, 0, s>>>(t->v, p->hdr, p->stack, kc, nullptr, q, nullptr, nullptr);
+      launch(t, CT_KERNEL_RANK, s, [&] { k_tile_count<<<ntiles, kBlock, 0, s>>>(t->v, q, 0); });
+      launch(t, CT_KERNEL_RANK, s, [&] { k_tile_scan<<<1, 1024, 0, s>>>(t->v, p->hdr, ntiles, 2); });
+      launch(t, CT_KERNEL_FINAL, s, [&] { k_final<0, 2><<<ntiles, kBlock, 0, s>>>(t->v, p->hdr, p->stack, kc, nullptr, q, nullptr, nullptr); });
     }
     ct_status r = launched();
     if (r != CT_OK) return r;
@@ -1090,8 +1137,44 @@ ct_status ct_table_init(void* d_buf, int64_t bytes, const ct_table_desc* d, void
 
 ct_status ct_table_destroy(ct_table* t) {
   if (!t) return CT_E_INVALID;
+  for (hipEvent_t e : t->prof.events) hipEventDestroy(e);
   delete t;
   return CT_OK;
+}
+
+ct_status ct_table_set_profiling(ct_table* t, int enable) {
+  if (!t) return CT_E_INVALID;
+  Profiler& P = t->prof;
+  if (enable && !P.on) {
+    if (P.events.empty()) {
+      P.events.resize(8192);
+      for (hipEvent_t& e : P.events)
+        if (hipEventCreate(&e) != hipSuccess) return CT_E_HIP;
+    }
+    P.on = true;
+  } else if (!enable && P.on) {
+    P.on = false;
+    return prof_drain(P);
+  }
+  return CT_OK;
+}
+
+ct_status ct_table_profile(ct_table* t, int32_t kind, double* total_ms, int64_t* launches) {
+  if (!t || kind < 0 || kind >= CT_KERNEL_KINDS) return CT_E_INVALID;
+  ct_status r = prof_drain(t->prof);
+  if (total_ms) *total_ms = t->prof.total_ms[kind];
+  if (launches) *launches = t->prof.launches[kind];
+  return r;
+}
+
+ct_status ct_table_profile_reset(ct_table* t) {
+  if (!t) return CT_E_INVALID;
+  ct_status r = prof_drain(t->prof);
+  for (int k = 0; k < CT_KERNEL_KINDS; ++k) {
+    t->prof.total_ms[k] = 0.0;
+    t->prof.launches[k] = 0;
+  }
+  return r;
 }
 
 ct_status ct_table_info(const ct_table* t, int64_t* bucket_count, int64_t* chunk) {
@@ -1121,9 +1204,12 @@ ct_status ct_find_batch(ct_table* t, const uint64_t* keys, int64_t n, void* vals
   if (vk == CT_VAL_NONE && vals_out) return CT_E_INVALID;
   if (n == 0) return CT_OK;
   const int gb = group_blocks((n + kSlots - 1) / kSlots);
-  if (vk == CT_VAL_U32) k_find<1><<<gb, kBlock, 0, S(stream)>>>(t->v, keys, n, vals_out, found);
-  else if (vk == CT_VAL_U64) k_find<2><<<gb, kBlock, 0, S(stream)>>>(t->v, keys, n, vals_out, found);
-  else k_find<0><<<gb, kBlock, 0, S(stream)>>>(t->v, keys, n, nullptr, found);
+  hipStream_t s = S(stream);
+  launch(t, CT_KERNEL_FIND, s, [&] {
+    if (vk == CT_VAL_U32) k_find<1><<<gb, kBlock, 0, s>>>(t->v, keys, n, vals_out, found);
+    else if (vk == CT_VAL_U64) k_find<2><<<gb, kBlock, 0, s>>>(t->v, keys, n, vals_out, found);
+    else k_find<0><<<gb, kBlock, 0, s>>>(t->v, keys, n, nullptr, found);
+  });
   return launched();
 }
 
@@ -1147,7 +1233,7 @@ ct_status ct_size(ct_table* t, int64_t* h_size, void* stream) {
 
 ct_status ct_clear(ct_table* t, void* stream) {
   if (!t) return CT_E_INVALID;
-  k_table_reset<<<flat_blocks((int64_t)t->v.nb * kSlots), kBlock, 0, S(stream)>>>(t->v, 0);
+  launch(t, CT_KERNEL_CLEAR, S(stream), [&] { k_table_reset<<<flat_blocks((int64_t)t->v.nb * kSlots), kBlock, 0, S(stream)>>>(t->v, 0); });
   t->size_ub = 0;
   return launched();
 }
@@ -1283,13 +1369,13 @@ ct_status ct_insert_alloc_batch(ct_table* t, ct_pool* p, const uint64_t* keys, i
     int32_t* vc = vals_out ? vals_out + c0 : nullptr;
     const int gb = group_blocks((q + kSlots - 1) / kSlots);
     const int ntiles = (int)((q + kTile - 1) / kTile);
-    k_prologue<<<flat_blocks(db / 2), kBlock, 0, s>>>(t->v, p->hdr, db, q);
-    k_dedup<<<flat_blocks(q), kBlock, 0, s>>>(t->v, kc, q, db - 1);
-    k_insert<1, true><<<gb, kBlock, 0, s>>>(t->v, kc, nullptr, q, db - 1, sc, vc);
-    k_tile_count<<<ntiles, kBlock, 0, s>>>(t->v, q, 0);
-    k_tile_scan<<<1, 1024, 0, s>>>(t->v, p->hdr, ntiles, 1);
-    k_final<1, 1><<<ntiles, kBlock, 0, s>>>(t->v, p->hdr, p->stack, kc, nullptr, q, sc, vc);
-    if (sc || vc) k_fix<<<flat_blocks(q), kBlock, 0, s>>>(t->v, sc, vc);
+    launch(t, CT_KERNEL_PROLOGUE, s, [&] { k_prologue<<<flat_blocks(db / 2), kBlock, 0, s>>>(t->v, p->hdr, db, q); });
+    launch(t, CT_KERNEL_DEDUP, s, [&] { k_dedup<<<flat_blocks(q), kBlock, 0, s>>>(t->v, kc, q, db - 1); });
+    launch(t, CT_KERNEL_INSERT, s, [&] { k_insert<1, true><<<gb, kBlock, 0, s>>>(t->v, kc, nullptr, q, db - 1, sc, vc); });
+    launch(t, CT_KERNEL_RANK, s, [&] { k_tile_count<<<ntiles, kBlock, 0, s>>>(t->v, q, 0); });
+    launch(t, CT_KERNEL_RANK, s, [&] { k_tile_scan<<<1, 1024, 0, s>>>(t->v, p->hdr, ntiles, 1); });
+    launch(t, CT_KERNEL_FINAL, s, [&] { k_final<1, 1><<<ntiles, kBlock, 0, s>>>(t->v, p->hdr, p->stack, kc, nullptr, q, sc, vc); });
+    if (sc || vc) launch(t, CT_KERNEL_FIX, s, [&] { k_fix<<<flat_blocks(q), kBlock, 0, s>>>(t->v, sc, vc); });
     t->size_ub = std::min<uint64_t>(t->size_ub + (uint64_t)q, (uint64_t)t->desc.capacity);
     r = launched();
     if (r != CT_OK) return r;

@@ -20,6 +20,7 @@ LIB_PATH = os.path.join(_PKG, "libct.so")
 CT_OK, CT_E_INVALID, CT_E_FULL, CT_E_EMPTY, CT_E_NOMEM, CT_E_HIP = range(6)
 PRESENT, INSERTED, FULL = 0, 1, 2
 ERR_FULL, ERR_POOL = 1, 2
+KERNELS = ["clear", "prologue", "dedup", "insert", "erase", "apply", "rank", "final", "fix", "find"]
 VAL_NONE, VAL_U32, VAL_U64 = 0, 1, 2
 HASH_MIX64, HASH_VOXEL21 = 0, 1
 
@@ -44,6 +45,9 @@ SIGNATURES = {
     "ct_table_init": (C.c_int, [_P, _I64, C.POINTER(TableDesc), _P, C.POINTER(_P)]),
     "ct_table_destroy": (C.c_int, [_P]),
     "ct_table_info": (C.c_int, [_P, _PI64, _PI64]),
+    "ct_table_set_profiling": (C.c_int, [_P, C.c_int]),
+    "ct_table_profile": (C.c_int, [_P, C.c_int32, C.POINTER(C.c_double), _PI64]),
+    "ct_table_profile_reset": (C.c_int, [_P]),
     "ct_insert_batch": (C.c_int, [_P, _P, _P, _I64, _P, _P]),
     "ct_find_batch": (C.c_int, [_P, _P, _I64, _P, _P, _P]),
     "ct_erase_batch": (C.c_int, [_P, _P, _I64, _P, _P]),
@@ -282,6 +286,22 @@ class Table:
         e = C.c_uint32(0)
         _check(lib().ct_get_error(self._h, C.byref(e), _stream(self.device)), "ct_get_error")
         return e.value
+
+    def profiling(self, enable: bool = True):
+        _check(lib().ct_table_set_profiling(self._h, int(enable)), "ct_table_set_profiling")
+
+    def profile(self) -> dict:
+        """{kernel kind: (total ms, launches)} recorded since profiling was enabled or reset."""
+        out = {}
+        for k, name in enumerate(KERNELS):
+            ms = C.c_double(0)
+            n = C.c_int64(0)
+            _check(lib().ct_table_profile(self._h, k, C.byref(ms), C.byref(n)), "ct_table_profile")
+            out[name] = (ms.value, n.value)
+        return out
+
+    def profile_reset(self):
+        _check(lib().ct_table_profile_reset(self._h), "ct_table_profile_reset")
 
 
 # --- measured ceilings (include/ct_roofline.h) ------------------------------------------------
