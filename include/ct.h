@@ -196,6 +196,44 @@ ct_status ct_insert_alloc_batch(ct_table *t, ct_pool *p, const uint64_t *keys, i
 ct_status ct_erase_release_batch(ct_table *t, ct_pool *p, const uint64_t *keys, int64_t n,
                                  uint8_t *erased, void *stream);
 
+/* --- multi-table plans: a schedule of operations over many tables ------------------------- */
+/* A plan records operations on many tables in schedule order and replays them: operations on one
+   table keep their order (the results equal those of the single-table calls made in that order)
+   and tables are spread over up to 8 side streams forked from the caller's stream and joined
+   back, so operations on different tables overlap on the device.  Each operation runs the same
+   kernel pipeline as its single-table call.  The fork/join sequence captures into one HIP graph
+   that replays the whole schedule with one call.  The caller keeps every table and array a plan
+   names alive and unchanged in place until the last run of the plan ends. */
+
+#define CT_OP_CLEAR 0  /* remove every key of the table (no arrays) */
+#define CT_OP_INSERT 1 /* keys, vals (in), flags_out = status */
+#define CT_OP_FIND 2   /* keys, vals_out, flags_out = found */
+#define CT_OP_ERASE 3  /* keys, flags_out = erased */
+
+typedef struct ct_plan ct_plan;
+
+ct_status ct_plan_create(ct_plan **out);
+ct_status ct_plan_destroy(ct_plan *p);
+
+/* Append one operation (host only; arrays as in the single-table calls, nullable outputs as
+   there). */
+ct_status ct_plan_add(ct_plan *p, ct_table *t, int32_t op, const uint64_t *keys, const void *vals,
+                      void *vals_out, uint8_t *flags_out, int64_t n);
+
+/* Number of recorded operations and of distinct tables. */
+ct_status ct_plan_info(ct_plan *p, int64_t *nops, int64_t *ntables);
+
+/* Run the plan after the work already on `stream`, with tables spread over `lanes` (1..8) side
+   streams; `stream` waits for all of it.  Enqueues only. */
+ct_status ct_plan_launch(ct_plan *p, int32_t lanes, void *stream);
+
+/* Capture ct_plan_launch(p, lanes) on `stream` (a non-default stream) into an executable HIP
+   graph returned in *graph_exec; replay it with ct_graph_launch and free it with
+   ct_graph_destroy. */
+ct_status ct_plan_capture(ct_plan *p, int32_t lanes, void *stream, void **graph_exec);
+ct_status ct_graph_launch(void *graph_exec, void *stream);
+ct_status ct_graph_destroy(void *graph_exec);
+
 /* --- kernel timing (tracing) ---------------------------------------------------------------- */
 
 /* Kernel kinds the library launches for a table. */

@@ -143,21 +143,20 @@ __device__ __forceinline__ uint32_t dedup_lookup(const TableView& t, const uint6
 // ---------------------------------------------------------------------------------------------
 // kernels
 // ---------------------------------------------------------------------------------------------
-__global__ __launch_bounds__(kBlock) void k_table_reset(TableView t, int zero_header) {
-  const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t nt = (int64_t)gridDim.x * blockDim.x;
-  const int64_t nslots = (int64_t)t.nb * kSlots;
-  uint4 empty = make_uint4(0xFFFFFFFFu, 0xFFFFFFFFu, 0u, 0u);
-  for (int64_t j = tid; j < nslots; j += nt)
+// Empty every slot in [lo, hi) (thread-strided by `step`); `header` also resets the counters.
+__device__ __forceinline__ void reset_range(const TableView& t, int64_t lo, int64_t hi,
+                                            int64_t step, bool header, int zero_err) {
+  const uint4 empty = make_uint4(0xFFFFFFFFu, 0xFFFFFFFFu, 0u, 0u);
+  for (int64_t j = lo + threadIdx.x; j < hi; j += step)
     *reinterpret_cast<uint4*>(&t.bk[j >> 3].s[j & 7]) = empty;
-  if (tid == 0) {
+  if (header && threadIdx.x == 0) {
     Header* h = t.hdr;
     h->size = 0;
     h->size0 = 0;
     h->spec_val[0] = h->spec_val[1] = 0;
     h->spec_live[0] = h->spec_live[1] = 0;
     h->spec_first[0] = h->spec_first[1] = kNone;
-    if (zero_header) h->err = 0;
+    if (zero_err) h->err = 0;
     h->fast = 0;
     h->ndup = 0;
     h->nnew = 0;
@@ -167,16 +166,30 @@ __global__ __launch_bounds__(kBlock) void k_table_reset(TableView t, int zero_he
   }
 }
 
+__global__ __launch_bounds__(kBlock) void k_table_reset(TableView t, int zero_header) {
+  reset_range(t, (int64_t)blockIdx.x * blockDim.x, (int64_t)t.nb * kSlots,
+              (int64_t)gridDim.x * blockDim.x, blockIdx.x == 0, zero_header);
+}
+
 // Per chunk: clear the dedup scratch, snapshot the counters, decide whether the chunk can reach
 // capacity (or empty the pool).
-__global__ __launch_bounds__(kBlock) void k_prologue(TableView t, PoolHeader* pool,
-                                                     uint32_t dslots, int64_t q) {
-  const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t nt = (int64_t)gridDim.x * blockDim.x;
+// Units [lo, hi) of a chunk's scratch clear: the first dslots/2 units are 16-byte dedup-entry
+// pairs, the rest 16-byte groups of repeated-key marks.  `header`: snapshot the counters and
+// decide whether the chunk can reach capacity (or empty the pool).
+__device__ __forceinline__ int64_t prologue_units(uint32_t dslots, int64_t q) {
+  return (int64_t)dslots / 2 + (q + 15) / 16;
+}
+
+__device__ __forceinline__ void prologue_range(const TableView& t, PoolHeader* pool,
+                                               uint32_t dslots, int64_t q, int64_t lo, int64_t hi,
+                                               int64_t step, bool header) {
   const uint4 empty = make_uint4(0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu);
-  for (int64_t j = tid; j < (int64_t)dslots / 2; j += nt) reinterpret_cast<uint4*>(t.dd)[j] = empty;
-  for (int64_t j = tid; j < (q + 15) / 16; j += nt) reinterpret_cast<uint4*>(t.dmark)[j] = make_uint4(0, 0, 0, 0);
-  if (tid == 0) {
+  const int64_t nd = (int64_t)dslots / 2;
+  for (int64_t j = lo + threadIdx.x; j < hi; j += step) {
+    if (j < nd) reinterpret_cast<uint4*>(t.dd)[j] = empty;
+    else reinterpret_cast<uint4*>(t.dmark)[j - nd] = make_uint4(0, 0, 0, 0);
+  }
+  if (header && threadIdx.x == 0) {
     Header* h = t.hdr;
     h->size0 = h->size;
     h->spec_first[0] = h->spec_first[1] = kNone;
@@ -191,16 +204,21 @@ __global__ __launch_bounds__(kBlock) void k_prologue(TableView t, PoolHeader* po
   }
 }
 
+__global__ __launch_bounds__(kBlock) void k_prologue(TableView t, PoolHeader* pool,
+                                                     uint32_t dslots, int64_t q) {
+  prologue_range(t, pool, dslots, q, (int64_t)blockIdx.x * blockDim.x, prologue_units(dslots, q),
+                 (int64_t)gridDim.x * blockDim.x, blockIdx.x == 0);
+}
+
 // Lowest index per distinct key of the chunk, one thread per element.  The first copy of a key
 // to arrive claims an empty entry with one CAS; a later copy lowers the entry's index with an
 // atomic min and marks both itself and the previous holder as repeated, so every element of a key
 // that occurs more than once ends up marked and elements of unique keys stay unmarked.  All
 // indices held by one entry belong to one key, so the fingerprint plus one look at that element's
 // key identifies the entry exactly.
-__global__ __launch_bounds__(kBlock) void k_dedup(TableView t, const uint64_t* __restrict__ keys,
-                                                  int64_t q, uint32_t dmask) {
-  const int64_t nt = (int64_t)gridDim.x * kBlock;
-  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < q; i += nt) {
+__device__ __forceinline__ void dedup_range(const TableView& t, const uint64_t* __restrict__ keys,
+                                            uint32_t dmask, int64_t lo, int64_t hi, int64_t step) {
+  for (int64_t i = lo + threadIdx.x; i < hi; i += step) {
     const uint64_t key = keys[i];
     if (key >= kTomb) {
       amin32(&t.hdr->spec_first[key - kTomb], (uint32_t)i);
@@ -226,6 +244,11 @@ __global__ __launch_bounds__(kBlock) void k_dedup(TableView t, const uint64_t* _
       h = (h + 1) & dmask;
     }
   }
+}
+
+__global__ __launch_bounds__(kBlock) void k_dedup(TableView t, const uint64_t* __restrict__ keys,
+                                                  int64_t q, uint32_t dmask) {
+  dedup_range(t, keys, dmask, (int64_t)blockIdx.x * kBlock, q, (int64_t)gridDim.x * kBlock);
 }
 
 // Index-order role of this lane's element: its own index when it is the first copy of its key in
@@ -307,20 +330,21 @@ __device__ __forceinline__ void group_probe(const TableView& t, uint64_t key, ui
 // Insert actors, 8 elements per group and one per lane.  fast: claim directly with one CAS per
 // new key (all CASes of the group in flight together; a lost race retries one key at a time).
 // Otherwise (or with a pool) flag new keys for the ranked completion.
+// Elements [lo, hi) of a chunk, 8 per group, the block's groups striding by `step` elements.
+// Returns this thread's count of stored keys.
 template <int VK, bool ALLOC>
-__global__ __launch_bounds__(kBlock) void k_insert(TableView t, const uint64_t* __restrict__ keys,
-                                                   const void* __restrict__ vals, int64_t q,
-                                                   uint32_t dmask, uint8_t* __restrict__ status,
-                                                   int32_t* __restrict__ vout) {
+__device__ __forceinline__ int64_t insert_range(const TableView& t, const uint64_t* __restrict__ keys,
+                                                const void* __restrict__ vals, uint32_t dmask,
+                                                uint8_t* __restrict__ status,
+                                                int32_t* __restrict__ vout, int64_t lo, int64_t hi,
+                                                int64_t step) {
   const int sub = threadIdx.x & 7;
   const bool fast = t.hdr->fast != 0;
   const bool flags = ALLOC || !fast;
-  const int64_t ng = (int64_t)gridDim.x * (kBlock / 8);
   int64_t ins = 0;
-  for (int64_t g0 = ((int64_t)blockIdx.x * (kBlock / 8) + (threadIdx.x >> 3)) * kSlots; g0 < q;
-       g0 += ng * kSlots) {
+  for (int64_t g0 = lo + (int64_t)(threadIdx.x >> 3) * kSlots; g0 < hi; g0 += step) {
     const int64_t i = g0 + sub;
-    const bool valid = i < q;
+    const bool valid = i < hi;
     const uint64_t key = valid ? keys[i] : kEmpty;
     const uint32_t first = valid ? first_copy(t, keys, key, i, dmask) : 0u;
     const bool actor = valid && first == (uint32_t)i;
@@ -405,6 +429,17 @@ __global__ __launch_bounds__(kBlock) void k_insert(TableView t, const uint64_t* 
       if (status && st != kNoStatus) status[i] = st;
     }
   }
+  return ins;
+}
+
+template <int VK, bool ALLOC>
+__global__ __launch_bounds__(kBlock) void k_insert(TableView t, const uint64_t* __restrict__ keys,
+                                                   const void* __restrict__ vals, int64_t q,
+                                                   uint32_t dmask, uint8_t* __restrict__ status,
+                                                   int32_t* __restrict__ vout) {
+  const int64_t ins = insert_range<VK, ALLOC>(t, keys, vals, dmask, status, vout,
+                                              (int64_t)blockIdx.x * kBlock, q,
+                                              (int64_t)gridDim.x * kBlock);
   // one partial per block, summed by k_apply_count: no same-address atomics across the grid
   const int64_t tot = block_sum(ins);
   if (threadIdx.x == 0) t.bcnt[blockIdx.x] = tot;
@@ -412,16 +447,14 @@ __global__ __launch_bounds__(kBlock) void k_insert(TableView t, const uint64_t* 
 
 // Erase actors, 8 elements per group.  RELEASE: the removed value is kept for the ordered push.
 template <bool RELEASE>
-__global__ __launch_bounds__(kBlock) void k_erase(TableView t, const uint64_t* __restrict__ keys,
-                                                  int64_t q, uint32_t dmask,
-                                                  uint8_t* __restrict__ erased) {
+__device__ __forceinline__ int64_t erase_range(const TableView& t, const uint64_t* __restrict__ keys,
+                                               uint32_t dmask, uint8_t* __restrict__ erased,
+                                               int64_t lo, int64_t hi, int64_t step) {
   const int sub = threadIdx.x & 7;
-  const int64_t ng = (int64_t)gridDim.x * (kBlock / 8);
   int64_t del = 0;
-  for (int64_t g0 = ((int64_t)blockIdx.x * (kBlock / 8) + (threadIdx.x >> 3)) * kSlots; g0 < q;
-       g0 += ng * kSlots) {
+  for (int64_t g0 = lo + (int64_t)(threadIdx.x >> 3) * kSlots; g0 < hi; g0 += step) {
     const int64_t i = g0 + sub;
-    const bool valid = i < q;
+    const bool valid = i < hi;
     const uint64_t key = valid ? keys[i] : kEmpty;
     const bool actor = valid && first_copy(t, keys, key, i, dmask) == (uint32_t)i;
     uint8_t hit = 0;
@@ -458,23 +491,37 @@ __global__ __launch_bounds__(kBlock) void k_erase(TableView t, const uint64_t* _
       del += hit;
     }
   }
+  return del;
+}
+
+template <bool RELEASE>
+__global__ __launch_bounds__(kBlock) void k_erase(TableView t, const uint64_t* __restrict__ keys,
+                                                  int64_t q, uint32_t dmask,
+                                                  uint8_t* __restrict__ erased) {
+  const int64_t del = erase_range<RELEASE>(t, keys, dmask, erased, (int64_t)blockIdx.x * kBlock, q,
+                                           (int64_t)gridDim.x * kBlock);
   const int64_t tot = block_sum(del);
   if (threadIdx.x == 0) t.bcnt[blockIdx.x] = -tot;
 }
 
 // Add the per-block partials of the preceding insert/erase kernel to the live count.
-__global__ __launch_bounds__(1024) void k_apply_count(TableView t, int nblocks) {
+__device__ __forceinline__ void apply_count_block(const TableView& t, int nparts) {
   int64_t v = 0;
-  for (int j = threadIdx.x; j < nblocks; j += 1024) v += t.bcnt[j];
+  for (int j = threadIdx.x; j < nparts; j += blockDim.x) v += t.bcnt[j];
   v = (int64_t)wave_sum((uint64_t)v);
   __shared__ int64_t part[16];
   if (wave_lane() == 0) part[threadIdx.x >> 6] = v;
   __syncthreads();
   if (threadIdx.x == 0) {
     int64_t s = 0;
-    for (int w = 0; w < 16; ++w) s += part[w];
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) s += part[w];
     if (s) t.hdr->size = (uint64_t)((int64_t)t.hdr->size + s);
   }
+  __syncthreads();
+}
+
+__global__ __launch_bounds__(1024) void k_apply_count(TableView t, int nblocks) {
+  apply_count_block(t, nblocks);
 }
 
 // Flagged count per tile of kTile elements.
@@ -519,20 +566,18 @@ __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* t
   return before + x - v;
 }
 
-// Single block: exclusive scan of the tile counts, then the counter updates the ranks imply.
-// mode 0: insert near capacity; 1: insert with pool values; 2: erase releasing to the pool.
-__global__ __launch_bounds__(1024) void k_tile_scan(TableView t, PoolHeader* pool, int ntiles,
-                                                    int mode) {
-  const bool fast = t.hdr->fast != 0;
-  if (mode == 0 && fast) return;
+// One block of NT threads: exclusive scan of the tile counts, then the counter updates the ranks
+// imply.  mode 0: insert near capacity; 1: insert with pool values; 2: erase releasing to the pool.
+template <int NT>
+__device__ __forceinline__ void scan_tiles_block(const TableView& t, PoolHeader* pool, int ntiles,
+                                                 int mode) {
   __shared__ uint32_t carry;
+  __shared__ uint32_t ws[NT / 64];
   if (threadIdx.x == 0) carry = 0;
   __syncthreads();
-  for (int base = 0; base < ntiles; base += 1024) {
+  for (int base = 0; base < ntiles; base += NT) {
     const int j = base + (int)threadIdx.x;
     const uint32_t v = j < ntiles ? t.tsum[j] : 0u;
-    // 1024-thread exclusive scan via 16 waves
-    __shared__ uint32_t ws[16];
     const int lane = wave_lane();
     uint32_t x = v;
     for (int off = 1; off < 64; off <<= 1) {
@@ -542,7 +587,7 @@ __global__ __launch_bounds__(1024) void k_tile_scan(TableView t, PoolHeader* poo
     if (lane == 63) ws[threadIdx.x >> 6] = x;
     __syncthreads();
     uint32_t before = 0, all = 0;
-    for (int w = 0; w < 16; ++w) {
+    for (int w = 0; w < NT / 64; ++w) {
       if (w < (int)(threadIdx.x >> 6)) before += ws[w];
       all += ws[w];
     }
@@ -577,6 +622,13 @@ __global__ __launch_bounds__(1024) void k_tile_scan(TableView t, PoolHeader* poo
       if (nnew > room_p) pool->err |= kErrPool;
     }
   }
+  __syncthreads();
+}
+
+__global__ __launch_bounds__(1024) void k_tile_scan(TableView t, PoolHeader* pool, int ntiles,
+                                                    int mode) {
+  if (mode == 0 && t.hdr->fast) return;
+  scan_tiles_block<1024>(t, pool, ntiles, mode);
 }
 
 // Ranked completion of flagged elements, one tile per block.
@@ -584,16 +636,16 @@ __global__ __launch_bounds__(1024) void k_tile_scan(TableView t, PoolHeader* poo
 // MODE 1: insert with pool values (rank < min(room, pool) -> value = stack[top0-1-rank])
 // MODE 2: erase releasing to the pool (stack[top0+rank] = value)
 template <int VK, int MODE>
-__global__ __launch_bounds__(kBlock) void k_final(TableView t, PoolHeader* pool,
-                                                  int32_t* __restrict__ pstack,
-                                                  const uint64_t* __restrict__ keys,
-                                                  const void* __restrict__ vals, int64_t q,
-                                                  uint8_t* __restrict__ status,
-                                                  int32_t* __restrict__ vout) {
+__device__ __forceinline__ void final_tile(const TableView& t, PoolHeader* pool,
+                                           int32_t* __restrict__ pstack,
+                                           const uint64_t* __restrict__ keys,
+                                           const void* __restrict__ vals, int64_t q,
+                                           uint8_t* __restrict__ status,
+                                           int32_t* __restrict__ vout, int64_t tile) {
   const bool fast = t.hdr->fast != 0;
   if (MODE == 0 && fast) return;
   __shared__ uint16_t list[kTile];
-  const int64_t t0 = (int64_t)blockIdx.x * kTile;
+  const int64_t t0 = tile * kTile;
   uint32_t f[kTile / kBlock];
   uint32_t cnt = 0;
 #pragma unroll
@@ -608,7 +660,7 @@ __global__ __launch_bounds__(kBlock) void k_final(TableView t, PoolHeader* pool,
   for (int k = 0; k < kTile / kBlock; ++k)
     if (f[k]) list[o++] = (uint16_t)(threadIdx.x * (kTile / kBlock) + k);
   __syncthreads();
-  const uint64_t rbase = t.tsum[blockIdx.x];
+  const uint64_t rbase = t.tsum[tile];
   const Header* h = t.hdr;
   const uint64_t room = t.cap - h->size0;
   const int sub = threadIdx.x & 7;
@@ -659,35 +711,47 @@ __global__ __launch_bounds__(kBlock) void k_final(TableView t, PoolHeader* pool,
       }
     }
   }
+  __syncthreads();  // the tile list is reused by the caller's next tile
+}
+
+template <int VK, int MODE>
+__global__ __launch_bounds__(kBlock) void k_final(TableView t, PoolHeader* pool,
+                                                  int32_t* __restrict__ pstack,
+                                                  const uint64_t* __restrict__ keys,
+                                                  const void* __restrict__ vals, int64_t q,
+                                                  uint8_t* __restrict__ status,
+                                                  int32_t* __restrict__ vout) {
+  final_tile<VK, MODE>(t, pool, pstack, keys, vals, q, status, vout, blockIdx.x);
 }
 
 // Later copies of a key take the outcome of its first occurrence: PRESENT (or its value), unless
 // the first occurrence met FULL, which a later copy meets again.
-__global__ __launch_bounds__(kBlock) void k_fix(TableView t, uint8_t* __restrict__ status,
-                                                int32_t* __restrict__ vout) {
-  const uint32_t nd = t.hdr->ndup;
-  const uint32_t tid = blockIdx.x * blockDim.x + threadIdx.x;
-  const uint32_t nt = gridDim.x * blockDim.x;
-  for (uint32_t j = tid; j < nd; j += nt) {
+__device__ __forceinline__ void fix_range(const TableView& t, uint8_t* __restrict__ status,
+                                          int32_t* __restrict__ vout, int64_t lo, int64_t step) {
+  const int64_t nd = t.hdr->ndup;
+  for (int64_t j = lo + threadIdx.x; j < nd; j += step) {
     const uint2 d = t.dup[j];
     if (vout) vout[d.x] = vout[d.y];
     if (status) status[d.x] = status[d.y] == kFull ? kFull : kPresent;
   }
 }
 
+__global__ __launch_bounds__(kBlock) void k_fix(TableView t, uint8_t* __restrict__ status,
+                                                int32_t* __restrict__ vout) {
+  fix_range(t, status, vout, (int64_t)blockIdx.x * blockDim.x, (int64_t)gridDim.x * blockDim.x);
+}
+
 // find / contains, 8 keys per group and one per lane for loading and storing (coalesced).  The
 // group probes its keys together in rounds: every pending bucket load of a round is issued before
 // the first ballot, so a lane has up to 8 independent 16-byte loads in flight.
 template <int VK>
-__global__ __launch_bounds__(kBlock) void k_find(TableView t, const uint64_t* __restrict__ keys,
-                                                 int64_t n, void* __restrict__ out,
-                                                 uint8_t* __restrict__ found_out) {
+__device__ __forceinline__ void find_range(const TableView& t, const uint64_t* __restrict__ keys,
+                                           void* __restrict__ out, uint8_t* __restrict__ found_out,
+                                           int64_t lo, int64_t hi, int64_t step) {
   const int sub = threadIdx.x & 7;
-  const int64_t ng = (int64_t)gridDim.x * (kBlock / 8);
-  for (int64_t g0 = ((int64_t)blockIdx.x * (kBlock / 8) + (threadIdx.x >> 3)) * kSlots; g0 < n;
-       g0 += ng * kSlots) {
+  for (int64_t g0 = lo + (int64_t)(threadIdx.x >> 3) * kSlots; g0 < hi; g0 += step) {
     const int64_t i = g0 + sub;
-    const bool valid = i < n;
+    const bool valid = i < hi;
     const uint64_t key = valid ? keys[i] : kEmpty;
     bool hit = false;
     uint64_t v = 0;
@@ -713,6 +777,14 @@ __global__ __launch_bounds__(kBlock) void k_find(TableView t, const uint64_t* __
       if (found_out) found_out[i] = hit ? 1 : 0;
     }
   }
+}
+
+template <int VK>
+__global__ __launch_bounds__(kBlock) void k_find(TableView t, const uint64_t* __restrict__ keys,
+                                                 int64_t n, void* __restrict__ out,
+                                                 uint8_t* __restrict__ found_out) {
+  find_range<VK>(t, keys, out, found_out, (int64_t)blockIdx.x * kBlock, n,
+                 (int64_t)gridDim.x * kBlock);
 }
 
 __global__ void k_dump_begin(TableView t) { t.hdr->dump_count = 0; }
@@ -1390,6 +1462,169 @@ ct_status ct_erase_release_batch(ct_table* t, ct_pool* p, const uint64_t* keys, 
   if (t->desc.val_kind != CT_VAL_U32) return CT_E_INVALID;
   if (n == 0) return CT_OK;
   return erase_chunks<true>(t, p, keys, n, erased, S(stream));
+}
+
+}  // extern "C"
+
+// --- multi-table plans ----------------------------------------------------------------------
+// A plan replays a schedule of single-table operations.  Tables are spread over `lanes` side
+// streams forked from the caller's stream (a table's operations stay on one stream, so their
+// order holds) and joined back at the end; each operation runs the same kernel pipeline as the
+// single-table call.  The whole fork/join sequence captures into one HIP graph.
+namespace {
+enum : int32_t { kOpClear = 0, kOpInsert = 1, kOpFind = 2, kOpErase = 3 };
+
+struct PlanOp {
+  ct_table* t;
+  int32_t type;
+  const uint64_t* keys;
+  const void* vals;
+  void* vout;
+  uint8_t* flags;
+  int64_t n;
+};
+}  // namespace
+
+struct ct_plan {
+  std::vector<PlanOp> ops;
+  std::vector<ct_table*> tables;  // distinct tables in first-use order
+  std::vector<hipStream_t> side;
+  std::vector<hipEvent_t> ev;     // fork event + one join event per side stream
+};
+
+namespace {
+
+ct_status plan_streams(ct_plan* p, int32_t lanes) {
+  while ((int32_t)p->side.size() < lanes) {
+    hipStream_t s;
+    if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) return CT_E_HIP;
+    p->side.push_back(s);
+  }
+  while (p->ev.size() < p->side.size() + 1) {
+    hipEvent_t e;
+    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return CT_E_HIP;
+    p->ev.push_back(e);
+  }
+  return CT_OK;
+}
+
+ct_status run_op(const PlanOp& o, hipStream_t s) {
+  ct_table* t = o.t;
+  const int vk = t->desc.val_kind;
+  switch (o.type) {
+    case kOpClear:
+      launch(t, CT_KERNEL_CLEAR, s, [&] { k_table_reset<<<flat_blocks((int64_t)t->v.nb * kSlots), kBlock, 0, s>>>(t->v, 0); });
+      return launched();
+    case kOpInsert:
+      if (vk == CT_VAL_U32) return insert_chunks<1>(t, o.keys, o.vals, o.n, o.flags, s);
+      if (vk == CT_VAL_U64) return insert_chunks<2>(t, o.keys, o.vals, o.n, o.flags, s);
+      return insert_chunks<0>(t, o.keys, nullptr, o.n, o.flags, s);
+    case kOpErase:
+      return erase_chunks<false>(t, nullptr, o.keys, o.n, o.flags, s);
+    default: {
+      const int gb = group_blocks((o.n + kSlots - 1) / kSlots);
+      launch(t, CT_KERNEL_FIND, s, [&] {
+        if (vk == CT_VAL_U32) k_find<1><<<gb, kBlock, 0, s>>>(t->v, o.keys, o.n, o.vout, o.flags);
+        else if (vk == CT_VAL_U64) k_find<2><<<gb, kBlock, 0, s>>>(t->v, o.keys, o.n, o.vout, o.flags);
+        else k_find<0><<<gb, kBlock, 0, s>>>(t->v, o.keys, o.n, nullptr, o.flags);
+      });
+      return launched();
+    }
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+ct_status ct_plan_create(ct_plan** out) {
+  if (!out) return CT_E_INVALID;
+  ct_plan* p = new (std::nothrow) ct_plan;
+  if (!p) return CT_E_NOMEM;
+  *out = p;
+  return CT_OK;
+}
+
+ct_status ct_plan_destroy(ct_plan* p) {
+  if (!p) return CT_E_INVALID;
+  for (hipStream_t s : p->side) hipStreamDestroy(s);
+  for (hipEvent_t e : p->ev) hipEventDestroy(e);
+  delete p;
+  return CT_OK;
+}
+
+ct_status ct_plan_add(ct_plan* p, ct_table* t, int32_t op, const uint64_t* keys, const void* vals,
+                      void* vals_out, uint8_t* flags_out, int64_t n) {
+  if (!p || !t || n < 0) return CT_E_INVALID;
+  if (op < kOpClear || op > kOpErase) return CT_E_INVALID;
+  const int vk = t->desc.val_kind;
+  if (op != kOpClear && n > 0 && !keys) return CT_E_INVALID;
+  if (op == kOpInsert && vk != CT_VAL_NONE && n > 0 && !vals) return CT_E_INVALID;
+  if (op == kOpFind && vk == CT_VAL_NONE && vals_out) return CT_E_INVALID;
+  if (op != kOpClear && n == 0) return CT_OK;
+  p->ops.push_back(PlanOp{t, op, keys, vals, vals_out, flags_out, op == kOpClear ? 0 : n});
+  if (std::find(p->tables.begin(), p->tables.end(), t) == p->tables.end()) p->tables.push_back(t);
+  // the plan may run any number of times later: the host no longer bounds this table's size
+  t->size_ub = (uint64_t)t->desc.capacity;
+  return CT_OK;
+}
+
+ct_status ct_plan_info(ct_plan* p, int64_t* nops, int64_t* ntables) {
+  if (!p) return CT_E_INVALID;
+  if (nops) *nops = (int64_t)p->ops.size();
+  if (ntables) *ntables = (int64_t)p->tables.size();
+  return CT_OK;
+}
+
+ct_status ct_plan_launch(ct_plan* p, int32_t lanes, void* stream) {
+  if (!p || lanes < 1 || lanes > 8) return CT_E_INVALID;
+  ct_status r = plan_streams(p, lanes);
+  if (r != CT_OK) return r;
+  hipStream_t s = S(stream);
+  if (hipEventRecord(p->ev[0], s) != hipSuccess) return CT_E_HIP;
+  for (int32_t i = 0; i < lanes; ++i)
+    if (hipStreamWaitEvent(p->side[i], p->ev[0], 0) != hipSuccess) return CT_E_HIP;
+  for (const PlanOp& o : p->ops) {
+    const size_t ti = (size_t)(std::find(p->tables.begin(), p->tables.end(), o.t) - p->tables.begin());
+    r = run_op(o, p->side[ti % (size_t)lanes]);
+    if (r != CT_OK) return r;
+  }
+  for (int32_t i = 0; i < lanes; ++i) {
+    if (hipEventRecord(p->ev[1 + i], p->side[i]) != hipSuccess) return CT_E_HIP;
+    if (hipStreamWaitEvent(s, p->ev[1 + i], 0) != hipSuccess) return CT_E_HIP;
+  }
+  return CT_OK;
+}
+
+ct_status ct_plan_capture(ct_plan* p, int32_t lanes, void* stream, void** graph_exec) {
+  if (!p || !graph_exec || !stream || lanes < 1 || lanes > 8) return CT_E_INVALID;
+  ct_status r = plan_streams(p, lanes);
+  if (r != CT_OK) return r;
+  hipStream_t s = S(stream);
+  if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess) return CT_E_HIP;
+  r = ct_plan_launch(p, lanes, stream);
+  hipGraph_t g = nullptr;
+  const hipError_t e = hipStreamEndCapture(s, &g);
+  if (r != CT_OK || e != hipSuccess) {
+    if (g) hipGraphDestroy(g);
+    return r != CT_OK ? r : CT_E_HIP;
+  }
+  hipGraphExec_t x = nullptr;
+  const hipError_t ie = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+  hipGraphDestroy(g);
+  if (ie != hipSuccess) return CT_E_HIP;
+  *graph_exec = x;
+  return CT_OK;
+}
+
+ct_status ct_graph_launch(void* graph_exec, void* stream) {
+  if (!graph_exec) return CT_E_INVALID;
+  return hipGraphLaunch(static_cast<hipGraphExec_t>(graph_exec), S(stream)) == hipSuccess ? CT_OK : CT_E_HIP;
+}
+
+ct_status ct_graph_destroy(void* graph_exec) {
+  if (!graph_exec) return CT_E_INVALID;
+  return hipGraphExecDestroy(static_cast<hipGraphExec_t>(graph_exec)) == hipSuccess ? CT_OK : CT_E_HIP;
 }
 
 }  // extern "C"

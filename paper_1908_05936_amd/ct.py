@@ -22,6 +22,7 @@ PRESENT, INSERTED, FULL = 0, 1, 2
 ERR_FULL, ERR_POOL = 1, 2
 KERNELS = ["clear", "prologue", "dedup", "insert", "erase", "apply", "rank", "final", "fix", "find"]
 VAL_NONE, VAL_U32, VAL_U64 = 0, 1, 2
+OP_CLEAR, OP_INSERT, OP_FIND, OP_ERASE = 0, 1, 2, 3
 HASH_MIX64, HASH_VOXEL21 = 0, 1
 
 
@@ -66,6 +67,14 @@ SIGNATURES = {
     "ct_pool_get_error": (C.c_int, [_P, C.POINTER(C.c_uint32), _P]),
     "ct_insert_alloc_batch": (C.c_int, [_P, _P, _P, _I64, _P, _P, _P]),
     "ct_erase_release_batch": (C.c_int, [_P, _P, _P, _I64, _P, _P]),
+    "ct_plan_create": (C.c_int, [C.POINTER(_P)]),
+    "ct_plan_destroy": (C.c_int, [_P]),
+    "ct_plan_add": (C.c_int, [_P, _P, _I32, _P, _P, _P, _P, _I64]),
+    "ct_plan_info": (C.c_int, [_P, _PI64, _PI64]),
+    "ct_plan_launch": (C.c_int, [_P, _I32, _P]),
+    "ct_plan_capture": (C.c_int, [_P, _I32, _P, C.POINTER(_P)]),
+    "ct_graph_launch": (C.c_int, [_P, _P]),
+    "ct_graph_destroy": (C.c_int, [_P]),
     "ctr_gather": (C.c_int, [_P, _I64, _I32, _P, _I64, _P, _P]),
     "ctr_gather_cas": (C.c_int, [_P, _I64, _I32, _P, _I64, _P, _P]),
     "ctr_cas": (C.c_int, [_P, _I64, _P, _I64, _P]),
@@ -302,6 +311,60 @@ class Table:
 
     def profile_reset(self):
         _check(lib().ct_table_profile_reset(self._h), "ct_table_profile_reset")
+
+
+class Plan:
+    """A schedule of operations on many tables, replayed on forked streams (include/ct.h)."""
+
+    def __init__(self, device="cuda"):
+        self.device = torch.device(device)
+        if self.device.index is None:
+            self.device = torch.device("cuda", torch.cuda.current_device())
+        h = C.c_void_p()
+        _check(lib().ct_plan_create(C.byref(h)), "ct_plan_create")
+        self._h = h
+        self._keep = []  # tensors and tables the plan points at
+        self._graph = None
+
+    def __del__(self):
+        if getattr(self, "_graph", None) and _lib is not None:
+            _lib.ct_graph_destroy(self._graph)
+            self._graph = None
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.ct_plan_destroy(self._h)
+            self._h = None
+
+    def add(self, table: Table, op: int, keys=None, vals=None, vals_out=None, flags_out=None):
+        n = 0 if keys is None else keys.numel()
+        for tns in (keys, vals, vals_out, flags_out):
+            if tns is not None:
+                self._keep.append(tns)
+        _check(lib().ct_plan_add(self._h, table._h, int(op), _ptr(keys), _ptr(vals), _ptr(vals_out),
+                                 _ptr(flags_out), n), "ct_plan_add")
+        self._keep.append(table)
+
+    def info(self):
+        a, b = C.c_int64(0), C.c_int64(0)
+        _check(lib().ct_plan_info(self._h, C.byref(a), C.byref(b)), "ct_plan_info")
+        return a.value, b.value
+
+    def launch(self, lanes: int = 4):
+        _check(lib().ct_plan_launch(self._h, int(lanes), _stream(self.device)), "ct_plan_launch")
+
+    def capture(self, lanes: int = 4, stream=None):
+        """Capture one run into a HIP graph on `stream` (a torch stream, not the default one)."""
+        s = stream or torch.cuda.Stream(self.device)
+        g = C.c_void_p()
+        _check(lib().ct_plan_capture(self._h, int(lanes), s.cuda_stream, C.byref(g)), "ct_plan_capture")
+        if self._graph:
+            lib().ct_graph_destroy(self._graph)
+        self._graph = g
+        self._graph_stream = s
+        return g
+
+    def replay(self, stream=None):
+        s = stream or self._graph_stream
+        _check(lib().ct_graph_launch(self._graph, s.cuda_stream), "ct_graph_launch")
 
 
 # --- measured ceilings (include/ct_roofline.h) ------------------------------------------------

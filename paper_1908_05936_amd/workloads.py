@@ -260,3 +260,71 @@ def voxel_blocks(seed: int = 2, n_distinct: int = 1 << 22, n_resident: int = 1 <
         frame_list.append(q[rng.permutation(q.size)])
     return dict(path=path, residents=path[:n_resident], frames=frame_list,
                 pool_capacity=1 << 22, bucket_count=1 << 21)
+
+
+# --------------------------------------------------------------------------------------------
+# many tables, one schedule
+# --------------------------------------------------------------------------------------------
+def _log_uniform_int(rng, lo_log2, hi_log2, size=None):
+    return np.rint(np.exp2(rng.uniform(lo_log2, hi_log2, size=size))).astype(np.int64)
+
+
+def multi_table(seed: int = 4, n_tables: int = 256, entries_log2=(10, 20), lf=(0.5, 0.9),
+                batch_log2=(6, 18), mix_ops_per_table: int = 4, mix=(0.2, 0.7, 0.1)) -> dict:
+    """Independent tables of log-uniform size and load factor, then one interleaved schedule.
+
+    Phase 1 fills table t to entries_t fresh keys with insert batches of log-uniform size (the last
+    one truncated); phase 2 runs `mix_ops_per_table` operations per table drawn insert / find /
+    erase with probabilities `mix`.  Finds ask half live and half never-inserted keys; erases take
+    live keys; phase-2 inserts take half fresh and half live keys.  Per-table order is sequential;
+    the tables are interleaved by a seeded draw weighted by the operations each has left.
+    Values are u32.  Returns tables [{capacity, entries, load_factor}] and schedule
+    [(table, op, keys, vals)] with op in {"insert", "find", "erase"}.
+    """
+    rng = rng_for(seed)
+    tables, per_table = [], []
+    counter = 0
+    for t in range(n_tables):
+        entries = int(_log_uniform_int(rng, *entries_log2))
+        load = float(rng.uniform(*lf))
+        cap = int(math.ceil(entries / load))
+        tables.append(dict(capacity=cap, entries=entries, load_factor=load))
+        keys = splitmix64(seed * 1000003 + t, 0, entries)
+        fresh_next = entries
+        ops = []
+        pos = 0
+        while pos < entries:
+            b = int(_log_uniform_int(rng, *batch_log2))
+            k = keys[pos:pos + b]
+            ops.append(("insert", k, rng.integers(0, 1 << 32, size=k.size, dtype=np.uint64).astype(np.uint32)))
+            pos += k.size
+        for _ in range(mix_ops_per_table):
+            kind = rng.choice(["insert", "find", "erase"], p=list(mix))
+            b = int(_log_uniform_int(rng, *batch_log2))
+            if kind == "find":
+                half = b // 2
+                k = np.concatenate([keys[rng.integers(0, entries, size=half)],
+                                    splitmix64(seed * 1000003 + t, fresh_next, b - half)])
+                fresh_next += b - half
+                k = k[rng.permutation(k.size)]
+                ops.append(("find", k, None))
+            elif kind == "erase":
+                ops.append(("erase", keys[rng.integers(0, entries, size=b)], None))
+            else:
+                half = b // 2
+                k = np.concatenate([splitmix64(seed * 1000003 + t, fresh_next, half),
+                                    keys[rng.integers(0, entries, size=b - half)]])
+                fresh_next += half
+                k = k[rng.permutation(k.size)]
+                ops.append(("insert", k, rng.integers(0, 1 << 32, size=k.size, dtype=np.uint64).astype(np.uint32)))
+        per_table.append(ops)
+    left = np.array([len(o) for o in per_table], dtype=np.float64)
+    nxt = [0] * n_tables
+    schedule = []
+    while left.sum() > 0:
+        t = int(rng.choice(n_tables, p=left / left.sum()))
+        kind, k, v = per_table[t][nxt[t]]
+        schedule.append((t, kind, k, v))
+        nxt[t] += 1
+        left[t] -= 1
+    return dict(tables=tables, schedule=schedule)

@@ -1,0 +1,164 @@
+"""GPU parity of multi-table plans: a plan run (and its HIP-graph replays) gives, for every
+operation of an interleaved schedule over many tables, exactly the oracle's result -- the same as
+the single-table calls made in schedule order."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1908_05936_amd import ct
+from paper_1908_05936_amd.workloads import multi_table
+
+pytestmark = pytest.mark.gpu
+
+OPS = {"insert": ct.OP_INSERT, "find": ct.OP_FIND, "erase": ct.OP_ERASE}
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    ct.lib()
+    return torch.device("cuda", 0)
+
+
+def g64(a, dev):
+    return torch.from_numpy(np.ascontiguousarray(np.asarray(a, dtype=np.uint64)).view(np.int64)).to(dev)
+
+
+def g32(a, dev):
+    return torch.from_numpy(np.ascontiguousarray(np.asarray(a, dtype=np.uint32)).view(np.int32)).to(dev)
+
+
+def expected(w):
+    """Oracle replay of the schedule, table by table in schedule order."""
+    tabs = [oracle.OracleTable(t["capacity"], 32) for t in w["tables"]]
+    out = []
+    for ti, kind, keys, vals in w["schedule"]:
+        o = tabs[ti]
+        if kind == "insert":
+            out.append((o.insert(keys, vals), None))
+        elif kind == "find":
+            v, f = o.find(keys)
+            out.append((f, v))
+        else:
+            out.append((o.erase(keys), None))
+    return out, tabs
+
+
+class Run:
+    """GPU tables plus device inputs and outputs for every scheduled operation."""
+
+    def __init__(self, w, dev, chunk=0, provision=1.0):
+        self.w = w
+        self.tables = []
+        for t in w["tables"]:
+            nb = int(np.ceil(t["capacity"] * provision / 8)) if provision != 1.0 else 0
+            self.tables.append(ct.Table(t["capacity"], ct.VAL_U32, ct.HASH_MIX64, bucket_count=nb,
+                                        chunk=chunk, device=dev))
+        self.ops = []
+        for ti, kind, keys, vals in w["schedule"]:
+            k = g64(keys, dev)
+            v = g32(vals, dev) if vals is not None else None
+            flags = torch.empty(keys.size, dtype=torch.uint8, device=dev)
+            vout = torch.empty(keys.size, dtype=torch.int32, device=dev) if kind == "find" else None
+            self.ops.append((ti, kind, k, v, flags, vout))
+
+    def plan(self, dev):
+        p = ct.Plan(device=dev)
+        for t in self.tables:
+            p.add(t, ct.OP_CLEAR)
+        for ti, kind, k, v, flags, vout in self.ops:
+            p.add(self.tables[ti], OPS[kind], keys=k, vals=v, vals_out=vout, flags_out=flags)
+        return p
+
+    def per_batch(self):
+        for t in self.tables:
+            t.clear()
+        for ti, kind, k, v, flags, vout in self.ops:
+            t = self.tables[ti]
+            if kind == "insert":
+                flags.copy_(t.insert(k, v))
+            elif kind == "find":
+                vv, ff = t.find(k)
+                flags.copy_(ff)
+                vout.copy_(vv)
+            else:
+                flags.copy_(t.erase(k))
+
+    def check(self, exp):
+        torch.cuda.synchronize()
+        for (ti, kind, k, v, flags, vout), (ef, ev) in zip(self.ops, exp):
+            np.testing.assert_array_equal(flags.cpu().numpy(), ef)
+            if kind == "find":
+                np.testing.assert_array_equal(vout.cpu().numpy().view(np.uint32), ev)
+
+    def scramble(self):
+        for _, _, _, _, flags, vout in self.ops:
+            flags.fill_(7)
+            if vout is not None:
+                vout.fill_(-5)
+
+
+def small():
+    return multi_table(seed=5, n_tables=24, entries_log2=(6, 13), batch_log2=(3, 12),
+                       mix_ops_per_table=3)
+
+
+@pytest.mark.parametrize("lanes", [1, 4, 8])
+def test_plan_matches_oracle_and_per_batch(dev, lanes):
+    w = small()
+    exp, tabs = expected(w)
+    r = Run(w, dev)
+    p = r.plan(dev)
+    p.launch(lanes=lanes)
+    r.check(exp)
+    for t, o in zip(r.tables, tabs):
+        assert t.size() == o.size()
+        assert t.check() == 0
+    r.scramble()
+    r.per_batch()
+    r.check(exp)
+
+
+def test_plan_small_chunks_and_provisioning(dev):
+    w = small()
+    exp, _ = expected(w)
+    r = Run(w, dev, chunk=1024, provision=1.5)
+    p = r.plan(dev)
+    p.launch(lanes=2)
+    r.check(exp)
+
+
+def test_plan_graph_replays(dev):
+    w = small()
+    exp, _ = expected(w)
+    r = Run(w, dev)
+    p = r.plan(dev)
+    s = torch.cuda.Stream(dev)
+    p.capture(lanes=4, stream=s)
+    for rep in range(4):
+        r.scramble()              # eager work between replays
+        torch.cuda.synchronize()
+        p.replay(s)
+        s.synchronize()
+        r.check(exp)
+
+
+def test_plan_full_size(dev):
+    """The full schedule: 256 tables of 2^10..2^20 entries, 2794 operations, 76 M keys."""
+    w = multi_table(seed=4)
+    exp, tabs = expected(w)
+    r = Run(w, dev)
+    p = r.plan(dev)
+    p.launch(lanes=4)
+    r.check(exp)
+    for t, o in zip(r.tables, tabs):
+        assert t.size() == o.size()
+
+
+@pytest.mark.skip(reason="a single persistent launch with in-kernel dependency waits between work "
+                         "items faulted the GPU on its first run; its cause was not found and the "
+                         "executor was removed (see DESIGN.md)")
+def test_persistent_single_launch_executor():
+    pass
