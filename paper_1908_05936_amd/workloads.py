@@ -328,3 +328,99 @@ def multi_table(seed: int = 4, n_tables: int = 256, entries_log2=(10, 20), lf=(0
         nxt[t] += 1
         left[t] -= 1
     return dict(tables=tables, schedule=schedule)
+
+
+# --------------------------------------------------------------------------------------------
+# serving: many resident tables, Poisson arrivals of uneven requests
+# --------------------------------------------------------------------------------------------
+def splitmix64_at(seed: int, idx) -> np.ndarray:
+    """splitmix64 outputs at arbitrary counter positions `idx` (same values as ``splitmix64``)."""
+    gamma = np.uint64(0x9E3779B97F4A7C15)
+    i = np.asarray(idx, dtype=np.uint64) + np.uint64(1)
+    z = np.uint64(int(seed) & ((1 << 64) - 1)) + i * gamma
+    z = (z ^ (z >> np.uint64(30))) * np.uint64(0xBF58476D1CE4E5B9)
+    z = (z ^ (z >> np.uint64(27))) * np.uint64(0x94D049BB133111EB)
+    return z ^ (z >> np.uint64(31))
+
+
+class Serving:
+    """Tables of log-uniform size with a key universe of twice their entries (the first half
+    resident at start) and a stream of requests: table uniform, kind by `mix` (insert, find,
+    erase), size log-uniform, keys Zipf(`zipf_s`) over a seeded permutation of the table's
+    universe, values request_id * 2^32 + position.  Requests are drawn on demand, so the key
+    universe is never materialised: key(t, j) = splitmix64 output j of the table's seed, and the
+    permutation is j = (a * (rank - 1) + b) mod U with a coprime to U.
+    """
+
+    def __init__(self, seed: int = 5, n_tables: int = 64, entries_log2=(16, 26),
+                 req_log2=(8, 20), mix=(0.2, 0.7, 0.1), zipf_s: float = 1.1,
+                 rank_pool: int = 1 << 22):
+        self.seed = seed
+        self.rng = rng_for(seed, 1)
+        r0 = rng_for(seed, 0)
+        self.entries = [int(x) for x in _log_uniform_int(r0, *entries_log2, size=n_tables)]
+        self.universe = [2 * e for e in self.entries]
+        self.seeds = [seed * 7919 + t for t in range(n_tables)]
+        self.perm = []
+        for u in self.universe:
+            while True:
+                a = int(r0.integers(1, u))
+                if math.gcd(a, u) == 1:
+                    break
+            self.perm.append((a, int(r0.integers(0, u))))
+        self.req_log2 = req_log2
+        self.mix = mix
+        umax = max(self.universe)
+        self.ranks = zipf_ranks(r0, rank_pool, umax, zipf_s)  # shared pool, filtered per table
+        self._ranks2 = np.concatenate([self.ranks, self.ranks])  # windows wrap around the pool
+        self.next_id = 0
+
+    def resident(self, t: int, lo: int, hi: int) -> np.ndarray:
+        """Keys j in [lo, hi) of table t's resident half."""
+        return splitmix64_at(self.seeds[t], np.arange(lo, hi, dtype=np.uint64))
+
+    def _header(self):
+        """Draw the next request's id, table, kind and Zipf ranks (the sequential part)."""
+        rng = self.rng
+        t = int(rng.integers(0, len(self.entries)))
+        kind = ["insert", "find", "erase"][int(rng.choice(3, p=list(self.mix)))]
+        n = int(_log_uniform_int(rng, *self.req_log2))
+        u = self.universe[t]
+        parts, have = [], 0
+        pool = self.ranks.size
+        while have < n:
+            off = int(rng.integers(0, pool))
+            m = min(2 * n + 64, pool)
+            r = self._ranks2[off:off + m]
+            r = r[r <= u]
+            parts.append(r)
+            have += r.size
+        ranks = np.concatenate(parts)[:n] if len(parts) > 1 else parts[0][:n]
+        rid = self.next_id
+        self.next_id += 1
+        return rid, t, kind, ranks
+
+    def _materialise(self, head):
+        rid, t, kind, ranks = head
+        a, b = self.perm[t]
+        u = self.universe[t]
+        j = (a * (ranks - 1) + b) % u        # a, rank < 2^28: the product fits in int64
+        keys = splitmix64_at(self.seeds[t], j.astype(np.uint64))
+        vals = None
+        if kind == "insert":
+            vals = (np.uint64(rid) << np.uint64(32)) + np.arange(ranks.size, dtype=np.uint64)
+        return rid, t, kind, keys, vals
+
+    def request(self):
+        """(id, table, kind, keys, vals) of the next request."""
+        return self._materialise(self._header())
+
+    def requests(self, k: int, threads: int = 8):
+        """The next `k` requests, equal to `k` calls of ``request``; keys computed on `threads`
+        host threads."""
+        heads = [self._header() for _ in range(k)]
+        if threads <= 1:
+            return [self._materialise(h) for h in heads]
+        from concurrent.futures import ThreadPoolExecutor
+        with ThreadPoolExecutor(threads) as ex:
+            return list(ex.map(self._materialise, heads))

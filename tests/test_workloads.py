@@ -49,3 +49,24 @@ def test_pack_int3_fields():
     assert int(pack_int3(0, 0, 1)) == 1 << 42
     assert int(pack_int3(-1, 0, 0)) == (1 << 21) - 1
     assert int(pack_int3(0, 0, -1)) == ((1 << 21) - 1) << 42
+
+
+def test_serving_requests_threaded_equal_sequential():
+    from paper_1908_05936_amd.workloads import Serving
+    a = Serving(seed=3, n_tables=5, entries_log2=(8, 12), req_log2=(2, 9), rank_pool=1 << 12)
+    b = Serving(seed=3, n_tables=5, entries_log2=(8, 12), req_log2=(2, 9), rank_pool=1 << 12)
+    one = [a.request() for _ in range(40)]
+    many = b.requests(40, threads=4)
+    kinds = set()
+    for x, y in zip(one, many):
+        assert x[:3] == y[:3]
+        np.testing.assert_array_equal(x[3], y[3])
+        assert (x[4] is None) == (y[4] is None)
+        if x[4] is not None:
+            np.testing.assert_array_equal(x[4], y[4])
+            assert int(x[4][0]) >> 32 == x[0]
+        u = a.universe[x[1]]
+        allowed = set(a.resident(x[1], 0, u).tolist())   # keys come from the table's universe
+        assert set(x[3].tolist()) <= allowed
+        kinds.add(x[2])
+    assert kinds == {"insert", "find", "erase"}
