@@ -11,6 +11,8 @@ The printed JSON line carries:
   breakdown    per-operation Mops/s from HIP events on the library's stream
   roofline     the dominant kernel's algorithmic bytes per launch / its mean duration vs 8 TB/s
   random_access the same kernels against ceilings measured in this run on this chip
+  served       the serving sweep on 64 device-resident tables: p50/p99 latency and achieved
+               keys/s at fractions of the saturated rate
   cpu_baseline the CPU oracle timed on a bounded sample of the same workload
 """
 from __future__ import annotations
@@ -77,6 +79,11 @@ def parse():
     ap.add_argument("--log2-queries", type=int, default=27)
     ap.add_argument("--log2-churn", type=int, default=24)
     ap.add_argument("--chunk", type=int, default=0, help="table chunk (0 = library default)")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving sweep")
+    ap.add_argument("--serve-footprint-gb", type=float, default=40.0)
+    ap.add_argument("--serve-warmup", type=int, default=200)
+    ap.add_argument("--serve-measured", type=int, default=2000)
+    ap.add_argument("--serve-distinct", type=int, default=1000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-ceilings", action="store_true")
     ap.add_argument("--cpu-sample-shift", type=int, default=1,
@@ -329,6 +336,23 @@ def main():
         ceil["find_frac_of_R5"] = f_mops / ceil["R5_find_stream_Mlines_s"]
         ceil["insert_frac_of_R2"] = i_mops / ceil["R2_gather128_cas_Mops_s"]
         line["random_access"] = ceil
+    if not a.no_serve:
+        del table, K_fill, V_fill, Q, E, K_re, V_re
+        torch.cuda.empty_cache()
+        from paper_1908_05936_amd import bench_serve
+        res = bench_serve.run(a.serve_footprint_gb, a.serve_warmup, a.serve_measured,
+                              a.serve_distinct, log=log)
+        line["served"] = {
+            "workload": (f"{res['tables']} tables, {res['resident_entries']} resident u64->u64 "
+                         f"entries, {res['table_bytes'] / 1e9:.1f} GB; requests 20/70/10 "
+                         "insert/find/erase, 2^8..2^20 keys, Zipf(1.1); Poisson arrivals"),
+            "saturated_Mkeys_s": res["saturated_Mkeys_s"],
+            "points": [{k: p[k] for k in ("offered_fraction", "p50_ms", "p99_ms", "achieved_Mkeys_s",
+                                          "batches")} for p in res["points"]],
+            "requests_per_point": res["requests"],
+            "budget_bytes": res["budget_bytes"], "max_inflight": res["max_inflight"],
+            "streams": res["streams"],
+        }
     if not a.no_cpu_baseline:
         log("timing the CPU oracle sample")
         line["cpu_baseline"] = cpu_baseline(a.cpu_sample_shift)

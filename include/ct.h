@@ -116,6 +116,9 @@ ct_status ct_table_destroy(ct_table *t);
 /* Geometry of a table: home buckets and chunk size (host only, either pointer nullable). */
 ct_status ct_table_info(const ct_table *t, int64_t *bucket_count, int64_t *chunk);
 
+/* Bytes per mapped value: 0 for a set, 4 for CT_VAL_U32, 8 for CT_VAL_U64.  Host only. */
+ct_status ct_table_value_bytes(const ct_table *t, int32_t *bytes);
+
 /* Iterator-based insert of an array (Section 4.1, insert).  keys[n] u64; vals[n] u32 or u64 by the
    table's value kind (ignored and nullable for sets, required otherwise).  status[n] (nullable):
    CT_PRESENT, CT_INSERTED or CT_FULL per element. */

@@ -1256,6 +1256,12 @@ ct_status ct_table_info(const ct_table* t, int64_t* bucket_count, int64_t* chunk
   return CT_OK;
 }
 
+ct_status ct_table_value_bytes(const ct_table* t, int32_t* bytes) {
+  if (!t || !bytes) return CT_E_INVALID;
+  *bytes = t->desc.val_kind == CT_VAL_U64 ? 8 : t->desc.val_kind == CT_VAL_U32 ? 4 : 0;
+  return CT_OK;
+}
+
 ct_status ct_insert_batch(ct_table* t, const uint64_t* keys, const void* vals, int64_t n,
                           uint8_t* status, void* stream) {
   ct_status r = check_batch(t, keys, n);

@@ -35,6 +35,16 @@ class TableDesc(C.Structure):
                 ("bucket_count", C.c_int64), ("chunk", C.c_int64)]
 
 
+class ServerDesc(C.Structure):
+    _fields_ = [("streams", C.c_int32), ("max_inflight", C.c_int32), ("max_batch_keys", C.c_int64)]
+
+
+class ServerStats(C.Structure):
+    _fields_ = [("submitted", C.c_int64), ("completed", C.c_int64), ("batches", C.c_int64),
+                ("peak_staging_bytes", C.c_int64), ("peak_inflight", C.c_int64),
+                ("error", C.c_int32)]
+
+
 _lib = None
 
 # name -> (restype, argtypes)
@@ -75,6 +85,15 @@ SIGNATURES = {
     "ct_plan_capture": (C.c_int, [_P, _I32, _P, C.POINTER(_P)]),
     "ct_graph_launch": (C.c_int, [_P, _P]),
     "ct_graph_destroy": (C.c_int, [_P]),
+    "ct_table_value_bytes": (C.c_int, [_P, C.POINTER(C.c_int32)]),
+    "ct_server_create": (C.c_int, [C.POINTER(_P), _I32, C.POINTER(ServerDesc), _P, _I64,
+                                   C.POINTER(_P)]),
+    "ct_server_submit": (C.c_int, [_P, _I32, _I32, _P, _P, _I64, _P, _P, _PI64]),
+    "ct_server_poll": (C.c_int, [_P, _P, _P, _P, _P, _I64, _PI64]),
+    "ct_server_wait_idle": (C.c_int, [_P]),
+    "ct_server_get_stats": (C.c_int, [_P, C.POINTER(ServerStats)]),
+    "ct_server_now": (C.c_int, [_P, _PI64]),
+    "ct_server_destroy": (C.c_int, [_P]),
     "ctr_gather": (C.c_int, [_P, _I64, _I32, _P, _I64, _P, _P]),
     "ctr_gather_cas": (C.c_int, [_P, _I64, _I32, _P, _I64, _P, _P]),
     "ctr_cas": (C.c_int, [_P, _I64, _P, _I64, _P]),
@@ -365,6 +384,77 @@ class Plan:
     def replay(self, stream=None):
         s = stream or self._graph_stream
         _check(lib().ct_graph_launch(self._graph, s.cuda_stream), "ct_graph_launch")
+
+
+# --- request server (include/ct_server.h) -------------------------------------------------------
+class NativeServer:
+    """Handle of a ct_server over `tables`, with a device staging buffer of `staging_bytes`.
+
+    Host arrays handed to ``submit`` must stay alive until their request is reported complete;
+    the caller keeps them (this class only keeps the tables and the staging buffer alive)."""
+
+    def __init__(self, tables, staging_bytes: int, streams: int = 8, max_inflight: int = 64,
+                 max_batch_keys: int = 1 << 21, device="cuda"):
+        self.device = torch.device(device)
+        if self.device.index is None:
+            self.device = torch.device("cuda", torch.cuda.current_device())
+        self.tables = list(tables)
+        self.staging = torch.empty(int(staging_bytes), dtype=torch.uint8, device=self.device)
+        torch.cuda.synchronize(self.device)
+        arr = (C.c_void_p * len(self.tables))(*[t._h.value for t in self.tables])
+        d = ServerDesc(int(streams), int(max_inflight), int(max_batch_keys))
+        h = C.c_void_p()
+        with torch.cuda.device(self.device):
+            _check(lib().ct_server_create(C.cast(arr, C.POINTER(C.c_void_p)), len(self.tables),
+                                          C.byref(d), _ptr(self.staging), self.staging.numel(),
+                                          C.byref(h)), "ct_server_create")
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _check(_lib.ct_server_destroy(self._h), "ct_server_destroy")
+            self._h = None
+
+    def __del__(self):
+        self.close()
+
+    def submit(self, table: int, op: int, keys, vals=None, vals_out=None, flags_out=None) -> int:
+        """Queue one request; the arrays are host tensors (pinned for asynchronous copies)."""
+        n = keys.numel()
+        for t in (keys, vals, vals_out, flags_out):
+            if t is not None and (t.is_cuda or not t.is_contiguous()):
+                raise CtError("server arrays must be contiguous host tensors")
+        tk = C.c_int64(0)
+        _check(lib().ct_server_submit(self._h, int(table), int(op), _ptr(keys), _ptr(vals), n,
+                                      _ptr(vals_out), _ptr(flags_out), C.byref(tk)),
+               "ct_server_submit")
+        return tk.value
+
+    def poll(self, max_items: int = 1 << 16):
+        """Completed requests: (tickets, submit_ns, done_ns, status) numpy arrays."""
+        import numpy as np
+        t = np.empty(max_items, dtype=np.int64)
+        a = np.empty(max_items, dtype=np.int64)
+        d = np.empty(max_items, dtype=np.int64)
+        st = np.empty(max_items, dtype=np.int32)
+        cnt = C.c_int64(0)
+        _check(lib().ct_server_poll(self._h, t.ctypes.data, a.ctypes.data, d.ctypes.data,
+                                    st.ctypes.data, max_items, C.byref(cnt)), "ct_server_poll")
+        k = cnt.value
+        return t[:k], a[:k], d[:k], st[:k]
+
+    def wait_idle(self):
+        _check(lib().ct_server_wait_idle(self._h), "ct_server_wait_idle")
+
+    def now_ns(self) -> int:
+        v = C.c_int64(0)
+        _check(lib().ct_server_now(self._h, C.byref(v)), "ct_server_now")
+        return v.value
+
+    def stats(self) -> dict:
+        st = ServerStats()
+        _check(lib().ct_server_get_stats(self._h, C.byref(st)), "ct_server_get_stats")
+        return {name: getattr(st, name) for name, _ in ServerStats._fields_}
 
 
 # --- measured ceilings (include/ct_roofline.h) ------------------------------------------------

@@ -1,13 +1,13 @@
-"""GPU serving loop: every request served in the mix gets exactly the result the oracle gives when
-the table's requests are replayed in arrival order, the same as when that table is served alone;
-admission never exceeds its byte budget or slot cap."""
+"""GPU serving loop through the native server: every request served in the mix gets exactly the
+result the oracle gives when the table's requests are replayed in submission order, the same as
+when that table is served alone; admission never exceeds its staging budget or slot cap."""
 import numpy as np
 import pytest
 import torch
 
 import oracle
 from paper_1908_05936_amd import ct
-from paper_1908_05936_amd.serve import Request, Server, build_tables, poisson_arrivals
+from paper_1908_05936_amd.serve import Request, Server, build_tables, poisson_arrivals, sweep
 from paper_1908_05936_amd.workloads import Serving
 
 pytestmark = pytest.mark.gpu
@@ -34,9 +34,10 @@ def oracle_tables(sv):
     return tabs
 
 
-def expected(tabs, reqs):
+def replay(tabs, reqs):
+    """Oracle results of `reqs` applied in submission order (request id order here)."""
     out = {}
-    for r in sorted(reqs, key=lambda r: r.rid):   # arrival order = request id order
+    for r in sorted(reqs, key=lambda r: r.rid):
         o = tabs[r.table]
         if r.kind == "insert":
             out[r.rid] = {"status": o.insert(r.keys, r.vals)}
@@ -48,61 +49,96 @@ def expected(tabs, reqs):
     return out
 
 
-def same(r, exp):
-    for k, v in exp.items():
-        got = r.result[k]
-        if k == "vals":
-            got = got.view(np.uint64)
-        np.testing.assert_array_equal(got, v, err_msg=f"request {r.rid} {r.kind} {k}")
+def check_same(reqs, exp):
+    for r in reqs:
+        assert r.status == 0, (r.rid, r.status)
+        for k, v in exp[r.rid].items():
+            got = r.result[k]
+            if k == "vals":
+                got = got.view(np.uint64)
+            np.testing.assert_array_equal(got, v, err_msg=f"request {r.rid} {r.kind} {k}")
 
 
 def draw(sv, n):
     return [Request(*x) for x in sv.requests(n)]
 
 
-@pytest.mark.parametrize("chunk", [0, 1024])
-def test_served_results_match_sequential_replay(dev, chunk):
+@pytest.mark.parametrize("chunk,budget,inflight,streams", [
+    (0, 1 << 20, 8, 4),        # default chunk, roomy budget
+    (1024, 1 << 20, 8, 3),     # batches split into several chunks inside the library
+    (0, 1 << 17, 2, 2),        # tight budget and two slots: back-pressure and fragmentation
+])
+def test_served_results_match_sequential_replay(dev, chunk, budget, inflight, streams):
     sv = small_workload()
     tables = build_tables(sv, dev, chunk=chunk)
     reqs = draw(sv, 400)
-    budget = 1 << 18
-    srv = Server(tables, dev, streams=4, budget_bytes=budget, max_inflight=8)
-    srv.run(reqs, poisson_arrivals(np.random.default_rng(1), len(reqs), 20000.0))
-    exp = expected(oracle_tables(sv), reqs)
-    for r in reqs:
-        same(r, exp[r.rid])
-    assert srv.peak_slots <= 8
-    biggest = max(r.staging_bytes() for r in reqs)
-    assert srv.peak_bytes <= max(budget, biggest)
-    assert srv.batches < len(reqs)   # some requests were coalesced
-    for t, o in zip(tables, oracle_tables_after(sv, reqs)):
-        assert t.size() == o.size()
-
-
-def oracle_tables_after(sv, reqs):
+    srv = Server(tables, dev, streams=streams, budget_bytes=budget, max_inflight=inflight)
+    st = srv.run(reqs, poisson_arrivals(np.random.default_rng(1), len(reqs), 20000.0))
+    srv.close()
     tabs = oracle_tables(sv)
-    expected(tabs, reqs)
-    return tabs
+    check_same(reqs, replay(tabs, reqs))
+    assert st["error"] == 0 and st["completed"] == len(reqs)
+    assert st["peak_inflight"] <= inflight
+    assert st["peak_staging_bytes"] <= budget
+    assert st["batches"] <= len(reqs)
+    for t, o in zip(tables, tabs):
+        assert t.size() == o.size()
+        assert t.check() == 0
+
+
+def test_saturated_burst_coalesces_and_matches(dev):
+    sv = small_workload()
+    tables = build_tables(sv, dev)
+    reqs = draw(sv, 300)
+    srv = Server(tables, dev, streams=4, budget_bytes=1 << 22, max_inflight=16)
+    st = srv.run(reqs, np.zeros(len(reqs)))   # every request queued at once
+    srv.close()
+    check_same(reqs, replay(oracle_tables(sv), reqs))
+    assert st["batches"] < len(reqs)           # same-kind neighbours were merged
+    assert all(r.done >= r.arrival for r in reqs)
 
 
 def test_result_alone_equals_result_in_mix(dev):
     sv = small_workload()
     tables = build_tables(sv, dev)
     reqs = draw(sv, 300)
-    Server(tables, dev, streams=4).run(reqs, np.zeros(len(reqs)))   # all at once: the mix
+    srv = Server(tables, dev, streams=4)
+    srv.run(reqs, np.zeros(len(reqs)))
+    srv.close()
     t0 = reqs[0].table
     alone = [Request(r.rid, r.table, r.kind, r.keys, r.vals) for r in reqs if r.table == t0]
-    sv2 = small_workload()
-    tables2 = build_tables(sv2, dev)
-    Server(tables2, dev, streams=1).run(alone, np.zeros(len(alone)))
+    tables2 = build_tables(small_workload(), dev)
+    srv = Server(tables2, dev, streams=1)
+    srv.run(alone, np.zeros(len(alone)))
+    srv.close()
     mix = {r.rid: r for r in reqs}
     for a in alone:
         for k, v in a.result.items():
             np.testing.assert_array_equal(v, mix[a.rid].result[k])
 
 
+def test_submit_rejects_bad_requests(dev):
+    sv = small_workload()
+    tables = build_tables(sv, dev)
+    srv = ct.NativeServer(tables, 1 << 12, streams=1, max_inflight=1, device=dev)
+    k = torch.zeros(1 << 10, dtype=torch.int64).pin_memory()
+    with pytest.raises(ct.CtError):      # 1024 keys need more than the 4 KiB staging buffer
+        srv.submit(0, ct.OP_FIND, k)
+    with pytest.raises(ct.CtError):      # table index out of range
+        srv.submit(len(tables), ct.OP_FIND, k[:8])
+    with pytest.raises(ct.CtError):      # clear is not a served operation
+        srv.submit(0, ct.OP_CLEAR, k[:8])
+    with pytest.raises(ct.CtError):      # insert into a map needs values
+        srv.submit(0, ct.OP_INSERT, k[:8])
+    f = torch.empty(8, dtype=torch.uint8).pin_memory()
+    srv.submit(0, ct.OP_FIND, k[:8], flags_out=f)
+    srv.wait_idle()
+    tk, _, _, st = srv.poll()
+    assert tk.tolist() == [0] and st.tolist() == [0]
+    srv.close()
+
+
 def test_sweep_runs_and_reports(dev):
-    from paper_1908_05936_amd.serve import sweep
     sv = small_workload()
     tables = build_tables(sv, dev)
     res = sweep(sv, tables, dev, fractions=(0.5, 1.0), warmup=20, measured=100, pool_size=50,
