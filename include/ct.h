@@ -237,6 +237,33 @@ ct_status ct_plan_capture(ct_plan *p, int32_t lanes, void *stream, void **graph_
 ct_status ct_graph_launch(void *graph_exec, void *stream);
 ct_status ct_graph_destroy(void *graph_exec);
 
+/* Grouped form of a plan: one kernel launch per pipeline stage covers that stage for many tables.
+   Insert and erase operations are cut into chunk-steps of their table's chunk; the k-th step of
+   every table forms level k, and each level runs the pipeline stages (reset, prologue, dedup,
+   find / insert / erase, count update, rank scan, ranked completion, repeated-key outcomes) as
+   one launch each over all of its steps.  Steps of one level touch different tables, so a table's
+   steps still run in schedule order and every result equals that of the single-table calls.
+   The step descriptors live in a caller-provided device buffer. */
+
+/* Bytes of device memory the grouped form of `p` needs (host only). */
+ct_status ct_plan_group_bytes(ct_plan *p, int64_t *bytes);
+
+/* Build the grouped form of `p` into `d_buf` (device, `bytes` >= ct_plan_group_bytes, 256-byte
+   aligned, owned by the caller and kept alive and unmodified while the grouped form is used).
+   Copies synchronously.  Adding an operation to `p` afterwards invalidates the grouped form
+   (launching it then returns CT_E_INVALID until it is built again). */
+ct_status ct_plan_group(ct_plan *p, void *d_buf, int64_t bytes);
+
+/* Launches and steps of the grouped form (either pointer nullable). */
+ct_status ct_plan_group_info(ct_plan *p, int64_t *nlaunches, int64_t *nsteps);
+
+/* Run the grouped form on `stream` after the work already there.  Enqueues only. */
+ct_status ct_plan_launch_grouped(ct_plan *p, void *stream);
+
+/* Capture ct_plan_launch_grouped(p) on `stream` (a non-default stream) into an executable HIP
+   graph, replayed with ct_graph_launch and freed with ct_graph_destroy. */
+ct_status ct_plan_capture_grouped(ct_plan *p, void *stream, void **graph_exec);
+
 /* --- kernel timing (tracing) ---------------------------------------------------------------- */
 
 /* Kernel kinds the library launches for a table. */

@@ -915,6 +915,174 @@ __global__ __launch_bounds__(kBlock) void k_pool_copy(const PoolHeader* ph, cons
   for (int64_t j = tid; j < m; j += nt) out[j] = stack[j];
 }
 
+// ---------------------------------------------------------------------------------------------
+// grouped execution of a plan: one launch per pipeline stage covers the same stage of many
+// tables.  A plan is cut into levels holding at most one chunk-step per table (the k-th step of
+// every table); within a level the steps touch disjoint tables, scratch and arrays, so a stage's
+// blocks of all steps can run in one grid.  Block b of a stage launch finds its step from the
+// launch's entry list (first block of each step, ascending) and then runs exactly the range code
+// of the single-table kernel with the step's own block index and block count.
+// ---------------------------------------------------------------------------------------------
+struct GStep {
+  TableView v;
+  const uint64_t* keys;
+  const void* vals;
+  void* vout;
+  uint8_t* flags;
+  int64_t q;      // elements of this step (at most the table's chunk for insert and erase)
+  uint32_t db;    // dedup slots of the step's chunk
+  int32_t vk;     // value kind of the table
+  int32_t type;   // plan operation
+  int32_t gb;     // blocks of the step's insert / erase / find stage
+  int32_t ntiles; // rank-scan tiles
+  int32_t pad;
+};
+
+struct GEntry {
+  int32_t first;  // first block of the step in this launch
+  int32_t step;   // index into the step array
+};
+
+struct GLoc {
+  int32_t step, lb, nblk;
+};
+
+// Step of this block: the last entry whose first block is <= blockIdx.x.  Uniform per block.
+__device__ __forceinline__ GLoc g_locate(const GEntry* __restrict__ e, int32_t n) {
+  const int32_t b = (int32_t)blockIdx.x;
+  int32_t lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int32_t mid = (lo + hi + 1) >> 1;
+    if (e[mid].first <= b) lo = mid;
+    else hi = mid - 1;
+  }
+  const int32_t end = lo + 1 < n ? e[lo + 1].first : (int32_t)gridDim.x;
+  return GLoc{e[lo].step, b - e[lo].first, end - e[lo].first};
+}
+
+__global__ __launch_bounds__(kBlock) void k_g_reset(const GStep* __restrict__ st,
+                                                    const GEntry* __restrict__ e, int32_t n) {
+  const GLoc L = g_locate(e, n);
+  const TableView t = st[L.step].v;
+  reset_range(t, (int64_t)L.lb * kBlock, (int64_t)t.nb * kSlots, (int64_t)L.nblk * kBlock,
+              L.lb == 0, 0);
+}
+
+__global__ __launch_bounds__(kBlock) void k_g_prologue(const GStep* __restrict__ st,
+                                                       const GEntry* __restrict__ e, int32_t n) {
+  const GLoc L = g_locate(e, n);
+  const GStep& g = st[L.step];
+  const TableView t = g.v;
+  prologue_range(t, nullptr, g.db, g.q, (int64_t)L.lb * kBlock, prologue_units(g.db, g.q),
+                 (int64_t)L.nblk * kBlock, L.lb == 0);
+}
+
+__global__ __launch_bounds__(kBlock) void k_g_dedup(const GStep* __restrict__ st,
+                                                    const GEntry* __restrict__ e, int32_t n) {
+  const GLoc L = g_locate(e, n);
+  const GStep& g = st[L.step];
+  const TableView t = g.v;
+  dedup_range(t, g.keys, g.db - 1, (int64_t)L.lb * kBlock, g.q, (int64_t)L.nblk * kBlock);
+}
+
+__global__ __launch_bounds__(kBlock) void k_g_insert(const GStep* __restrict__ st,
+                                                     const GEntry* __restrict__ e, int32_t n) {
+  const GLoc L = g_locate(e, n);
+  const GStep& g = st[L.step];
+  const TableView t = g.v;
+  const int64_t lo = (int64_t)L.lb * kBlock, step = (int64_t)L.nblk * kBlock;
+  int64_t ins;
+  if (g.vk == 1)
+    ins = insert_range<1, false>(t, g.keys, g.vals, g.db - 1, g.flags, nullptr, lo, g.q, step);
+  else if (g.vk == 2)
+    ins = insert_range<2, false>(t, g.keys, g.vals, g.db - 1, g.flags, nullptr, lo, g.q, step);
+  else
+    ins = insert_range<0, false>(t, g.keys, nullptr, g.db - 1, g.flags, nullptr, lo, g.q, step);
+  const int64_t tot = block_sum(ins);
+  if (threadIdx.x == 0) t.bcnt[L.lb] = tot;
+}
+
+__global__ __launch_bounds__(kBlock) void k_g_erase(const GStep* __restrict__ st,
+                                                    const GEntry* __restrict__ e, int32_t n) {
+  const GLoc L = g_locate(e, n);
+  const GStep& g = st[L.step];
+  const TableView t = g.v;
+  const int64_t del = erase_range<false>(t, g.keys, g.db - 1, g.flags, (int64_t)L.lb * kBlock,
+                                         g.q, (int64_t)L.nblk * kBlock);
+  const int64_t tot = block_sum(del);
+  if (threadIdx.x == 0) t.bcnt[L.lb] = -tot;
+}
+
+__global__ __launch_bounds__(kBlock) void k_g_find(const GStep* __restrict__ st,
+                                                   const GEntry* __restrict__ e, int32_t n) {
+  const GLoc L = g_locate(e, n);
+  const GStep& g = st[L.step];
+  const TableView t = g.v;
+  const int64_t lo = (int64_t)L.lb * kBlock, step = (int64_t)L.nblk * kBlock;
+  if (g.vk == 1) find_range<1>(t, g.keys, g.vout, g.flags, lo, g.q, step);
+  else if (g.vk == 2) find_range<2>(t, g.keys, g.vout, g.flags, lo, g.q, step);
+  else find_range<0>(t, g.keys, nullptr, g.flags, lo, g.q, step);
+}
+
+__global__ __launch_bounds__(1024) void k_g_apply(const GStep* __restrict__ st,
+                                                  const GEntry* __restrict__ e, int32_t n) {
+  const GLoc L = g_locate(e, n);
+  const TableView t = st[L.step].v;
+  apply_count_block(t, st[L.step].gb);
+}
+
+__global__ __launch_bounds__(kBlock) void k_g_tile_count(const GStep* __restrict__ st,
+                                                         const GEntry* __restrict__ e, int32_t n) {
+  const GLoc L = g_locate(e, n);
+  const GStep& g = st[L.step];
+  const TableView t = g.v;
+  if (t.hdr->fast) return;
+  __shared__ uint32_t part[kBlock / 64];
+  const int64_t t0 = (int64_t)L.lb * kTile;
+  uint64_t c = 0;
+  for (int j = threadIdx.x; j < kTile; j += kBlock) {
+    const int64_t i = t0 + j;
+    if (i < g.q) c += t.flag[i];
+  }
+  c = wave_sum(c);
+  if (wave_lane() == 0) part[threadIdx.x >> 6] = (uint32_t)c;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t sum = 0;
+    for (int w = 0; w < kBlock / 64; ++w) sum += part[w];
+    t.tsum[L.lb] = sum;
+  }
+}
+
+__global__ __launch_bounds__(1024) void k_g_tile_scan(const GStep* __restrict__ st,
+                                                      const GEntry* __restrict__ e, int32_t n) {
+  const GLoc L = g_locate(e, n);
+  const TableView t = st[L.step].v;
+  if (t.hdr->fast) return;
+  scan_tiles_block<1024>(t, nullptr, st[L.step].ntiles, 0);
+}
+
+__global__ __launch_bounds__(kBlock) void k_g_final(const GStep* __restrict__ st,
+                                                    const GEntry* __restrict__ e, int32_t n) {
+  const GLoc L = g_locate(e, n);
+  const GStep& g = st[L.step];
+  const TableView t = g.v;
+  if (g.vk == 1)
+    final_tile<1, 0>(t, nullptr, nullptr, g.keys, g.vals, g.q, g.flags, nullptr, L.lb);
+  else if (g.vk == 2)
+    final_tile<2, 0>(t, nullptr, nullptr, g.keys, g.vals, g.q, g.flags, nullptr, L.lb);
+  else
+    final_tile<0, 0>(t, nullptr, nullptr, g.keys, nullptr, g.q, g.flags, nullptr, L.lb);
+}
+
+__global__ __launch_bounds__(kBlock) void k_g_fix(const GStep* __restrict__ st,
+                                                  const GEntry* __restrict__ e, int32_t n) {
+  const GLoc L = g_locate(e, n);
+  const GStep& g = st[L.step];
+  const TableView t = g.v;
+  fix_range(t, g.flags, nullptr, (int64_t)L.lb * kBlock, (int64_t)L.nblk * kBlock);
+}
+
 }  // namespace
 
 // =============================================================================================
@@ -1491,11 +1659,24 @@ struct PlanOp {
 };
 }  // namespace
 
+namespace ct_group {
+// One kernel launch of a grouped plan: `n` entries from `entry_off` of the entry array.
+struct Launch {
+  int32_t stage, n, blocks;
+  int64_t entry_off;
+};
+}  // namespace ct_group
+
 struct ct_plan {
   std::vector<PlanOp> ops;
   std::vector<ct_table*> tables;  // distinct tables in first-use order
   std::vector<hipStream_t> side;
   std::vector<hipEvent_t> ev;     // fork event + one join event per side stream
+  // grouped form (ct_plan_group): valid while the plan still has `grouped_ops` operations
+  std::vector<ct_group::Launch> glaunch;
+  const void* gsteps = nullptr;    // device: GStep[]
+  const void* gentries = nullptr;  // device: GEntry[]
+  size_t grouped_ops = (size_t)-1;
 };
 
 namespace {
@@ -1539,9 +1720,163 @@ ct_status run_op(const PlanOp& o, hipStream_t s) {
   }
 }
 
+enum GStage : int32_t {
+  gReset, gPro, gDedup, gFind, gInsert, gErase, gApply, gCount, gScan, gFinal, gFix, gStages
+};
+
+bool inserts_or_erases(const GStep& g) { return g.type == kOpInsert || g.type == kOpErase; }
+
+// Blocks of step `g` in stage `stage` (0: the step has no such stage); the same grids as the
+// single-table pipeline.
+int stage_blocks(int stage, const GStep& g) {
+  switch (stage) {
+    case gReset: return g.type == kOpClear ? flat_blocks((int64_t)g.v.nb * kSlots) : 0;
+    case gPro: return inserts_or_erases(g) ? flat_blocks(g.db / 2) : 0;
+    case gDedup: return inserts_or_erases(g) ? flat_blocks(g.q) : 0;
+    case gFind: return g.type == kOpFind ? g.gb : 0;
+    case gInsert: return g.type == kOpInsert ? g.gb : 0;
+    case gErase: return g.type == kOpErase ? g.gb : 0;
+    case gApply: return inserts_or_erases(g) ? 1 : 0;
+    case gCount: return g.type == kOpInsert ? g.ntiles : 0;
+    case gScan: return g.type == kOpInsert ? 1 : 0;
+    case gFinal: return g.type == kOpInsert ? g.ntiles : 0;
+    case gFix: return g.type == kOpInsert && g.flags ? flat_blocks(g.q) : 0;
+  }
+  return 0;
+}
+
+// Cut the plan into chunk-steps, assign each the per-table ordinal as its level, and lay out one
+// launch per (level, stage) that has steps.  Host only.
+ct_status group_build(const ct_plan* p, std::vector<GStep>& steps, std::vector<GEntry>& entries,
+                      std::vector<ct_group::Launch>& launches) {
+  std::vector<int32_t> level;
+  std::vector<int32_t> next(p->tables.size(), 0);
+  for (const PlanOp& o : p->ops) {
+    ct_table* t = o.t;
+    const size_t ti = (size_t)(std::find(p->tables.begin(), p->tables.end(), t) - p->tables.begin());
+    const int vk = t->desc.val_kind;
+    const int64_t vb = vk == CT_VAL_U32 ? 4 : 8;
+    const bool ie = o.type == kOpInsert || o.type == kOpErase;
+    const int64_t span = ie ? t->chunk : std::max<int64_t>(o.n, 1);
+    for (int64_t c0 = 0; c0 < std::max<int64_t>(o.n, 1); c0 += span) {
+      const int64_t q = o.type == kOpClear ? 0 : std::min<int64_t>(span, o.n - c0);
+      GStep g{};
+      g.v = t->v;
+      g.type = o.type;
+      g.vk = vk;
+      g.q = q;
+      g.keys = o.keys ? o.keys + c0 : nullptr;
+      g.vals = (o.type == kOpInsert && vk != CT_VAL_NONE)
+                   ? static_cast<const uint8_t*>(o.vals) + c0 * vb : nullptr;
+      g.vout = (o.type == kOpFind && o.vout) ? static_cast<uint8_t*>(o.vout) + c0 * vb : nullptr;
+      g.flags = o.flags ? o.flags + c0 : nullptr;
+      g.db = ie ? dedup_slots_for(q) : 0u;
+      g.gb = group_blocks((q + kSlots - 1) / kSlots);
+      g.ntiles = (int32_t)((q + kTile - 1) / kTile);
+      steps.push_back(g);
+      level.push_back(next[ti]++);
+    }
+  }
+  int32_t nlev = 0;
+  for (int32_t l : level) nlev = std::max(nlev, l + 1);
+  std::vector<std::vector<int32_t>> by_level(nlev);
+  for (size_t i = 0; i < steps.size(); ++i) by_level[level[i]].push_back((int32_t)i);
+  for (int32_t l = 0; l < nlev; ++l) {
+    for (int stage = 0; stage < gStages; ++stage) {
+      int64_t blocks = 0;
+      const int64_t off = (int64_t)entries.size();
+      for (int32_t i : by_level[l]) {
+        const int b = stage_blocks(stage, steps[i]);
+        if (!b) continue;
+        entries.push_back(GEntry{(int32_t)blocks, i});
+        blocks += b;
+        if (blocks > (int64_t)INT32_MAX / 2) return CT_E_INVALID;
+      }
+      const int64_t n = (int64_t)entries.size() - off;
+      if (n) launches.push_back(ct_group::Launch{stage, (int32_t)n, (int32_t)blocks, off});
+    }
+  }
+  return CT_OK;
+}
+
+int64_t group_steps_bytes(size_t nsteps) { return align_up((int64_t)(nsteps * sizeof(GStep))); }
+
 }  // namespace
 
 extern "C" {
+
+ct_status ct_plan_group_bytes(ct_plan* p, int64_t* bytes) {
+  if (!p || !bytes) return CT_E_INVALID;
+  std::vector<GStep> steps;
+  std::vector<GEntry> entries;
+  std::vector<ct_group::Launch> launches;
+  ct_status r = group_build(p, steps, entries, launches);
+  if (r != CT_OK) return r;
+  *bytes = std::max<int64_t>(kAlign, group_steps_bytes(steps.size()) +
+                                         (int64_t)(entries.size() * sizeof(GEntry)));
+  return CT_OK;
+}
+
+ct_status ct_plan_group(ct_plan* p, void* d_buf, int64_t bytes) {
+  if (!p || !d_buf || reinterpret_cast<uintptr_t>(d_buf) % kAlign) return CT_E_INVALID;
+  std::vector<GStep> steps;
+  std::vector<GEntry> entries;
+  std::vector<ct_group::Launch> launches;
+  ct_status r = group_build(p, steps, entries, launches);
+  if (r != CT_OK) return r;
+  const int64_t sb = group_steps_bytes(steps.size());
+  const int64_t eb = (int64_t)(entries.size() * sizeof(GEntry));
+  if (bytes < std::max<int64_t>(kAlign, sb + eb)) return CT_E_INVALID;
+  uint8_t* base = static_cast<uint8_t*>(d_buf);
+  if (!steps.empty() &&
+      hipMemcpy(base, steps.data(), steps.size() * sizeof(GStep), hipMemcpyHostToDevice) != hipSuccess)
+    return CT_E_HIP;
+  if (eb && hipMemcpy(base + sb, entries.data(), (size_t)eb, hipMemcpyHostToDevice) != hipSuccess)
+    return CT_E_HIP;
+  p->glaunch = std::move(launches);
+  p->gsteps = base;
+  p->gentries = base + sb;
+  p->grouped_ops = p->ops.size();
+  return CT_OK;
+}
+
+ct_status ct_plan_launch_grouped(ct_plan* p, void* stream) {
+  if (!p || p->grouped_ops != p->ops.size()) return CT_E_INVALID;
+  hipStream_t s = S(stream);
+  const GStep* st = static_cast<const GStep*>(p->gsteps);
+  const GEntry* en = static_cast<const GEntry*>(p->gentries);
+  for (const ct_group::Launch& L : p->glaunch) {
+    const GEntry* e = en + L.entry_off;
+    switch (L.stage) {
+      case gReset: k_g_reset<<<L.blocks, kBlock, 0, s>>>(st, e, L.n); break;
+      case gPro: k_g_prologue<<<L.blocks, kBlock, 0, s>>>(st, e, L.n); break;
+      case gDedup: k_g_dedup<<<L.blocks, kBlock, 0, s>>>(st, e, L.n); break;
+      case gFind: k_g_find<<<L.blocks, kBlock, 0, s>>>(st, e, L.n); break;
+      case gInsert: k_g_insert<<<L.blocks, kBlock, 0, s>>>(st, e, L.n); break;
+      case gErase: k_g_erase<<<L.blocks, kBlock, 0, s>>>(st, e, L.n); break;
+      case gApply: k_g_apply<<<L.blocks, 1024, 0, s>>>(st, e, L.n); break;
+      case gCount: k_g_tile_count<<<L.blocks, kBlock, 0, s>>>(st, e, L.n); break;
+      case gScan: k_g_tile_scan<<<L.blocks, 1024, 0, s>>>(st, e, L.n); break;
+      case gFinal: k_g_final<<<L.blocks, kBlock, 0, s>>>(st, e, L.n); break;
+      case gFix: k_g_fix<<<L.blocks, kBlock, 0, s>>>(st, e, L.n); break;
+      default: return CT_E_INVALID;
+    }
+    if (launched() != CT_OK) return CT_E_HIP;
+  }
+  return CT_OK;
+}
+
+ct_status ct_plan_group_info(ct_plan* p, int64_t* nlaunches, int64_t* nsteps) {
+  if (!p || p->grouped_ops != p->ops.size()) return CT_E_INVALID;
+  if (nlaunches) *nlaunches = (int64_t)p->glaunch.size();
+  if (nsteps) {
+    int64_t m = 0;
+    for (const ct_group::Launch& L : p->glaunch)
+      if (L.stage == gReset || L.stage == gPro || L.stage == gFind) m += L.n;
+    *nsteps = m;
+  }
+  return CT_OK;
+}
 
 ct_status ct_plan_create(ct_plan** out) {
   if (!out) return CT_E_INVALID;
@@ -1609,6 +1944,25 @@ ct_status ct_plan_capture(ct_plan* p, int32_t lanes, void* stream, void** graph_
   hipStream_t s = S(stream);
   if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess) return CT_E_HIP;
   r = ct_plan_launch(p, lanes, stream);
+  hipGraph_t g = nullptr;
+  const hipError_t e = hipStreamEndCapture(s, &g);
+  if (r != CT_OK || e != hipSuccess) {
+    if (g) hipGraphDestroy(g);
+    return r != CT_OK ? r : CT_E_HIP;
+  }
+  hipGraphExec_t x = nullptr;
+  const hipError_t ie = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+  hipGraphDestroy(g);
+  if (ie != hipSuccess) return CT_E_HIP;
+  *graph_exec = x;
+  return CT_OK;
+}
+
+ct_status ct_plan_capture_grouped(ct_plan* p, void* stream, void** graph_exec) {
+  if (!p || !graph_exec || !stream || p->grouped_ops != p->ops.size()) return CT_E_INVALID;
+  hipStream_t s = S(stream);
+  if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess) return CT_E_HIP;
+  ct_status r = ct_plan_launch_grouped(p, stream);
   hipGraph_t g = nullptr;
   const hipError_t e = hipStreamEndCapture(s, &g);
   if (r != CT_OK || e != hipSuccess) {

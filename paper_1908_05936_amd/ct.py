@@ -83,6 +83,11 @@ SIGNATURES = {
     "ct_plan_info": (C.c_int, [_P, _PI64, _PI64]),
     "ct_plan_launch": (C.c_int, [_P, _I32, _P]),
     "ct_plan_capture": (C.c_int, [_P, _I32, _P, C.POINTER(_P)]),
+    "ct_plan_group_bytes": (C.c_int, [_P, _PI64]),
+    "ct_plan_group": (C.c_int, [_P, _P, _I64]),
+    "ct_plan_group_info": (C.c_int, [_P, _PI64, _PI64]),
+    "ct_plan_launch_grouped": (C.c_int, [_P, _P]),
+    "ct_plan_capture_grouped": (C.c_int, [_P, _P, C.POINTER(_P)]),
     "ct_graph_launch": (C.c_int, [_P, _P]),
     "ct_graph_destroy": (C.c_int, [_P]),
     "ct_table_value_bytes": (C.c_int, [_P, C.POINTER(C.c_int32)]),
@@ -384,6 +389,34 @@ class Plan:
     def replay(self, stream=None):
         s = stream or self._graph_stream
         _check(lib().ct_graph_launch(self._graph, s.cuda_stream), "ct_graph_launch")
+
+    # grouped form: one launch per stage per level over all tables
+    def group(self):
+        """Build the grouped form (descriptor buffer allocated here, kept by the plan)."""
+        nb = C.c_int64(0)
+        _check(lib().ct_plan_group_bytes(self._h, C.byref(nb)), "ct_plan_group_bytes")
+        self._gbuf = torch.empty(nb.value, dtype=torch.uint8, device=self.device)
+        torch.cuda.synchronize(self.device)
+        _check(lib().ct_plan_group(self._h, _ptr(self._gbuf), nb.value), "ct_plan_group")
+
+    def group_info(self):
+        a, b = C.c_int64(0), C.c_int64(0)
+        _check(lib().ct_plan_group_info(self._h, C.byref(a), C.byref(b)), "ct_plan_group_info")
+        return a.value, b.value
+
+    def launch_grouped(self):
+        _check(lib().ct_plan_launch_grouped(self._h, _stream(self.device)), "ct_plan_launch_grouped")
+
+    def capture_grouped(self, stream=None):
+        s = stream or torch.cuda.Stream(self.device)
+        g = C.c_void_p()
+        _check(lib().ct_plan_capture_grouped(self._h, s.cuda_stream, C.byref(g)),
+               "ct_plan_capture_grouped")
+        if self._graph:
+            lib().ct_graph_destroy(self._graph)
+        self._graph = g
+        self._graph_stream = s
+        return g
 
 
 # --- request server (include/ct_server.h) -------------------------------------------------------

@@ -4,8 +4,10 @@ Every operation still runs in the HIP library (ct_plan_* in include/ct.h); this 
 creates tables and device arrays, records the schedule into a plan, and measures launches.
 
 Autotuner.  The knobs of a plan run are
-  * lanes       -- side streams the tables are spread over (operations on different tables
-                   overlap on the device; a table's operations keep their order),
+  * lanes       -- 0: the grouped form (one launch per pipeline stage per level, covering every
+                   table); 1..8: side streams the tables are spread over, each operation running
+                   its own pipeline (operations on different tables overlap on the device; a
+                   table's operations keep their order),
   * chunk       -- per-table insert/erase chunk (a larger chunk means fewer chained sub-operations
                    for big batches on small tables, at 34 bytes of scratch per chunk element),
   * provision   -- physical slots per requested capacity (1.0 = the requested load factor; more
@@ -28,7 +30,7 @@ import torch
 from . import ct
 
 OPS = {"insert": ct.OP_INSERT, "find": ct.OP_FIND, "erase": ct.OP_ERASE}
-DEFAULT = dict(lanes=4, chunk=0, provision=1.0)
+DEFAULT = dict(lanes=0, chunk=0, provision=1.0)
 
 
 def _g64(a, dev):
@@ -107,6 +109,15 @@ def time_fn(fn, reps=3, warmup=1):
     return float(np.median(ts))
 
 
+def runner(p: ct.Plan, lanes: int):
+    """Callable running plan `p` once: grouped (lanes 0, built on first use) or on side streams."""
+    if lanes == 0:
+        if getattr(p, "_gbuf", None) is None:
+            p.group()
+        return p.launch_grouped
+    return lambda: p.launch(lanes)
+
+
 def signature(w: dict) -> str:
     sizes = [t["capacity"] for t in w["tables"]]
     return (f"tables={len(sizes)},cap_sum={sum(sizes)},ops={len(w['schedule'])},"
@@ -135,13 +146,13 @@ def tune(w: dict, dev, cache: str | None = None, reps: int = 3, log=print) -> di
             built[wk] = Workload(w, dev, chunk=cfg["chunk"], provision=cfg["provision"])
         wl = built[wk]
         p = wl.plan()
-        t = time_fn(lambda: p.launch(cfg["lanes"]), reps=reps)
+        t = time_fn(runner(p, cfg["lanes"]), reps=reps)
         trials.append(dict(cfg, seconds=t))
         log(f"[tune] {cfg} -> {t * 1e3:.2f} ms")
         return t
 
     best_t = run(best)
-    space = [("lanes", [1, 2, 4, 8]), ("chunk", [0, -1]), ("provision", [1.0, 1.25, 1.5])]
+    space = [("lanes", [0, 1, 2, 4, 8]), ("chunk", [0, -1]), ("provision", [1.0, 1.25, 1.5])]
     for name, values in space:
         for v in values:
             if v == best[name]:
@@ -166,9 +177,12 @@ def measure(w: dict, dev, cfg: dict, reps: int = 5, graph_replays: int = 10) -> 
     """Plan run, its HIP-graph replay and one-stream per-batch calls on schedule `w` with `cfg`."""
     wl = Workload(w, dev, chunk=cfg["chunk"], provision=cfg["provision"])
     p = wl.plan()
-    t_plan = time_fn(lambda: p.launch(cfg["lanes"]), reps=reps)
+    t_plan = time_fn(runner(p, cfg["lanes"]), reps=reps)
     s = torch.cuda.Stream(dev)
-    p.capture(cfg["lanes"], stream=s)
+    if cfg["lanes"] == 0:
+        p.capture_grouped(stream=s)
+    else:
+        p.capture(cfg["lanes"], stream=s)
 
     def replays():
         with torch.cuda.stream(s):
@@ -182,7 +196,12 @@ def measure(w: dict, dev, cfg: dict, reps: int = 5, graph_replays: int = 10) -> 
     t_graph = (time.perf_counter() - w0) / graph_replays
     t_batch = time_fn(wl.per_batch, reps=max(1, reps // 2))
     n = wl.n_keys
-    return dict(keys=n, ops=len(w["schedule"]), tables=len(w["tables"]),
+    extra = {}
+    if cfg["lanes"] == 0:
+        extra = dict(zip(("grouped_launches", "grouped_steps"), p.group_info()))
+    t_streams = time_fn(lambda: p.launch(4), reps=reps)
+    return dict(extra, keys=n, ops=len(w["schedule"]), tables=len(w["tables"]),
+                streams4_ms=t_streams * 1e3,
                 table_bytes=wl.table_bytes, plan_ms=t_plan * 1e3, graph_replay_ms=t_graph * 1e3,
                 per_batch_ms=t_batch * 1e3, plan_Mkeys_s=n / t_plan / 1e6,
                 graph_Mkeys_s=n / t_graph / 1e6, per_batch_Mkeys_s=n / t_batch / 1e6,

@@ -157,6 +157,59 @@ def test_plan_full_size(dev):
         assert t.size() == o.size()
 
 
+@pytest.mark.parametrize("chunk", [0, 1024])
+def test_grouped_matches_oracle(dev, chunk):
+    """Grouped form: one launch per stage per level over all tables; chunk 1024 cuts the larger
+    batches into several steps (levels) per operation."""
+    w = small()
+    exp, tabs = expected(w)
+    r = Run(w, dev, chunk=chunk)
+    p = r.plan(dev)
+    p.group()
+    nl, ns = p.group_info()
+    assert ns >= len(w["schedule"]) and nl > 0
+    p.launch_grouped()
+    r.check(exp)
+    for t, o in zip(r.tables, tabs):
+        assert t.size() == o.size()
+        assert t.check() == 0
+    r.scramble()
+    p.launch_grouped()            # the plan starts with clears: a second run gives the same
+    r.check(exp)
+
+
+def test_grouped_graph_replays_and_invalidation(dev):
+    w = small()
+    exp, _ = expected(w)
+    r = Run(w, dev, provision=1.5)
+    p = r.plan(dev)
+    p.group()
+    s = torch.cuda.Stream(dev)
+    p.capture_grouped(stream=s)
+    for rep in range(4):
+        r.scramble()
+        torch.cuda.synchronize()
+        p.replay(s)
+        s.synchronize()
+        r.check(exp)
+    p.add(r.tables[0], ct.OP_CLEAR)   # a new operation invalidates the grouped form
+    with pytest.raises(ct.CtError):
+        p.launch_grouped()
+
+
+def test_grouped_full_size(dev):
+    """The full schedule grouped: 256 tables of 2^10..2^20 entries, every result bit-exact."""
+    w = multi_table(seed=4)
+    exp, tabs = expected(w)
+    r = Run(w, dev)
+    p = r.plan(dev)
+    p.group()
+    p.launch_grouped()
+    r.check(exp)
+    for t, o in zip(r.tables, tabs):
+        assert t.size() == o.size()
+
+
 @pytest.mark.skip(reason="a single persistent launch with in-kernel dependency waits between work "
                          "items faulted the GPU on its first run; its cause was not found and the "
                          "executor was removed (see DESIGN.md)")
