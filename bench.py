@@ -11,6 +11,7 @@ The printed JSON line carries:
   breakdown    per-operation Mops/s from HIP events on the library's stream
   roofline     the dominant kernel's algorithmic bytes per launch / its mean duration vs 8 TB/s
   random_access the same kernels against ceilings measured in this run on this chip
+  voxel        the voxel-block frames: per-frame p50/p99, find and insert_alloc Mkeys/s
   served       the serving sweep on 64 device-resident tables: p50/p99 latency and achieved
                keys/s at fractions of the saturated rate
   cpu_baseline the CPU oracle timed on a bounded sample of the same workload
@@ -80,6 +81,7 @@ def parse():
     ap.add_argument("--log2-churn", type=int, default=24)
     ap.add_argument("--chunk", type=int, default=0, help="table chunk (0 = library default)")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving sweep")
+    ap.add_argument("--no-voxel", action="store_true", help="skip the voxel-block frames")
     ap.add_argument("--serve-footprint-gb", type=float, default=40.0)
     ap.add_argument("--serve-warmup", type=int, default=200)
     ap.add_argument("--serve-measured", type=int, default=2000)
@@ -138,6 +140,21 @@ def measure_ceilings(ct, torch, dev, nlines, find_keys, uniform_keys):
     res["R5_find_stream_Mlines_s"] = find_keys.numel() / t / 1e6
     del buf, out, out2
     torch.cuda.empty_cache()
+    # the same gathers (and gather + CAS) over the footprints of the other workloads: L2 (4 MiB
+    # per XCD), the 256 MiB last-level cache, HBM at the large table's and the serving tables' size
+    sweep = {}
+    keys = uniform_keys[: 1 << 24]
+    for name, nbytes in (("2MiB", 2 << 20), ("32MiB", 32 << 20), ("256MiB", 256 << 20),
+                         ("1.34GB", nlines * 128), ("40GB", 40 << 30)):
+        lines = nbytes // 128
+        b = torch.zeros(lines * 128, dtype=torch.uint8, device=dev)
+        o = torch.empty(keys.numel(), dtype=torch.int64, device=dev)
+        t1 = timed(lambda: ct.gather(b, lines, 128, keys, o))
+        t2 = timed(lambda: ct.gather(b, lines, 128, keys, o, cas=True))
+        sweep[name] = {"R1_Mlines_s": keys.numel() / t1 / 1e6, "R2_Mops_s": keys.numel() / t2 / 1e6}
+        del b, o
+        torch.cuda.empty_cache()
+    res["by_footprint"] = sweep
     return res
 
 
@@ -336,6 +353,9 @@ def main():
         ceil["find_frac_of_R5"] = f_mops / ceil["R5_find_stream_Mlines_s"]
         ceil["insert_frac_of_R2"] = i_mops / ceil["R2_gather128_cas_Mops_s"]
         line["random_access"] = ceil
+    if not a.no_voxel:
+        from paper_1908_05936_amd import bench_voxel
+        line["voxel"] = bench_voxel.run(log=log)
     if not a.no_serve:
         del table, K_fill, V_fill, Q, E, K_re, V_re
         torch.cuda.empty_cache()

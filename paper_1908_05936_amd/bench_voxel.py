@@ -1,0 +1,84 @@
+"""Voxel-block frames: the reconstruction-style workload on the spatial hash.
+
+2^20 resident blocks (packed int3 keys, values popped from the index pool) in a table of 2^21
+buckets, then 100 frames of find(2^18 keys, 90 % hits) followed by insert_alloc of the frame's
+misses.  Reports per-frame wall time p50/p99 (find, selecting the misses, insert_alloc, with the
+results on the device) and find / insert_alloc Mkeys/s from HIP events on the launching stream.
+
+    python -m paper_1908_05936_amd.bench_voxel [--repeats 3]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import sys
+import time
+
+import numpy as np
+import torch
+
+from . import ct
+from .workloads import voxel_blocks
+
+
+def _dev64(a, dev):
+    return torch.from_numpy(np.ascontiguousarray(a).view(np.int64)).to(dev)
+
+
+def run(repeats: int = 3, seed: int = 2, log=print) -> dict:
+    dev = torch.device("cuda", 0)
+    w = voxel_blocks(seed=seed)
+    nb, cap = w["bucket_count"], w["pool_capacity"]
+    res_keys = _dev64(w["residents"], dev)
+    frames = [_dev64(q, dev) for q in w["frames"]]
+    t = ct.Table(cap, ct.VAL_U32, ct.HASH_VOXEL21, bucket_count=nb, device=dev)
+    pool = ct.Pool(cap, device=dev)
+    frame_ms, find_s, ins_s, n_find, n_ins = [], 0.0, 0.0, 0, 0
+    for rep in range(repeats):
+        t.clear()
+        pool = ct.Pool(cap, device=dev)   # a fresh free list: pops 0, 1, 2, ... again
+        t.insert_alloc(pool, res_keys)
+        torch.cuda.synchronize()
+        for q in frames:
+            e = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+            w0 = time.perf_counter()
+            e[0].record()
+            _, found = t.find(q, values=True)
+            e[1].record()
+            miss = q[found == 0]
+            e[2].record()
+            t.insert_alloc(pool, miss)
+            e[3].record()
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - w0
+            if rep > 0:   # the first pass warms up
+                frame_ms.append(wall * 1e3)
+                find_s += e[0].elapsed_time(e[1]) * 1e-3
+                ins_s += e[2].elapsed_time(e[3]) * 1e-3
+                n_find += q.numel()
+                n_ins += miss.numel()
+    size = t.size()
+    out = {
+        "workload": (f"voxel blocks: {w['residents'].size} residents, 2^21 buckets, spatial hash, "
+                     f"{len(frames)} frames of find 2^18 (90% hits) + insert_alloc of the misses"),
+        "frames_timed": len(frame_ms),
+        "frame_p50_ms": float(np.percentile(frame_ms, 50)),
+        "frame_p99_ms": float(np.percentile(frame_ms, 99)),
+        "find_Mkeys_s": n_find / find_s / 1e6,
+        "insert_alloc_Mkeys_s": n_ins / ins_s / 1e6,
+        "final_size": size,
+    }
+    log(f"[voxel] p50 {out['frame_p50_ms']:.3f} ms p99 {out['frame_p99_ms']:.3f} ms, find "
+        f"{out['find_Mkeys_s']:.0f} Mkeys/s, insert_alloc {out['insert_alloc_Mkeys_s']:.0f} Mkeys/s")
+    return out
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--repeats", type=int, default=3)
+    a = ap.parse_args(argv)
+    print(json.dumps(run(a.repeats, log=lambda m: print(m, file=sys.stderr, flush=True))), flush=True)
+
+
+if __name__ == "__main__":
+    main()
