@@ -120,7 +120,8 @@ struct ct_server {
   // worker-private
   std::vector<std::deque<Req>> queues;
   std::set<std::pair<int64_t, int32_t>> order;  // (ticket of the queued head, table), oldest first
-  std::vector<Batch> inflight;
+  std::vector<std::deque<Batch>> inflight;  // per stream, in launch (= completion) order
+  int64_t n_inflight = 0;
   std::vector<hipEvent_t> spare_events;
   Ranges ranges;
   int64_t inflight_bytes = 0;
@@ -206,7 +207,7 @@ struct ct_server {
     while (!order.empty()) {
       const int32_t t = order.begin()->second;
       std::deque<Req>& q = queues[t];
-      if ((int32_t)inflight.size() >= max_inflight) break;
+      if (n_inflight >= max_inflight) break;
       const Req& h = q.front();
       const int64_t room = ranges.largest();
       int64_t n = h.n;
@@ -231,39 +232,39 @@ struct ct_server {
       dispatch(b);
       inflight_bytes += b.bytes;
       any += (int64_t)take;
-      inflight.push_back(std::move(b));
+      inflight[t % streams.size()].push_back(std::move(b));
+      ++n_inflight;
       std::lock_guard<std::mutex> g(mu);
       ++batches;
       if (inflight_bytes > peak_bytes) peak_bytes = inflight_bytes;
-      if ((int64_t)inflight.size() > peak_inflight) peak_inflight = (int64_t)inflight.size();
+      if (n_inflight > peak_inflight) peak_inflight = n_inflight;
     }
     return any;
   }
 
-  // Retire the batches whose events have completed; returns true if any was.
+  // Retire the batches whose events have completed; returns true if any was.  A stream runs its
+  // batches in launch order, so only the oldest batch of each stream needs to be queried.
   bool retire() {
     std::vector<Done> fin;
-    size_t keep = 0;
-    for (size_t i = 0; i < inflight.size(); ++i) {
-      Batch& b = inflight[i];
-      hipError_t e = hipEventQuery(b.ev);
-      if (e == hipErrorNotReady) {
-        if (keep != i) inflight[keep] = std::move(b);
-        ++keep;
-        continue;
+    for (auto& q : inflight) {
+      while (!q.empty()) {
+        Batch& b = q.front();
+        const hipError_t e = hipEventQuery(b.ev);
+        if (e == hipErrorNotReady) break;
+        ct_status st = b.status;
+        if (e != hipSuccess) {
+          st = CT_E_HIP;
+          note_error(st);
+        }
+        const int64_t now = now_ns();
+        for (auto& r : b.reqs) fin.push_back(Done{r.ticket, r.submit_ns, now, (int32_t)st});
+        ranges.give(b.off, b.bytes);
+        inflight_bytes -= b.bytes;
+        spare_events.push_back(b.ev);
+        q.pop_front();
+        --n_inflight;
       }
-      ct_status st = b.status;
-      if (e != hipSuccess) {
-        st = CT_E_HIP;
-        note_error(st);
-      }
-      const int64_t now = now_ns();
-      for (auto& r : b.reqs) fin.push_back(Done{r.ticket, r.submit_ns, now, (int32_t)st});
-      ranges.give(b.off, b.bytes);
-      inflight_bytes -= b.bytes;
-      spare_events.push_back(b.ev);
     }
-    inflight.resize(keep);
     if (fin.empty()) return false;
     std::lock_guard<std::mutex> g(mu);
     for (auto& d : fin) done.push_back(d);
@@ -279,9 +280,9 @@ struct ct_server {
     for (;;) {
       {
         std::unique_lock<std::mutex> lk(mu);
-        if (inflight.empty() && queued == 0)
+        if (n_inflight == 0 && queued == 0)
           wake.wait(lk, [&] { return stop || !inbox.empty(); });
-        if (stop && inbox.empty() && inflight.empty() && queued == 0) return;
+        if (stop && inbox.empty() && n_inflight == 0 && queued == 0) return;
         got.assign(inbox.begin(), inbox.end());
         inbox.clear();
       }
@@ -321,6 +322,7 @@ ct_status ct_server_create(ct_table* const* tables, int32_t ntables, const ct_se
   s->staging_bytes = staging_bytes / kStageAlign * kStageAlign;
   s->ranges.reset(s->staging_bytes);
   s->queues.resize(ntables);
+  s->inflight.resize(d->streams);
   s->t0 = std::chrono::steady_clock::now();
   ct_status rc = CT_OK;
   if (hipGetDevice(&s->device) != hipSuccess) rc = CT_E_HIP;

@@ -210,6 +210,79 @@ def test_grouped_full_size(dev):
         assert t.size() == o.size()
 
 
+def mixed_kinds_schedule(seed=9, n_tables=12, n_ops=160):
+    """Sets, u32 maps and u64 maps side by side; keys from small universes so that batches hold
+    repeated keys and inserts run into capacity (FULL)."""
+    rng = np.random.default_rng(seed)
+    kinds = [ct.VAL_NONE, ct.VAL_U32, ct.VAL_U64]
+    tables = []
+    for i in range(n_tables):
+        cap = int(rng.integers(40, 3000))
+        tables.append(dict(capacity=cap, kind=kinds[i % 3], universe=int(cap * rng.uniform(0.8, 2.5))))
+    sched = []
+    for _ in range(n_ops):
+        ti = int(rng.integers(0, n_tables))
+        t = tables[ti]
+        kind = ["insert", "find", "erase"][int(rng.choice(3, p=[0.45, 0.35, 0.2]))]
+        n = int(rng.integers(1, 2500))
+        keys = rng.integers(0, t["universe"], size=n).astype(np.uint64) * np.uint64(0x9E3779B97F4A7C15)
+        vals = None
+        if kind == "insert" and t["kind"] != ct.VAL_NONE:
+            hi = 1 << 32 if t["kind"] == ct.VAL_U32 else 1 << 63
+            vals = rng.integers(0, hi, size=n, dtype=np.uint64)
+        sched.append((ti, kind, keys, vals))
+    return tables, sched
+
+
+@pytest.mark.parametrize("chunk", [1024, 4096])
+def test_grouped_mixed_value_kinds_and_capacity(dev, chunk):
+    tables, sched = mixed_kinds_schedule()
+    bits = {ct.VAL_NONE: 0, ct.VAL_U32: 32, ct.VAL_U64: 64}
+    otabs = [oracle.OracleTable(t["capacity"], bits[t["kind"]]) for t in tables]
+    gtabs = [ct.Table(t["capacity"], t["kind"], ct.HASH_MIX64, chunk=chunk, device=dev) for t in tables]
+    p = ct.Plan(device=dev)
+    for g in gtabs:
+        p.add(g, ct.OP_CLEAR)
+    outs, exp = [], []
+    for ti, kind, keys, vals in sched:
+        g, o, vk = gtabs[ti], otabs[ti], tables[ti]["kind"]
+        k = g64(keys, dev)
+        flags = torch.full((keys.size,), 7, dtype=torch.uint8, device=dev)
+        vout = None
+        if kind == "insert":
+            v = None
+            if vk == ct.VAL_U32:
+                v = g32(vals, dev)
+            elif vk == ct.VAL_U64:
+                v = g64(vals, dev)
+            p.add(g, ct.OP_INSERT, keys=k, vals=v, flags_out=flags)
+            exp.append((o.insert(keys, vals), None))
+        elif kind == "find":
+            if vk != ct.VAL_NONE:
+                vout = torch.empty(keys.size, dtype=torch.int32 if vk == ct.VAL_U32 else torch.int64,
+                                   device=dev)
+            p.add(g, ct.OP_FIND, keys=k, vals_out=vout, flags_out=flags)
+            v, f = o.find(keys)
+            exp.append((f, v if vk != ct.VAL_NONE else None))
+        else:
+            p.add(g, ct.OP_ERASE, keys=k, flags_out=flags)
+            exp.append((o.erase(keys), None))
+        outs.append((flags, vout, vk))
+    assert any((e[0] == 2).any() for e, (_, kind, _, _) in zip(exp, sched) if kind == "insert"), \
+        "the schedule should reach capacity"
+    p.group()
+    p.launch_grouped()
+    torch.cuda.synchronize()
+    for (flags, vout, vk), (ef, ev) in zip(outs, exp):
+        np.testing.assert_array_equal(flags.cpu().numpy(), ef)
+        if ev is not None:
+            got = vout.cpu().numpy().view(np.uint32 if vk == ct.VAL_U32 else np.uint64)
+            np.testing.assert_array_equal(got, ev)
+    for g, o in zip(gtabs, otabs):
+        assert g.size() == o.size()
+        assert g.check() == 0
+
+
 @pytest.mark.skip(reason="a single persistent launch with in-kernel dependency waits between work "
                          "items faulted the GPU on its first run; its cause was not found and the "
                          "executor was removed (see DESIGN.md)")
