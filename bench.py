@@ -189,7 +189,8 @@ def main():
     a = parse()
     if a.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {a.gpus} is not supported "
-              "(the container path is single-GPU; sharding is described in DESIGN.md)",
+              "(the container path runs on a single GPU; tables would shard by key hash across "
+              "GPUs, which this library does not do)",
               file=sys.stderr)
         sys.exit(2)
     import torch

@@ -285,6 +285,6 @@ def test_grouped_mixed_value_kinds_and_capacity(dev, chunk):
 
 @pytest.mark.skip(reason="a single persistent launch with in-kernel dependency waits between work "
                          "items faulted the GPU on its first run; its cause was not found and the "
-                         "executor was removed (see DESIGN.md)")
+                         "executor was removed; the grouped plan form replaces it")
 def test_persistent_single_launch_executor():
     pass
