@@ -172,6 +172,19 @@ def cpu_baseline(shift, seed=3):
     o.erase(w["erase"])
     o.insert(w["reinsert_keys"], w["reinsert_vals"])
     dt = time.perf_counter() - t0
+    del o
+    # the same sample on all host cores available to this process (up to 16): partitioned by key
+    # hash, one oracle table and thread per partition, index order kept within each partition
+    parts = max(1, min(16, len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity")
+                      else os.cpu_count() or 1))
+    po = oracle.PartitionedOracle(w["capacity"], parts)
+    t1 = time.perf_counter()
+    po.insert(w["insert_keys"], w["insert_vals"])
+    po.find(w["find"])
+    po.erase(w["erase"])
+    po.insert(w["reinsert_keys"], w["reinsert_vals"])
+    dtp = time.perf_counter() - t1
+    del po
     return {
         "value": ops / dt / 1e6,
         "unit": "Mops/s",
@@ -182,6 +195,9 @@ def cpu_baseline(shift, seed=3):
                    f"re-insert 2^{24 - shift}; {ops} ops in {dt:.2f} s, single thread"),
         "host_cpu": platform.processor() or platform.machine(),
         "host_threads_available": os.cpu_count(),
+        "partitioned": {"value": ops / dtp / 1e6, "unit": "Mops/s", "cores": parts,
+                        "kind": "oracle tables partitioned by key hash, one thread each",
+                        "seconds": dtp},
     }
 
 
@@ -342,6 +358,27 @@ def main():
         "kernels": kernels,
         "roofline": roof,
     }
+    # the find again with uniform popularity (80 % live keys drawn uniformly, 20 % absent): no
+    # hot buckets, so it is compared with the uniform gather ceiling R1
+    op_clear()
+    op_fill()
+    g = torch.Generator(device=dev)
+    g.manual_seed(7)
+    n_hit = n_present_expected
+    idx = torch.randint(0, n_fill, (n_hit,), device=dev, generator=g)
+    absent = torch.randint(-(1 << 62), 1 << 62, (n_find - n_hit,), device=dev, generator=g)
+    QU = torch.cat([K_fill[idx], absent])[torch.randperm(n_find, device=dev, generator=g)]
+    del idx, absent
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ts = []
+    for _ in range(3):
+        e0.record()
+        ct._check(L.ct_find_batch(h, P(QU), n_find, P(vals_out), P(found), s), "find uniform")
+        e1.record()
+        torch.cuda.synchronize()
+        ts.append(e0.elapsed_time(e1) * 1e-3)
+    line["find_uniform_Mops_s"] = n_find / float(np.median(ts)) / 1e6
+    del QU
     if not a.no_ceilings:
         rng = np.random.default_rng(99)
         uni = torch.from_numpy(rng.integers(0, 1 << 63, size=n_find, dtype=np.int64)).to(dev)
@@ -353,6 +390,7 @@ def main():
         ceil["find_frac_of_R1"] = f_mops / ceil["R1_gather128_Mlines_s"]
         ceil["find_frac_of_R5"] = f_mops / ceil["R5_find_stream_Mlines_s"]
         ceil["insert_frac_of_R2"] = i_mops / ceil["R2_gather128_cas_Mops_s"]
+        ceil["find_uniform_frac_of_R1"] = line["find_uniform_Mops_s"] / ceil["R1_gather128_Mlines_s"]
         line["random_access"] = ceil
     if not a.no_voxel:
         from paper_1908_05936_amd import bench_voxel

@@ -12,6 +12,8 @@ Parity status of each function (what pins it is in the test suite):
                                                decomposition, 21-bit field independence
   mix64 hash                                   decides bucket membership only; results do not
                                                depend on it (checked by a hash-swap test)
+  partitioned multi-core replay                timing baseline only; checked equal to the
+                                               sequential replay (per-key independence)
 """
 from __future__ import annotations
 
@@ -23,6 +25,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "oracle.c")
+_SRC_PART = os.path.join(_HERE, "partitioned.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
 PRESENT, INSERTED, FULL = 0, 1, 2
@@ -34,7 +37,8 @@ _lib = None
 def build(force: bool = True) -> str:
     """Compile ``oracle.c`` with gcc into ``liboracle.so`` next to it."""
     if force or not os.path.exists(_LIB):
-        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", _SRC, "-o", _LIB])
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-pthread", _SRC,
+                               _SRC_PART, "-o", _LIB])
     return _LIB
 
 
@@ -60,6 +64,12 @@ def lib():
             "or_pool_new": (P, [I64]),
             "or_pool_free": (None, [P]),
             "or_pool_size": (I64, [P]),
+            "or_part_new": (P, [I64, I, C.c_double]),
+            "or_part_free": (None, [P]),
+            "or_part_size": (I64, [P]),
+            "or_part_insert": (I, [P, P, P, I64, P]),
+            "or_part_find": (I, [P, P, I64, P, U64, P]),
+            "or_part_erase": (I, [P, P, I64, P]),
             "or_pool_dump": (I64, [P, P, I64]),
             "or_pool_pop": (None, [P, I64, P, P]),
             "or_pool_push": (None, [P, P, I64, P]),
@@ -92,6 +102,48 @@ def voxel21_hash(key: int) -> int:
 
 def fmix64(key: int) -> int:
     return int(lib().or_fmix64(int(key)))
+
+
+class PartitionedOracle:
+    """Multi-core timing baseline: `parts` oracle tables, one thread each, keys split by hash
+    (``partitioned.c``).  u64 values.  Results equal the sequential replay while no partition
+    fills up (each gets `slack` times its share of the capacity)."""
+
+    def __init__(self, capacity: int, parts: int, slack: float = 1.25):
+        self.parts = int(parts)
+        self._h = lib().or_part_new(int(capacity), self.parts, float(slack))
+        if not self._h:
+            raise MemoryError("partitioned oracle allocation failed")
+
+    def __del__(self):
+        if getattr(self, "_h", None):
+            lib().or_part_free(self._h)
+            self._h = None
+
+    def size(self) -> int:
+        return int(lib().or_part_size(self._h))
+
+    def insert(self, keys, vals) -> np.ndarray:
+        k, v = _u64(keys), _u64(vals)
+        st = np.empty(k.size, dtype=np.uint8)
+        if lib().or_part_insert(self._h, _ptr(k), _ptr(v), k.size, _ptr(st)):
+            raise MemoryError("partitioned insert")
+        return st
+
+    def find(self, keys):
+        k = _u64(keys)
+        out = np.empty(k.size, dtype=np.uint64)
+        fd = np.empty(k.size, dtype=np.uint8)
+        if lib().or_part_find(self._h, _ptr(k), k.size, _ptr(out), (1 << 64) - 1, _ptr(fd)):
+            raise MemoryError("partitioned find")
+        return out, fd
+
+    def erase(self, keys) -> np.ndarray:
+        k = _u64(keys)
+        er = np.empty(k.size, dtype=np.uint8)
+        if lib().or_part_erase(self._h, _ptr(k), k.size, _ptr(er)):
+            raise MemoryError("partitioned erase")
+        return er
 
 
 class OraclePool:

@@ -275,3 +275,23 @@ def test_results_do_not_depend_on_layout():
         if ref is None:
             ref = res
         assert res == ref
+
+
+def test_partitioned_baseline_equals_sequential_replay():
+    """The multi-core timing baseline gives the sequential oracle's results (keys never interact,
+    so splitting them by hash keeps every per-key history) while no partition fills up."""
+    rng = np.random.default_rng(11)
+    keys = rng.integers(0, 1 << 20, size=60000, dtype=np.uint64)   # many repeated keys
+    vals = rng.integers(0, 1 << 62, size=keys.size, dtype=np.uint64)
+    o = oracle.OracleTable(80000, 64)
+    for parts in (1, 3, 8):
+        p = oracle.PartitionedOracle(80000, parts)
+        o.clear()
+        np.testing.assert_array_equal(p.insert(keys, vals), o.insert(keys, vals))
+        q = np.concatenate([keys[:3000], rng.integers(0, 1 << 20, size=3000, dtype=np.uint64)])
+        (pv, pf), (ov, of) = p.find(q), o.find(q)
+        np.testing.assert_array_equal(pf, of)
+        np.testing.assert_array_equal(pv, ov)
+        e = keys[rng.integers(0, keys.size, size=9000)]
+        np.testing.assert_array_equal(p.erase(e), o.erase(e))
+        assert p.size() == o.size()
