@@ -271,15 +271,19 @@ __device__ __forceinline__ void group_probe(const TableView& t, uint64_t key, ui
                                             uint64_t* mypos, uint64_t* myval, uint64_t* myfb,
                                             int* myc, uint64_t* myexp, uint64_t* mystep) {
   const int gb = group_base();
-  uint64_t kk[kSlots], b[kSlots], st[kSlots];
+  // bucket indices and strides fit 32 bits (fewer than 2^31 buckets): half the registers and
+  // shuffles of 64-bit copies
+  uint64_t kk[kSlots];
+  uint32_t b[kSlots], st[kSlots];
   Slot sl[kSlots];
   Seq mine = {0, 0};
   if ((A >> sub) & 1) mine = probe_seq(t, key);  // each lane hashes its own key once
+  const uint32_t nb32 = (uint32_t)t.nb;
 #pragma unroll
   for (int u = 0; u < kSlots; ++u) {
     kk[u] = __shfl(key, gb + u, 64);
-    b[u] = __shfl(mine.home, gb + u, 64);
-    st[u] = __shfl(mine.step, gb + u, 64);
+    b[u] = (uint32_t)__shfl((uint32_t)mine.home, gb + u, 64);
+    st[u] = (uint32_t)__shfl((uint32_t)mine.step, gb + u, 64);
   }
   uint32_t live = A, fnd = 0, he = 0, frb = 0;
   for (uint64_t round = 0; live && round < t.nb; ++round) {
@@ -296,7 +300,7 @@ __device__ __forceinline__ void group_probe(const TableView& t, uint64_t key, ui
         const int c = lowest(m);
         const uint64_t v = __shfl(sl[u].val, gb + c, 64);
         if (sub == u) {
-          *mypos = b[u] * kSlots + (uint64_t)c;
+          *mypos = (uint64_t)b[u] * kSlots + (uint64_t)c;
           *myval = v;
         }
         fnd |= 1u << u;
@@ -317,8 +321,12 @@ __device__ __forceinline__ void group_probe(const TableView& t, uint64_t key, ui
           }
         }
       }
-      if (e) live &= ~(1u << u);
-      else b[u] = next_bucket(t, b[u], st[u]);
+      if (e) {
+        live &= ~(1u << u);
+      } else {
+        const uint32_t nx = b[u] + st[u];   // < 2^32: both terms are below 2^31
+        b[u] = nx >= nb32 ? nx - nb32 : nx;
+      }
     }
   }
   *found = fnd;
@@ -1155,7 +1163,7 @@ bool make_layout(const ct_table_desc* d, Layout* L) {
   int64_t nb = d->bucket_count;
   if (nb == 0) nb = next_prime(std::max<int64_t>(1, (d->capacity + kSlots - 1) / kSlots));
   if (nb < 1) nb = 1;
-  if (nb > ((int64_t)1 << 40)) return false;
+  if (nb >= ((int64_t)1 << 31)) return false;  // 32-bit bucket arithmetic in the probes
   if (nb * kSlots < d->capacity) return false;
   int64_t q = d->chunk;
   if (q == 0) {
@@ -1218,13 +1226,17 @@ void launch(ct_table* t, int kind, hipStream_t s, F&& f) {
   if (t && t->prof.on) {
     Profiler& P = t->prof;
     if (P.used + 2 > P.events.size()) prof_drain(P);
-    hipEventRecord(P.events[P.used], s);
-    end = P.events[P.used + 1];
-    P.kinds.push_back(kind);
-    P.used += 2;
+    if (hipEventRecord(P.events[P.used], s) == hipSuccess) {  // else this launch goes untimed
+      end = P.events[P.used + 1];
+      P.kinds.push_back(kind);
+      P.used += 2;
+    }
   }
   f();
-  if (end) hipEventRecord(end, s);
+  if (end && hipEventRecord(end, s) != hipSuccess) {  // drop the half-recorded pair
+    t->prof.kinds.pop_back();
+    t->prof.used -= 2;
+  }
 }
 
 int group_blocks(int64_t n) {
@@ -1377,7 +1389,7 @@ ct_status ct_table_init(void* d_buf, int64_t bytes, const ct_table_desc* d, void
 
 ct_status ct_table_destroy(ct_table* t) {
   if (!t) return CT_E_INVALID;
-  for (hipEvent_t e : t->prof.events) hipEventDestroy(e);
+  for (hipEvent_t e : t->prof.events) (void)hipEventDestroy(e);
   delete t;
   return CT_OK;
 }
@@ -1888,8 +1900,8 @@ ct_status ct_plan_create(ct_plan** out) {
 
 ct_status ct_plan_destroy(ct_plan* p) {
   if (!p) return CT_E_INVALID;
-  for (hipStream_t s : p->side) hipStreamDestroy(s);
-  for (hipEvent_t e : p->ev) hipEventDestroy(e);
+  for (hipStream_t s : p->side) (void)hipStreamDestroy(s);
+  for (hipEvent_t e : p->ev) (void)hipEventDestroy(e);
   delete p;
   return CT_OK;
 }
@@ -1947,12 +1959,12 @@ ct_status ct_plan_capture(ct_plan* p, int32_t lanes, void* stream, void** graph_
   hipGraph_t g = nullptr;
   const hipError_t e = hipStreamEndCapture(s, &g);
   if (r != CT_OK || e != hipSuccess) {
-    if (g) hipGraphDestroy(g);
+    if (g) (void)hipGraphDestroy(g);
     return r != CT_OK ? r : CT_E_HIP;
   }
   hipGraphExec_t x = nullptr;
   const hipError_t ie = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
-  hipGraphDestroy(g);
+  (void)hipGraphDestroy(g);
   if (ie != hipSuccess) return CT_E_HIP;
   *graph_exec = x;
   return CT_OK;
@@ -1966,12 +1978,12 @@ ct_status ct_plan_capture_grouped(ct_plan* p, void* stream, void** graph_exec) {
   hipGraph_t g = nullptr;
   const hipError_t e = hipStreamEndCapture(s, &g);
   if (r != CT_OK || e != hipSuccess) {
-    if (g) hipGraphDestroy(g);
+    if (g) (void)hipGraphDestroy(g);
     return r != CT_OK ? r : CT_E_HIP;
   }
   hipGraphExec_t x = nullptr;
   const hipError_t ie = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
-  hipGraphDestroy(g);
+  (void)hipGraphDestroy(g);
   if (ie != hipSuccess) return CT_E_HIP;
   *graph_exec = x;
   return CT_OK;

@@ -149,3 +149,31 @@ def test_sweep_runs_and_reports(dev):
         assert p["requests"] == 100
         assert 0 < p["p50_ms"] <= p["p99_ms"]
         assert p["peak_inflight_batches"] <= res["max_inflight"]
+
+
+def test_full_size_serving_sampled_tables(dev):
+    """The 64-table workload at full size (about 42 GB of tables): 600 requests served under
+    Poisson arrivals with the default budget; three tables (the smallest and largest that received
+    requests, and the table of the first request) are replayed through the oracle in full --
+    their resident halves, then every one of their requests -- and compared bit-exact."""
+    from paper_1908_05936_amd.serve import headroom_for, serving_chunk
+    sv = Serving(seed=5)
+    head = headroom_for(sv, 40e9)
+    print("serving full: building tables", flush=True)
+    tables = build_tables(sv, dev, headroom=head, chunk=serving_chunk())
+    reqs = draw(sv, 600)
+    srv = Server(tables, dev)
+    print("serving full: serving", flush=True)
+    st = srv.run(reqs, poisson_arrivals(np.random.default_rng(2), len(reqs), 5000.0))
+    srv.close()
+    assert st["error"] == 0 and st["completed"] == len(reqs)
+    used = sorted({r.table for r in reqs}, key=lambda t: sv.entries[t])
+    pick = sorted({used[0], used[-1], reqs[0].table})
+    for t in pick:
+        print(f"serving full: oracle replay of table {t} ({sv.entries[t]} resident)", flush=True)
+        e, u = sv.entries[t], sv.universe[t]
+        o = oracle.OracleTable(int(u * head), 64, oracle.HASH_MIX64, u)
+        o.insert(sv.resident(t, 0, e), np.arange(e, dtype=np.uint64))
+        mine = [r for r in reqs if r.table == t]
+        check_same(mine, replay([o if i == t else None for i in range(len(sv.entries))], mine))
+        assert tables[t].size() == o.size()
