@@ -36,6 +36,12 @@ constexpr uint64_t kNoPos = ~0ull;
 constexpr uint64_t kSpecRef = ~0ull - 3;  // refs kSpecRef+0/+1 name the out-of-band keys
 constexpr int kTile = 1024;             // elements per tile of the rank scan
 constexpr int kBlock = 256;             // threads per block of every group kernel
+constexpr int64_t kBinMinChunk = 1 << 16; // chunks at least this large dedup through bins
+constexpr int kBinFine = 1024;          // mean elements per fine bin
+constexpr int kBinCoarse = 64;          // coarse bins
+constexpr int kBinTile = 4096;          // elements per block of the scatter kernels
+constexpr int kBinLds = 4096;           // LDS hash slots of the fine-bin dedup (> 2 x mean + 256)
+constexpr int kMaxFinePerCoarse = 256;  // fine bins per coarse bin at the largest chunk (2^24)
 
 enum : uint8_t { kPresent = 0, kInserted = 1, kFull = 2, kNoStatus = 0xFF };
 enum : uint32_t { kErrFull = 1u, kErrPool = 2u, kErrInternal = 0x80000000u };
@@ -61,6 +67,8 @@ struct alignas(256) Header {
   uint64_t dump_count;
   uint64_t live_count;
   uint64_t violations;
+  uint32_t dmode;          // 1: the chunk's repeated keys were resolved by bins (dfirst valid)
+  uint32_t dovf;           // 1: a bin of the current chunk overflowed; the chunk uses dd instead
 };
 
 struct alignas(256) PoolHeader {
@@ -83,6 +91,17 @@ struct TableView {
   uint64_t* ref;    // per chunk element: claimed slot, or the value an erase releases
   uint32_t* tsum;   // per tile: flagged count, then its exclusive prefix
   int64_t* bcnt;    // per block of the last insert/erase kernel: change of the live count
+  // binned dedup (chunks of at least kBinMinChunk elements): elements are scattered by a hash of
+  // their key into P1 coarse bins, then into P = P1 * P2 fine bins, and each fine bin resolves its
+  // repeated keys in LDS.  dd aliases r1k: it is needed only when a bin overflows.
+  uint64_t* r1k;    // coarse bins: keys, P1 x c1
+  uint32_t* r1i;    //              chunk indices
+  uint64_t* r2k;    // fine bins: keys, P x c2
+  uint32_t* r2i;
+  uint32_t* bcur;   // fill counts: P1 coarse, then P fine
+  uint32_t* dfirst; // per repeated element: index of its key's first occurrence
+  uint32_t c1, c2;  // bin capacities
+  int lp1, lp;      // log2 of P1 and of P
   int hash;         // 0 mix64, 1 voxel21
   int nb_pow2;
   int step_mode;    // probe step between buckets: 0 linear (1), 1 odd (nb a power of two),

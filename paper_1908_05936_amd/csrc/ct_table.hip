@@ -180,6 +180,25 @@ __device__ __forceinline__ int64_t prologue_units(uint32_t dslots, int64_t q) {
   return (int64_t)dslots / 2 + (q + 15) / 16;
 }
 
+// Per-chunk counters: snapshot size (and pool top), reset the chunk's lists, decide whether the
+// chunk can reach capacity (or empty the pool), and record how repeated keys are resolved.
+__device__ __forceinline__ void chunk_header(const TableView& t, PoolHeader* pool, int64_t q,
+                                             uint32_t dmode) {
+  Header* h = t.hdr;
+  h->size0 = h->size;
+  h->spec_first[0] = h->spec_first[1] = kNone;
+  h->ndup = 0;
+  h->nnew = 0;
+  bool fast = h->size + (uint64_t)q <= t.cap;
+  if (pool) {
+    pool->top0 = pool->top;
+    fast = fast && pool->top >= q;
+  }
+  h->fast = fast ? 1u : 0u;
+  h->dmode = dmode;
+  h->dovf = 0;
+}
+
 __device__ __forceinline__ void prologue_range(const TableView& t, PoolHeader* pool,
                                                uint32_t dslots, int64_t q, int64_t lo, int64_t hi,
                                                int64_t step, bool header) {
@@ -189,19 +208,7 @@ __device__ __forceinline__ void prologue_range(const TableView& t, PoolHeader* p
     if (j < nd) reinterpret_cast<uint4*>(t.dd)[j] = empty;
     else reinterpret_cast<uint4*>(t.dmark)[j - nd] = make_uint4(0, 0, 0, 0);
   }
-  if (header && threadIdx.x == 0) {
-    Header* h = t.hdr;
-    h->size0 = h->size;
-    h->spec_first[0] = h->spec_first[1] = kNone;
-    h->ndup = 0;
-    h->nnew = 0;
-    bool fast = h->size + (uint64_t)q <= t.cap;
-    if (pool) {
-      pool->top0 = pool->top;
-      fast = fast && pool->top >= q;
-    }
-    h->fast = fast ? 1u : 0u;
-  }
+  if (header && threadIdx.x == 0) chunk_header(t, pool, q, 0u);
 }
 
 __global__ __launch_bounds__(kBlock) void k_prologue(TableView t, PoolHeader* pool,
@@ -251,12 +258,212 @@ __global__ __launch_bounds__(kBlock) void k_dedup(TableView t, const uint64_t* _
   dedup_range(t, keys, dmask, (int64_t)blockIdx.x * kBlock, q, (int64_t)gridDim.x * kBlock);
 }
 
+// ---------------------------------------------------------------------------------------------
+// Binned dedup: the same marks as dedup_range (every element of a key that occurs more than once
+// in the chunk), plus each marked element's first occurrence in dfirst, without a device-scope
+// atomic per element.  Keys move into 64 coarse bins and then into P fine bins by the high bits
+// of dedup_mix, so all copies of a key share a fine bin; each fine bin (about 1024 elements)
+// finds its repeated keys in an LDS hash table.  The only global atomics reserve room in a bin,
+// one per block and non-empty bin.  A bin that would overflow its capacity sets dovf; the chunk
+// then clears dd and runs dedup_range instead, so results never depend on the key distribution.
+// ---------------------------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t fine_bin(const TableView& t, uint64_t mix) {
+  return (uint32_t)(mix >> (64 - t.lp));
+}
+
+// Units [lo, hi) of a binned chunk's prologue: the marks (16 per unit), then the bin counts
+// (4 per unit); `header` also takes the chunk's counter snapshot.
+__device__ __forceinline__ int64_t bin_prologue_units(const TableView& t, int64_t q) {
+  return (q + 15) / 16 + (((int64_t)1 << t.lp1) + ((int64_t)1 << t.lp)) / 4;
+}
+
+__global__ __launch_bounds__(kBlock) void k_bin_prologue(TableView t, PoolHeader* pool, int64_t q) {
+  const int64_t nm = (q + 15) / 16;
+  const int64_t hi = bin_prologue_units(t, q);
+  const uint4 zero = make_uint4(0, 0, 0, 0);
+  for (int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x; j < hi; j += (int64_t)gridDim.x * kBlock) {
+    if (j < nm) reinterpret_cast<uint4*>(t.dmark)[j] = zero;
+    else reinterpret_cast<uint4*>(t.bcur)[j - nm] = zero;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) chunk_header(t, pool, q, 1u);
+}
+
+// Coarse scatter: block b takes elements [b * kBinTile, (b + 1) * kBinTile), ranks them within
+// their coarse bin in LDS, reserves one run per non-empty bin, and writes (key, index) pairs.
+// The out-of-band keys take their lowest index directly, as in dedup_range.
+__global__ __launch_bounds__(kBlock) void k_bin_scatter1(TableView t, const uint64_t* __restrict__ keys,
+                                                         int64_t q) {
+  constexpr int kPer = kBinTile / kBlock;
+  __shared__ uint32_t cnt[kBinCoarse];
+  __shared__ uint32_t base[kBinCoarse];
+  const int64_t t0 = (int64_t)blockIdx.x * kBinTile;
+  if (threadIdx.x < kBinCoarse) cnt[threadIdx.x] = 0;
+  __syncthreads();
+  uint64_t k[kPer];
+  uint32_t code[kPer];  // rank << 8 | coarse bin, or ~0 for no element
+#pragma unroll
+  for (int e = 0; e < kPer; ++e) {
+    const int64_t i = t0 + e * kBlock + threadIdx.x;
+    code[e] = ~0u;
+    k[e] = 0;
+    if (i < q) {
+      k[e] = keys[i];
+      if (k[e] >= kTomb) {
+        amin32(&t.hdr->spec_first[k[e] - kTomb], (uint32_t)i);
+      } else {
+        const uint32_t b = (uint32_t)(dedup_mix(k[e]) >> (64 - t.lp1));
+        code[e] = (atomicAdd(&cnt[b], 1u) << 8) | b;
+      }
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x < kBinCoarse) {
+    const uint32_t c = cnt[threadIdx.x];
+    uint32_t o = 0;
+    if (c) {
+      o = aadd32(&t.bcur[threadIdx.x], c);
+      if (o + c > t.c1) t.hdr->dovf = 1u;
+    }
+    base[threadIdx.x] = o;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int e = 0; e < kPer; ++e) {
+    if (code[e] == ~0u) continue;
+    const uint32_t b = code[e] & 0xFFu;
+    const uint32_t pos = base[b] + (code[e] >> 8);
+    if (pos < t.c1) {
+      const int64_t at = (int64_t)b * t.c1 + pos;
+      t.r1k[at] = k[e];
+      t.r1i[at] = (uint32_t)(t0 + e * kBlock + threadIdx.x);
+    }
+  }
+}
+
+// Fine scatter: block (coarse bin b, tile) moves that tile of bin b into its 2^(lp - lp1) fine
+// bins, the same way.
+__global__ __launch_bounds__(kBlock) void k_bin_scatter2(TableView t, int tiles_per_bin) {
+  if (t.hdr->dovf) return;
+  constexpr int kPer = kBinTile / kBlock;
+  __shared__ uint32_t cnt[kMaxFinePerCoarse];
+  __shared__ uint32_t base[kMaxFinePerCoarse];
+  const int b = (int)blockIdx.x / tiles_per_bin;
+  const uint32_t j0 = (uint32_t)((int)blockIdx.x % tiles_per_bin) * kBinTile;
+  const uint32_t n1 = min(t.bcur[b], t.c1);
+  if (j0 >= n1) return;
+  const int lp2 = t.lp - t.lp1;
+  const uint32_t p2 = 1u << lp2;
+  for (uint32_t j = threadIdx.x; j < p2; j += kBlock) cnt[j] = 0;
+  __syncthreads();
+  const int64_t src = (int64_t)b * t.c1;
+  uint64_t k[kPer];
+  uint32_t idx[kPer], code[kPer];  // rank << 8 | fine bin within the coarse bin
+#pragma unroll
+  for (int e = 0; e < kPer; ++e) {
+    const uint32_t j = j0 + e * kBlock + threadIdx.x;
+    code[e] = ~0u;
+    k[e] = 0;
+    idx[e] = 0;
+    if (j < n1) {
+      k[e] = t.r1k[src + j];
+      idx[e] = t.r1i[src + j];
+      const uint32_t f2 = fine_bin(t, dedup_mix(k[e])) & (p2 - 1u);
+      code[e] = (atomicAdd(&cnt[f2], 1u) << 8) | f2;
+    }
+  }
+  __syncthreads();
+  for (uint32_t j = threadIdx.x; j < p2; j += kBlock) {
+    const uint32_t c = cnt[j];
+    uint32_t o = 0;
+    if (c) {
+      o = aadd32(&t.bcur[(1u << t.lp1) + ((uint32_t)b << lp2) + j], c);
+      if (o + c > t.c2) t.hdr->dovf = 1u;
+    }
+    base[j] = o;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int e = 0; e < kPer; ++e) {
+    if (code[e] == ~0u) continue;
+    const uint32_t f2 = code[e] & 0xFFu;
+    const uint32_t pos = base[f2] + (code[e] >> 8);
+    if (pos < t.c2) {
+      const int64_t at = (int64_t)(((uint32_t)b << lp2) | f2) * t.c2 + pos;
+      t.r2k[at] = k[e];
+      t.r2i[at] = idx[e];
+    }
+  }
+}
+
+// One fine bin per block: insert its keys into an LDS table (CAS on the key word, atomic min on
+// the index, a flag when a key arrives again), then mark every element of a repeated key and
+// give it the key's lowest index.  A bin holds at most c2 < kBinLds elements, so every probe
+// finds a free or matching slot.
+__global__ __launch_bounds__(kBlock) void k_bin_dedup(TableView t) {
+  if (t.hdr->dovf) return;
+  __shared__ unsigned long long hk[kBinLds];
+  __shared__ uint32_t hm[kBinLds];
+  __shared__ uint8_t hx[kBinLds];
+  const uint32_t f = blockIdx.x;
+  const uint32_t n = min(t.bcur[(1u << t.lp1) + f], t.c2);
+  for (uint32_t j = threadIdx.x; j < (uint32_t)kBinLds; j += kBlock) {
+    hk[j] = kEmpty;
+    hm[j] = kNone;
+    hx[j] = 0;
+  }
+  __syncthreads();
+  const uint64_t* rk = t.r2k + (int64_t)f * t.c2;
+  const uint32_t* ri = t.r2i + (int64_t)f * t.c2;
+  for (uint32_t j = threadIdx.x; j < n; j += kBlock) {
+    const uint64_t key = rk[j];
+    uint32_t s = (uint32_t)dedup_mix(key) & (kBinLds - 1);
+    for (;;) {
+      const unsigned long long old = atomicCAS(&hk[s], (unsigned long long)kEmpty,
+                                               (unsigned long long)key);
+      if (old == kEmpty || old == key) {
+        if (old == key) hx[s] = 1;
+        atomicMin(&hm[s], ri[j]);
+        break;
+      }
+      s = (s + 1) & (kBinLds - 1);
+    }
+  }
+  __syncthreads();
+  for (uint32_t j = threadIdx.x; j < n; j += kBlock) {
+    const uint64_t key = rk[j];
+    uint32_t s = (uint32_t)dedup_mix(key) & (kBinLds - 1);
+    while (hk[s] != key) s = (s + 1) & (kBinLds - 1);
+    if (hx[s]) {
+      const uint32_t i = ri[j];
+      t.dmark[i] = 1;
+      t.dfirst[i] = hm[s];
+    }
+  }
+}
+
+// Overflow path: clear dd (it aliases the coarse bins) and switch the chunk to dedup_range.
+__global__ __launch_bounds__(kBlock) void k_bin_fallback_clear(TableView t, uint32_t dslots) {
+  if (!t.hdr->dovf) return;
+  const uint4 empty = make_uint4(0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu);
+  for (int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x; j < (int64_t)dslots / 2;
+       j += (int64_t)gridDim.x * kBlock)
+    reinterpret_cast<uint4*>(t.dd)[j] = empty;
+  if (blockIdx.x == 0 && threadIdx.x == 0) t.hdr->dmode = 0;
+}
+
+__global__ __launch_bounds__(kBlock) void k_bin_fallback_dedup(TableView t,
+                                                               const uint64_t* __restrict__ keys,
+                                                               int64_t q, uint32_t dmask) {
+  if (!t.hdr->dovf) return;
+  dedup_range(t, keys, dmask, (int64_t)blockIdx.x * kBlock, q, (int64_t)gridDim.x * kBlock);
+}
+
 // Index-order role of this lane's element: its own index when it is the first copy of its key in
 // the chunk, else the index of that first copy.
 __device__ __forceinline__ uint32_t first_copy(const TableView& t, const uint64_t* keys,
                                                uint64_t key, int64_t i, uint32_t dmask) {
   if (key >= kTomb) return t.hdr->spec_first[key - kTomb];
-  if (t.dmark[i]) return dedup_lookup(t, keys, key, dmask, (uint32_t)i);
+  if (t.dmark[i]) return t.hdr->dmode ? t.dfirst[i] : dedup_lookup(t, keys, key, dmask, (uint32_t)i);
   return (uint32_t)i;
 }
 
@@ -1155,7 +1362,14 @@ int64_t pow2ceil(int64_t x) {
 struct Layout {
   int64_t nb, chunk, dslots, ntiles;
   int64_t off_bk, off_dd, off_dmark, off_dup, off_flag, off_ref, off_tsum, off_bcnt, total;
+  // binned dedup (chunk >= kBinMinChunk; otherwise bins == false and the offsets are unused)
+  bool bins;
+  int64_t nfine, c1, c2;
+  int lp, lp1;
+  int64_t off_r1k, off_r1i, off_r2k, off_r2i, off_bcur, off_dfirst;
 };
+
+static_assert(2 * kBinFine + 256 < kBinLds, "a fine bin must fit the LDS table");
 
 bool make_layout(const ct_table_desc* d, Layout* L) {
   if (!d || d->capacity < 0) return false;
@@ -1181,8 +1395,33 @@ bool make_layout(const ct_table_desc* d, Layout* L) {
   int64_t off = align_up((int64_t)sizeof(Header));
   L->off_bk = off;
   off = align_up(off + nb * (int64_t)sizeof(Bucket));
-  L->off_dd = off;
-  off = align_up(off + L->dslots * 8);
+  L->bins = q >= kBinMinChunk;
+  if (L->bins) {
+    L->nfine = q / kBinFine;
+    L->lp = 0;
+    while (((int64_t)1 << L->lp) < L->nfine) ++L->lp;
+    L->lp1 = 0;
+    while ((1 << L->lp1) < kBinCoarse) ++L->lp1;
+    L->c1 = 2 * (q / kBinCoarse) + kBinTile;
+    L->c2 = 2 * kBinFine + 256;
+    if (L->nfine / kBinCoarse > kMaxFinePerCoarse) return false;
+    L->off_r1k = off;  // also dd, which needs 16 bytes per chunk element: c1 * 64 * 8 is more
+    L->off_dd = off;
+    off = align_up(off + kBinCoarse * L->c1 * 8);
+    L->off_r1i = off;
+    off = align_up(off + kBinCoarse * L->c1 * 4);
+    L->off_r2k = off;
+    off = align_up(off + L->nfine * L->c2 * 8);
+    L->off_r2i = off;
+    off = align_up(off + L->nfine * L->c2 * 4);
+    L->off_bcur = off;
+    off = align_up(off + (kBinCoarse + L->nfine) * 4);
+    L->off_dfirst = off;
+    off = align_up(off + q * 4);
+  } else {
+    L->off_dd = off;
+    off = align_up(off + L->dslots * 8);
+  }
   L->off_dmark = off;
   off = align_up(off + q);
   L->off_dup = off;
@@ -1239,6 +1478,10 @@ void launch(ct_table* t, int kind, hipStream_t s, F&& f) {
   }
 }
 
+int64_t bin_prologue_units_host(const TableView& v, int64_t q) {
+  return (q + 15) / 16 + (((int64_t)1 << v.lp1) + ((int64_t)1 << v.lp)) / 4;
+}
+
 int group_blocks(int64_t n) {
   const int64_t b = (n + (kBlock / 8) - 1) / (kBlock / 8);
   return (int)std::max<int64_t>(1, std::min<int64_t>(b, kMaxGroupBlocks));
@@ -1263,6 +1506,25 @@ ct_status read_back(const T* dev, T* host, hipStream_t s) {
 // ---------------------------------------------------------------------------------------------
 // insert / erase drivers
 // ---------------------------------------------------------------------------------------------
+// Resolve the repeated keys of one chunk: binned for large chunks, dd otherwise.
+void dedup_chunk(ct_table* t, PoolHeader* pool, const uint64_t* kc, int64_t q, hipStream_t s) {
+  const uint32_t db = dedup_slots_for(q);
+  if (t->v.r1k && q >= kBinMinChunk) {
+    const TableView& v = t->v;
+    const int tiles_per_bin = (int)((v.c1 + kBinTile - 1) / kBinTile);
+    const int nfine = 1 << v.lp;
+    launch(t, CT_KERNEL_PROLOGUE, s, [&] { k_bin_prologue<<<flat_blocks(bin_prologue_units_host(v, q)), kBlock, 0, s>>>(v, pool, q); });
+    launch(t, CT_KERNEL_DEDUP, s, [&] { k_bin_scatter1<<<(int)((q + kBinTile - 1) / kBinTile), kBlock, 0, s>>>(v, kc, q); });
+    launch(t, CT_KERNEL_DEDUP, s, [&] { k_bin_scatter2<<<kBinCoarse * tiles_per_bin, kBlock, 0, s>>>(v, tiles_per_bin); });
+    launch(t, CT_KERNEL_DEDUP, s, [&] { k_bin_dedup<<<nfine, kBlock, 0, s>>>(v); });
+    launch(t, CT_KERNEL_DEDUP, s, [&] { k_bin_fallback_clear<<<flat_blocks(db / 2), kBlock, 0, s>>>(v, db); });
+    launch(t, CT_KERNEL_DEDUP, s, [&] { k_bin_fallback_dedup<<<flat_blocks(q), kBlock, 0, s>>>(v, kc, q, db - 1); });
+  } else {
+    launch(t, CT_KERNEL_PROLOGUE, s, [&] { k_prologue<<<flat_blocks(db / 2), kBlock, 0, s>>>(t->v, pool, db, q); });
+    launch(t, CT_KERNEL_DEDUP, s, [&] { k_dedup<<<flat_blocks(q), kBlock, 0, s>>>(t->v, kc, q, db - 1); });
+  }
+}
+
 template <int VK>
 ct_status insert_chunks(ct_table* t, const uint64_t* keys, const void* vals, int64_t n,
                         uint8_t* status, hipStream_t s) {
@@ -1275,8 +1537,7 @@ ct_status insert_chunks(ct_table* t, const uint64_t* keys, const void* vals, int
     uint8_t* sc = status ? status + c0 : nullptr;
     const int gb = group_blocks((q + kSlots - 1) / kSlots);
     const int ntiles = (int)((q + kTile - 1) / kTile);
-    launch(t, CT_KERNEL_PROLOGUE, s, [&] { k_prologue<<<flat_blocks(db / 2), kBlock, 0, s>>>(t->v, nullptr, db, q); });
-    launch(t, CT_KERNEL_DEDUP, s, [&] { k_dedup<<<flat_blocks(q), kBlock, 0, s>>>(t->v, kc, q, db - 1); });
+    dedup_chunk(t, nullptr, kc, q, s);
     launch(t, CT_KERNEL_INSERT, s, [&] { k_insert<VK, false><<<gb, kBlock, 0, s>>>(t->v, kc, vc, q, db - 1, sc, nullptr); });
     launch(t, CT_KERNEL_APPLY, s, [&] { k_apply_count<<<1, 1024, 0, s>>>(t->v, gb); });
     // the host bound proves that no element can meet FULL: the rank pass is not needed
@@ -1304,8 +1565,7 @@ ct_status erase_chunks(ct_table* t, ct_pool* p, const uint64_t* keys, int64_t n,
     uint8_t* ec = erased ? erased + c0 : nullptr;
     const int gb = group_blocks((q + kSlots - 1) / kSlots);
     const int ntiles = (int)((q + kTile - 1) / kTile);
-    launch(t, CT_KERNEL_PROLOGUE, s, [&] { k_prologue<<<flat_blocks(db / 2), kBlock, 0, s>>>(t->v, RELEASE ? p->hdr : nullptr, db, q); });
-    launch(t, CT_KERNEL_DEDUP, s, [&] { k_dedup<<<flat_blocks(q), kBlock, 0, s>>>(t->v, kc, q, db - 1); });
+    dedup_chunk(t, RELEASE ? p->hdr : nullptr, kc, q, s);
     launch(t, CT_KERNEL_ERASE, s, [&] { k_erase<RELEASE><<<gb, kBlock, 0, s>>>(t->v, kc, q, db - 1, ec); });
     launch(t, CT_KERNEL_APPLY, s, [&] { k_apply_count<<<1, 1024, 0, s>>>(t->v, gb); });
     if (RELEASE) {
@@ -1375,6 +1635,16 @@ ct_status ct_table_init(void* d_buf, int64_t bytes, const ct_table_desc* d, void
   v.ref = reinterpret_cast<uint64_t*>(base + L.off_ref);
   v.tsum = reinterpret_cast<uint32_t*>(base + L.off_tsum);
   v.bcnt = reinterpret_cast<int64_t*>(base + L.off_bcnt);
+  v.r1k = L.bins ? reinterpret_cast<uint64_t*>(base + L.off_r1k) : nullptr;
+  v.r1i = L.bins ? reinterpret_cast<uint32_t*>(base + L.off_r1i) : nullptr;
+  v.r2k = L.bins ? reinterpret_cast<uint64_t*>(base + L.off_r2k) : nullptr;
+  v.r2i = L.bins ? reinterpret_cast<uint32_t*>(base + L.off_r2i) : nullptr;
+  v.bcur = L.bins ? reinterpret_cast<uint32_t*>(base + L.off_bcur) : nullptr;
+  v.dfirst = L.bins ? reinterpret_cast<uint32_t*>(base + L.off_dfirst) : nullptr;
+  v.c1 = L.bins ? (uint32_t)L.c1 : 0u;
+  v.c2 = L.bins ? (uint32_t)L.c2 : 0u;
+  v.lp = L.bins ? L.lp : 0;
+  v.lp1 = L.bins ? L.lp1 : 0;
   v.hash = d->hash_kind;
   v.nb_pow2 = (L.nb & (L.nb - 1)) == 0;
   v.step_mode = v.nb_pow2 ? 1 : (is_prime(L.nb) ? 2 : 0);
@@ -1627,8 +1897,7 @@ ct_status ct_insert_alloc_batch(ct_table* t, ct_pool* p, const uint64_t* keys, i
     int32_t* vc = vals_out ? vals_out + c0 : nullptr;
     const int gb = group_blocks((q + kSlots - 1) / kSlots);
     const int ntiles = (int)((q + kTile - 1) / kTile);
-    launch(t, CT_KERNEL_PROLOGUE, s, [&] { k_prologue<<<flat_blocks(db / 2), kBlock, 0, s>>>(t->v, p->hdr, db, q); });
-    launch(t, CT_KERNEL_DEDUP, s, [&] { k_dedup<<<flat_blocks(q), kBlock, 0, s>>>(t->v, kc, q, db - 1); });
+    dedup_chunk(t, p->hdr, kc, q, s);
     launch(t, CT_KERNEL_INSERT, s, [&] { k_insert<1, true><<<gb, kBlock, 0, s>>>(t->v, kc, nullptr, q, db - 1, sc, vc); });
     launch(t, CT_KERNEL_RANK, s, [&] { k_tile_count<<<ntiles, kBlock, 0, s>>>(t->v, q, 0); });
     launch(t, CT_KERNEL_RANK, s, [&] { k_tile_scan<<<1, 1024, 0, s>>>(t->v, p->hdr, ntiles, 1); });

@@ -234,3 +234,27 @@ def test_pool_stack(dev):
     np.testing.assert_array_equal(st.cpu().numpy(), es)
     assert gp.size() == op.size() == 0
     assert gp.error() & ct.ERR_POOL
+
+
+@pytest.mark.parametrize("chunk,universe", [(1 << 16, 1 << 15), (1 << 17, 1 << 12), (1 << 16, 3)])
+def test_binned_dedup_repeated_keys(dev, chunk, universe):
+    """Chunks of at least 2^16 elements resolve repeated keys through bins: keys drawn from a
+    small universe (about 2, 32 and 20,000 copies of each key per chunk; the last overflows its bin
+    and takes the dd path), reserved-looking keys mixed in, ragged batches spanning chunks;
+    inserts, erases and pool-valued inserts all compared with the oracle."""
+    rng = rng_for(71)
+    p = Pair(dev, 1 << 19, 64, chunk=chunk)
+    for rep in range(3):
+        n = int(chunk * 2.5) + 77 * rep
+        keys = rng.integers(0, universe, size=n, dtype=np.uint64) * np.uint64(0x9E3779B97F4A7C15)
+        keys[rng.integers(0, n, size=64)] = RESERVED[rng.integers(0, RESERVED.size, size=64)]
+        p.insert(keys, rng.integers(0, 1 << 62, size=n, dtype=np.uint64))
+        p.find(np.concatenate([keys[:5000], rng.integers(0, 1 << 62, size=5000, dtype=np.uint64)]))
+        p.erase(keys[rng.integers(0, n, size=n // 3)])
+        p.same_state()
+    q = Pair(dev, 1 << 18, 32, chunk=chunk, pool=1 << 18)
+    keys = rng.integers(0, universe, size=chunk * 2 + 5, dtype=np.uint64) + np.uint64(7)
+    q.insert_alloc(keys)
+    q.erase_release(keys[: chunk // 2])
+    q.insert_alloc(keys[::-1].copy())
+    q.same_state()
