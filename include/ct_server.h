@@ -54,6 +54,8 @@ typedef struct ct_server_stats {
     int64_t submitted, completed, batches;
     int64_t peak_staging_bytes; /* most staging bytes in flight at once */
     int64_t peak_inflight;      /* most batches in flight at once */
+    int64_t dispatch_ns;        /* worker time spent enqueueing batches (copies, kernels, events) */
+    int64_t retire_ns;          /* worker time spent polling events and retiring batches */
     int32_t error;              /* first ct_status other than CT_OK met by the worker */
 } ct_server_stats;
 

@@ -8,7 +8,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libct.so")
-SOURCES = ["ct_table.hip", "ct_roofline.hip", "ct_server.hip"]
+SOURCES = ["ct_table.hip", "ct_roofline.hip", "ct_server.hip", "ct_segcopy.hip"]
 
 HIPCC_FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "-shared", "--offload-arch=gfx950",

@@ -16,6 +16,7 @@
 #include <vector>
 
 #include "ct.h"
+#include "ct_segcopy.h"
 #include "ct_server.h"
 
 namespace ct_serve {
@@ -33,7 +34,22 @@ struct Req {
   void* vals_out;
   uint8_t* flags_out;
   int64_t submit_ns;
+  // device addresses of the host arrays when they are mapped pinned memory (zc): the batch then
+  // moves them with copy kernels; otherwise with DMA copies
+  bool zc;
+  const void* dkeys;
+  const void* dvals;
+  void* dvout;
+  void* dflags;
 };
+
+// Device address of host array `h` if it is mapped pinned memory, else null (h null: null).
+inline void* mapped(const void* h) {
+  if (!h) return nullptr;
+  void* d = nullptr;
+  if (hipHostGetDevicePointer(&d, const_cast<void*>(h), 0) != hipSuccess) return nullptr;
+  return d;
+}
 
 struct Done {
   int64_t ticket, submit_ns, done_ns;
@@ -114,6 +130,7 @@ struct ct_server {
   std::deque<Done> done;
   int64_t submitted = 0, completed = 0, batches = 0;
   int64_t peak_bytes = 0, peak_inflight = 0;
+  int64_t dispatch_ns = 0, retire_ns = 0;
   int32_t error = CT_OK;
   bool stop = false;
 
@@ -161,15 +178,37 @@ struct ct_server {
     }
     uint8_t* df = base + p;
     ct_status rc = CT_OK;
+    bool zc = true;
+    for (auto& r : b.reqs) zc = zc && r.zc;
+    Seg seg[kMaxSegs];
+    int nseg = 0;
+    auto add = [&](const void* src, void* dst, int64_t bytes) {
+      if (bytes <= 0) return;
+      seg[nseg++] = Seg{src, dst, bytes};
+      if (nseg == kMaxSegs) {
+        if (segcopy(seg, nseg, st) != hipSuccess) rc = CT_E_HIP;
+        nseg = 0;
+      }
+    };
+    auto flush = [&] {
+      if (nseg && segcopy(seg, nseg, st) != hipSuccess) rc = CT_E_HIP;
+      nseg = 0;
+    };
     int64_t pos = 0;
     for (auto& r : b.reqs) {
-      if (r.n && hipMemcpyAsync(dk + pos, r.keys, r.n * 8, hipMemcpyHostToDevice, st) != hipSuccess)
-        rc = CT_E_HIP;
-      if (b.op == CT_OP_INSERT && dv && r.n &&
-          hipMemcpyAsync(dv + pos * vb, r.vals, r.n * vb, hipMemcpyHostToDevice, st) != hipSuccess)
-        rc = CT_E_HIP;
+      if (zc) {
+        add(r.dkeys, dk + pos, r.n * 8);
+        if (b.op == CT_OP_INSERT && dv) add(r.dvals, dv + pos * vb, r.n * vb);
+      } else {
+        if (r.n && hipMemcpyAsync(dk + pos, r.keys, r.n * 8, hipMemcpyHostToDevice, st) != hipSuccess)
+          rc = CT_E_HIP;
+        if (b.op == CT_OP_INSERT && dv && r.n &&
+            hipMemcpyAsync(dv + pos * vb, r.vals, r.n * vb, hipMemcpyHostToDevice, st) != hipSuccess)
+          rc = CT_E_HIP;
+      }
       pos += r.n;
     }
+    flush();
     if (rc == CT_OK) {
       ct_table* tab = tables[t];
       if (b.op == CT_OP_INSERT)
@@ -181,15 +220,21 @@ struct ct_server {
     }
     pos = 0;
     for (auto& r : b.reqs) {
-      if (rc == CT_OK && r.n && r.flags_out &&
-          hipMemcpyAsync(r.flags_out, df + pos, r.n, hipMemcpyDeviceToHost, st) != hipSuccess)
-        rc = CT_E_HIP;
-      if (rc == CT_OK && r.n && b.op == CT_OP_FIND && dv && r.vals_out &&
-          hipMemcpyAsync(r.vals_out, dv + pos * vb, r.n * vb, hipMemcpyDeviceToHost, st) !=
-              hipSuccess)
-        rc = CT_E_HIP;
+      if (rc == CT_OK && zc) {
+        if (r.flags_out) add(df + pos, r.dflags, r.n);
+        if (b.op == CT_OP_FIND && dv && r.vals_out) add(dv + pos * vb, r.dvout, r.n * vb);
+      } else {
+        if (rc == CT_OK && r.n && r.flags_out &&
+            hipMemcpyAsync(r.flags_out, df + pos, r.n, hipMemcpyDeviceToHost, st) != hipSuccess)
+          rc = CT_E_HIP;
+        if (rc == CT_OK && r.n && b.op == CT_OP_FIND && dv && r.vals_out &&
+            hipMemcpyAsync(r.vals_out, dv + pos * vb, r.n * vb, hipMemcpyDeviceToHost, st) !=
+                hipSuccess)
+          rc = CT_E_HIP;
+      }
       pos += r.n;
     }
+    if (rc == CT_OK) flush();
     // the event marks the end of everything enqueued for the batch, failed or not; without it
     // the stream is drained here so that the staging range is idle before it is reused
     if (hipEventRecord(b.ev, st) != hipSuccess) {
@@ -229,13 +274,16 @@ struct ct_server {
       spare_events.pop_back();
       order.erase(order.begin());
       if (!q.empty()) order.insert({q.front().ticket, t});
+      const int64_t d0 = now_ns();
       dispatch(b);
+      const int64_t d1 = now_ns();
       inflight_bytes += b.bytes;
       any += (int64_t)take;
       inflight[t % streams.size()].push_back(std::move(b));
       ++n_inflight;
       std::lock_guard<std::mutex> g(mu);
       ++batches;
+      dispatch_ns += d1 - d0;
       if (inflight_bytes > peak_bytes) peak_bytes = inflight_bytes;
       if (n_inflight > peak_inflight) peak_inflight = n_inflight;
     }
@@ -245,6 +293,7 @@ struct ct_server {
   // Retire the batches whose events have completed; returns true if any was.  A stream runs its
   // batches in launch order, so only the oldest batch of each stream needs to be queried.
   bool retire() {
+    const int64_t r0 = now_ns();
     std::vector<Done> fin;
     for (auto& q : inflight) {
       while (!q.empty()) {
@@ -265,8 +314,9 @@ struct ct_server {
         --n_inflight;
       }
     }
-    if (fin.empty()) return false;
     std::lock_guard<std::mutex> g(mu);
+    retire_ns += now_ns() - r0;
+    if (fin.empty()) return false;
     for (auto& d : fin) done.push_back(d);
     completed += (int64_t)fin.size();
     if (completed == submitted) idle.notify_all();
@@ -361,7 +411,17 @@ ct_status ct_server_submit(ct_server* s, int32_t table, int32_t op, const uint64
   if (n > 0 && !h_keys) return CT_E_INVALID;
   if (n > 0 && op == CT_OP_INSERT && s->vbytes[table] && !h_vals) return CT_E_INVALID;
   if (n > (INT64_MAX / 32) || s->need(table, op, n) > s->staging_bytes) return CT_E_INVALID;
-  Req r{0, table, op, h_keys, h_vals, n, h_vals_out, h_flags_out, 0};
+  Req r{0, table, op, h_keys, h_vals, n, h_vals_out, h_flags_out, 0,
+        false, nullptr, nullptr, nullptr, nullptr};
+  if (n > 0) {  // map the arrays the batch will move; any unmapped one sends it through DMA
+    const int64_t vb = s->vbytes[table];
+    r.dkeys = mapped(h_keys);
+    r.dvals = (op == CT_OP_INSERT && vb) ? mapped(h_vals) : nullptr;
+    r.dvout = (op == CT_OP_FIND && vb && h_vals_out) ? mapped(h_vals_out) : nullptr;
+    r.dflags = h_flags_out ? mapped(h_flags_out) : nullptr;
+    r.zc = r.dkeys && (op != CT_OP_INSERT || !vb || r.dvals) &&
+           (op != CT_OP_FIND || !vb || !h_vals_out || r.dvout) && (!h_flags_out || r.dflags);
+  }
   {
     std::lock_guard<std::mutex> g(s->mu);
     if (s->stop) return CT_E_INVALID;
@@ -407,6 +467,8 @@ ct_status ct_server_get_stats(ct_server* s, ct_server_stats* out) {
   out->batches = s->batches;
   out->peak_staging_bytes = s->peak_bytes;
   out->peak_inflight = s->peak_inflight;
+  out->dispatch_ns = s->dispatch_ns;
+  out->retire_ns = s->retire_ns;
   out->error = s->error;
   return CT_OK;
 }

@@ -42,7 +42,7 @@ class ServerDesc(C.Structure):
 class ServerStats(C.Structure):
     _fields_ = [("submitted", C.c_int64), ("completed", C.c_int64), ("batches", C.c_int64),
                 ("peak_staging_bytes", C.c_int64), ("peak_inflight", C.c_int64),
-                ("error", C.c_int32)]
+                ("dispatch_ns", C.c_int64), ("retire_ns", C.c_int64), ("error", C.c_int32)]
 
 
 _lib = None

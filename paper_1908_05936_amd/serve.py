@@ -202,6 +202,10 @@ def sweep(sv, tables, device, fractions=(0.1, 0.25, 0.5, 0.75, 0.9, 1.0, 1.2), w
 
     srv, reqs = serve(np.zeros(total))
     sat = latency_stats(reqs[warmup:], reqs[:warmup])
+    sat_span = max(r.done for r in reqs) - min(r.arrival for r in reqs)
+    sat_worker = dict(dispatch_share=srv["dispatch_ns"] * 1e-9 / sat_span,
+                      retire_share=srv["retire_ns"] * 1e-9 / sat_span,
+                      batches=srv["batches"])
     sat_keys = sat["achieved_Mkeys_s"] * 1e6
     log(f"[serve] saturated {sat['achieved_Mkeys_s']:.1f} Mkeys/s, {srv['batches']} batches, "
         f"p50 {sat['p50_ms']:.2f} ms p99 {sat['p99_ms']:.2f} ms")
@@ -216,7 +220,8 @@ def sweep(sv, tables, device, fractions=(0.1, 0.25, 0.5, 0.75, 0.9, 1.0, 1.2), w
         log(f"[serve] {f:.2f} x: p50 {st['p50_ms']:.2f} ms p99 {st['p99_ms']:.2f} ms "
             f"achieved {st['achieved_Mkeys_s']:.1f} Mkeys/s")
         points.append(st)
-    return dict(saturated_Mkeys_s=sat["achieved_Mkeys_s"], saturated_p50_ms=sat["p50_ms"],
+    return dict(saturated_Mkeys_s=sat["achieved_Mkeys_s"], saturated_worker=sat_worker,
+                saturated_p50_ms=sat["p50_ms"],
                 saturated_p99_ms=sat["p99_ms"], mean_request_keys=mean_keys, points=points,
                 requests=dict(warmup=warmup, measured=measured, distinct=len(pool)),
                 budget_bytes=budget_bytes, max_inflight=max_inflight, streams=streams,

@@ -10,6 +10,17 @@
 #include <random>
 #include <unordered_map>
 
+// --- the copy kernel of the server, done on the host ---------------------------------------------
+static std::atomic<int64_t> g_segcopies{0};
+namespace ct_serve {
+hipError_t segcopy(const Seg* segs, int n, hipStream_t) {
+  if (n <= 0 || n > kMaxSegs) std::abort();
+  for (int i = 0; i < n; ++i) std::memcpy(segs[i].dst, segs[i].src, (size_t)segs[i].bytes);
+  ++g_segcopies;
+  return hipSuccess;
+}
+}  // namespace ct_serve
+
 // --- reference tables behind the ct.h batch calls ---------------------------------------------
 struct ct_table {
   std::unordered_map<uint64_t, uint64_t> m;
@@ -208,6 +219,10 @@ int main() {
   bad |= run_case(2, 7, 1, 1, 1 << 20, 1 << 20, 2000);  // one stream, one slot
   bad |= run_case(3, 3, 8, 64, 1 << 20, 64, 3000);   // many slots, small merge cap
   bad |= run_case(4, 1, 2, 16, 4096, 1 << 10, 1500); // one table, staging for a few small batches
+  if (g_segcopies.load() == 0) {
+    std::printf("FAIL the copy-kernel path was never taken\n");
+    bad = 1;
+  }
   if (!bad) std::printf("server host test passed\n");
   return bad;
 }
