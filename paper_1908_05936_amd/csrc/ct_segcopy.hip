@@ -1,7 +1,7 @@
 // Multi-range copy kernel for the request server (interface in ct_segcopy.h).  Segment y of the
-// launch is copied by the blocks with blockIdx.y == y, in the widest unit (8, 4 or 1 bytes) that
-// its source, destination and length allow, so reads of mapped host memory are 512-byte
-// transactions per wave when the arrays are 8-byte aligned.
+// launch is copied by the blocks with blockIdx.y == y, in the widest unit (16, 8, 4 or 1 bytes)
+// that its source, destination and length allow, so a wave reads mapped host memory in 512-byte
+// or 1 KiB pieces when the arrays are aligned.
 #include "ct_segcopy.h"
 
 namespace ct_serve {
@@ -20,7 +20,11 @@ __global__ __launch_bounds__(kCopyBlock) void k_segcopy(SegList L) {
                       (uintptr_t)g.bytes;
   const int64_t stride = (int64_t)gridDim.x * kCopyBlock;
   const int64_t first = (int64_t)blockIdx.x * kCopyBlock + threadIdx.x;
-  if ((a & 7) == 0) {
+  if ((a & 15) == 0) {
+    const uint4* s = static_cast<const uint4*>(g.src);
+    uint4* d = static_cast<uint4*>(g.dst);
+    for (int64_t i = first; i < g.bytes / 16; i += stride) d[i] = s[i];
+  } else if ((a & 7) == 0) {
     const uint64_t* s = static_cast<const uint64_t*>(g.src);
     uint64_t* d = static_cast<uint64_t*>(g.dst);
     for (int64_t i = first; i < g.bytes / 8; i += stride) d[i] = s[i];

@@ -243,9 +243,13 @@ __device__ __forceinline__ void dedup_range(const TableView& t, const uint64_t* 
         e = expected;
       }
       if ((e & 0xFFFFFFFF00000000ull) == tag && keys[(uint32_t)e] == key) {
-        const uint64_t old = amin64(&t.dd[h], mine);
+        // the entry's index only decreases: a copy above the index it sees cannot lower it, so
+        // only lower copies pay an atomic (copies of a hot key stop contending on one address)
+        const uint32_t held = (uint32_t)e;
+        uint32_t prev = held;
+        if ((uint32_t)i < held) prev = (uint32_t)amin64(&t.dd[h], mine);
         t.dmark[i] = 1;
-        t.dmark[(uint32_t)old] = 1;
+        if (!t.dmark[prev]) t.dmark[prev] = 1;
         break;
       }
       h = (h + 1) & dmask;
@@ -414,29 +418,37 @@ __global__ __launch_bounds__(kBlock) void k_bin_dedup(TableView t) {
   __syncthreads();
   const uint64_t* rk = t.r2k + (int64_t)f * t.c2;
   const uint32_t* ri = t.r2i + (int64_t)f * t.c2;
-  for (uint32_t j = threadIdx.x; j < n; j += kBlock) {
-    const uint64_t key = rk[j];
-    uint32_t s = (uint32_t)dedup_mix(key) & (kBinLds - 1);
-    for (;;) {
-      const unsigned long long old = atomicCAS(&hk[s], (unsigned long long)kEmpty,
-                                               (unsigned long long)key);
-      if (old == kEmpty || old == key) {
-        if (old == key) hx[s] = 1;
-        atomicMin(&hm[s], ri[j]);
-        break;
+  // a bin holds at most c2 <= kPer * kBlock elements: each thread keeps its own in registers
+  constexpr int kPer = (2 * kBinFine + 256 + kBlock - 1) / kBlock;
+  uint32_t slot[kPer], idx[kPer];
+#pragma unroll
+  for (int e = 0; e < kPer; ++e) {
+    const uint32_t j = threadIdx.x + e * kBlock;
+    slot[e] = kNone;
+    idx[e] = 0;
+    if (j < n) {
+      const uint64_t key = rk[j];
+      idx[e] = ri[j];
+      uint32_t s = (uint32_t)dedup_mix(key) & (kBinLds - 1);
+      for (;;) {
+        const unsigned long long old = atomicCAS(&hk[s], (unsigned long long)kEmpty,
+                                                 (unsigned long long)key);
+        if (old == kEmpty || old == key) {
+          if (old == key) hx[s] = 1;
+          atomicMin(&hm[s], idx[e]);
+          break;
+        }
+        s = (s + 1) & (kBinLds - 1);
       }
-      s = (s + 1) & (kBinLds - 1);
+      slot[e] = s;
     }
   }
   __syncthreads();
-  for (uint32_t j = threadIdx.x; j < n; j += kBlock) {
-    const uint64_t key = rk[j];
-    uint32_t s = (uint32_t)dedup_mix(key) & (kBinLds - 1);
-    while (hk[s] != key) s = (s + 1) & (kBinLds - 1);
-    if (hx[s]) {
-      const uint32_t i = ri[j];
-      t.dmark[i] = 1;
-      t.dfirst[i] = hm[s];
+#pragma unroll
+  for (int e = 0; e < kPer; ++e) {
+    if (slot[e] != kNone && hx[slot[e]]) {
+      t.dmark[idx[e]] = 1;
+      t.dfirst[idx[e]] = hm[slot[e]];
     }
   }
 }
