@@ -82,6 +82,8 @@ def parse():
     ap.add_argument("--chunk", type=int, default=0, help="table chunk (0 = library default)")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving sweep")
     ap.add_argument("--no-voxel", action="store_true", help="skip the voxel-block frames")
+    ap.add_argument("--no-find-uniform", action="store_true",
+                    help="skip the uniform-popularity find (counter runs keep to the step's kernels)")
     ap.add_argument("--serve-footprint-gb", type=float, default=40.0)
     ap.add_argument("--serve-warmup", type=int, default=200)
     ap.add_argument("--serve-measured", type=int, default=2000)
@@ -199,6 +201,33 @@ def cpu_baseline(shift, seed=3):
                         "kind": "oracle tables partitioned by key hash, one thread each",
                         "seconds": dtp},
     }
+
+
+def find_uniform(op_clear, op_fill, dev, K_fill, n_fill, n_find, n_hit, L, h, s, vals_out, found):
+    """The find with uniform popularity (n_hit live keys drawn uniformly, the rest absent) right
+    after a fill: no hot buckets, so it is compared with the uniform gather ceiling R1.  Mops/s,
+    median of 3 runs timed with HIP events."""
+    import torch
+    from paper_1908_05936_amd import ct
+
+    op_clear()
+    op_fill()
+    g = torch.Generator(device=dev)
+    g.manual_seed(7)
+    idx = torch.randint(0, n_fill, (n_hit,), device=dev, generator=g)
+    absent = torch.randint(-(1 << 62), 1 << 62, (n_find - n_hit,), device=dev, generator=g)
+    q = torch.cat([K_fill[idx], absent])[torch.randperm(n_find, device=dev, generator=g)]
+    del idx, absent
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ts = []
+    for _ in range(3):
+        e0.record()
+        ct._check(L.ct_find_batch(h, ct._ptr(q), n_find, ct._ptr(vals_out), ct._ptr(found), s),
+                  "find uniform")
+        e1.record()
+        torch.cuda.synchronize()
+        ts.append(e0.elapsed_time(e1) * 1e-3)
+    return n_find / float(np.median(ts)) / 1e6
 
 
 def main():
@@ -358,27 +387,9 @@ def main():
         "kernels": kernels,
         "roofline": roof,
     }
-    # the find again with uniform popularity (80 % live keys drawn uniformly, 20 % absent): no
-    # hot buckets, so it is compared with the uniform gather ceiling R1
-    op_clear()
-    op_fill()
-    g = torch.Generator(device=dev)
-    g.manual_seed(7)
-    n_hit = n_present_expected
-    idx = torch.randint(0, n_fill, (n_hit,), device=dev, generator=g)
-    absent = torch.randint(-(1 << 62), 1 << 62, (n_find - n_hit,), device=dev, generator=g)
-    QU = torch.cat([K_fill[idx], absent])[torch.randperm(n_find, device=dev, generator=g)]
-    del idx, absent
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    ts = []
-    for _ in range(3):
-        e0.record()
-        ct._check(L.ct_find_batch(h, P(QU), n_find, P(vals_out), P(found), s), "find uniform")
-        e1.record()
-        torch.cuda.synchronize()
-        ts.append(e0.elapsed_time(e1) * 1e-3)
-    line["find_uniform_Mops_s"] = n_find / float(np.median(ts)) / 1e6
-    del QU
+    if not a.no_find_uniform:
+        line["find_uniform_Mops_s"] = find_uniform(op_clear, op_fill, dev, K_fill, n_fill, n_find,
+                                                   n_present_expected, L, h, s, vals_out, found)
     if not a.no_ceilings:
         rng = np.random.default_rng(99)
         uni = torch.from_numpy(rng.integers(0, 1 << 63, size=n_find, dtype=np.int64)).to(dev)
@@ -390,7 +401,9 @@ def main():
         ceil["find_frac_of_R1"] = f_mops / ceil["R1_gather128_Mlines_s"]
         ceil["find_frac_of_R5"] = f_mops / ceil["R5_find_stream_Mlines_s"]
         ceil["insert_frac_of_R2"] = i_mops / ceil["R2_gather128_cas_Mops_s"]
-        ceil["find_uniform_frac_of_R1"] = line["find_uniform_Mops_s"] / ceil["R1_gather128_Mlines_s"]
+        if "find_uniform_Mops_s" in line:
+            ceil["find_uniform_frac_of_R1"] = (line["find_uniform_Mops_s"]
+                                               / ceil["R1_gather128_Mlines_s"])
         line["random_access"] = ceil
     if not a.no_voxel:
         from paper_1908_05936_amd import bench_voxel
