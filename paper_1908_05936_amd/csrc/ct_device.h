@@ -39,7 +39,7 @@ constexpr int kBlock = 256;             // threads per block of every group kern
 constexpr int64_t kBinMinChunk = 1 << 16; // chunks at least this large dedup through bins
 constexpr int kBinFine = 1024;          // mean elements per fine bin
 constexpr int kBinCoarse = 64;          // coarse bins
-constexpr int kBinTile = 4096;          // elements per block of the scatter kernels
+constexpr int kBinTile = 2048;          // elements per block of the scatter kernels
 constexpr int kBinLds = 4096;           // LDS hash slots of the fine-bin dedup (> 2 x mean + 256)
 constexpr int kMaxFinePerCoarse = 256;  // fine bins per coarse bin at the largest chunk (2^24)
 

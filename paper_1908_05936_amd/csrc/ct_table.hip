@@ -271,6 +271,28 @@ __global__ __launch_bounds__(kBlock) void k_dedup(TableView t, const uint64_t* _
 // one per block and non-empty bin.  A bin that would overflow its capacity sets dovf; the chunk
 // then clears dd and runs dedup_range instead, so results never depend on the key distribution.
 // ---------------------------------------------------------------------------------------------
+// Exclusive block-wide scan of one value per thread (kBlock threads); returns the prefix and
+// writes the block total to *total.
+__device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* total) {
+  __shared__ uint32_t wsum[kBlock / 64];
+  const int lane = wave_lane();
+  uint32_t x = v;
+  for (int off = 1; off < 64; off <<= 1) {
+    const uint32_t y = __shfl_up(x, off, 64);
+    if (lane >= off) x += y;
+  }
+  if (lane == 63) wsum[threadIdx.x >> 6] = x;
+  __syncthreads();
+  uint32_t before = 0, all = 0;
+  for (int w = 0; w < kBlock / 64; ++w) {
+    if (w < (int)(threadIdx.x >> 6)) before += wsum[w];
+    all += wsum[w];
+  }
+  *total = all;
+  __syncthreads();
+  return before + x - v;
+}
+
 __device__ __forceinline__ uint32_t fine_bin(const TableView& t, uint64_t mix) {
   return (uint32_t)(mix >> (64 - t.lp));
 }
@@ -292,111 +314,124 @@ __global__ __launch_bounds__(kBlock) void k_bin_prologue(TableView t, PoolHeader
   if (blockIdx.x == 0 && threadIdx.x == 0) chunk_header(t, pool, q, 1u);
 }
 
-// Coarse scatter: block b takes elements [b * kBinTile, (b + 1) * kBinTile), ranks them within
-// their coarse bin in LDS, reserves one run per non-empty bin, and writes (key, index) pairs.
-// The out-of-band keys take their lowest index directly, as in dedup_range.
+// Both scatters: the block's elements, ranked within their bin (code = rank << 8 | bin, or ~0 for
+// none), are staged in LDS in bin order and each bin's run is written by consecutive threads, so
+// the stores of a wave go to consecutive positions of one bin.  cnt[b] holds the block's count
+// for bin b; this reserves the runs (bin b's fill count at bcur[cur0 + b]), flags an overflow of
+// `cap`, and writes bin b of the block to out[(gbin0 + b) * cap + position].
+struct BinStage {
+  uint64_t k[kBinTile];
+  uint32_t i[kBinTile];
+  uint8_t b[kBinTile];
+  uint32_t cnt[kMaxFinePerCoarse];
+  uint32_t base[kMaxFinePerCoarse];
+  uint32_t loc[kMaxFinePerCoarse];
+};
+
+template <int PER>
+__device__ __forceinline__ void bin_write(const TableView& t, BinStage& S, uint32_t nbins,
+                                          const uint64_t (&k)[PER], const uint32_t (&ix)[PER],
+                                          const uint32_t (&code)[PER], uint32_t cur0,
+                                          uint32_t gbin0, uint32_t cap, uint64_t* __restrict__ outk,
+                                          uint32_t* __restrict__ outi) {
+  const uint32_t c = threadIdx.x < nbins ? S.cnt[threadIdx.x] : 0u;
+  uint32_t total;
+  const uint32_t pre = block_exclusive_scan(c, &total);
+  if (threadIdx.x < nbins) {
+    uint32_t o = 0;
+    if (c) {
+      o = aadd32(&t.bcur[cur0 + threadIdx.x], c);
+      if (o + c > cap) t.hdr->dovf = 1u;
+    }
+    S.base[threadIdx.x] = o;
+    S.loc[threadIdx.x] = pre;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int e = 0; e < PER; ++e) {
+    if (code[e] == ~0u) continue;
+    const uint32_t b = code[e] & 0xFFu;
+    const uint32_t p = S.loc[b] + (code[e] >> 8);
+    S.k[p] = k[e];
+    S.i[p] = ix[e];
+    S.b[p] = (uint8_t)b;
+  }
+  __syncthreads();
+  for (uint32_t p = threadIdx.x; p < total; p += kBlock) {
+    const uint32_t b = S.b[p];
+    const uint32_t pos = S.base[b] + (p - S.loc[b]);
+    if (pos < cap) {
+      const int64_t at = (int64_t)(gbin0 + b) * cap + pos;
+      outk[at] = S.k[p];
+      outi[at] = S.i[p];
+    }
+  }
+}
+
+// Coarse scatter: block b takes elements [b * kBinTile, (b + 1) * kBinTile) into the 64 coarse
+// bins.  The out-of-band keys take their lowest index directly, as in dedup_range.
 __global__ __launch_bounds__(kBlock) void k_bin_scatter1(TableView t, const uint64_t* __restrict__ keys,
                                                          int64_t q) {
   constexpr int kPer = kBinTile / kBlock;
-  __shared__ uint32_t cnt[kBinCoarse];
-  __shared__ uint32_t base[kBinCoarse];
+  __shared__ BinStage S;
   const int64_t t0 = (int64_t)blockIdx.x * kBinTile;
-  if (threadIdx.x < kBinCoarse) cnt[threadIdx.x] = 0;
+  if (threadIdx.x < kBinCoarse) S.cnt[threadIdx.x] = 0;
   __syncthreads();
   uint64_t k[kPer];
-  uint32_t code[kPer];  // rank << 8 | coarse bin, or ~0 for no element
+  uint32_t ix[kPer], code[kPer];
 #pragma unroll
   for (int e = 0; e < kPer; ++e) {
     const int64_t i = t0 + e * kBlock + threadIdx.x;
     code[e] = ~0u;
     k[e] = 0;
+    ix[e] = (uint32_t)i;
     if (i < q) {
       k[e] = keys[i];
       if (k[e] >= kTomb) {
         amin32(&t.hdr->spec_first[k[e] - kTomb], (uint32_t)i);
       } else {
         const uint32_t b = (uint32_t)(dedup_mix(k[e]) >> (64 - t.lp1));
-        code[e] = (atomicAdd(&cnt[b], 1u) << 8) | b;
+        code[e] = (atomicAdd(&S.cnt[b], 1u) << 8) | b;
       }
     }
   }
   __syncthreads();
-  if (threadIdx.x < kBinCoarse) {
-    const uint32_t c = cnt[threadIdx.x];
-    uint32_t o = 0;
-    if (c) {
-      o = aadd32(&t.bcur[threadIdx.x], c);
-      if (o + c > t.c1) t.hdr->dovf = 1u;
-    }
-    base[threadIdx.x] = o;
-  }
-  __syncthreads();
-#pragma unroll
-  for (int e = 0; e < kPer; ++e) {
-    if (code[e] == ~0u) continue;
-    const uint32_t b = code[e] & 0xFFu;
-    const uint32_t pos = base[b] + (code[e] >> 8);
-    if (pos < t.c1) {
-      const int64_t at = (int64_t)b * t.c1 + pos;
-      t.r1k[at] = k[e];
-      t.r1i[at] = (uint32_t)(t0 + e * kBlock + threadIdx.x);
-    }
-  }
+  bin_write<kPer>(t, S, kBinCoarse, k, ix, code, 0u, 0u, t.c1, t.r1k, t.r1i);
 }
 
-// Fine scatter: block (coarse bin b, tile) moves that tile of bin b into its 2^(lp - lp1) fine
+// Fine scatter: block (coarse bin c, tile) moves that tile of bin c into its 2^(lp - lp1) fine
 // bins, the same way.
 __global__ __launch_bounds__(kBlock) void k_bin_scatter2(TableView t, int tiles_per_bin) {
   if (t.hdr->dovf) return;
   constexpr int kPer = kBinTile / kBlock;
-  __shared__ uint32_t cnt[kMaxFinePerCoarse];
-  __shared__ uint32_t base[kMaxFinePerCoarse];
-  const int b = (int)blockIdx.x / tiles_per_bin;
+  __shared__ BinStage S;
+  const int c = (int)blockIdx.x / tiles_per_bin;
   const uint32_t j0 = (uint32_t)((int)blockIdx.x % tiles_per_bin) * kBinTile;
-  const uint32_t n1 = min(t.bcur[b], t.c1);
+  const uint32_t n1 = min(t.bcur[c], t.c1);
   if (j0 >= n1) return;
   const int lp2 = t.lp - t.lp1;
   const uint32_t p2 = 1u << lp2;
-  for (uint32_t j = threadIdx.x; j < p2; j += kBlock) cnt[j] = 0;
+  for (uint32_t j = threadIdx.x; j < p2; j += kBlock) S.cnt[j] = 0;
   __syncthreads();
-  const int64_t src = (int64_t)b * t.c1;
+  const int64_t src = (int64_t)c * t.c1;
   uint64_t k[kPer];
-  uint32_t idx[kPer], code[kPer];  // rank << 8 | fine bin within the coarse bin
+  uint32_t ix[kPer], code[kPer];
 #pragma unroll
   for (int e = 0; e < kPer; ++e) {
     const uint32_t j = j0 + e * kBlock + threadIdx.x;
     code[e] = ~0u;
     k[e] = 0;
-    idx[e] = 0;
+    ix[e] = 0;
     if (j < n1) {
       k[e] = t.r1k[src + j];
-      idx[e] = t.r1i[src + j];
+      ix[e] = t.r1i[src + j];
       const uint32_t f2 = fine_bin(t, dedup_mix(k[e])) & (p2 - 1u);
-      code[e] = (atomicAdd(&cnt[f2], 1u) << 8) | f2;
+      code[e] = (atomicAdd(&S.cnt[f2], 1u) << 8) | f2;
     }
   }
   __syncthreads();
-  for (uint32_t j = threadIdx.x; j < p2; j += kBlock) {
-    const uint32_t c = cnt[j];
-    uint32_t o = 0;
-    if (c) {
-      o = aadd32(&t.bcur[(1u << t.lp1) + ((uint32_t)b << lp2) + j], c);
-      if (o + c > t.c2) t.hdr->dovf = 1u;
-    }
-    base[j] = o;
-  }
-  __syncthreads();
-#pragma unroll
-  for (int e = 0; e < kPer; ++e) {
-    if (code[e] == ~0u) continue;
-    const uint32_t f2 = code[e] & 0xFFu;
-    const uint32_t pos = base[f2] + (code[e] >> 8);
-    if (pos < t.c2) {
-      const int64_t at = (int64_t)(((uint32_t)b << lp2) | f2) * t.c2 + pos;
-      t.r2k[at] = k[e];
-      t.r2i[at] = idx[e];
-    }
-  }
+  bin_write<kPer>(t, S, p2, k, ix, code, (1u << t.lp1) + ((uint32_t)c << lp2),
+                  (uint32_t)c << lp2, t.c2, t.r2k, t.r2i);
 }
 
 // One fine bin per block: insert its keys into an LDS table (CAS on the key word, atomic min on
@@ -771,27 +806,6 @@ __global__ __launch_bounds__(kBlock) void k_tile_count(TableView t, int64_t q, i
   }
 }
 
-// Exclusive block-wide scan of one value per thread (kBlock threads); returns the prefix and
-// writes the block total to *total.
-__device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* total) {
-  __shared__ uint32_t wsum[kBlock / 64];
-  const int lane = wave_lane();
-  uint32_t x = v;
-  for (int off = 1; off < 64; off <<= 1) {
-    const uint32_t y = __shfl_up(x, off, 64);
-    if (lane >= off) x += y;
-  }
-  if (lane == 63) wsum[threadIdx.x >> 6] = x;
-  __syncthreads();
-  uint32_t before = 0, all = 0;
-  for (int w = 0; w < kBlock / 64; ++w) {
-    if (w < (int)(threadIdx.x >> 6)) before += wsum[w];
-    all += wsum[w];
-  }
-  *total = all;
-  __syncthreads();
-  return before + x - v;
-}
 
 // One block of NT threads: exclusive scan of the tile counts, then the counter updates the ranks
 // imply.  mode 0: insert near capacity; 1: insert with pool values; 2: erase releasing to the pool.
