@@ -217,43 +217,73 @@ __global__ __launch_bounds__(kBlock) void k_prologue(TableView t, PoolHeader* po
                  (int64_t)gridDim.x * blockDim.x, blockIdx.x == 0);
 }
 
-// Lowest index per distinct key of the chunk, one thread per element.  The first copy of a key
-// to arrive claims an empty entry with one CAS; a later copy lowers the entry's index with an
-// atomic min and marks both itself and the previous holder as repeated, so every element of a key
-// that occurs more than once ends up marked and elements of unique keys stay unmarked.  All
-// indices held by one entry belong to one key, so the fingerprint plus one look at that element's
-// key identifies the entry exactly.
+// Lowest index per distinct key of the chunk.  The block takes 256 consecutive elements at a time
+// and first resolves them among themselves in LDS: every element of a key repeated inside the
+// window is marked, and only the window's lowest copy of each key (its representative) goes on
+// to the chunk-wide table dd.  There the first representative to arrive claims an empty entry
+// with one CAS; a later one marks itself and the holder, and lowers the entry's index with an
+// atomic min when its own index is lower (the index only decreases, so a representative above
+// the index it reads cannot lower it).  Every element of a key that occurs more than once ends
+// up marked, unique keys stay unmarked, and the entry ends at the key's lowest index.  All
+// indices held by one entry belong to one key, so the fingerprint plus one look at that
+// element's key identifies the entry exactly.  A key repeated many times therefore costs one
+// global operation per window, not per copy.  Needs blockDim.x == kBlock.
 __device__ __forceinline__ void dedup_range(const TableView& t, const uint64_t* __restrict__ keys,
                                             uint32_t dmask, int64_t lo, int64_t hi, int64_t step) {
-  for (int64_t i = lo + threadIdx.x; i < hi; i += step) {
-    const uint64_t key = keys[i];
-    if (key >= kTomb) {
-      amin32(&t.hdr->spec_first[key - kTomb], (uint32_t)i);
-      continue;
+  constexpr uint32_t kW = 2 * kBlock;  // LDS slots of a window's table
+  __shared__ unsigned long long wk[kW];
+  __shared__ uint32_t wmin[kW], wcnt[kW];
+  for (int64_t b0 = lo; b0 < hi; b0 += step) {  // uniform trip count: barriers below
+    for (uint32_t j = threadIdx.x; j < kW; j += kBlock) {
+      wk[j] = kEmpty;
+      wmin[j] = kNone;
+      wcnt[j] = 0;
     }
+    __syncthreads();
+    const int64_t i = b0 + threadIdx.x;
+    const bool valid = i < hi;
+    const uint64_t key = valid ? keys[i] : kEmpty;
+    const bool normal = valid && key < kTomb;
+    if (valid && !normal) amin32(&t.hdr->spec_first[key - kTomb], (uint32_t)i);
     const uint64_t mix = dedup_mix(key);
-    const uint64_t tag = mix & 0xFFFFFFFF00000000ull;
-    const uint64_t mine = tag | (uint64_t)i;
-    uint32_t h = (uint32_t)mix & dmask;
-    for (uint32_t step = 0; step <= dmask; ++step) {
-      uint64_t e = t.dd[h];
-      if (e == kEmpty) {
-        uint64_t expected = kEmpty;
-        if (cas64(&t.dd[h], expected, mine)) break;
-        e = expected;
+    uint32_t s = (uint32_t)(mix >> 32) & (kW - 1);
+    if (normal) {
+      for (;;) {  // at most kBlock keys in kW slots: a free or matching slot exists
+        const unsigned long long old = atomicCAS(&wk[s], (unsigned long long)kEmpty,
+                                                 (unsigned long long)key);
+        if (old == kEmpty || old == key) break;
+        s = (s + 1) & (kW - 1);
       }
-      if ((e & 0xFFFFFFFF00000000ull) == tag && keys[(uint32_t)e] == key) {
-        // the entry's index only decreases: a copy above the index it sees cannot lower it, so
-        // only lower copies pay an atomic (copies of a hot key stop contending on one address)
-        const uint32_t held = (uint32_t)e;
-        uint32_t prev = held;
-        if ((uint32_t)i < held) prev = (uint32_t)amin64(&t.dd[h], mine);
-        t.dmark[i] = 1;
-        if (!t.dmark[prev]) t.dmark[prev] = 1;
-        break;
-      }
-      h = (h + 1) & dmask;
+      atomicMin(&wmin[s], (uint32_t)i);
+      atomicAdd(&wcnt[s], 1u);
     }
+    __syncthreads();
+    if (normal) {
+      if (wcnt[s] > 1) t.dmark[i] = 1;
+      if (wmin[s] == (uint32_t)i) {  // the window's representative of this key
+        const uint64_t tag = mix & 0xFFFFFFFF00000000ull;
+        const uint64_t mine = tag | (uint64_t)i;
+        uint32_t h = (uint32_t)mix & dmask;
+        for (uint32_t probe = 0; probe <= dmask; ++probe) {
+          uint64_t e = t.dd[h];
+          if (e == kEmpty) {
+            uint64_t expected = kEmpty;
+            if (cas64(&t.dd[h], expected, mine)) break;
+            e = expected;
+          }
+          if ((e & 0xFFFFFFFF00000000ull) == tag && keys[(uint32_t)e] == key) {
+            const uint32_t held = (uint32_t)e;
+            uint32_t prev = held;
+            if ((uint32_t)i < held) prev = (uint32_t)amin64(&t.dd[h], mine);
+            t.dmark[i] = 1;
+            if (!t.dmark[prev]) t.dmark[prev] = 1;
+            break;
+          }
+          h = (h + 1) & dmask;
+        }
+      }
+    }
+    __syncthreads();  // the window's LDS table is reused by the next window
   }
 }
 
