@@ -47,7 +47,10 @@ struct Req {
 inline void* mapped(const void* h) {
   if (!h) return nullptr;
   void* d = nullptr;
-  if (hipHostGetDevicePointer(&d, const_cast<void*>(h), 0) != hipSuccess) return nullptr;
+  if (hipHostGetDevicePointer(&d, const_cast<void*>(h), 0) != hipSuccess) {
+    (void)hipGetLastError();  // pageable memory: an expected miss, not a pending error for later calls
+    return nullptr;
+  }
   return d;
 }
 

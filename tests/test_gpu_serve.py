@@ -177,3 +177,45 @@ def test_full_size_serving_sampled_tables(dev):
         mine = [r for r in reqs if r.table == t]
         check_same(mine, replay([o if i == t else None for i in range(len(sv.entries))], mine))
         assert tables[t].size() == o.size()
+
+
+@pytest.mark.parametrize("memory", ["pageable", "pinned_views"])
+def test_native_server_host_memory_kinds(dev, memory):
+    """Pageable host arrays take the DMA copies, slices inside pinned allocations the copy kernels;
+    both give the oracle's results."""
+    sv = small_workload()
+    tables = build_tables(sv, dev)
+    reqs = draw(sv, 120)
+    srv = ct.NativeServer(tables, 1 << 22, streams=3, max_inflight=8, device=dev)
+    outs = []
+    pin = memory == "pinned_views"
+    for r in reqs:
+        n = r.keys.size
+        # arrays at an odd 8-byte offset inside a larger allocation
+        kb = torch.empty(n + 1, dtype=torch.int64, pin_memory=pin)
+        kb[1:] = torch.from_numpy(r.keys.view(np.int64))
+        vb = None
+        if r.vals is not None:
+            vb = torch.empty(n + 1, dtype=torch.int64, pin_memory=pin)
+            vb[1:] = torch.from_numpy(r.vals.view(np.int64))
+        fb = torch.full((n + 3,), 9, dtype=torch.uint8, pin_memory=pin)
+        ob = torch.zeros(n + 1, dtype=torch.int64, pin_memory=pin) if r.kind == "find" else None
+        srv.submit(r.table, {"insert": ct.OP_INSERT, "find": ct.OP_FIND, "erase": ct.OP_ERASE}[r.kind],
+                   kb[1:], None if vb is None else vb[1:], None if ob is None else ob[1:], fb[3:])
+        outs.append((kb, vb, fb, ob))
+    srv.wait_idle()
+    tk, _, _, st = srv.poll(len(reqs) + 1)
+    assert sorted(tk.tolist()) == list(range(len(reqs))) and not st.any()
+    srv.close()
+    exp = replay(oracle_tables(sv), reqs)
+    for r, (kb, vb, fb, ob) in zip(reqs, outs):
+        e = exp[r.rid]
+        f = fb[3:].numpy()
+        if r.kind == "insert":
+            np.testing.assert_array_equal(f, e["status"])
+        elif r.kind == "find":
+            np.testing.assert_array_equal(f, e["found"])
+            np.testing.assert_array_equal(ob[1:].numpy().view(np.uint64), e["vals"])
+        else:
+            np.testing.assert_array_equal(f, e["erased"])
+        assert fb[:3].tolist() == [9, 9, 9]   # nothing written before the array
