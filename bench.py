@@ -42,12 +42,18 @@ KERNEL_SOURCES = ["include/ct.h", "paper_1908_05936_amd/csrc/ct_device.h",
 
 
 def kernel_source_hash() -> str:
+    """SHA-256 of the kernel sources with comments and blank space removed, so that recorded
+    counter figures stay attached to the code they measured and not to its comments."""
     import hashlib
+    import re
 
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, f), encoding="utf-8") as fh:
+            src = fh.read()
+        src = re.sub(r"/\*.*?\*/", " ", src, flags=re.S)   # block comments
+        src = re.sub(r"//[^\n]*", " ", src)                  # line comments
+        h.update(" ".join(src.split()).encode())
     return h.hexdigest()
 
 

@@ -21,6 +21,11 @@
  *    are reported in the status arrays and OR-ed into a sticky device error word (ct_get_error).
  *  * Every 2^64 key value is a legal key: occupancy is kept without reserving key values
  *    (the indicator principle of Section 5.1).
+ *  * Memory order: inside a batch, slots are claimed with relaxed compare-and-swap at device
+ *    (agent) scope; a claim only has to be unique, since equal keys of one batch are resolved to
+ *    their lowest index before any claim.  Batches are ordered by the stream: the outputs of a
+ *    call, and the table state it leaves, are visible to work enqueued after it on the same
+ *    stream (or after an event that follows it); the host sees them after synchronising.
  *
  * Batch semantics
  * ---------------

@@ -1,17 +1,18 @@
 // ct_device.h -- device-side layout and wave64 helpers of the batch hash containers (gfx950).
 //
 // Layout of a table buffer (one caller-owned device allocation):
-//   [Header, 256 B][home buckets: nb x 128 B][dedup buckets][dup list][flags][refs][tile sums]
+//   [Header, 256 B][buckets: nb x 128 B][dedup scratch, or the bins of the binned dedup with the
+//   dedup scratch aliasing the coarse bins][marks][dup list][flags][refs][tile sums][block sums]
 //
-// Home buckets.  A bucket is one 128-byte line of 8 slots {u64 key, u64 value}.  A key's home
-// bucket is h(key) mod nb; a key that does not fit overflows into the following buckets
-// (cyclically), so every one of the 8*nb slots can hold any key and the fixed capacity of
-// Section 4 is a hard guarantee.  Occupancy is kept in the key word with two reserved bit
+// Buckets.  A bucket is one 128-byte line of 8 slots {u64 key, u64 value}.  A key's probe
+// sequence starts at its home bucket and steps by a key-dependent stride (double hashing) that
+// visits all nb buckets, so every one of the 8*nb slots can hold any key and the fixed capacity
+// of Section 4 is a hard guarantee.  Occupancy is kept in the key word with two reserved bit
 // patterns, kEmpty and kTomb; the two keys that share those patterns are stored out of band in
 // the header (spec_*), so every 2^64 key value stays legal (the indicator principle of
 // Section 5.1 without a separate bitset).
 //
-// Probe rule.  A lookup scans buckets from home and stops at the first bucket holding the key or
+// Probe rule.  A lookup scans its probe sequence and stops at the first bucket holding the key or
 // holding a kEmpty slot.  Inserts claim the first free (kEmpty or kTomb) slot at or before the
 // first bucket that holds a kEmpty slot, so every live key is reachable.  Erase writes kEmpty
 // when its bucket already holds a kEmpty slot (no probe sequence passes such a bucket) and kTomb
