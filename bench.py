@@ -111,9 +111,11 @@ def to_dev(a, dev):
     return torch.from_numpy(np.ascontiguousarray(a).view(np.int64)).to(dev)
 
 
-def measure_ceilings(ct, torch, dev, nlines, find_keys, uniform_keys):
+def measure_ceilings(ct, torch, dev, nlines, find_keys, uniform_keys, fill_keys=None):
     """Random 128-byte line gathers (R1), gather + CAS (R2), bare CAS (R3), stream copy (R4) at
-    the table's footprint; R5 replays the find's own key stream through the R1 kernel."""
+    the table's footprint (nlines = the table's bucket count, so a key's line is its home
+    bucket); R5 replays the find's own key stream through the R1 kernel and the fill's key stream
+    through the R2 kernel."""
     buf = torch.zeros(nlines * 128, dtype=torch.uint8, device=dev)
     out = torch.empty(uniform_keys.numel(), dtype=torch.int64, device=dev)
     res = {}
@@ -146,6 +148,11 @@ def measure_ceilings(ct, torch, dev, nlines, find_keys, uniform_keys):
     out2 = torch.empty(find_keys.numel(), dtype=torch.int64, device=dev)
     t = timed(lambda: ct.gather(buf, nlines, 128, find_keys, out2))
     res["R5_find_stream_Mlines_s"] = find_keys.numel() / t / 1e6
+    if fill_keys is not None:
+        del out2
+        out2 = torch.empty(fill_keys.numel(), dtype=torch.int64, device=dev)
+        t = timed(lambda: ct.gather(buf, nlines, 128, fill_keys, out2, cas=True))
+        res["R5_insert_stream_Mops_s"] = fill_keys.numel() / t / 1e6
     del buf, out, out2
     torch.cuda.empty_cache()
     # the same gathers (and gather + CAS) over the footprints of the other workloads: L2 (4 MiB
@@ -401,12 +408,13 @@ def main():
         uni = torch.from_numpy(rng.integers(0, 1 << 63, size=n_find, dtype=np.int64)).to(dev)
         del vals_out, found
         torch.cuda.empty_cache()
-        ceil = measure_ceilings(ct, torch, dev, cap // 8, Q, uni)
+        ceil = measure_ceilings(ct, torch, dev, table.bucket_count, Q, uni, K_fill)
         f_mops = breakdown["find"]["Mops_s"]
         i_mops = breakdown["insert_fill"]["Mops_s"]
         ceil["find_frac_of_R1"] = f_mops / ceil["R1_gather128_Mlines_s"]
         ceil["find_frac_of_R5"] = f_mops / ceil["R5_find_stream_Mlines_s"]
         ceil["insert_frac_of_R2"] = i_mops / ceil["R2_gather128_cas_Mops_s"]
+        ceil["insert_frac_of_R5"] = i_mops / ceil["R5_insert_stream_Mops_s"]
         if "find_uniform_Mops_s" in line:
             ceil["find_uniform_frac_of_R1"] = (line["find_uniform_Mops_s"]
                                                / ceil["R1_gather128_Mlines_s"])
