@@ -250,14 +250,22 @@ ct_status ct_graph_destroy(void *graph_exec);
    steps still run in schedule order and every result equals that of the single-table calls.
    The step descriptors live in a caller-provided device buffer. */
 
-/* Bytes of device memory the grouped form of `p` needs (host only). */
-ct_status ct_plan_group_bytes(ct_plan *p, int64_t *bytes);
+/* Options of the grouped form. */
+#define CT_GROUP_MERGE_RUNS 1 /* a run of consecutive operations of one kind on one table runs as
+                                 one operation over a contiguous copy of its arrays (gathered from
+                                 the operations' arrays before the first level and scattered back
+                                 after the last): fewer, larger steps and levels, for up to
+                                 (8 + 2 value widths + 1) bytes per merged element of device
+                                 memory in the grouped form's buffer */
 
-/* Build the grouped form of `p` into `d_buf` (device, `bytes` >= ct_plan_group_bytes, 256-byte
-   aligned, owned by the caller and kept alive and unmodified while the grouped form is used).
-   Copies synchronously.  Adding an operation to `p` afterwards invalidates the grouped form
-   (launching it then returns CT_E_INVALID until it is built again). */
-ct_status ct_plan_group(ct_plan *p, void *d_buf, int64_t bytes);
+/* Bytes of device memory the grouped form of `p` with `options` needs (host only). */
+ct_status ct_plan_group_bytes(ct_plan *p, int32_t options, int64_t *bytes);
+
+/* Build the grouped form of `p` into `d_buf` (device, `bytes` >= ct_plan_group_bytes with the
+   same options, 256-byte aligned, owned by the caller and kept alive and unmodified while the
+   grouped form is used).  Copies synchronously.  Adding an operation to `p` afterwards
+   invalidates the grouped form (launching it then returns CT_E_INVALID until it is built again). */
+ct_status ct_plan_group(ct_plan *p, int32_t options, void *d_buf, int64_t bytes);
 
 /* Launches and steps of the grouped form (either pointer nullable). */
 ct_status ct_plan_group_info(ct_plan *p, int64_t *nlaunches, int64_t *nsteps);

@@ -35,7 +35,7 @@ def main(argv=None):
     torch.cuda.empty_cache()
     log(f"[multi] tuned: {cfg}")
     we = multi_table(seed=a.eval_seed)
-    res = measure(we, dev, {k: cfg[k] for k in ("lanes", "chunk", "provision")})
+    res = measure(we, dev, {k: cfg[k] for k in ("lanes", "merge", "chunk", "provision")})
     res["tuned_on_seed"] = a.tune_seed
     res["evaluated_on_seed"] = a.eval_seed
     res["tuning"] = cfg

@@ -1346,6 +1346,37 @@ __global__ __launch_bounds__(kBlock) void k_g_final(const GStep* __restrict__ st
     final_tile<0, 0>(t, nullptr, nullptr, g.keys, nullptr, g.q, g.flags, nullptr, L.lb);
 }
 
+// A byte range moved by the grouped plan's copy stages (operations merged into one step).
+struct GCopy {
+  const void* src;
+  void* dst;
+  int64_t bytes;
+};
+
+// Segment of this block's entry, copied by the entry's blocks in the widest aligned unit.
+__global__ __launch_bounds__(kBlock) void k_g_copy(const GCopy* __restrict__ segs,
+                                                   const GEntry* __restrict__ e, int32_t n) {
+  const GLoc L = g_locate(e, n);
+  const GCopy g = segs[L.step];
+  const uintptr_t a = reinterpret_cast<uintptr_t>(g.src) | reinterpret_cast<uintptr_t>(g.dst) |
+                      (uintptr_t)g.bytes;
+  const int64_t first = (int64_t)L.lb * kBlock + threadIdx.x;
+  const int64_t stride = (int64_t)L.nblk * kBlock;
+  if ((a & 15) == 0) {
+    const uint4* s = static_cast<const uint4*>(g.src);
+    uint4* d = static_cast<uint4*>(g.dst);
+    for (int64_t i = first; i < g.bytes / 16; i += stride) d[i] = s[i];
+  } else if ((a & 7) == 0) {
+    const uint64_t* s = static_cast<const uint64_t*>(g.src);
+    uint64_t* d = static_cast<uint64_t*>(g.dst);
+    for (int64_t i = first; i < g.bytes / 8; i += stride) d[i] = s[i];
+  } else {
+    const uint8_t* s = static_cast<const uint8_t*>(g.src);
+    uint8_t* d = static_cast<uint8_t*>(g.dst);
+    for (int64_t i = first; i < g.bytes; i += stride) d[i] = s[i];
+  }
+}
+
 __global__ __launch_bounds__(kBlock) void k_g_fix(const GStep* __restrict__ st,
                                                   const GEntry* __restrict__ e, int32_t n) {
   const GLoc L = g_locate(e, n);
@@ -2013,6 +2044,7 @@ struct ct_plan {
   std::vector<ct_group::Launch> glaunch;
   const void* gsteps = nullptr;    // device: GStep[]
   const void* gentries = nullptr;  // device: GEntry[]
+  const void* gcopies = nullptr;   // device: GCopy[] of the merged operations' copy stages
   size_t grouped_ops = (size_t)-1;
 };
 
@@ -2058,8 +2090,15 @@ ct_status run_op(const PlanOp& o, hipStream_t s) {
 }
 
 enum GStage : int32_t {
-  gReset, gPro, gDedup, gFind, gInsert, gErase, gApply, gCount, gScan, gFinal, gFix, gStages
+  gReset, gPro, gDedup, gFind, gInsert, gErase, gApply, gCount, gScan, gFinal, gFix, gStages,
+  gCopy = 100  // copy stage of merged operations (before the first and after the last level)
 };
+
+// Copy-stage blocks for a segment: enough 256-thread blocks for 16-byte units, at most 2048.
+int copy_blocks(int64_t bytes) {
+  const int64_t b = (bytes / 16 + kBlock - 1) / kBlock;
+  return (int)std::max<int64_t>(1, std::min<int64_t>(b, 2048));
+}
 
 bool inserts_or_erases(const GStep& g) { return g.type == kOpInsert || g.type == kOpErase; }
 
@@ -2082,97 +2121,227 @@ int stage_blocks(int stage, const GStep& g) {
   return 0;
 }
 
+// The grouped form of a plan, built on the host.  `base` is the device buffer the form will live
+// in (null while only sizing it): steps, entries, copy segments, then the merge area.
+struct GroupForm {
+  std::vector<GStep> steps;
+  std::vector<GEntry> entries;
+  std::vector<GCopy> copies;
+  std::vector<ct_group::Launch> launches;
+  int64_t merge_bytes = 0;
+  int64_t steps_off = 0, entries_off = 0, copies_off = 0, merge_off = 0, total = 0;
+};
+
 // Cut the plan into chunk-steps, assign each the per-table ordinal as its level, and lay out one
-// launch per (level, stage) that has steps.  Host only.
-ct_status group_build(const ct_plan* p, std::vector<GStep>& steps, std::vector<GEntry>& entries,
-                      std::vector<ct_group::Launch>& launches) {
-  std::vector<int32_t> level;
-  std::vector<int32_t> next(p->tables.size(), 0);
-  for (const PlanOp& o : p->ops) {
-    ct_table* t = o.t;
-    const size_t ti = (size_t)(std::find(p->tables.begin(), p->tables.end(), t) - p->tables.begin());
-    const int vk = t->desc.val_kind;
-    const int64_t vb = vk == CT_VAL_U32 ? 4 : 8;
-    const bool ie = o.type == kOpInsert || o.type == kOpErase;
-    const int64_t span = ie ? t->chunk : std::max<int64_t>(o.n, 1);
-    for (int64_t c0 = 0; c0 < std::max<int64_t>(o.n, 1); c0 += span) {
-      const int64_t q = o.type == kOpClear ? 0 : std::min<int64_t>(span, o.n - c0);
-      GStep g{};
-      g.v = t->v;
-      g.type = o.type;
-      g.vk = vk;
-      g.q = q;
-      g.keys = o.keys ? o.keys + c0 : nullptr;
-      g.vals = (o.type == kOpInsert && vk != CT_VAL_NONE)
-                   ? static_cast<const uint8_t*>(o.vals) + c0 * vb : nullptr;
-      g.vout = (o.type == kOpFind && o.vout) ? static_cast<uint8_t*>(o.vout) + c0 * vb : nullptr;
-      g.flags = o.flags ? o.flags + c0 : nullptr;
-      g.db = ie ? dedup_slots_for(q) : 0u;
-      g.gb = group_blocks((q + kSlots - 1) / kSlots);
-      g.ntiles = (int32_t)((q + kTile - 1) / kTile);
-      steps.push_back(g);
-      level.push_back(next[ti]++);
+// launch per (level, stage) that has steps.  With CT_GROUP_MERGE_RUNS, a run of consecutive
+// operations of one kind on one table becomes one operation over a contiguous copy of its arrays
+// in the merge area (a batch equals its parts applied in order), gathered before the first level
+// and scattered back after the last.  Host only.
+ct_status group_build(const ct_plan* p, int32_t options, uint8_t* base, GroupForm& F) {
+  const bool merge = (options & CT_GROUP_MERGE_RUNS) != 0;
+  struct Eff {  // an operation of one table as it will be cut into steps
+    PlanOp op;
+    size_t first, count;  // its run of plan operations
+  };
+  std::vector<std::vector<Eff>> per(p->tables.size());
+  for (size_t k = 0; k < p->ops.size(); ++k) {
+    const PlanOp& o = p->ops[k];
+    const size_t ti = (size_t)(std::find(p->tables.begin(), p->tables.end(), o.t) - p->tables.begin());
+    std::vector<Eff>& v = per[ti];
+    if (merge && o.type != kOpClear && !v.empty() && v.back().op.type == o.type) {
+      v.back().count += 1;
+      v.back().op.n += o.n;
+    } else {
+      v.push_back(Eff{o, k, 1});
     }
   }
+  // merge area: contiguous arrays for every run of two or more operations
+  std::vector<GCopy> copy_out;
+  int64_t moff = 0;
+  auto take = [&](int64_t bytes) {
+    const int64_t o = moff;
+    moff += align_up(bytes);
+    return o;
+  };
+  struct Fix {  // device addresses of a merged run's arrays, as offsets into the merge area
+    int64_t keys = -1, vals = -1, flags = -1, vout = -1;
+  };
+  std::vector<std::vector<Fix>> fixes(per.size());
+  for (size_t ti = 0; ti < per.size(); ++ti) {
+    fixes[ti].resize(per[ti].size());
+    for (size_t r = 0; r < per[ti].size(); ++r) {
+      const Eff& e = per[ti][r];
+      if (e.count < 2) continue;
+      const ct_table* t = e.op.t;
+      const int vk = t->desc.val_kind;
+      const int64_t vb = vk == CT_VAL_U32 ? 4 : 8;
+      bool want_flags = false, want_vout = false;
+      for (size_t k = e.first, c = 0; c < e.count; ++k) {
+        const PlanOp& o = p->ops[k];
+        if (o.t != t) continue;
+        want_flags = want_flags || o.flags;
+        want_vout = want_vout || o.vout;
+        ++c;
+      }
+      Fix& f = fixes[ti][r];
+      f.keys = take(e.op.n * 8);
+      if (e.op.type == kOpInsert && vk != CT_VAL_NONE) f.vals = take(e.op.n * vb);
+      if (want_flags) f.flags = take(e.op.n);
+      if (e.op.type == kOpFind && vk != CT_VAL_NONE && want_vout) f.vout = take(e.op.n * vb);
+    }
+  }
+  F.merge_bytes = moff;
+  // device layout: steps | entries | copies | merge area (filled in below once counts are known)
+  // while only sizing, a placeholder base keeps every merged array non-null, so the steps and
+  // their stages (a fix stage needs a status array) are the same as when building
+  uint8_t* const b0 = base ? base : reinterpret_cast<uint8_t*>((uintptr_t)kAlign);
+  auto dev = [&](int64_t merge_off) -> uint8_t* { return b0 + F.merge_off + merge_off; };
+
+  std::vector<int32_t> level;
+  std::vector<GCopy> copy_in;
+  // first pass only counts steps and copies so the layout offsets are known; the second fills
+  for (int pass = 0; pass < 2; ++pass) {
+    F.steps.clear();
+    level.clear();
+    copy_in.clear();
+    copy_out.clear();
+    for (size_t ti = 0; ti < per.size(); ++ti) {
+      int32_t lev = 0;
+      for (size_t r = 0; r < per[ti].size(); ++r) {
+        const Eff& e = per[ti][r];
+        PlanOp o = e.op;
+        ct_table* t = o.t;
+        const int vk = t->desc.val_kind;
+        const int64_t vb = vk == CT_VAL_U32 ? 4 : 8;
+        if (e.count >= 2) {
+          const Fix& f = fixes[ti][r];
+          uint8_t* mk = dev(f.keys);
+          uint8_t* mv = f.vals >= 0 ? dev(f.vals) : nullptr;
+          uint8_t* mf = f.flags >= 0 ? dev(f.flags) : nullptr;
+          uint8_t* mo = f.vout >= 0 ? dev(f.vout) : nullptr;
+          int64_t pos = 0;
+          for (size_t k = e.first, c = 0; c < e.count; ++k) {
+            const PlanOp& part = p->ops[k];
+            if (part.t != t) continue;
+            ++c;
+            copy_in.push_back(GCopy{part.keys, mk + pos * 8, part.n * 8});
+            if (mv) copy_in.push_back(GCopy{part.vals, mv + pos * vb, part.n * vb});
+            if (mf && part.flags) copy_out.push_back(GCopy{mf + pos, part.flags, part.n});
+            if (mo && part.vout) copy_out.push_back(GCopy{mo + pos * vb, part.vout, part.n * vb});
+            pos += part.n;
+          }
+          o.keys = reinterpret_cast<const uint64_t*>(mk);
+          o.vals = mv;
+          o.flags = mf;
+          o.vout = mo;
+        }
+        const bool ie = o.type == kOpInsert || o.type == kOpErase;
+        const int64_t span = ie ? t->chunk : std::max<int64_t>(o.n, 1);
+        for (int64_t c0 = 0; c0 < std::max<int64_t>(o.n, 1); c0 += span) {
+          const int64_t q = o.type == kOpClear ? 0 : std::min<int64_t>(span, o.n - c0);
+          GStep g{};
+          g.v = t->v;
+          g.type = o.type;
+          g.vk = vk;
+          g.q = q;
+          g.keys = o.keys ? o.keys + c0 : nullptr;
+          g.vals = (o.type == kOpInsert && vk != CT_VAL_NONE)
+                       ? static_cast<const uint8_t*>(o.vals) + c0 * vb : nullptr;
+          g.vout = (o.type == kOpFind && o.vout) ? static_cast<uint8_t*>(o.vout) + c0 * vb : nullptr;
+          g.flags = o.flags ? o.flags + c0 : nullptr;
+          g.db = ie ? dedup_slots_for(q) : 0u;
+          g.gb = group_blocks((q + kSlots - 1) / kSlots);
+          g.ntiles = (int32_t)((q + kTile - 1) / kTile);
+          F.steps.push_back(g);
+          level.push_back(lev++);
+        }
+      }
+    }
+    F.copies = copy_in;
+    F.copies.insert(F.copies.end(), copy_out.begin(), copy_out.end());
+    F.steps_off = 0;
+    F.entries_off = align_up((int64_t)(F.steps.size() * sizeof(GStep)));
+    // entries: one per (level, stage, step) plus one per copy segment (bounded by a count pass)
+    int64_t nent = (int64_t)F.copies.size();
+    for (const GStep& g : F.steps)
+      for (int stage = 0; stage < gStages; ++stage) nent += stage_blocks(stage, g) ? 1 : 0;
+    F.copies_off = F.entries_off + align_up(nent * (int64_t)sizeof(GEntry));
+    F.merge_off = F.copies_off + align_up((int64_t)(F.copies.size() * sizeof(GCopy)));
+    F.total = std::max<int64_t>(kAlign, F.merge_off + F.merge_bytes);
+  }
+  // launches: copy in, the levels, copy out
+  F.entries.clear();
+  F.launches.clear();
+  auto copy_launch = [&](size_t from, size_t to) {
+    if (from == to) return CT_OK;
+    int64_t blocks = 0;
+    const int64_t off = (int64_t)F.entries.size();
+    for (size_t i = from; i < to; ++i) {
+      F.entries.push_back(GEntry{(int32_t)blocks, (int32_t)i});
+      blocks += copy_blocks(F.copies[i].bytes);
+      if (blocks > (int64_t)INT32_MAX / 2) return CT_E_INVALID;
+    }
+    F.launches.push_back(ct_group::Launch{gCopy, (int32_t)(to - from), (int32_t)blocks, off});
+    return CT_OK;
+  };
+  if (copy_launch(0, copy_in.size()) != CT_OK) return CT_E_INVALID;
   int32_t nlev = 0;
   for (int32_t l : level) nlev = std::max(nlev, l + 1);
   std::vector<std::vector<int32_t>> by_level(nlev);
-  for (size_t i = 0; i < steps.size(); ++i) by_level[level[i]].push_back((int32_t)i);
+  for (size_t i = 0; i < F.steps.size(); ++i) by_level[level[i]].push_back((int32_t)i);
   for (int32_t l = 0; l < nlev; ++l) {
     for (int stage = 0; stage < gStages; ++stage) {
       int64_t blocks = 0;
-      const int64_t off = (int64_t)entries.size();
+      const int64_t off = (int64_t)F.entries.size();
       for (int32_t i : by_level[l]) {
-        const int b = stage_blocks(stage, steps[i]);
+        const int b = stage_blocks(stage, F.steps[i]);
         if (!b) continue;
-        entries.push_back(GEntry{(int32_t)blocks, i});
+        F.entries.push_back(GEntry{(int32_t)blocks, i});
         blocks += b;
         if (blocks > (int64_t)INT32_MAX / 2) return CT_E_INVALID;
       }
-      const int64_t n = (int64_t)entries.size() - off;
-      if (n) launches.push_back(ct_group::Launch{stage, (int32_t)n, (int32_t)blocks, off});
+      const int64_t n = (int64_t)F.entries.size() - off;
+      if (n) F.launches.push_back(ct_group::Launch{stage, (int32_t)n, (int32_t)blocks, off});
     }
   }
+  if (copy_launch(copy_in.size(), F.copies.size()) != CT_OK) return CT_E_INVALID;
   return CT_OK;
 }
-
-int64_t group_steps_bytes(size_t nsteps) { return align_up((int64_t)(nsteps * sizeof(GStep))); }
 
 }  // namespace
 
 extern "C" {
 
-ct_status ct_plan_group_bytes(ct_plan* p, int64_t* bytes) {
-  if (!p || !bytes) return CT_E_INVALID;
-  std::vector<GStep> steps;
-  std::vector<GEntry> entries;
-  std::vector<ct_group::Launch> launches;
-  ct_status r = group_build(p, steps, entries, launches);
+ct_status ct_plan_group_bytes(ct_plan* p, int32_t options, int64_t* bytes) {
+  if (!p || !bytes || (options & ~CT_GROUP_MERGE_RUNS)) return CT_E_INVALID;
+  GroupForm F;
+  ct_status r = group_build(p, options, nullptr, F);
   if (r != CT_OK) return r;
-  *bytes = std::max<int64_t>(kAlign, group_steps_bytes(steps.size()) +
-                                         (int64_t)(entries.size() * sizeof(GEntry)));
+  *bytes = F.total;
   return CT_OK;
 }
 
-ct_status ct_plan_group(ct_plan* p, void* d_buf, int64_t bytes) {
+ct_status ct_plan_group(ct_plan* p, int32_t options, void* d_buf, int64_t bytes) {
   if (!p || !d_buf || reinterpret_cast<uintptr_t>(d_buf) % kAlign) return CT_E_INVALID;
-  std::vector<GStep> steps;
-  std::vector<GEntry> entries;
-  std::vector<ct_group::Launch> launches;
-  ct_status r = group_build(p, steps, entries, launches);
-  if (r != CT_OK) return r;
-  const int64_t sb = group_steps_bytes(steps.size());
-  const int64_t eb = (int64_t)(entries.size() * sizeof(GEntry));
-  if (bytes < std::max<int64_t>(kAlign, sb + eb)) return CT_E_INVALID;
+  if (options & ~CT_GROUP_MERGE_RUNS) return CT_E_INVALID;
   uint8_t* base = static_cast<uint8_t*>(d_buf);
-  if (!steps.empty() &&
-      hipMemcpy(base, steps.data(), steps.size() * sizeof(GStep), hipMemcpyHostToDevice) != hipSuccess)
+  GroupForm F;
+  ct_status r = group_build(p, options, base, F);
+  if (r != CT_OK) return r;
+  if (bytes < F.total) return CT_E_INVALID;
+  if (!F.steps.empty() && hipMemcpy(base + F.steps_off, F.steps.data(), F.steps.size() * sizeof(GStep),
+                                    hipMemcpyHostToDevice) != hipSuccess)
     return CT_E_HIP;
-  if (eb && hipMemcpy(base + sb, entries.data(), (size_t)eb, hipMemcpyHostToDevice) != hipSuccess)
+  if (!F.entries.empty() && hipMemcpy(base + F.entries_off, F.entries.data(),
+                                      F.entries.size() * sizeof(GEntry), hipMemcpyHostToDevice) != hipSuccess)
     return CT_E_HIP;
-  p->glaunch = std::move(launches);
-  p->gsteps = base;
-  p->gentries = base + sb;
+  if (!F.copies.empty() && hipMemcpy(base + F.copies_off, F.copies.data(),
+                                     F.copies.size() * sizeof(GCopy), hipMemcpyHostToDevice) != hipSuccess)
+    return CT_E_HIP;
+  p->glaunch = std::move(F.launches);
+  p->gsteps = base + F.steps_off;
+  p->gentries = base + F.entries_off;
+  p->gcopies = base + F.copies_off;
   p->grouped_ops = p->ops.size();
   return CT_OK;
 }
@@ -2196,6 +2365,9 @@ ct_status ct_plan_launch_grouped(ct_plan* p, void* stream) {
       case gScan: k_g_tile_scan<<<L.blocks, 1024, 0, s>>>(st, e, L.n); break;
       case gFinal: k_g_final<<<L.blocks, kBlock, 0, s>>>(st, e, L.n); break;
       case gFix: k_g_fix<<<L.blocks, kBlock, 0, s>>>(st, e, L.n); break;
+      case gCopy:
+        k_g_copy<<<L.blocks, kBlock, 0, s>>>(static_cast<const GCopy*>(p->gcopies), e, L.n);
+        break;
       default: return CT_E_INVALID;
     }
     if (launched() != CT_OK) return CT_E_HIP;

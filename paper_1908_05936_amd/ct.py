@@ -22,6 +22,7 @@ PRESENT, INSERTED, FULL = 0, 1, 2
 ERR_FULL, ERR_POOL = 1, 2
 KERNELS = ["clear", "prologue", "dedup", "insert", "erase", "apply", "rank", "final", "fix", "find"]
 VAL_NONE, VAL_U32, VAL_U64 = 0, 1, 2
+GROUP_MERGE_RUNS = 1
 OP_CLEAR, OP_INSERT, OP_FIND, OP_ERASE = 0, 1, 2, 3
 HASH_MIX64, HASH_VOXEL21 = 0, 1
 
@@ -83,8 +84,8 @@ SIGNATURES = {
     "ct_plan_info": (C.c_int, [_P, _PI64, _PI64]),
     "ct_plan_launch": (C.c_int, [_P, _I32, _P]),
     "ct_plan_capture": (C.c_int, [_P, _I32, _P, C.POINTER(_P)]),
-    "ct_plan_group_bytes": (C.c_int, [_P, _PI64]),
-    "ct_plan_group": (C.c_int, [_P, _P, _I64]),
+    "ct_plan_group_bytes": (C.c_int, [_P, _I32, _PI64]),
+    "ct_plan_group": (C.c_int, [_P, _I32, _P, _I64]),
     "ct_plan_group_info": (C.c_int, [_P, _PI64, _PI64]),
     "ct_plan_launch_grouped": (C.c_int, [_P, _P]),
     "ct_plan_capture_grouped": (C.c_int, [_P, _P, C.POINTER(_P)]),
@@ -391,13 +392,14 @@ class Plan:
         _check(lib().ct_graph_launch(self._graph, s.cuda_stream), "ct_graph_launch")
 
     # grouped form: one launch per stage per level over all tables
-    def group(self):
+    def group(self, merge_runs: bool = False):
         """Build the grouped form (descriptor buffer allocated here, kept by the plan)."""
+        opt = GROUP_MERGE_RUNS if merge_runs else 0
         nb = C.c_int64(0)
-        _check(lib().ct_plan_group_bytes(self._h, C.byref(nb)), "ct_plan_group_bytes")
+        _check(lib().ct_plan_group_bytes(self._h, opt, C.byref(nb)), "ct_plan_group_bytes")
         self._gbuf = torch.empty(nb.value, dtype=torch.uint8, device=self.device)
         torch.cuda.synchronize(self.device)
-        _check(lib().ct_plan_group(self._h, _ptr(self._gbuf), nb.value), "ct_plan_group")
+        _check(lib().ct_plan_group(self._h, opt, _ptr(self._gbuf), nb.value), "ct_plan_group")
 
     def group_info(self):
         a, b = C.c_int64(0), C.c_int64(0)

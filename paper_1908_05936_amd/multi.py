@@ -8,6 +8,8 @@ Autotuner.  The knobs of a plan run are
                    table); 1..8: side streams the tables are spread over, each operation running
                    its own pipeline (operations on different tables overlap on the device; a
                    table's operations keep their order),
+  * merge       -- grouped form only: merge each table's runs of same-kind operations into one
+                   operation over gathered copies (fewer levels and launches, more memory),
   * chunk       -- per-table insert/erase chunk (a larger chunk means fewer chained sub-operations
                    for big batches on small tables, at 34 bytes of scratch per chunk element),
   * provision   -- physical slots per requested capacity (1.0 = the requested load factor; more
@@ -30,7 +32,7 @@ import torch
 from . import ct
 
 OPS = {"insert": ct.OP_INSERT, "find": ct.OP_FIND, "erase": ct.OP_ERASE}
-DEFAULT = dict(lanes=0, chunk=0, provision=1.0)
+DEFAULT = dict(lanes=0, merge=False, chunk=0, provision=1.0)
 
 
 def _g64(a, dev):
@@ -109,11 +111,11 @@ def time_fn(fn, reps=3, warmup=1):
     return float(np.median(ts))
 
 
-def runner(p: ct.Plan, lanes: int):
+def runner(p: ct.Plan, lanes: int, merge: bool = False):
     """Callable running plan `p` once: grouped (lanes 0, built on first use) or on side streams."""
     if lanes == 0:
         if getattr(p, "_gbuf", None) is None:
-            p.group()
+            p.group(merge_runs=merge)
         return p.launch_grouped
     return lambda: p.launch(lanes)
 
@@ -125,7 +127,8 @@ def signature(w: dict) -> str:
 
 
 def tune(w: dict, dev, cache: str | None = None, reps: int = 3, log=print) -> dict:
-    """Coordinate descent over lanes, chunk and provision on schedule `w`."""
+    """Coordinate descent over lanes, chunk, provision and run merging on schedule `w` (up to two
+    sweeps over the knobs)."""
     key = f"{torch.cuda.get_device_name(dev)}|{signature(w)}"
     if cache and os.path.exists(cache):
         try:
@@ -146,21 +149,28 @@ def tune(w: dict, dev, cache: str | None = None, reps: int = 3, log=print) -> di
             built[wk] = Workload(w, dev, chunk=cfg["chunk"], provision=cfg["provision"])
         wl = built[wk]
         p = wl.plan()
-        t = time_fn(runner(p, cfg["lanes"]), reps=reps)
+        t = time_fn(runner(p, cfg["lanes"], cfg.get("merge", False)), reps=reps)
         trials.append(dict(cfg, seconds=t))
         log(f"[tune] {cfg} -> {t * 1e3:.2f} ms")
         return t
 
     best_t = run(best)
-    space = [("lanes", [0, 1, 2, 4, 8]), ("chunk", [0, -1]), ("provision", [1.0, 1.25, 1.5])]
-    for name, values in space:
-        for v in values:
-            if v == best[name]:
-                continue
-            cfg = dict(best, **{name: v})
-            t = run(cfg)
-            if t < best_t:
-                best, best_t = cfg, t
+    space = [("lanes", [0, 1, 2, 4, 8]), ("chunk", [0, -1]), ("provision", [1.0, 1.25, 1.5]),
+             ("merge", [False, True])]
+    seen = {repr(sorted(best.items()))}
+    for sweep in range(2):  # a second sweep revisits each knob at the others' new values
+        improved = False
+        for name, values in space:
+            for v in values:
+                cfg = dict(best, **{name: v})
+                if repr(sorted(cfg.items())) in seen:
+                    continue
+                seen.add(repr(sorted(cfg.items())))
+                t = run(cfg)
+                if t < best_t:
+                    best, best_t, improved = cfg, t, True
+        if not improved:
+            break
     result = dict(best, seconds=best_t, trials=len(trials))
     if cache:
         try:
@@ -177,7 +187,7 @@ def measure(w: dict, dev, cfg: dict, reps: int = 5, graph_replays: int = 10) -> 
     """Plan run, its HIP-graph replay and one-stream per-batch calls on schedule `w` with `cfg`."""
     wl = Workload(w, dev, chunk=cfg["chunk"], provision=cfg["provision"])
     p = wl.plan()
-    t_plan = time_fn(runner(p, cfg["lanes"]), reps=reps)
+    t_plan = time_fn(runner(p, cfg["lanes"], cfg.get("merge", False)), reps=reps)
     s = torch.cuda.Stream(dev)
     if cfg["lanes"] == 0:
         p.capture_grouped(stream=s)

@@ -157,17 +157,20 @@ def test_plan_full_size(dev):
         assert t.size() == o.size()
 
 
-@pytest.mark.parametrize("chunk", [0, 1024])
-def test_grouped_matches_oracle(dev, chunk):
+@pytest.mark.parametrize("chunk,merge", [(0, False), (1024, False), (0, True), (1024, True)])
+def test_grouped_matches_oracle(dev, chunk, merge):
     """Grouped form: one launch per stage per level over all tables; chunk 1024 cuts the larger
-    batches into several steps (levels) per operation."""
+    batches into several steps (levels) per operation; merged runs turn each table's consecutive
+    same-kind operations into one operation over gathered copies of their arrays."""
     w = small()
     exp, tabs = expected(w)
     r = Run(w, dev, chunk=chunk)
     p = r.plan(dev)
-    p.group()
+    p.group(merge_runs=merge)
     nl, ns = p.group_info()
-    assert ns >= len(w["schedule"]) and nl > 0
+    assert nl > 0 and ns > 0
+    if not merge:   # merging runs gives fewer steps than operations
+        assert ns >= len(w["schedule"])
     p.launch_grouped()
     r.check(exp)
     for t, o in zip(r.tables, tabs):
@@ -178,12 +181,13 @@ def test_grouped_matches_oracle(dev, chunk):
     r.check(exp)
 
 
-def test_grouped_graph_replays_and_invalidation(dev):
+@pytest.mark.parametrize("merge", [False, True])
+def test_grouped_graph_replays_and_invalidation(dev, merge):
     w = small()
     exp, _ = expected(w)
     r = Run(w, dev, provision=1.5)
     p = r.plan(dev)
-    p.group()
+    p.group(merge_runs=merge)
     s = torch.cuda.Stream(dev)
     p.capture_grouped(stream=s)
     for rep in range(4):
@@ -197,13 +201,14 @@ def test_grouped_graph_replays_and_invalidation(dev):
         p.launch_grouped()
 
 
-def test_grouped_full_size(dev):
+@pytest.mark.parametrize("merge", [False, True])
+def test_grouped_full_size(dev, merge):
     """The full schedule grouped: 256 tables of 2^10..2^20 entries, every result bit-exact."""
     w = multi_table(seed=4)
     exp, tabs = expected(w)
     r = Run(w, dev)
     p = r.plan(dev)
-    p.group()
+    p.group(merge_runs=merge)
     p.launch_grouped()
     r.check(exp)
     for t, o in zip(r.tables, tabs):
@@ -234,8 +239,8 @@ def mixed_kinds_schedule(seed=9, n_tables=12, n_ops=160):
     return tables, sched
 
 
-@pytest.mark.parametrize("chunk", [1024, 4096])
-def test_grouped_mixed_value_kinds_and_capacity(dev, chunk):
+@pytest.mark.parametrize("chunk,merge", [(1024, False), (4096, False), (1024, True)])
+def test_grouped_mixed_value_kinds_and_capacity(dev, chunk, merge):
     tables, sched = mixed_kinds_schedule()
     bits = {ct.VAL_NONE: 0, ct.VAL_U32: 32, ct.VAL_U64: 64}
     otabs = [oracle.OracleTable(t["capacity"], bits[t["kind"]]) for t in tables]
@@ -270,7 +275,7 @@ def test_grouped_mixed_value_kinds_and_capacity(dev, chunk):
         outs.append((flags, vout, vk))
     assert any((e[0] == 2).any() for e, (_, kind, _, _) in zip(exp, sched) if kind == "insert"), \
         "the schedule should reach capacity"
-    p.group()
+    p.group(merge_runs=merge)
     p.launch_grouped()
     torch.cuda.synchronize()
     for (flags, vout, vk), (ef, ev) in zip(outs, exp):
