@@ -1,6 +1,7 @@
 """Multi-table schedule benchmark: tune on one seed, evaluate on another.
 
     python -m paper_1908_05936_amd.bench_multi [--tune-seed 4] [--eval-seed 6] [--out FILE]
+        [--config JSON]   (skip tuning, e.g. for a kernel trace of the measured runs only)
 
 Prints one JSON line: the tuned configuration, then for the evaluation schedule the plan run, its
 HIP-graph replay and the same operations as one-stream single-table calls (keys/s and speedup).
@@ -23,19 +24,26 @@ def main(argv=None):
     ap.add_argument("--tune-seed", type=int, default=4)
     ap.add_argument("--eval-seed", type=int, default=6)
     ap.add_argument("--cache", default=None)
+    ap.add_argument("--config", default=None,
+                    help='skip tuning and use this configuration, e.g. '
+                         '\'{"lanes": 0, "merge": true, "chunk": -1, "provision": 1.5}\'')
     ap.add_argument("--out", default=None)
     a = ap.parse_args(argv)
     dev = torch.device("cuda", 0)
     ct.lib()
     log = lambda m: print(m, file=sys.stderr, flush=True)  # noqa: E731
-    log("[multi] generating tuning schedule")
-    wt = multi_table(seed=a.tune_seed)
-    cfg = tune(wt, dev, cache=a.cache, log=log)
-    del wt
-    torch.cuda.empty_cache()
+    if a.config:
+        cfg = dict(json.loads(a.config), trials=0)
+    else:
+        log("[multi] generating tuning schedule")
+        wt = multi_table(seed=a.tune_seed)
+        cfg = tune(wt, dev, cache=a.cache, log=log)
+        del wt
+        torch.cuda.empty_cache()
     log(f"[multi] tuned: {cfg}")
     we = multi_table(seed=a.eval_seed)
-    res = measure(we, dev, {k: cfg[k] for k in ("lanes", "merge", "chunk", "provision")})
+    res = measure(we, dev, {k: cfg.get(k, False) if k == "merge" else cfg[k]
+                            for k in ("lanes", "merge", "chunk", "provision")})
     res["tuned_on_seed"] = a.tune_seed
     res["evaluated_on_seed"] = a.eval_seed
     res["tuning"] = cfg
