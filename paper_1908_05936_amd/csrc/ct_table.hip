@@ -638,6 +638,8 @@ __device__ __forceinline__ int64_t insert_range(const TableView& t, const uint64
     const int64_t i = g0 + sub;
     const bool valid = i < hi;
     const uint64_t key = valid ? keys[i] : kEmpty;
+    // the value is loaded with the key (coalesced) so that its latency hides behind the probe
+    const uint64_t val = (!ALLOC && valid) ? load_val<VK>(vals, i) : 0;
     const uint32_t first = valid ? first_copy(t, keys, key, i, dmask) : 0u;
     const bool actor = valid && first == (uint32_t)i;
     const bool dup = valid && !actor;
@@ -660,7 +662,7 @@ __device__ __forceinline__ int64_t insert_range(const TableView& t, const uint64
         newf = 1;
       } else {
         t.hdr->spec_live[s] = 1;
-        t.hdr->spec_val[s] = load_val<VK>(vals, i);
+        t.hdr->spec_val[s] = val;
         st = kInserted;
         ++ins;
       }
@@ -709,7 +711,7 @@ __device__ __forceinline__ int64_t insert_range(const TableView& t, const uint64
           ref = mypos;
           newf = 1;
         } else {
-          t.bk[mypos >> 3].s[mypos & 7].val = load_val<VK>(vals, i);
+          t.bk[mypos >> 3].s[mypos & 7].val = val;
           st = kInserted;
           ++ins;
         }
