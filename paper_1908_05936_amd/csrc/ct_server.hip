@@ -183,6 +183,21 @@ struct ct_server {
     ct_status rc = CT_OK;
     bool zc = true;
     for (auto& r : b.reqs) zc = zc && r.zc;
+    if (zc && b.op == CT_OP_FIND) {
+      // a find reads each key once and writes each result once: with mapped host arrays it runs
+      // directly on them, request by request, with no staging copies
+      for (auto& r : b.reqs)
+        if (rc == CT_OK && r.n)
+          rc = ct_find_batch(tables[t], static_cast<const uint64_t*>(r.dkeys), r.n,
+                             r.vals_out ? r.dvout : nullptr, static_cast<uint8_t*>(r.dflags), st);
+      if (hipEventRecord(b.ev, st) != hipSuccess) {
+        rc = CT_E_HIP;
+        (void)hipStreamSynchronize(st);
+      }
+      b.status = rc;
+      if (rc != CT_OK) note_error(rc);
+      return;
+    }
     Seg seg[kMaxSegs];
     int nseg = 0;
     auto add = [&](const void* src, void* dst, int64_t bytes) {
