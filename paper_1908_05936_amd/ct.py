@@ -446,12 +446,16 @@ class NativeServer:
         self._h = h
 
     def close(self):
+        """Wait for every submitted request, stop the worker and free the server."""
         if getattr(self, "_h", None) and _lib is not None:
-            _check(_lib.ct_server_destroy(self._h), "ct_server_destroy")
-            self._h = None
+            h, self._h = self._h, None
+            _check(_lib.ct_server_destroy(h), "ct_server_destroy")
 
     def __del__(self):
-        self.close()
+        try:
+            self.close()
+        except Exception:  # noqa: BLE001 -- never raise from a finaliser
+            pass
 
     def submit(self, table: int, op: int, keys, vals=None, vals_out=None, flags_out=None) -> int:
         """Queue one request; the arrays are host tensors (pinned for asynchronous copies)."""
