@@ -11,6 +11,7 @@ The printed JSON line carries:
   breakdown    per-operation Mops/s from HIP events on the library's stream
   roofline     the dominant kernel's algorithmic bytes per launch / its mean duration vs 8 TB/s
   random_access the same kernels against ceilings measured in this run on this chip
+  pool         the index pool at 2^24 keys: insert_alloc, erase_release, bare pop and push
   voxel        the voxel-block frames: per-frame p50/p99, find and insert_alloc Mkeys/s
   served       the serving sweep on 64 device-resident tables: p50/p99 latency and achieved
                keys/s at fractions of the saturated rate
@@ -88,6 +89,7 @@ def parse():
     ap.add_argument("--chunk", type=int, default=0, help="table chunk (0 = library default)")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving sweep")
     ap.add_argument("--no-voxel", action="store_true", help="skip the voxel-block frames")
+    ap.add_argument("--no-pool", action="store_true", help="skip the index-pool operations")
     ap.add_argument("--no-find-uniform", action="store_true",
                     help="skip the uniform-popularity find (counter runs keep to the step's kernels)")
     ap.add_argument("--serve-footprint-gb", type=float, default=40.0)
@@ -243,6 +245,51 @@ def find_uniform(op_clear, op_fill, dev, K_fill, n_fill, n_find, n_hit, L, h, s,
     return n_find / float(np.median(ts)) / 1e6
 
 
+def pool_ops(dev, keys, reps=3):
+    """The index pool (vector/deque back operations) at scale: n = keys.numel() distinct keys into
+    a table of capacity n / 0.8 whose values are popped from a pool of capacity n, then released
+    back (erase_release); also bare pops and pushes of n indices.  Mops/s, medians of `reps` runs
+    timed with HIP events after one warm-up; the table is cleared before each insert."""
+    import torch
+    from paper_1908_05936_amd import ct
+
+    L = ct.lib()
+    s = ct._stream(dev)
+    P = ct._ptr
+    n = keys.numel()
+    t = ct.Table(int(n / 0.8), ct.VAL_U32, ct.HASH_MIX64, device=dev)
+    pool = ct.Pool(n, device=dev)
+    idx = torch.empty(n, dtype=torch.int32, device=dev)
+    st = torch.empty(n, dtype=torch.uint8, device=dev)
+    er = torch.empty(n, dtype=torch.uint8, device=dev)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(6)]
+    times = {k: [] for k in ("insert_alloc", "erase_release", "pop", "push")}
+    for r in range(reps + 1):
+        ct._check(L.ct_clear(t._h, s), "clear")
+        ev[0].record()
+        ct._check(L.ct_insert_alloc_batch(t._h, pool._h, P(keys), n, P(idx), P(st), s), "insert_alloc")
+        ev[1].record()
+        ct._check(L.ct_erase_release_batch(t._h, pool._h, P(keys), n, P(er), s), "erase_release")
+        ev[2].record()
+        ct._check(L.ct_pool_pop_batch(pool._h, n, P(idx), P(st), s), "pop")
+        ev[3].record()
+        ct._check(L.ct_pool_push_batch(pool._h, P(idx), n, P(st), s), "push")
+        ev[4].record()
+        torch.cuda.synchronize()
+        if r == 0:   # the warm-up also checks the results the workload fixes
+            assert int(er.sum()) == n and pool.size() == n and t.size() == 0
+            continue
+        for j, k in enumerate(times):
+            times[k].append(ev[j].elapsed_time(ev[j + 1]) * 1e-3)
+    out = {k + "_Mops_s": n / float(np.median(v)) / 1e6 for k, v in times.items()}
+    out["workload"] = (f"{n} distinct u64 keys, table capacity {int(n / 0.8)} (u32 values from a "
+                       f"pool of {n} indices)")
+    log(f"[pool] insert_alloc {out['insert_alloc_Mops_s']:.0f} erase_release "
+        f"{out['erase_release_Mops_s']:.0f} pop {out['pop_Mops_s']:.0f} push "
+        f"{out['push_Mops_s']:.0f} Mops/s")
+    return out
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -339,6 +386,9 @@ def main():
     breakdown = {name: {"ms": per[name] / a.steps * 1e3,
                         "Mops_s": (counts[name] * a.steps / per[name] / 1e6) if counts[name] else None}
                  for name, _ in ops}
+    # clear rewrites every 16-byte slot: the table's bytes over its time against HBM bandwidth
+    breakdown["clear"]["GB_s"] = table.bucket_count * 128 * a.steps / per["clear"] / 1e9
+    breakdown["clear"]["frac_of_hbm_peak"] = breakdown["clear"]["GB_s"] / HBM_PEAK_GBS
     prof = table.profile()
     table.profiling(False)
     n_ins = (n_fill + n_re) * a.steps
@@ -419,6 +469,8 @@ def main():
             ceil["find_uniform_frac_of_R1"] = (line["find_uniform_Mops_s"]
                                                / ceil["R1_gather128_Mlines_s"])
         line["random_access"] = ceil
+    if not a.no_pool:
+        line["pool"] = pool_ops(dev, K_fill[: min(n_fill, 1 << 24)])
     if not a.no_voxel:
         from paper_1908_05936_amd import bench_voxel
         line["voxel"] = bench_voxel.run(log=log)

@@ -40,6 +40,9 @@ constexpr int kBlock = 256;             // threads per block of every group kern
 constexpr int64_t kBinMinChunk = 1 << 16; // chunks at least this large dedup through bins
 constexpr int kBinFine = 1024;          // mean elements per fine bin
 constexpr int kBinCoarse = 64;          // coarse bins
+constexpr int kBinSub = 8;              // segments per coarse bin, each with its own fill count
+constexpr int kCtrStride = 32;          // u32 words between coarse fill counts (one 128-byte line)
+constexpr int kCoarseCtrWords = kBinCoarse * kBinSub * kCtrStride;  // fine counts follow
 constexpr int kBinTile = 2048;          // elements per block of the scatter kernels
 constexpr int kBinLds = 4096;           // LDS hash slots of the fine-bin dedup (> 2 x mean + 256)
 constexpr int kMaxFinePerCoarse = 256;  // fine bins per coarse bin at the largest chunk (2^24)
@@ -94,14 +97,16 @@ struct TableView {
   int64_t* bcnt;    // per block of the last insert/erase kernel: change of the live count
   // binned dedup (chunks of at least kBinMinChunk elements): elements are scattered by a hash of
   // their key into P1 coarse bins, then into P = P1 * P2 fine bins, and each fine bin resolves its
-  // repeated keys in LDS.  dd aliases r1k: it is needed only when a bin overflows.
-  uint64_t* r1k;    // coarse bins: keys, P1 x c1
-  uint32_t* r1i;    //              chunk indices
+  // repeated keys in LDS.  A coarse bin is kBinSub segments: scatter block b appends to segment
+  // b mod kBinSub, so each fill count takes 1/kBinSub of the blocks' reservations.  dd aliases
+  // r1k: it is needed only when a bin overflows.
+  uint64_t* r1k;    // coarse bin segments: keys, (P1 x kBinSub) x c1
+  uint32_t* r1i;    //                      chunk indices
   uint64_t* r2k;    // fine bins: keys, P x c2
   uint32_t* r2i;
-  uint32_t* bcur;   // fill counts: P1 coarse, then P fine
+  uint32_t* bcur;   // fill counts: P1 x kBinSub coarse, kCtrStride words apart; then P fine
   uint32_t* dfirst; // per repeated element: index of its key's first occurrence
-  uint32_t c1, c2;  // bin capacities
+  uint32_t c1, c2;  // capacities of a coarse segment and of a fine bin
   int lp1, lp;      // log2 of P1 and of P
   int hash;         // 0 mix64, 1 voxel21
   int nb_pow2;

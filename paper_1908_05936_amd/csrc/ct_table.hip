@@ -330,7 +330,7 @@ __device__ __forceinline__ uint32_t fine_bin(const TableView& t, uint64_t mix) {
 // Units [lo, hi) of a binned chunk's prologue: the marks (16 per unit), then the bin counts
 // (4 per unit); `header` also takes the chunk's counter snapshot.
 __device__ __forceinline__ int64_t bin_prologue_units(const TableView& t, int64_t q) {
-  return (q + 15) / 16 + (((int64_t)1 << t.lp1) + ((int64_t)1 << t.lp)) / 4;
+  return (q + 15) / 16 + ((int64_t)kCoarseCtrWords + ((int64_t)1 << t.lp)) / 4;
 }
 
 __global__ __launch_bounds__(kBlock) void k_bin_prologue(TableView t, PoolHeader* pool, int64_t q) {
@@ -347,8 +347,8 @@ __global__ __launch_bounds__(kBlock) void k_bin_prologue(TableView t, PoolHeader
 // Both scatters: the block's elements, ranked within their bin (code = rank << 8 | bin, or ~0 for
 // none), are staged in LDS in bin order and each bin's run is written by consecutive threads, so
 // the stores of a wave go to consecutive positions of one bin.  cnt[b] holds the block's count
-// for bin b; this reserves the runs (bin b's fill count at bcur[cur0 + b]), flags an overflow of
-// `cap`, and writes bin b of the block to out[(gbin0 + b) * cap + position].
+// for bin b; this reserves the runs (bin b's fill count at bcur[cur0 + b * cur_stride]), flags an
+// overflow of `cap`, and writes bin b of the block to out[(gbin0 + b * gstride) * cap + position].
 struct BinStage {
   uint64_t k[kBinTile];
   uint32_t i[kBinTile];
@@ -362,7 +362,8 @@ template <int PER>
 __device__ __forceinline__ void bin_write(const TableView& t, BinStage& S, uint32_t nbins,
                                           const uint64_t (&k)[PER], const uint32_t (&ix)[PER],
                                           const uint32_t (&code)[PER], uint32_t cur0,
-                                          uint32_t gbin0, uint32_t cap, uint64_t* __restrict__ outk,
+                                          uint32_t cur_stride, uint32_t gbin0, uint32_t gstride,
+                                          uint32_t cap, uint64_t* __restrict__ outk,
                                           uint32_t* __restrict__ outi) {
   const uint32_t c = threadIdx.x < nbins ? S.cnt[threadIdx.x] : 0u;
   uint32_t total;
@@ -370,7 +371,7 @@ __device__ __forceinline__ void bin_write(const TableView& t, BinStage& S, uint3
   if (threadIdx.x < nbins) {
     uint32_t o = 0;
     if (c) {
-      o = aadd32(&t.bcur[cur0 + threadIdx.x], c);
+      o = aadd32(&t.bcur[cur0 + threadIdx.x * cur_stride], c);
       if (o + c > cap) t.hdr->dovf = 1u;
     }
     S.base[threadIdx.x] = o;
@@ -391,15 +392,16 @@ __device__ __forceinline__ void bin_write(const TableView& t, BinStage& S, uint3
     const uint32_t b = S.b[p];
     const uint32_t pos = S.base[b] + (p - S.loc[b]);
     if (pos < cap) {
-      const int64_t at = (int64_t)(gbin0 + b) * cap + pos;
+      const int64_t at = (int64_t)(gbin0 + b * gstride) * cap + pos;
       outk[at] = S.k[p];
       outi[at] = S.i[p];
     }
   }
 }
 
-// Coarse scatter: block b takes elements [b * kBinTile, (b + 1) * kBinTile) into the 64 coarse
-// bins.  The out-of-band keys take their lowest index directly, as in dedup_range.
+// Coarse scatter: block b takes elements [b * kBinTile, (b + 1) * kBinTile) into segment
+// b mod kBinSub of the 64 coarse bins.  The out-of-band keys take their lowest index directly, as
+// in dedup_range.
 __global__ __launch_bounds__(kBlock) void k_bin_scatter1(TableView t, const uint64_t* __restrict__ keys,
                                                          int64_t q) {
   constexpr int kPer = kBinTile / kBlock;
@@ -426,24 +428,27 @@ __global__ __launch_bounds__(kBlock) void k_bin_scatter1(TableView t, const uint
     }
   }
   __syncthreads();
-  bin_write<kPer>(t, S, kBinCoarse, k, ix, code, 0u, 0u, t.c1, t.r1k, t.r1i);
+  const uint32_t seg = blockIdx.x % kBinSub;
+  bin_write<kPer>(t, S, kBinCoarse, k, ix, code, seg * kCtrStride, kBinSub * kCtrStride, seg,
+                  kBinSub, t.c1, t.r1k, t.r1i);
 }
 
-// Fine scatter: block (coarse bin c, tile) moves that tile of bin c into its 2^(lp - lp1) fine
-// bins, the same way.
-__global__ __launch_bounds__(kBlock) void k_bin_scatter2(TableView t, int tiles_per_bin) {
+// Fine scatter: block (segment g of coarse bin c = g / kBinSub, tile) moves that tile of the
+// segment into the 2^(lp - lp1) fine bins of c, the same way.
+__global__ __launch_bounds__(kBlock) void k_bin_scatter2(TableView t, int tiles_per_seg) {
   if (t.hdr->dovf) return;
   constexpr int kPer = kBinTile / kBlock;
   __shared__ BinStage S;
-  const int c = (int)blockIdx.x / tiles_per_bin;
-  const uint32_t j0 = (uint32_t)((int)blockIdx.x % tiles_per_bin) * kBinTile;
-  const uint32_t n1 = min(t.bcur[c], t.c1);
+  const int g = (int)blockIdx.x / tiles_per_seg;
+  const int c = g / kBinSub;
+  const uint32_t j0 = (uint32_t)((int)blockIdx.x % tiles_per_seg) * kBinTile;
+  const uint32_t n1 = min(t.bcur[g * kCtrStride], t.c1);
   if (j0 >= n1) return;
   const int lp2 = t.lp - t.lp1;
   const uint32_t p2 = 1u << lp2;
   for (uint32_t j = threadIdx.x; j < p2; j += kBlock) S.cnt[j] = 0;
   __syncthreads();
-  const int64_t src = (int64_t)c * t.c1;
+  const int64_t src = (int64_t)g * t.c1;
   uint64_t k[kPer];
   uint32_t ix[kPer], code[kPer];
 #pragma unroll
@@ -460,8 +465,8 @@ __global__ __launch_bounds__(kBlock) void k_bin_scatter2(TableView t, int tiles_
     }
   }
   __syncthreads();
-  bin_write<kPer>(t, S, p2, k, ix, code, (1u << t.lp1) + ((uint32_t)c << lp2),
-                  (uint32_t)c << lp2, t.c2, t.r2k, t.r2i);
+  bin_write<kPer>(t, S, p2, k, ix, code, kCoarseCtrWords + ((uint32_t)c << lp2), 1u,
+                  (uint32_t)c << lp2, 1u, t.c2, t.r2k, t.r2i);
 }
 
 // One fine bin per block: insert its keys into an LDS table (CAS on the key word, atomic min on
@@ -474,7 +479,7 @@ __global__ __launch_bounds__(kBlock) void k_bin_dedup(TableView t) {
   __shared__ uint32_t hm[kBinLds];
   __shared__ uint8_t hx[kBinLds];
   const uint32_t f = blockIdx.x;
-  const uint32_t n = min(t.bcur[(1u << t.lp1) + f], t.c2);
+  const uint32_t n = min(t.bcur[kCoarseCtrWords + f], t.c2);
   for (uint32_t j = threadIdx.x; j < (uint32_t)kBinLds; j += kBlock) {
     hk[j] = kEmpty;
     hm[j] = kNone;
@@ -1491,20 +1496,22 @@ bool make_layout(const ct_table_desc* d, Layout* L) {
     while (((int64_t)1 << L->lp) < L->nfine) ++L->lp;
     L->lp1 = 0;
     while ((1 << L->lp1) < kBinCoarse) ++L->lp1;
-    L->c1 = 2 * (q / kBinCoarse) + kBinTile;
+    const int64_t nseg = (int64_t)kBinCoarse * kBinSub;
+    L->c1 = 2 * (q / nseg) + 256;
     L->c2 = 2 * kBinFine + 256;
     if (L->nfine / kBinCoarse > kMaxFinePerCoarse) return false;
-    L->off_r1k = off;  // also dd, which needs 16 bytes per chunk element: c1 * 64 * 8 is more
+    if (nseg * L->c1 < L->dslots) return false;  // dd (8 bytes per slot) must fit in r1k
+    L->off_r1k = off;
     L->off_dd = off;
-    off = align_up(off + kBinCoarse * L->c1 * 8);
+    off = align_up(off + nseg * L->c1 * 8);
     L->off_r1i = off;
-    off = align_up(off + kBinCoarse * L->c1 * 4);
+    off = align_up(off + nseg * L->c1 * 4);
     L->off_r2k = off;
     off = align_up(off + L->nfine * L->c2 * 8);
     L->off_r2i = off;
     off = align_up(off + L->nfine * L->c2 * 4);
     L->off_bcur = off;
-    off = align_up(off + (kBinCoarse + L->nfine) * 4);
+    off = align_up(off + (kCoarseCtrWords + L->nfine) * 4);
     L->off_dfirst = off;
     off = align_up(off + q * 4);
   } else {
@@ -1568,7 +1575,7 @@ void launch(ct_table* t, int kind, hipStream_t s, F&& f) {
 }
 
 int64_t bin_prologue_units_host(const TableView& v, int64_t q) {
-  return (q + 15) / 16 + (((int64_t)1 << v.lp1) + ((int64_t)1 << v.lp)) / 4;
+  return (q + 15) / 16 + ((int64_t)kCoarseCtrWords + ((int64_t)1 << v.lp)) / 4;
 }
 
 int group_blocks(int64_t n) {
@@ -1600,11 +1607,11 @@ void dedup_chunk(ct_table* t, PoolHeader* pool, const uint64_t* kc, int64_t q, h
   const uint32_t db = dedup_slots_for(q);
   if (t->v.r1k && q >= kBinMinChunk) {
     const TableView& v = t->v;
-    const int tiles_per_bin = (int)((v.c1 + kBinTile - 1) / kBinTile);
+    const int tiles_per_seg = (int)((v.c1 + kBinTile - 1) / kBinTile);
     const int nfine = 1 << v.lp;
     launch(t, CT_KERNEL_PROLOGUE, s, [&] { k_bin_prologue<<<flat_blocks(bin_prologue_units_host(v, q)), kBlock, 0, s>>>(v, pool, q); });
     launch(t, CT_KERNEL_DEDUP, s, [&] { k_bin_scatter1<<<(int)((q + kBinTile - 1) / kBinTile), kBlock, 0, s>>>(v, kc, q); });
-    launch(t, CT_KERNEL_DEDUP, s, [&] { k_bin_scatter2<<<kBinCoarse * tiles_per_bin, kBlock, 0, s>>>(v, tiles_per_bin); });
+    launch(t, CT_KERNEL_DEDUP, s, [&] { k_bin_scatter2<<<kBinCoarse * kBinSub * tiles_per_seg, kBlock, 0, s>>>(v, tiles_per_seg); });
     launch(t, CT_KERNEL_DEDUP, s, [&] { k_bin_dedup<<<nfine, kBlock, 0, s>>>(v); });
     launch(t, CT_KERNEL_DEDUP, s, [&] { k_bin_fallback_clear<<<flat_blocks(db / 2), kBlock, 0, s>>>(v, db); });
     launch(t, CT_KERNEL_DEDUP, s, [&] { k_bin_fallback_dedup<<<flat_blocks(q), kBlock, 0, s>>>(v, kc, q, db - 1); });
