@@ -411,14 +411,16 @@ __global__ __launch_bounds__(kBlock) void k_bin_scatter1(TableView t, const uint
   __syncthreads();
   uint64_t k[kPer];
   uint32_t ix[kPer], code[kPer];
+  // all loads first, from clamped (in-bounds) positions: a load under a branch would make the
+  // compiler wait for it before the next one is issued
+#pragma unroll
+  for (int e = 0; e < kPer; ++e) k[e] = keys[min(t0 + e * kBlock + (int64_t)threadIdx.x, q - 1)];
 #pragma unroll
   for (int e = 0; e < kPer; ++e) {
     const int64_t i = t0 + e * kBlock + threadIdx.x;
     code[e] = ~0u;
-    k[e] = 0;
     ix[e] = (uint32_t)i;
     if (i < q) {
-      k[e] = keys[i];
       if (k[e] >= kTomb) {
         amin32(&t.hdr->spec_first[k[e] - kTomb], (uint32_t)i);
       } else {
@@ -452,14 +454,16 @@ __global__ __launch_bounds__(kBlock) void k_bin_scatter2(TableView t, int tiles_
   uint64_t k[kPer];
   uint32_t ix[kPer], code[kPer];
 #pragma unroll
+  for (int e = 0; e < kPer; ++e) {   // loads first, clamped (n1 > j0 >= 0)
+    const uint32_t j = min(j0 + e * kBlock + threadIdx.x, n1 - 1u);
+    k[e] = t.r1k[src + j];
+    ix[e] = t.r1i[src + j];
+  }
+#pragma unroll
   for (int e = 0; e < kPer; ++e) {
     const uint32_t j = j0 + e * kBlock + threadIdx.x;
     code[e] = ~0u;
-    k[e] = 0;
-    ix[e] = 0;
     if (j < n1) {
-      k[e] = t.r1k[src + j];
-      ix[e] = t.r1i[src + j];
       const uint32_t f2 = fine_bin(t, dedup_mix(k[e])) & (p2 - 1u);
       code[e] = (atomicAdd(&S.cnt[f2], 1u) << 8) | f2;
     }
@@ -480,25 +484,32 @@ __global__ __launch_bounds__(kBlock) void k_bin_dedup(TableView t) {
   __shared__ uint8_t hx[kBinLds];
   const uint32_t f = blockIdx.x;
   const uint32_t n = min(t.bcur[kCoarseCtrWords + f], t.c2);
+  if (n == 0) return;
+  const uint64_t* rk = t.r2k + (int64_t)f * t.c2;
+  const uint32_t* ri = t.r2i + (int64_t)f * t.c2;
+  // a bin holds at most c2 <= kPer * kBlock elements: each thread keeps its own in registers.
+  // The loads are issued first, from clamped positions, and overlap the table's initialisation.
+  constexpr int kPer = (2 * kBinFine + 256 + kBlock - 1) / kBlock;
+  uint64_t kk[kPer];
+  uint32_t slot[kPer], idx[kPer];
+#pragma unroll
+  for (int e = 0; e < kPer; ++e) {
+    const uint32_t j = min(threadIdx.x + e * kBlock, n - 1u);
+    kk[e] = rk[j];
+    idx[e] = ri[j];
+  }
   for (uint32_t j = threadIdx.x; j < (uint32_t)kBinLds; j += kBlock) {
     hk[j] = kEmpty;
     hm[j] = kNone;
     hx[j] = 0;
   }
   __syncthreads();
-  const uint64_t* rk = t.r2k + (int64_t)f * t.c2;
-  const uint32_t* ri = t.r2i + (int64_t)f * t.c2;
-  // a bin holds at most c2 <= kPer * kBlock elements: each thread keeps its own in registers
-  constexpr int kPer = (2 * kBinFine + 256 + kBlock - 1) / kBlock;
-  uint32_t slot[kPer], idx[kPer];
 #pragma unroll
   for (int e = 0; e < kPer; ++e) {
     const uint32_t j = threadIdx.x + e * kBlock;
     slot[e] = kNone;
-    idx[e] = 0;
     if (j < n) {
-      const uint64_t key = rk[j];
-      idx[e] = ri[j];
+      const uint64_t key = kk[e];
       uint32_t s = (uint32_t)dedup_mix(key) & (kBinLds - 1);
       for (;;) {
         const unsigned long long old = atomicCAS(&hk[s], (unsigned long long)kEmpty,
@@ -541,11 +552,13 @@ __global__ __launch_bounds__(kBlock) void k_bin_fallback_dedup(TableView t,
 }
 
 // Index-order role of this lane's element: its own index when it is the first copy of its key in
-// the chunk, else the index of that first copy.
+// the chunk, else the index of that first copy.  `mark` is dmark[i], which the caller loads
+// together with the key (one memory round trip instead of two).
 __device__ __forceinline__ uint32_t first_copy(const TableView& t, const uint64_t* keys,
-                                               uint64_t key, int64_t i, uint32_t dmask) {
+                                               uint64_t key, int64_t i, uint32_t dmask,
+                                               uint32_t mark) {
   if (key >= kTomb) return t.hdr->spec_first[key - kTomb];
-  if (t.dmark[i]) return t.hdr->dmode ? t.dfirst[i] : dedup_lookup(t, keys, key, dmask, (uint32_t)i);
+  if (mark) return t.hdr->dmode ? t.dfirst[i] : dedup_lookup(t, keys, key, dmask, (uint32_t)i);
   return (uint32_t)i;
 }
 
@@ -645,7 +658,9 @@ __device__ __forceinline__ int64_t insert_range(const TableView& t, const uint64
     const uint64_t key = valid ? keys[i] : kEmpty;
     // the value is loaded with the key (coalesced) so that its latency hides behind the probe
     const uint64_t val = (!ALLOC && valid) ? load_val<VK>(vals, i) : 0;
-    const uint32_t first = valid ? first_copy(t, keys, key, i, dmask) : 0u;
+    const uint32_t mark = t.dmark[min(i, hi - 1)];
+    asm volatile("" ::"v"(mark));  // keep the load here, issued with the key's
+    const uint32_t first = valid ? first_copy(t, keys, key, i, dmask, mark) : 0u;
     const bool actor = valid && first == (uint32_t)i;
     const bool dup = valid && !actor;
     const uint32_t slot = wave_append(dup, &t.hdr->ndup);
@@ -731,8 +746,10 @@ __device__ __forceinline__ int64_t insert_range(const TableView& t, const uint64
   return ins;
 }
 
+// Map inserts are held to 96 VGPRs (5 waves per SIMD); the set and allocating variants need more
+// and keep the compiler's choice.
 template <int VK, bool ALLOC>
-__global__ __launch_bounds__(kBlock) void k_insert(TableView t, const uint64_t* __restrict__ keys,
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu((ALLOC || VK == 0) ? 1 : 5))) void k_insert(TableView t, const uint64_t* __restrict__ keys,
                                                    const void* __restrict__ vals, int64_t q,
                                                    uint32_t dmask, uint8_t* __restrict__ status,
                                                    int32_t* __restrict__ vout) {
@@ -755,7 +772,9 @@ __device__ __forceinline__ int64_t erase_range(const TableView& t, const uint64_
     const int64_t i = g0 + sub;
     const bool valid = i < hi;
     const uint64_t key = valid ? keys[i] : kEmpty;
-    const bool actor = valid && first_copy(t, keys, key, i, dmask) == (uint32_t)i;
+    const uint32_t mark = t.dmark[min(i, hi - 1)];
+    asm volatile("" ::"v"(mark));  // keep the load here, issued with the key's
+    const bool actor = valid && first_copy(t, keys, key, i, dmask, mark) == (uint32_t)i;
     uint8_t hit = 0;
     uint64_t val = 0;
     if (actor && key >= kTomb) {
