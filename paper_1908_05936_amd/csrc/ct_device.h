@@ -44,7 +44,8 @@ constexpr int kBinSub = 8;              // segments per coarse bin, each with it
 constexpr int kCtrStride = 32;          // u32 words between coarse fill counts (one 128-byte line)
 constexpr int kCoarseCtrWords = kBinCoarse * kBinSub * kCtrStride;  // fine counts follow
 constexpr int kBinTile = 2048;          // elements per block of the scatter kernels
-constexpr int kBinLds = 4096;           // LDS hash slots of the fine-bin dedup (> 2 x mean + 256)
+constexpr int kBinFineCap = 1792;       // capacity of a fine bin (1.75 x the mean; more overflows)
+constexpr int kBinLds = 2048;           // LDS hash slots of the fine-bin dedup (> kBinFineCap)
 constexpr int kMaxFinePerCoarse = 256;  // fine bins per coarse bin at the largest chunk (2^24)
 
 enum : uint8_t { kPresent = 0, kInserted = 1, kFull = 2, kNoStatus = 0xFF };

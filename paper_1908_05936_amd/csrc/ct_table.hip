@@ -435,42 +435,49 @@ __global__ __launch_bounds__(kBlock) void k_bin_scatter1(TableView t, const uint
                   kBinSub, t.c1, t.r1k, t.r1i);
 }
 
-// Fine scatter: block (segment g of coarse bin c = g / kBinSub, tile) moves that tile of the
-// segment into the 2^(lp - lp1) fine bins of c, the same way.
-__global__ __launch_bounds__(kBlock) void k_bin_scatter2(TableView t, int tiles_per_seg) {
-  if (t.hdr->dovf) return;
+// Fine scatter: the blocks of segment g of coarse bin c = g / kBinSub take its tiles in turn
+// (tile r, r + blocks_per_seg, ...) and move each into the 2^(lp - lp1) fine bins of c, the same
+// way.
+__global__ __launch_bounds__(kBlock) void k_bin_scatter2(TableView t, int blocks_per_seg) {
   constexpr int kPer = kBinTile / kBlock;
   __shared__ BinStage S;
-  const int g = (int)blockIdx.x / tiles_per_seg;
+  const int g = (int)blockIdx.x / blocks_per_seg;
   const int c = g / kBinSub;
-  const uint32_t j0 = (uint32_t)((int)blockIdx.x % tiles_per_seg) * kBinTile;
-  const uint32_t n1 = min(t.bcur[g * kCtrStride], t.c1);
-  if (j0 >= n1) return;
+  // the overflow flag and the segment's fill count in one round trip
+  const uint32_t ovf = t.hdr->dovf;
+  const uint32_t fill = t.bcur[g * kCtrStride];
+  asm volatile("" ::"v"(ovf), "v"(fill));
+  if (ovf) return;
+  const uint32_t n1 = min(fill, t.c1);
   const int lp2 = t.lp - t.lp1;
   const uint32_t p2 = 1u << lp2;
-  for (uint32_t j = threadIdx.x; j < p2; j += kBlock) S.cnt[j] = 0;
-  __syncthreads();
   const int64_t src = (int64_t)g * t.c1;
-  uint64_t k[kPer];
-  uint32_t ix[kPer], code[kPer];
+  for (uint32_t j0 = (uint32_t)((int)blockIdx.x % blocks_per_seg) * kBinTile; j0 < n1;
+       j0 += (uint32_t)blocks_per_seg * kBinTile) {
+    uint64_t k[kPer];
+    uint32_t ix[kPer], code[kPer];
 #pragma unroll
-  for (int e = 0; e < kPer; ++e) {   // loads first, clamped (n1 > j0 >= 0)
-    const uint32_t j = min(j0 + e * kBlock + threadIdx.x, n1 - 1u);
-    k[e] = t.r1k[src + j];
-    ix[e] = t.r1i[src + j];
-  }
-#pragma unroll
-  for (int e = 0; e < kPer; ++e) {
-    const uint32_t j = j0 + e * kBlock + threadIdx.x;
-    code[e] = ~0u;
-    if (j < n1) {
-      const uint32_t f2 = fine_bin(t, dedup_mix(k[e])) & (p2 - 1u);
-      code[e] = (atomicAdd(&S.cnt[f2], 1u) << 8) | f2;
+    for (int e = 0; e < kPer; ++e) {   // loads first, clamped (n1 > j0 >= 0)
+      const uint32_t j = min(j0 + e * kBlock + threadIdx.x, n1 - 1u);
+      k[e] = t.r1k[src + j];
+      ix[e] = t.r1i[src + j];
     }
+    // (the previous tile's writes read S.k, S.i, S.b, S.base and S.loc only: cnt is free)
+    for (uint32_t j = threadIdx.x; j < p2; j += kBlock) S.cnt[j] = 0;
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < kPer; ++e) {
+      const uint32_t j = j0 + e * kBlock + threadIdx.x;
+      code[e] = ~0u;
+      if (j < n1) {
+        const uint32_t f2 = fine_bin(t, dedup_mix(k[e])) & (p2 - 1u);
+        code[e] = (atomicAdd(&S.cnt[f2], 1u) << 8) | f2;
+      }
+    }
+    __syncthreads();
+    bin_write<kPer>(t, S, p2, k, ix, code, kCoarseCtrWords + ((uint32_t)c << lp2), 1u,
+                    (uint32_t)c << lp2, 1u, t.c2, t.r2k, t.r2i);
   }
-  __syncthreads();
-  bin_write<kPer>(t, S, p2, k, ix, code, kCoarseCtrWords + ((uint32_t)c << lp2), 1u,
-                  (uint32_t)c << lp2, 1u, t.c2, t.r2k, t.r2i);
 }
 
 // One fine bin per block: insert its keys into an LDS table (CAS on the key word, atomic min on
@@ -478,18 +485,22 @@ __global__ __launch_bounds__(kBlock) void k_bin_scatter2(TableView t, int tiles_
 // give it the key's lowest index.  A bin holds at most c2 < kBinLds elements, so every probe
 // finds a free or matching slot.
 __global__ __launch_bounds__(kBlock) void k_bin_dedup(TableView t) {
-  if (t.hdr->dovf) return;
   __shared__ unsigned long long hk[kBinLds];
   __shared__ uint32_t hm[kBinLds];
   __shared__ uint8_t hx[kBinLds];
   const uint32_t f = blockIdx.x;
-  const uint32_t n = min(t.bcur[kCoarseCtrWords + f], t.c2);
+  // the overflow flag and the bin's fill count in one round trip
+  const uint32_t ovf = t.hdr->dovf;
+  const uint32_t fill = t.bcur[kCoarseCtrWords + f];
+  asm volatile("" ::"v"(ovf), "v"(fill));
+  if (ovf) return;
+  const uint32_t n = min(fill, t.c2);
   if (n == 0) return;
   const uint64_t* rk = t.r2k + (int64_t)f * t.c2;
   const uint32_t* ri = t.r2i + (int64_t)f * t.c2;
   // a bin holds at most c2 <= kPer * kBlock elements: each thread keeps its own in registers.
   // The loads are issued first, from clamped positions, and overlap the table's initialisation.
-  constexpr int kPer = (2 * kBinFine + 256 + kBlock - 1) / kBlock;
+  constexpr int kPer = (kBinFineCap + kBlock - 1) / kBlock;
   uint64_t kk[kPer];
   uint32_t slot[kPer], idx[kPer];
 #pragma unroll
@@ -1482,7 +1493,7 @@ struct Layout {
   int64_t off_r1k, off_r1i, off_r2k, off_r2i, off_bcur, off_dfirst;
 };
 
-static_assert(2 * kBinFine + 256 < kBinLds, "a fine bin must fit the LDS table");
+static_assert(kBinFineCap < kBinLds, "a fine bin must fit the LDS table");
 
 bool make_layout(const ct_table_desc* d, Layout* L) {
   if (!d || d->capacity < 0) return false;
@@ -1517,7 +1528,7 @@ bool make_layout(const ct_table_desc* d, Layout* L) {
     while ((1 << L->lp1) < kBinCoarse) ++L->lp1;
     const int64_t nseg = (int64_t)kBinCoarse * kBinSub;
     L->c1 = 2 * (q / nseg) + 256;
-    L->c2 = 2 * kBinFine + 256;
+    L->c2 = kBinFineCap;
     if (L->nfine / kBinCoarse > kMaxFinePerCoarse) return false;
     if (nseg * L->c1 < L->dslots) return false;  // dd (8 bytes per slot) must fit in r1k
     L->off_r1k = off;
@@ -1626,11 +1637,12 @@ void dedup_chunk(ct_table* t, PoolHeader* pool, const uint64_t* kc, int64_t q, h
   const uint32_t db = dedup_slots_for(q);
   if (t->v.r1k && q >= kBinMinChunk) {
     const TableView& v = t->v;
-    const int tiles_per_seg = (int)((v.c1 + kBinTile - 1) / kBinTile);
+    // blocks per coarse segment: enough for its expected fill (about c1 / 2) in one tile each
+    const int blocks_per_seg = (int)std::max<int64_t>(1, (v.c1 / 2 + kBinTile - 1) / kBinTile);
     const int nfine = 1 << v.lp;
     launch(t, CT_KERNEL_PROLOGUE, s, [&] { k_bin_prologue<<<flat_blocks(bin_prologue_units_host(v, q)), kBlock, 0, s>>>(v, pool, q); });
     launch(t, CT_KERNEL_DEDUP, s, [&] { k_bin_scatter1<<<(int)((q + kBinTile - 1) / kBinTile), kBlock, 0, s>>>(v, kc, q); });
-    launch(t, CT_KERNEL_DEDUP, s, [&] { k_bin_scatter2<<<kBinCoarse * kBinSub * tiles_per_seg, kBlock, 0, s>>>(v, tiles_per_seg); });
+    launch(t, CT_KERNEL_DEDUP, s, [&] { k_bin_scatter2<<<kBinCoarse * kBinSub * blocks_per_seg, kBlock, 0, s>>>(v, blocks_per_seg); });
     launch(t, CT_KERNEL_DEDUP, s, [&] { k_bin_dedup<<<nfine, kBlock, 0, s>>>(v); });
     launch(t, CT_KERNEL_DEDUP, s, [&] { k_bin_fallback_clear<<<flat_blocks(db / 2), kBlock, 0, s>>>(v, db); });
     launch(t, CT_KERNEL_DEDUP, s, [&] { k_bin_fallback_dedup<<<flat_blocks(q), kBlock, 0, s>>>(v, kc, q, db - 1); });
