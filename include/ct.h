@@ -161,6 +161,11 @@ ct_status ct_check_invariants(ct_table *t, int64_t *h_violations, void *stream);
 /* Read and clear the sticky error word (CT_ERR_* bits).  Synchronises. */
 ct_status ct_get_error(ct_table *t, uint32_t *h_err, void *stream);
 
+/* Diagnostic: *h_skewed = 1 when a recent chunk of this table overflowed its dedup bins (keys
+   repeated thousands of times), so its large chunks fold each tile's repeated keys before binning;
+   0 otherwise.  Results never depend on it.  Synchronises. */
+ct_status ct_table_dedup_skewed(ct_table *t, int32_t *h_skewed, void *stream);
+
 /* --- index pool: vector/deque of int32 used as a LIFO free list (Sections 4.2, 4.3) -------- */
 
 /* Bytes of device memory a pool of `capacity` int32 entries needs.  Host only. */

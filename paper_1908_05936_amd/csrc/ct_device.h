@@ -39,6 +39,7 @@ constexpr int kTile = 1024;             // elements per tile of the rank scan
 constexpr int kBlock = 256;             // threads per block of every group kernel
 constexpr int64_t kBinMinChunk = 1 << 16; // chunks at least this large dedup through bins
 constexpr int kBinFine = 1024;          // mean elements per fine bin
+constexpr uint32_t kIndirect = 0x80000000u;  // dfirst entry: names a copy whose dfirst is final
 constexpr int kBinCoarse = 64;          // coarse bins
 constexpr int kBinSub = 8;              // segments per coarse bin, each with its own fill count
 constexpr int kCtrStride = 32;          // u32 words between coarse fill counts (one 128-byte line)
@@ -74,6 +75,9 @@ struct alignas(256) Header {
   uint64_t violations;
   uint32_t dmode;          // 1: the chunk's repeated keys were resolved by bins (dfirst valid)
   uint32_t dovf;           // 1: a bin of the current chunk overflowed; the chunk uses dd instead
+  uint32_t dagg;           // 1: the current chunk's coarse scatter folds each tile's repeats first
+  uint32_t dskew;          // 1: a recent chunk overflowed its bins (skewed keys): aggregate
+  uint32_t dskew_age;      // binned chunks since dskew was set; every 16th tries without folding
 };
 
 struct alignas(256) PoolHeader {

@@ -163,6 +163,9 @@ __device__ __forceinline__ void reset_range(const TableView& t, int64_t lo, int6
     h->dump_count = 0;
     h->live_count = 0;
     h->violations = 0;
+    h->dagg = 0;
+    h->dskew = 0;
+    h->dskew_age = 0;
   }
 }
 
@@ -197,6 +200,11 @@ __device__ __forceinline__ void chunk_header(const TableView& t, PoolHeader* poo
   h->fast = fast ? 1u : 0u;
   h->dmode = dmode;
   h->dovf = 0;
+  // binned chunks of a table whose keys recently overflowed the bins fold each tile's repeated
+  // keys before scattering; every 16th such chunk tries without, and ends the hint if it fits
+  uint32_t agg = 0;
+  if (dmode && h->dskew) agg = (++h->dskew_age & 15u) != 0u ? 1u : 0u;
+  h->dagg = agg;
 }
 
 __device__ __forceinline__ void prologue_range(const TableView& t, PoolHeader* pool,
@@ -402,19 +410,82 @@ __device__ __forceinline__ void bin_write(const TableView& t, BinStage& S, uint3
 // Coarse scatter: block b takes elements [b * kBinTile, (b + 1) * kBinTile) into segment
 // b mod kBinSub of the 64 coarse bins.  The out-of-band keys take their lowest index directly, as
 // in dedup_range.
+// When the chunk folds (dagg: its table's recent chunks overflowed the bins, i.e. skewed keys),
+// the tile first finds its own repeated keys in an LDS table.  Only each key's first copy in the
+// tile goes to the bins; when the tile holds other copies it is marked with dfirst = itself (the
+// fine bins replace that if an earlier tile holds the key), and every other copy is marked with
+// dfirst = kIndirect | that first copy.  A key repeated thousands of times then reaches its fine
+// bin once per tile instead of once per copy.  A copy that finds no slot within kFoldProbe probes
+// simply goes to the bins unfolded: the fine bins resolve whatever reaches them exactly.
+constexpr int kFoldProbe = 32;
+
 __global__ __launch_bounds__(kBlock) void k_bin_scatter1(TableView t, const uint64_t* __restrict__ keys,
                                                          int64_t q) {
   constexpr int kPer = kBinTile / kBlock;
+  constexpr uint32_t kFolded = ~0u - 1u;  // hs entry of a copy that stays out of the bins
   __shared__ BinStage S;
   const int64_t t0 = (int64_t)blockIdx.x * kBinTile;
-  if (threadIdx.x < kBinCoarse) S.cnt[threadIdx.x] = 0;
-  __syncthreads();
   uint64_t k[kPer];
-  uint32_t ix[kPer], code[kPer];
+  uint32_t ix[kPer], code[kPer], hs[kPer];
   // all loads first, from clamped (in-bounds) positions: a load under a branch would make the
-  // compiler wait for it before the next one is issued
+  // compiler wait for it before the next one is issued.  The chunk's mode comes with them.
 #pragma unroll
   for (int e = 0; e < kPer; ++e) k[e] = keys[min(t0 + e * kBlock + (int64_t)threadIdx.x, q - 1)];
+  const uint32_t agg = t.hdr->dagg;
+  if (threadIdx.x < kBinCoarse) S.cnt[threadIdx.x] = 0;
+#pragma unroll
+  for (int e = 0; e < kPer; ++e) hs[e] = ~0u;
+  if (agg) {
+    // H[s] (in S.i): tile position of a copy of slot s's key, the lowest once all have arrived;
+    // D[s] (in S.b): the key occurs more than once in the tile.  S.k holds the tile's keys by
+    // position.  All three are free until the bins are written.
+    uint32_t* H = S.i;
+    uint8_t* D = S.b;
+    for (uint32_t j = threadIdx.x; j < (uint32_t)kBinTile; j += kBlock) {
+      H[j] = ~0u;
+      D[j] = 0;
+    }
+#pragma unroll
+    for (int e = 0; e < kPer; ++e) S.k[e * kBlock + threadIdx.x] = k[e];
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < kPer; ++e) {
+      const uint32_t local = e * kBlock + threadIdx.x;
+      if (t0 + local < q && k[e] < kTomb) {
+        uint32_t s = (uint32_t)dedup_mix(k[e]) & (kBinTile - 1u);
+        for (int probe = 0; probe < kFoldProbe; ++probe) {
+          const uint32_t prev = atomicCAS(&H[s], ~0u, local);
+          if (prev == ~0u) {
+            hs[e] = s;
+            break;
+          }
+          if (S.k[prev] == k[e]) {
+            atomicMin(&H[s], local);
+            D[s] = 1;
+            hs[e] = s;
+            break;
+          }
+          s = (s + 1u) & (kBinTile - 1u);
+        }
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < kPer; ++e) {
+      if (hs[e] == ~0u || !D[hs[e]]) continue;
+      const uint32_t local = e * kBlock + threadIdx.x;
+      const uint32_t i = (uint32_t)(t0 + local);
+      const uint32_t rep = H[hs[e]];
+      t.dmark[i] = 1;
+      if (rep == local) {
+        t.dfirst[i] = i;
+      } else {
+        t.dfirst[i] = kIndirect | (uint32_t)(t0 + rep);
+        hs[e] = kFolded;
+      }
+    }
+  }
+  __syncthreads();
 #pragma unroll
   for (int e = 0; e < kPer; ++e) {
     const int64_t i = t0 + e * kBlock + threadIdx.x;
@@ -423,7 +494,7 @@ __global__ __launch_bounds__(kBlock) void k_bin_scatter1(TableView t, const uint
     if (i < q) {
       if (k[e] >= kTomb) {
         amin32(&t.hdr->spec_first[k[e] - kTomb], (uint32_t)i);
-      } else {
+      } else if (hs[e] != kFolded) {
         const uint32_t b = (uint32_t)(dedup_mix(k[e]) >> (64 - t.lp1));
         code[e] = (atomicAdd(&S.cnt[b], 1u) << 8) | b;
       }
@@ -547,12 +618,20 @@ __global__ __launch_bounds__(kBlock) void k_bin_dedup(TableView t) {
 
 // Overflow path: clear dd (it aliases the coarse bins) and switch the chunk to dedup_range.
 __global__ __launch_bounds__(kBlock) void k_bin_fallback_clear(TableView t, uint32_t dslots) {
-  if (!t.hdr->dovf) return;
+  if (!t.hdr->dovf) {
+    // the bins held: a chunk scattered without folding ends the skew hint
+    if (blockIdx.x == 0 && threadIdx.x == 0 && !t.hdr->dagg) t.hdr->dskew = 0;
+    return;
+  }
   const uint4 empty = make_uint4(0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu);
   for (int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x; j < (int64_t)dslots / 2;
        j += (int64_t)gridDim.x * kBlock)
     reinterpret_cast<uint4*>(t.dd)[j] = empty;
-  if (blockIdx.x == 0 && threadIdx.x == 0) t.hdr->dmode = 0;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    t.hdr->dmode = 0;
+    t.hdr->dskew = 1;   // later chunks of this table fold each tile's repeats first
+    t.hdr->dskew_age = 0;
+  }
 }
 
 __global__ __launch_bounds__(kBlock) void k_bin_fallback_dedup(TableView t,
@@ -569,7 +648,11 @@ __device__ __forceinline__ uint32_t first_copy(const TableView& t, const uint64_
                                                uint64_t key, int64_t i, uint32_t dmask,
                                                uint32_t mark) {
   if (key >= kTomb) return t.hdr->spec_first[key - kTomb];
-  if (mark) return t.hdr->dmode ? t.dfirst[i] : dedup_lookup(t, keys, key, dmask, (uint32_t)i);
+  if (mark) {
+    if (!t.hdr->dmode) return dedup_lookup(t, keys, key, dmask, (uint32_t)i);
+    const uint32_t f = t.dfirst[i];
+    return (f & kIndirect) ? t.dfirst[f & ~kIndirect] : f;
+  }
   return (uint32_t)i;
 }
 
@@ -1934,6 +2017,15 @@ ct_status ct_get_error(ct_table* t, uint32_t* h_err, void* stream) {
   if (hipMemcpyAsync(&t->v.hdr->err, &zero, sizeof(zero), hipMemcpyHostToDevice, S(stream)) != hipSuccess)
     return CT_E_HIP;
   return hipStreamSynchronize(S(stream)) == hipSuccess ? CT_OK : CT_E_HIP;
+}
+
+ct_status ct_table_dedup_skewed(ct_table* t, int32_t* h_skewed, void* stream) {
+  if (!t || !h_skewed) return CT_E_INVALID;
+  uint32_t v = 0;
+  ct_status r = read_back(&t->v.hdr->dskew, &v, S(stream));
+  if (r != CT_OK) return r;
+  *h_skewed = v ? 1 : 0;
+  return CT_OK;
 }
 
 // --- pools -------------------------------------------------------------------------------------

@@ -68,6 +68,7 @@ SIGNATURES = {
     "ct_dump": (C.c_int, [_P, _P, _P, _I64, _PI64, _P]),
     "ct_check_invariants": (C.c_int, [_P, _PI64, _P]),
     "ct_get_error": (C.c_int, [_P, C.POINTER(C.c_uint32), _P]),
+    "ct_table_dedup_skewed": (C.c_int, [_P, C.POINTER(C.c_int32), _P]),
     "ct_pool_bytes": (C.c_int, [_I64, _PI64]),
     "ct_pool_init": (C.c_int, [_P, _I64, _I64, _P, C.POINTER(_P)]),
     "ct_pool_destroy": (C.c_int, [_P]),
@@ -320,6 +321,14 @@ class Table:
         e = C.c_uint32(0)
         _check(lib().ct_get_error(self._h, C.byref(e), _stream(self.device)), "ct_get_error")
         return e.value
+
+    def dedup_skewed(self) -> bool:
+        """True when recent chunks overflowed the dedup bins, so large chunks fold each tile's
+        repeated keys first (a diagnostic: results never depend on it)."""
+        v = C.c_int32(0)
+        _check(lib().ct_table_dedup_skewed(self._h, C.byref(v), _stream(self.device)),
+               "ct_table_dedup_skewed")
+        return bool(v.value)
 
     def profiling(self, enable: bool = True):
         _check(lib().ct_table_set_profiling(self._h, int(enable)), "ct_table_set_profiling")

@@ -236,6 +236,50 @@ def test_pool_stack(dev):
     assert gp.error() & ct.ERR_POOL
 
 
+@pytest.mark.parametrize("chunk", [1 << 16, 1 << 18])
+def test_skewed_batches_fold_repeats_per_tile(dev, chunk):
+    """Zipf(1.1) batches repeat their hottest keys thousands of times per chunk and overflow the
+    dedup bins; the table then folds each tile's repeated keys before binning (a diagnostic shows
+    the hint), every 16th chunk retries without folding, and a batch of distinct keys ends the
+    hint.  Inserts, finds, erases and pool-valued inserts are compared with the oracle after every
+    batch; the reserved-looking keys ride along."""
+    rng = rng_for(83)
+    universe = 1 << 16
+    p = Pair(dev, 1 << 20, 64, chunk=chunk)
+
+    def zipf(n):
+        k = (rng.zipf(1.1, size=n) % universe).astype(np.uint64) * np.uint64(0x9E3779B97F4A7C15)
+        k[rng.integers(0, n, size=16)] = RESERVED[rng.integers(0, RESERVED.size, size=16)]
+        return k
+
+    p.insert(zipf(chunk), rng.integers(0, 1 << 62, size=chunk, dtype=np.uint64))
+    assert p.g.dedup_skewed()
+    for rep in range(20):   # more than 16 chunks: the periodic retry without folding runs too
+        n = chunk + 333 * rep
+        keys = zipf(n)
+        if rep % 3 == 2:
+            p.erase(keys)
+        else:
+            p.insert(keys, rng.integers(0, 1 << 62, size=n, dtype=np.uint64))
+        if rep % 5 == 0:
+            p.find(np.concatenate([keys[:4000], zipf(4000)]))
+    p.same_state()
+    assert p.g.dedup_skewed()
+    distinct = rng.permutation(np.arange(1, chunk + 1, dtype=np.uint64)) * np.uint64(0xD1B54A32D192ED03)
+    for _ in range(9):   # 18 chunks: one tries without folding, fits, and ends the hint
+        p.insert(distinct, rng.integers(0, 1 << 62, size=chunk, dtype=np.uint64))
+        p.erase(distinct)
+    p.find(distinct[: 1 << 12])
+    p.same_state()
+    assert not p.g.dedup_skewed()
+    q = Pair(dev, 1 << 19, 32, chunk=chunk, pool=1 << 19)
+    keys = zipf(chunk * 2 + 5)
+    q.insert_alloc(keys)
+    q.erase_release(keys[: chunk // 2])
+    q.insert_alloc(zipf(chunk * 3))
+    q.same_state()
+
+
 @pytest.mark.parametrize("chunk,universe", [(1 << 16, 1 << 15), (1 << 17, 1 << 12), (1 << 16, 3)])
 def test_binned_dedup_repeated_keys(dev, chunk, universe):
     """Chunks of at least 2^16 elements resolve repeated keys through bins: keys drawn from a
