@@ -45,8 +45,9 @@ constexpr int kBinSub = 8;              // segments per coarse bin, each with it
 constexpr int kCtrStride = 32;          // u32 words between coarse fill counts (one 128-byte line)
 constexpr int kCoarseCtrWords = kBinCoarse * kBinSub * kCtrStride;  // fine counts follow
 constexpr int kBinTile = 2048;          // elements per block of the scatter kernels
-constexpr int kBinFineCap = 1792;       // capacity of a fine bin (1.75 x the mean; more overflows)
-constexpr int kBinLds = 2048;           // LDS hash slots of the fine-bin dedup (> kBinFineCap)
+constexpr int kBinFineCap = 3072;       // entries of a fine bin (3 x the mean; more overflows)
+constexpr int kBinLds = 2048;           // LDS hash slots of the fine-bin dedup: distinct keys of a
+                                        // bin must be fewer (else the chunk takes the fallback)
 constexpr int kMaxFinePerCoarse = 256;  // fine bins per coarse bin at the largest chunk (2^24)
 
 enum : uint8_t { kPresent = 0, kInserted = 1, kFull = 2, kNoStatus = 0xFF };

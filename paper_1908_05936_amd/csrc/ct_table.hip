@@ -553,8 +553,10 @@ __global__ __launch_bounds__(kBlock) void k_bin_scatter2(TableView t, int blocks
 
 // One fine bin per block: insert its keys into an LDS table (CAS on the key word, atomic min on
 // the index, a flag when a key arrives again), then mark every element of a repeated key and
-// give it the key's lowest index.  A bin holds at most c2 < kBinLds elements, so every probe
-// finds a free or matching slot.
+// give it the key's lowest index.  A bin holds up to c2 entries but the table has kBinLds slots:
+// it needs fewer distinct keys than slots, which the bins of folded (skewed) chunks meet by far.
+// A bin with more distinct keys (no probe finds a free or matching slot) flags an overflow, and
+// the chunk takes the exact fallback.
 __global__ __launch_bounds__(kBlock) void k_bin_dedup(TableView t) {
   __shared__ unsigned long long hk[kBinLds];
   __shared__ uint32_t hm[kBinLds];
@@ -571,14 +573,30 @@ __global__ __launch_bounds__(kBlock) void k_bin_dedup(TableView t) {
   const uint32_t* ri = t.r2i + (int64_t)f * t.c2;
   // a bin holds at most c2 <= kPer * kBlock elements: each thread keeps its own in registers.
   // The loads are issued first, from clamped positions, and overlap the table's initialisation.
+  // The first kPer0 rows cover any bin of uniform keys (1.75 x the mean); the rest are loaded
+  // only when the fill reaches them (a uniform test).
   constexpr int kPer = (kBinFineCap + kBlock - 1) / kBlock;
+  constexpr int kPer0 = 7;
   uint64_t kk[kPer];
   uint32_t slot[kPer], idx[kPer];
 #pragma unroll
-  for (int e = 0; e < kPer; ++e) {
+  for (int e = 0; e < kPer0; ++e) {
     const uint32_t j = min(threadIdx.x + e * kBlock, n - 1u);
     kk[e] = rk[j];
     idx[e] = ri[j];
+  }
+#pragma unroll
+  for (int e = kPer0; e < kPer; ++e) {
+    kk[e] = kEmpty;
+    idx[e] = 0;
+  }
+  if (n > (uint32_t)(kPer0 * kBlock)) {
+#pragma unroll
+    for (int e = kPer0; e < kPer; ++e) {
+      const uint32_t j = min(threadIdx.x + e * kBlock, n - 1u);
+      kk[e] = rk[j];
+      idx[e] = ri[j];
+    }
   }
   for (uint32_t j = threadIdx.x; j < (uint32_t)kBinLds; j += kBlock) {
     hk[j] = kEmpty;
@@ -593,17 +611,18 @@ __global__ __launch_bounds__(kBlock) void k_bin_dedup(TableView t) {
     if (j < n) {
       const uint64_t key = kk[e];
       uint32_t s = (uint32_t)dedup_mix(key) & (kBinLds - 1);
-      for (;;) {
+      for (int probe = 0; probe < kBinLds; ++probe) {
         const unsigned long long old = atomicCAS(&hk[s], (unsigned long long)kEmpty,
                                                  (unsigned long long)key);
         if (old == kEmpty || old == key) {
           if (old == key) hx[s] = 1;
           atomicMin(&hm[s], idx[e]);
+          slot[e] = s;
           break;
         }
         s = (s + 1) & (kBinLds - 1);
       }
-      slot[e] = s;
+      if (slot[e] == kNone) t.hdr->dovf = 1u;  // every slot holds another key
     }
   }
   __syncthreads();
@@ -1576,7 +1595,7 @@ struct Layout {
   int64_t off_r1k, off_r1i, off_r2k, off_r2i, off_bcur, off_dfirst;
 };
 
-static_assert(kBinFineCap < kBinLds, "a fine bin must fit the LDS table");
+static_assert(kBinFineCap % kBlock == 0, "fine-bin entries are held kBlock per register row");
 
 bool make_layout(const ct_table_desc* d, Layout* L) {
   if (!d || d->capacity < 0) return false;
