@@ -96,8 +96,9 @@ typedef struct ct_table_desc {
     int64_t chunk;        /* keys handled per internal insert/erase chunk; a power of two in
                              [1024, 2^24]; 0 = the largest power of two <= C/8, clamped to
                              [1024, 2^23].  Batches larger than a chunk run as consecutive chunks
-                             (same results).  The table buffer holds 34 bytes of scratch per
-                             chunk element. */
+                             (same results).  The table buffer holds about 34 bytes of scratch
+                             per chunk element below 2^16, and 82-109 for larger chunks, which
+                             resolve repeated keys through bins (ct_table_bytes is exact). */
 } ct_table_desc;
 
 typedef struct ct_table ct_table;

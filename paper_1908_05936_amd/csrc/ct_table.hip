@@ -1608,7 +1608,8 @@ bool make_layout(const ct_table_desc* d, Layout* L) {
   int64_t q = d->chunk;
   if (q == 0) {
     // one chunk per ~capacity/8 keys: long kernels amortise launch and drain, and the scratch
-    // (34 bytes per chunk element) stays near a quarter of the 128 bytes per 8 slots
+    // (about 82 bytes per chunk element at these sizes) stays below two thirds of the buckets'
+    // 16 bytes per slot
     int64_t f = 1024;
     while (f * 2 <= d->capacity / 8 && f < ((int64_t)1 << 23)) f *= 2;
     q = f;

@@ -11,7 +11,7 @@ Autotuner.  The knobs of a plan run are
   * merge       -- grouped form only: merge each table's runs of same-kind operations into one
                    operation over gathered copies (fewer levels and launches, more memory),
   * chunk       -- per-table insert/erase chunk (a larger chunk means fewer chained sub-operations
-                   for big batches on small tables, at 34 bytes of scratch per chunk element),
+                   for big batches on small tables, at 34-109 bytes of scratch per chunk element),
   * provision   -- physical slots per requested capacity (1.0 = the requested load factor; more
                    slots lower the physical load and shorten probes, at the cost of memory).
 The lane-group width that probes one key is fixed at 8 lanes x 16 bytes = one 128-byte bucket

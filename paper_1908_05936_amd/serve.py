@@ -120,7 +120,7 @@ class Server:
 
 def serving_chunk(max_batch_keys: int = 1 << 21) -> int:
     """Insert/erase chunk for serving tables: half the largest coalesced batch (scratch is about
-    34 bytes per chunk element and table, so the chunk is sized to requests, not to capacity)."""
+    34-109 bytes per chunk element and table, so the chunk is sized to requests, not to capacity)."""
     return max(1024, max_batch_keys // 2)
 
 
