@@ -175,6 +175,37 @@ def test_empty_and_degenerate(dev):
     z.same_state()
 
 
+def test_clear_then_reuse(dev):
+    """clear empties the table (out-of-band keys included) and ends a skew hint; the cleared
+    table then behaves as a new one, compared with a cleared oracle table.  The sticky error word
+    survives clear until it is read."""
+    rng = rng_for(29)
+    chunk = 1 << 16
+    p = Pair(dev, 1 << 18, 64, chunk=chunk)
+    hot = np.full(chunk, 4242, dtype=np.uint64)      # overflows its bins: sets the skew hint
+    hot[::7] = distinct_u64(rng, hot[::7].size)
+    p.insert(np.concatenate([hot, RESERVED]), np.arange(chunk + RESERVED.size, dtype=np.uint64))
+    assert p.g.dedup_skewed()
+    p.g.clear()
+    p.o.clear()
+    assert p.g.size() == 0 and not p.g.dedup_skewed()
+    p.find(np.concatenate([hot[:100], RESERVED]))
+    p.same_state()
+    keys = distinct_u64(rng, 3 * chunk + 11)
+    p.insert(keys, np.arange(keys.size, dtype=np.uint64))
+    p.erase(keys[::5])
+    p.find(keys[:5000])
+    p.same_state()
+    small = Pair(dev, 4, 64)
+    small.insert(distinct_u64(rng, 6), np.arange(6, dtype=np.uint64))   # two are FULL
+    small.g.clear()
+    small.o.clear()
+    assert small.g.error() & ct.ERR_FULL     # kept through clear, cleared by reading it
+    assert small.g.error() == 0
+    small.insert(distinct_u64(rng, 4), np.arange(4, dtype=np.uint64))
+    small.same_state()
+
+
 @pytest.mark.parametrize("nb", [1, 37, 1 << 10])
 def test_full_physical_table_and_wraparound(dev, nb):
     """Capacity equal to every physical slot: probes wrap around the bucket array."""
