@@ -9,6 +9,7 @@ on the GPU; only the container calls are timed.
 The printed JSON line carries:
   value        whole-step throughput, container operations per second (Mops/s)
   breakdown    per-operation Mops/s from HIP events on the library's stream
+  insert_marginal_Mops_s  2^20 fresh keys inserted into the table at load 0.8
   roofline     the dominant kernel's algorithmic bytes per launch / its mean duration vs 8 TB/s
   random_access the same kernels against ceilings measured in this run on this chip
   pool         the index pool at 2^24 keys: insert_alloc, erase_release, bare pop and push
@@ -245,6 +246,34 @@ def find_uniform(op_clear, op_fill, dev, K_fill, n_fill, n_find, n_hit, L, h, s,
     return n_find / float(np.median(ts)) / 1e6
 
 
+def marginal_insert(dev, L, h, s, n=1 << 20, reps=3):
+    """Insert n fresh keys into the table as the step leaves it (load 0.8), then erase them again
+    (untimed) so the next run starts from the same state: Mops/s of the insert, median of `reps`
+    runs timed with HIP events.  Fresh uniform u64 keys collide with a live key with probability
+    about n * 2^26 / 2^64, so every status must read INSERTED."""
+    import torch
+    from paper_1908_05936_amd import ct
+
+    g = torch.Generator(device=dev)
+    g.manual_seed(11)
+    keys = torch.randint(-(1 << 62), 1 << 62, (n,), device=dev, generator=g)
+    vals = torch.arange(n, dtype=torch.int64, device=dev)
+    st = torch.empty(n, dtype=torch.uint8, device=dev)
+    er = torch.empty(n, dtype=torch.uint8, device=dev)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ts = []
+    for _ in range(reps):
+        e0.record()
+        ct._check(L.ct_insert_batch(h, ct._ptr(keys), ct._ptr(vals), n, ct._ptr(st), s), "marginal")
+        e1.record()
+        torch.cuda.synchronize()
+        ts.append(e0.elapsed_time(e1) * 1e-3)
+        assert int((st == 1).sum()) == n
+        ct._check(L.ct_erase_batch(h, ct._ptr(keys), n, ct._ptr(er), s), "marginal erase")
+    torch.cuda.synchronize()
+    return n / float(np.median(ts)) / 1e6
+
+
 def pool_ops(dev, keys, reps=3):
     """The index pool (vector/deque back operations) at scale: n = keys.numel() distinct keys into
     a table of capacity n / 0.8 whose values are popped from a pool of capacity n, then released
@@ -450,6 +479,8 @@ def main():
         "kernels": kernels,
         "roofline": roof,
     }
+    line["insert_marginal_Mops_s"] = marginal_insert(dev, L, h, s)
+    log(f"marginal insert of 2^20 fresh keys at load 0.8: {line['insert_marginal_Mops_s']:.0f} Mops/s")
     if not a.no_find_uniform:
         line["find_uniform_Mops_s"] = find_uniform(op_clear, op_fill, dev, K_fill, n_fill, n_find,
                                                    n_present_expected, L, h, s, vals_out, found)
