@@ -12,6 +12,7 @@ The printed JSON line carries:
   insert_marginal_Mops_s  2^20 fresh keys inserted into the table at load 0.8
   roofline     the dominant kernel's algorithmic bytes per launch / its mean duration vs 8 TB/s
   random_access the same kernels against ceilings measured in this run on this chip
+  rehash       the table rehashed into one of twice the capacity (host-side resize)
   pool         the index pool at 2^24 keys: insert_alloc, erase_release, bare pop and push
   voxel        the voxel-block frames: per-frame p50/p99, find and insert_alloc Mkeys/s
   served       the serving sweep on 64 device-resident tables: p50/p99 latency and achieved
@@ -91,6 +92,7 @@ def parse():
     ap.add_argument("--no-serve", action="store_true", help="skip the serving sweep")
     ap.add_argument("--no-voxel", action="store_true", help="skip the voxel-block frames")
     ap.add_argument("--no-pool", action="store_true", help="skip the index-pool operations")
+    ap.add_argument("--no-rehash", action="store_true", help="skip the resize (rehash) figure")
     ap.add_argument("--no-find-uniform", action="store_true",
                     help="skip the uniform-popularity find (counter runs keep to the step's kernels)")
     ap.add_argument("--serve-footprint-gb", type=float, default=40.0)
@@ -272,6 +274,34 @@ def marginal_insert(dev, L, h, s, n=1 << 20, reps=3):
         ct._check(L.ct_erase_batch(h, ct._ptr(keys), n, ct._ptr(er), s), "marginal erase")
     torch.cuda.synchronize()
     return n / float(np.median(ts)) / 1e6
+
+
+def rehash_leg(table, K_re, V_re):
+    """Host-side resize: the table as the step leaves it (2^26 live pairs at load 0.8) rehashed
+    into a new table of twice the capacity.  Time of the whole call (its two size reads included)
+    from HIP events on the stream, then a check of the size and of the re-inserted keys' values."""
+    import torch
+    from paper_1908_05936_amd import ct
+
+    n = table.size()
+    dst = ct.Table(2 * table.capacity, ct.VAL_U64, ct.HASH_MIX64, device=table.device)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    table.rehash_into(dst)
+    e1.record()
+    torch.cuda.synchronize()
+    sec = e0.elapsed_time(e1) * 1e-3
+    assert dst.size() == n
+    v, f = dst.find(K_re)
+    assert bool(f.all()) and bool((v == V_re).all())
+    out = {"pairs": n, "ms": sec * 1e3, "Mpairs_s": n / sec / 1e6,
+           "dst_capacity": dst.capacity, "dst_bytes": dst.nbytes}
+    log(f"[rehash] {n} pairs into capacity {dst.capacity}: {out['ms']:.2f} ms, "
+        f"{out['Mpairs_s']:.0f} Mpairs/s")
+    del dst
+    torch.cuda.empty_cache()
+    return out
 
 
 def pool_ops(dev, keys, reps=3):
@@ -481,6 +511,8 @@ def main():
     }
     line["insert_marginal_Mops_s"] = marginal_insert(dev, L, h, s)
     log(f"marginal insert of 2^20 fresh keys at load 0.8: {line['insert_marginal_Mops_s']:.0f} Mops/s")
+    if not a.no_rehash:
+        line["rehash"] = rehash_leg(table, K_re, V_re)
     if not a.no_find_uniform:
         line["find_uniform_Mops_s"] = find_uniform(op_clear, op_fill, dev, K_fill, n_fill, n_find,
                                                    n_present_expected, L, h, s, vals_out, found)

@@ -52,7 +52,8 @@ extern "C" {
 typedef enum ct_status {
     CT_OK = 0,
     CT_E_INVALID = 1, /* bad argument; nothing was enqueued */
-    CT_E_FULL = 2,    /* reserved for callers mapping the sticky error word */
+    CT_E_FULL = 2,    /* ct_table_rehash: the destination lacks room; otherwise reserved for
+                         callers mapping the sticky error word */
     CT_E_EMPTY = 3,   /* reserved for callers mapping the sticky error word */
     CT_E_NOMEM = 4,   /* host allocation of a handle failed */
     CT_E_HIP = 5      /* a HIP runtime call or kernel launch failed */
@@ -158,6 +159,15 @@ ct_status ct_dump(ct_table *t, uint64_t *keys_out, uint64_t *vals_out, int64_t c
 /* Check the layout invariants on the device: every live key is reachable from its home bucket,
    the live count equals the size counter.  *h_violations = number of failures.  Synchronises. */
 ct_status ct_check_invariants(ct_table *t, int64_t *h_violations, void *stream);
+
+/* Host-side resizing (a capacity is fixed at creation, Section 4; growth is a copy into a larger
+   table): insert every live (key, value) of `src` into `dst`, which must have the same value kind
+   and room for all of them (capacity(dst) >= size(dst) + size(src), else CT_E_FULL and nothing
+   is enqueued).  Keys `dst` already holds keep their value there.  `src` is unchanged.  Reads both
+   sizes (synchronises `stream`), then runs asynchronously on `stream`.  With a new empty `dst`
+   this is a rehash into a larger table; with a dump and an insert it is also how a table is
+   snapshot and restored. */
+ct_status ct_table_rehash(ct_table *src, ct_table *dst, void *stream);
 
 /* Read and clear the sticky error word (CT_ERR_* bits).  Synchronises. */
 ct_status ct_get_error(ct_table *t, uint32_t *h_err, void *stream);

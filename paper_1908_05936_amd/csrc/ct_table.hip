@@ -750,6 +750,36 @@ __device__ __forceinline__ void group_probe(const TableView& t, uint64_t key, ui
   *mystep = mine.step;
 }
 
+// Claims for the keys of the lanes in `want` (bit u: lane u's key is new and its probe saw a free
+// slot first at bucket myfb, slot myc, holding myexp): every lane claims for its own key, one CAS
+// instruction for the whole group; a key that lost its slot to another key scans on, one key at a
+// time.  Returns this lane's claimed slot (meaningful on `want` lanes), kNoPos when none is left.
+__device__ __forceinline__ uint64_t claim_group(const TableView& t, uint64_t key, uint32_t want,
+                                                int sub, uint64_t myfb, int myc, uint64_t myexp,
+                                                uint64_t mystep) {
+  uint64_t mypos = kNoPos;
+  int won = 0;
+  if ((want >> sub) & 1) {
+    uint64_t expected = myexp;
+    won = cas64(&t.bk[myfb].s[myc].key, expected, key) ? 1 : 0;
+  }
+  if (won) mypos = myfb * kSlots + (uint64_t)myc;
+  const uint32_t retry = want & ~group_bits(__ballot(won));
+  if (retry) {
+    const int gb = group_base();
+#pragma unroll
+    for (int u = 0; u < kSlots; ++u) {
+      if (!((retry >> u) & 1)) continue;
+      const uint64_t ku = __shfl(key, gb + u, 64);
+      const uint64_t fbu = __shfl(myfb, gb + u, 64);
+      const uint64_t stu = __shfl(mystep, gb + u, 64);
+      const uint64_t pos = claim(t, ku, fbu, stu, sub);
+      if (sub == u) mypos = pos;
+    }
+  }
+  return mypos;
+}
+
 // Insert actors, 8 elements per group and one per lane.  fast: claim directly with one CAS per
 // new key (all CASes of the group in flight together; a lost race retries one key at a time).
 // Otherwise (or with a pool) flag new keys for the ranked completion.
@@ -810,26 +840,8 @@ __device__ __forceinline__ int64_t insert_range(const TableView& t, const uint64
                         &mystep);
       const uint32_t want = fast ? (A & ~found & freeb) : 0u;
       if (want) {
-        // every lane claims for its own key: one CAS instruction for the whole group
-        int won = 0;
-        if ((want >> sub) & 1) {
-          uint64_t expected = myexp;
-          won = cas64(&t.bk[myfb].s[myc].key, expected, key) ? 1 : 0;
-        }
-        if (won) mypos = myfb * kSlots + (uint64_t)myc;
-        const uint32_t retry = want & ~group_bits(__ballot(won));
-        if (retry) {  // lost a race for the slot to another key: scan on, one key at a time
-          const int gb = group_base();
-#pragma unroll
-          for (int u = 0; u < kSlots; ++u) {
-            if (!((retry >> u) & 1)) continue;
-            const uint64_t ku = __shfl(key, gb + u, 64);
-            const uint64_t fbu = __shfl(myfb, gb + u, 64);
-            const uint64_t stu = __shfl(mystep, gb + u, 64);
-            const uint64_t pos = claim(t, ku, fbu, stu, sub);
-            if (sub == u) mypos = pos;
-          }
-        }
+        const uint64_t pos = claim_group(t, key, want, sub, myfb, myc, myexp, mystep);
+        if ((want >> sub) & 1) mypos = pos;
       }
       if ((A >> sub) & 1) {
         if ((found >> sub) & 1) {
@@ -872,6 +884,58 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu((ALLOC |
   // one partial per block, summed by k_apply_count: no same-address atomics across the grid
   const int64_t tot = block_sum(ins);
   if (threadIdx.x == 0) t.bcnt[blockIdx.x] = tot;
+}
+
+// Host-side resizing (a table's capacity is fixed when it is created, Section 4; it grows by a
+// copy into a larger table): every live pair of src is inserted into dst.  One 8-lane group per
+// src bucket, its 8 slots as the group's keys.  The keys of src are distinct and the host has
+// checked that dst has room for all of them, so a new key claims a slot directly; a key dst
+// already holds stays unchanged.  Counts per block, summed by k_apply_count.
+__global__ __launch_bounds__(kBlock) void k_rehash(TableView src, TableView dst) {
+  const int sub = threadIdx.x & 7;
+  const int64_t nbk = (int64_t)src.nb;
+  const int64_t gpb = kBlock / 8;
+  const int64_t ngroups = (int64_t)gridDim.x * gpb;
+  const int64_t span = ((nbk + ngroups - 1) / ngroups) * ngroups;  // equal trips for all lanes
+  int64_t ins = 0;
+  for (int64_t g = (int64_t)blockIdx.x * gpb + (threadIdx.x >> 3); g < span; g += ngroups) {
+    Slot sl;
+    sl.key = kEmpty;
+    sl.val = 0;
+    if (g < nbk) sl = src.bk[g].s[sub];
+    const bool live = sl.key != kEmpty && sl.key != kTomb;
+    const uint64_t key = live ? sl.key : kEmpty;
+    const uint32_t A = group_bits(__ballot(live));
+    if (!A) continue;
+    uint32_t found, hadE, freeb;
+    uint64_t mypos = kNoPos, myval = 0, myfb = 0, myexp = 0;
+    int myc = 0;
+    uint64_t mystep = 0;
+    group_probe<true>(dst, key, A, sub, &found, &hadE, &freeb, &mypos, &myval, &myfb, &myc, &myexp,
+                      &mystep);
+    const uint32_t want = A & ~found & freeb;
+    uint64_t pos = kNoPos;
+    if (want) pos = claim_group(dst, key, want, sub, myfb, myc, myexp, mystep);
+    if (live && !((found >> sub) & 1)) {
+      if (((want >> sub) & 1) && pos != kNoPos) {
+        dst.bk[pos >> 3].s[pos & 7].val = sl.val;
+        ++ins;
+      } else {
+        aor32(&dst.hdr->err, kErrFull);  // not reached while dst has the room the host checked
+      }
+    }
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {  // the out-of-band keys
+    for (int s = 0; s < 2; ++s) {
+      if (src.hdr->spec_live[s] && !dst.hdr->spec_live[s]) {
+        dst.hdr->spec_live[s] = 1;
+        dst.hdr->spec_val[s] = src.hdr->spec_val[s];
+        ++ins;
+      }
+    }
+  }
+  const int64_t tot = block_sum(ins);
+  if (threadIdx.x == 0) dst.bcnt[blockIdx.x] = tot;
 }
 
 // Erase actors, 8 elements per group.  RELEASE: the removed value is kept for the ordered push.
@@ -1993,6 +2057,22 @@ ct_status ct_clear(ct_table* t, void* stream) {
   if (!t) return CT_E_INVALID;
   launch(t, CT_KERNEL_CLEAR, S(stream), [&] { k_table_reset<<<flat_blocks((int64_t)t->v.nb * kSlots), kBlock, 0, S(stream)>>>(t->v, 0); });
   t->size_ub = 0;
+  return launched();
+}
+
+ct_status ct_table_rehash(ct_table* src, ct_table* dst, void* stream) {
+  if (!src || !dst || src == dst || src->desc.val_kind != dst->desc.val_kind) return CT_E_INVALID;
+  int64_t ns = 0, nd = 0;
+  ct_status r = ct_size(src, &ns, stream);
+  if (r == CT_OK) r = ct_size(dst, &nd, stream);
+  if (r != CT_OK) return r;
+  if (nd + ns > dst->desc.capacity) return CT_E_FULL;
+  if (ns == 0) return CT_OK;
+  const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(((int64_t)src->v.nb + kBlock / 8 - 1) / (kBlock / 8), kMaxGroupBlocks));
+  hipStream_t s = S(stream);
+  launch(dst, CT_KERNEL_INSERT, s, [&] { k_rehash<<<grid, kBlock, 0, s>>>(src->v, dst->v); });
+  launch(dst, CT_KERNEL_APPLY, s, [&] { k_apply_count<<<1, 1024, 0, s>>>(dst->v, grid); });
+  dst->size_ub = (uint64_t)(nd + ns);
   return launched();
 }
 

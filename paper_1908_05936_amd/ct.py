@@ -69,6 +69,7 @@ SIGNATURES = {
     "ct_check_invariants": (C.c_int, [_P, _PI64, _P]),
     "ct_get_error": (C.c_int, [_P, C.POINTER(C.c_uint32), _P]),
     "ct_table_dedup_skewed": (C.c_int, [_P, C.POINTER(C.c_int32), _P]),
+    "ct_table_rehash": (C.c_int, [_P, _P, _P]),
     "ct_pool_bytes": (C.c_int, [_I64, _PI64]),
     "ct_pool_init": (C.c_int, [_P, _I64, _I64, _P, C.POINTER(_P)]),
     "ct_pool_destroy": (C.c_int, [_P]),
@@ -310,6 +311,33 @@ class Table:
                "ct_dump")
         m = cnt.value
         return k[:m], v[:m]
+
+    def rehash_into(self, dst: "Table"):
+        """Insert every live pair of this table into `dst` (same value kind, room for all of them;
+        keys `dst` holds keep their value there)."""
+        if dst.device != self.device:
+            raise CtError("rehash_into: both tables must be on one device")
+        _check(lib().ct_table_rehash(self._h, dst._h, _stream(self.device)), "ct_table_rehash")
+
+    def resized(self, capacity: int, bucket_count: int = 0, chunk: int = 0) -> "Table":
+        """A new table of `capacity` (same value and hash kind) holding this table's pairs: the
+        host-side resize; this table is unchanged."""
+        t = Table(capacity, self.value_kind, self.desc.hash_kind, bucket_count, chunk,
+                  device=self.device)
+        self.rehash_into(t)
+        return t
+
+    def snapshot(self):
+        """(keys, values) of every live pair, as device tensors: restore() them into this or any
+        table of the same value kind."""
+        return self.dump()
+
+    def restore(self, keys: torch.Tensor, vals: torch.Tensor | None):
+        """Make this table hold exactly the pairs of a snapshot (keys distinct)."""
+        self.clear()
+        if keys.numel():
+            self.insert(keys, None if self.value_kind == VAL_NONE else
+                        vals.to(self.value_dtype) if vals is not None else None, status=False)
 
     def check(self) -> int:
         v = C.c_int64(0)

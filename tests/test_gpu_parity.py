@@ -206,6 +206,62 @@ def test_clear_then_reuse(dev):
     small.same_state()
 
 
+@pytest.mark.parametrize("bits,hash_kind", [(64, ct.HASH_MIX64), (32, ct.HASH_VOXEL21),
+                                             (0, ct.HASH_MIX64)])
+def test_rehash_resize_snapshot_restore(dev, bits, hash_kind):
+    """Host-side resizing: every live pair of a table goes into another one (a larger new table,
+    or one that already holds some of the keys, which keep their value there).  The oracle side is
+    the definition: its own dump inserted into its destination.  The source stays unchanged, both
+    tables keep working afterwards, a destination without room is refused before anything runs,
+    and a snapshot restores a table's exact contents."""
+    rng = rng_for(37, bits)
+    vb = 32 if bits == 32 else 64
+
+    def vals(n):
+        return rng.integers(0, 1 << vb, size=n, dtype=np.uint64) if bits else None
+
+    src = Pair(dev, 50_000, bits, hash_kind=hash_kind, chunk=1 << 12)
+    keys = distinct_u64(rng, 40_000)
+    keys[:4] = RESERVED[:4]
+    src.insert(keys, vals(keys.size))
+    src.erase(keys[::3])
+    src.insert(keys[::6], vals(keys[::6].size))
+    src.same_state()
+    dst = Pair(dev, 120_000, bits, hash_kind=hash_kind)
+    other = np.concatenate([keys[1::5], distinct_u64(rng, 20_000), RESERVED[1:3]])
+    dst.insert(other, vals(other.size))
+    src.g.rehash_into(dst.g)
+    ok, ov = src.o.dump()
+    dst.o.insert(ok, ov if bits else None)
+    dst.same_state()
+    src.same_state()
+    fresh = distinct_u64(rng, 30_000, exclude=np.concatenate([keys, other]))
+    dst.insert(fresh, vals(fresh.size))
+    dst.erase(np.concatenate([keys[::7], fresh[::2]]))
+    dst.find(np.concatenate([keys, fresh[:1000]]))
+    dst.same_state()
+    src.erase(keys[::2])
+    src.same_state()
+    big = Pair(dev, 1 << 17, bits, hash_kind=hash_kind)
+    big.g = src.g.resized(1 << 17)                      # a new, larger table with src's pairs
+    k2, v2 = src.o.dump()
+    big.o.insert(k2, v2 if bits else None)
+    big.same_state()
+    with pytest.raises(ct.CtError, match="capacity exhausted"):   # no room: refused
+        dst.g.rehash_into(Pair(dev, 100, bits, hash_kind=hash_kind).g)
+    if bits:
+        with pytest.raises(ct.CtError):                 # value kinds differ
+            src.g.rehash_into(ct.Table(1 << 17, ct.VAL_NONE, device=dev))
+    snap_k, snap_v = src.g.snapshot()
+    ek, ev = src.o.dump()
+    src.insert(fresh[:5000], vals(5000))
+    src.g.restore(snap_k, snap_v if bits else None)
+    src.o.clear()
+    src.o.insert(ek, ev if bits else None)
+    src.same_state()
+    src.find(np.concatenate([keys[:3000], fresh[:3000]]))
+
+
 @pytest.mark.parametrize("nb", [1, 37, 1 << 10])
 def test_full_physical_table_and_wraparound(dev, nb):
     """Capacity equal to every physical slot: probes wrap around the bucket array."""
