@@ -73,6 +73,8 @@ def lib():
             "or_pool_dump": (I64, [P, P, I64]),
             "or_pool_pop": (None, [P, I64, P, P]),
             "or_pool_push": (None, [P, P, I64, P]),
+            "or_pool_pop_front": (None, [P, I64, P, P]),
+            "or_pool_push_front": (None, [P, P, I64, P]),
             "or_insert_alloc": (None, [P, P, P, I64, P, P]),
             "or_erase_release": (None, [P, P, P, I64, P]),
             "or_dump": (I64, [P, P, P, I64]),
@@ -179,6 +181,20 @@ class OraclePool:
         v = np.ascontiguousarray(values, dtype=np.int32)
         st = np.empty(v.size, dtype=np.uint8)
         lib().or_pool_push(self._h, _ptr(v), v.size, _ptr(st))
+        return st
+
+    def pop_front(self, n: int):
+        """pop_front n times (deque front operation, Section 4.3)."""
+        out = np.empty(int(n), dtype=np.int32)
+        st = np.empty(int(n), dtype=np.uint8)
+        lib().or_pool_pop_front(self._h, int(n), _ptr(out), _ptr(st))
+        return out, st
+
+    def push_front(self, values):
+        """push_front of each value in order: the last one ends up first."""
+        v = np.ascontiguousarray(values, dtype=np.int32)
+        st = np.empty(v.size, dtype=np.uint8)
+        lib().or_pool_push_front(self._h, _ptr(v), v.size, _ptr(st))
         return st
 
 

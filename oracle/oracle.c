@@ -16,7 +16,9 @@
  *   find   : the mapped value or "not found" (find / contains, Section 4.1).
  *   erase  : removes the key, reporting whether it was present (Section 4.1).
  *   pool   : push_back appends, pop_back removes and returns the last element (Sections 4.2-4.3);
- *            used as a last-in first-out free list of int32 indices.
+ *            used as a last-in first-out free list of int32 indices.  The deque's front
+ *            operations (Section 4.3) remove or insert at the other end: pop_front then
+ *            push_back is a first-in first-out free list.
  * Duplicates inside one batch therefore resolve in index order: the lowest index acts first and
  * later copies see the state it left.
  *
@@ -273,6 +275,40 @@ void or_pool_push(or_pool *p, const int32_t *in, int64_t n, uint8_t *status)
             if (status) status[i] = 2;
         } else {
             p->stack[p->top++] = in[i];
+            if (status) status[i] = 1;
+        }
+    }
+}
+
+/* pop_front n times (a deque front operation, Section 4.3): out[i] is the removed first
+   element, or -1 (status 2) once the pool is empty.  The stack's bottom is the deque's front. */
+void or_pool_pop_front(or_pool *p, int64_t n, int32_t *out, uint8_t *status)
+{
+    for (int64_t i = 0; i < n; ++i) {
+        if (p->top == 0) {
+            if (out) out[i] = -1;
+            if (status) status[i] = 2;
+        } else {
+            int32_t v = p->stack[0];
+            memmove(p->stack, p->stack + 1, sizeof(int32_t) * (size_t)(p->top - 1));
+            --p->top;
+            if (out) out[i] = v;
+            if (status) status[i] = 1;
+        }
+    }
+}
+
+/* push_front n values in order (the last one ends up first): status 1 stored, 2 when the pool is
+   already at capacity. */
+void or_pool_push_front(or_pool *p, const int32_t *in, int64_t n, uint8_t *status)
+{
+    for (int64_t i = 0; i < n; ++i) {
+        if (p->top == p->capacity) {
+            if (status) status[i] = 2;
+        } else {
+            memmove(p->stack + 1, p->stack, sizeof(int32_t) * (size_t)p->top);
+            p->stack[0] = in[i];
+            ++p->top;
             if (status) status[i] = 1;
         }
     }

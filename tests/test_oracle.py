@@ -111,6 +111,58 @@ def test_pool_stack_matches_bruteforce(pcap, ops):
         assert p.dump().tolist() == bp.stack
 
 
+@settings(max_examples=200, deadline=None)
+@given(pcap=st.integers(0, 10),
+       ops=st.lists(st.tuples(st.sampled_from(["pop", "push", "pop_front", "push_front"]),
+                              st.integers(0, 8),
+                              st.lists(st.integers(-5, 20), min_size=8, max_size=8)), max_size=12))
+def test_pool_deque_matches_collections_deque(pcap, ops):
+    """The pool's four deque operations (Section 4.3) against Python's collections.deque, the
+    textbook double-ended queue, with the pool's fixed capacity: a pop on an empty deque gives
+    -1 (status 2), a push on a full one is refused (status 2).  The dump lists front to back."""
+    from collections import deque
+    p = OraclePool(pcap)
+    d = deque(range(pcap - 1, -1, -1))     # a fresh pool pops_back 0, 1, 2, ...
+    for kind, n, vals in ops:
+        if kind in ("pop", "pop_front"):
+            out, stt = p.pop(n) if kind == "pop" else p.pop_front(n)
+            eo, es = [], []
+            for _ in range(n):
+                if d:
+                    eo.append(d.pop() if kind == "pop" else d.popleft())
+                    es.append(1)
+                else:
+                    eo.append(-1)
+                    es.append(2)
+            assert out.tolist() == eo and stt.tolist() == es
+        else:
+            v = vals[:n]
+            stt = p.push(np.array(v, dtype=np.int32)) if kind == "push" else \
+                p.push_front(np.array(v, dtype=np.int32))
+            es = []
+            for x in v:
+                if len(d) == pcap:
+                    es.append(2)
+                else:
+                    (d.append if kind == "push" else d.appendleft)(x)
+                    es.append(1)
+            assert stt.tolist() == es
+        assert p.dump().tolist() == list(d)
+
+
+def test_fifo_free_list_closed_form():
+    """pop_front of a fresh pool of capacity c returns c-1, c-2, ...; used as a first-in
+    first-out free list (pop_front, push_back) released values come back after every older one."""
+    p = OraclePool(6)
+    out, stt = p.pop_front(3)
+    assert out.tolist() == [5, 4, 3] and stt.tolist() == [1, 1, 1]
+    assert p.push(np.array([4, 5], dtype=np.int32)).tolist() == [1, 1]
+    out, _ = p.pop_front(5)
+    assert out.tolist() == [2, 1, 0, 4, 5]
+    assert p.push_front(np.array([7, 8, 9], dtype=np.int32)).tolist() == [1, 1, 1]
+    assert p.dump().tolist() == [9, 8, 7]
+
+
 # ------------------------------------------------------------------------------------------
 # Python dict as the textbook map, at a size brute force cannot reach
 # ------------------------------------------------------------------------------------------
