@@ -196,11 +196,25 @@ ct_status ct_pool_pop_batch(ct_pool *p, int64_t n, int32_t *out, uint8_t *status
 ct_status ct_pool_push_batch(ct_pool *p, const int32_t *in, int64_t n, uint8_t *status,
                              void *stream);
 
+/* Deque front operations (Section 4.3: the deque also inserts and removes at its front).  The
+   pool is a double-ended queue whose back the operations above use; a fresh pool's front holds
+   capacity-1.  pop_front n times: out[n] (nullable) gets the removed first element or -1 once the
+   pool is empty; status[n] (nullable) 1 = popped, 2 = empty (CT_ERR_POOL set).  With push_back
+   this is a first-in first-out free list. */
+ct_status ct_pool_pop_front_batch(ct_pool *p, int64_t n, int32_t *out, uint8_t *status,
+                                  void *stream);
+
+/* push_front in[0..n) in order: each value goes in front of the previous one, so in[n-1] ends
+   up first.  status[n] (nullable) 1 = stored, 2 = the pool was at capacity (value dropped,
+   CT_ERR_POOL set). */
+ct_status ct_pool_push_front_batch(ct_pool *p, const int32_t *in, int64_t n, uint8_t *status,
+                                   void *stream);
+
 /* Number of entries in the pool.  Synchronises. */
 ct_status ct_pool_size(ct_pool *p, int64_t *h_size, void *stream);
 
-/* Copy the stack bottom-first into out (device, `cap` entries) and return the entry count in
-   *h_count.  Synchronises. */
+/* Copy the pool front first (the stack bottom first) into out (device, `cap` entries) and return
+   the entry count in *h_count.  Synchronises. */
 ct_status ct_pool_dump(ct_pool *p, int32_t *out, int64_t cap, int64_t *h_count, void *stream);
 
 /* Read and clear the pool's sticky error word.  Synchronises. */

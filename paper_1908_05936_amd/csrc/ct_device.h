@@ -81,12 +81,24 @@ struct alignas(256) Header {
   uint32_t dskew_age;      // binned chunks since dskew was set; every 16th tries without folding
 };
 
+// A pool is a deque of int32 in a ring of `cap` entries: element x (0 = front, top - 1 = back)
+// sits at stack[(head + x) mod cap].  Back operations move top; front operations move head too.
 struct alignas(256) PoolHeader {
-  int64_t top;   // entries on the stack
+  int64_t top;   // entries in the pool
   int64_t top0;  // top when the current batch started
   int64_t cap;
   uint32_t err;
+  int64_t head;  // ring position of the front element
+  int64_t head0; // head when the current batch started
 };
+
+// Ring position of pool element x, for head in [0, cap) and x in [-cap, 2 cap - head).
+__device__ __forceinline__ int64_t ring_pos(int64_t head, int64_t cap, int64_t x) {
+  int64_t p = head + x;
+  if (p >= cap) p -= cap;
+  else if (p < 0) p += cap;
+  return p;
+}
 
 // Everything a kernel needs to reach a table; passed by value (a shallow copy, Section 3.7).
 struct TableView {

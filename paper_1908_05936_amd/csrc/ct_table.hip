@@ -1107,8 +1107,9 @@ __global__ __launch_bounds__(1024) void k_tile_scan(TableView t, PoolHeader* poo
 
 // Ranked completion of flagged elements, one tile per block.
 // MODE 0: insert near capacity (rank < room -> claim, else FULL)
-// MODE 1: insert with pool values (rank < min(room, pool) -> value = stack[top0-1-rank])
-// MODE 2: erase releasing to the pool (stack[top0+rank] = value)
+// MODE 1: insert with pool values (rank < min(room, pool) -> value = pool element top0-1-rank)
+// MODE 2: erase releasing to the pool (pool element top0+rank = value)
+// (the batch moves only the back of the pool: head is fixed while it runs)
 template <int VK, int MODE>
 __device__ __forceinline__ void final_tile(const TableView& t, PoolHeader* pool,
                                            int32_t* __restrict__ pstack,
@@ -1144,7 +1145,8 @@ __device__ __forceinline__ void final_tile(const TableView& t, PoolHeader* pool,
     if constexpr (MODE == 2) {
       if (sub == 0) {
         const int64_t pos = pool->top0 + (int64_t)rank;
-        if (pos < pool->cap) pstack[pos] = (int32_t)(uint32_t)t.ref[i];
+        if (pos < pool->cap)
+          pstack[ring_pos(pool->head, pool->cap, pos)] = (int32_t)(uint32_t)t.ref[i];
       }
       continue;
     } else {
@@ -1162,7 +1164,8 @@ __device__ __forceinline__ void final_tile(const TableView& t, PoolHeader* pool,
       }
       const uint64_t key = keys[i];
       uint64_t v = 0;
-      if constexpr (MODE == 1) v = (uint64_t)(uint32_t)pstack[pool->top0 - 1 - (int64_t)rank];
+      if constexpr (MODE == 1)
+        v = (uint64_t)(uint32_t)pstack[ring_pos(pool->head, pool->cap, pool->top0 - 1 - (int64_t)rank)];
       else v = load_val<VK>(vals, i);
       uint64_t pos;
       if (MODE == 1 && fast) {
@@ -1342,20 +1345,25 @@ __global__ __launch_bounds__(kBlock) void k_pool_init(PoolHeader* ph, int32_t* s
     ph->top0 = cap;
     ph->cap = cap;
     ph->err = 0;
+    ph->head = 0;
+    ph->head0 = 0;
   }
 }
 
-__global__ void k_pool_snapshot(PoolHeader* ph) { ph->top0 = ph->top; }
+__global__ void k_pool_snapshot(PoolHeader* ph) {
+  ph->top0 = ph->top;
+  ph->head0 = ph->head;
+}
 
 __global__ __launch_bounds__(kBlock) void k_pool_pop(PoolHeader* ph, const int32_t* __restrict__ stack,
                                                      int64_t n, int32_t* __restrict__ out,
                                                      uint8_t* __restrict__ status) {
   const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t nt = (int64_t)gridDim.x * blockDim.x;
-  const int64_t top0 = ph->top0;
+  const int64_t top0 = ph->top0, head0 = ph->head0, cap = ph->cap;
   for (int64_t i = tid; i < n; i += nt) {
     const bool ok = i < top0;
-    if (out) out[i] = ok ? stack[top0 - 1 - i] : -1;
+    if (out) out[i] = ok ? stack[ring_pos(head0, cap, top0 - 1 - i)] : -1;
     if (status) status[i] = ok ? 1 : 2;
   }
   if (tid == 0) {
@@ -1369,10 +1377,10 @@ __global__ __launch_bounds__(kBlock) void k_pool_push(PoolHeader* ph, int32_t* _
                                                       uint8_t* __restrict__ status) {
   const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t nt = (int64_t)gridDim.x * blockDim.x;
-  const int64_t top0 = ph->top0, cap = ph->cap;
+  const int64_t top0 = ph->top0, head0 = ph->head0, cap = ph->cap;
   for (int64_t i = tid; i < n; i += nt) {
     const bool ok = top0 + i < cap;
-    if (ok) stack[top0 + i] = in[i];
+    if (ok) stack[ring_pos(head0, cap, top0 + i)] = in[i];
     if (status) status[i] = ok ? 1 : 2;
   }
   if (tid == 0) {
@@ -1386,7 +1394,49 @@ __global__ __launch_bounds__(kBlock) void k_pool_copy(const PoolHeader* ph, cons
   const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t nt = (int64_t)gridDim.x * blockDim.x;
   const int64_t m = ph->top < cap ? ph->top : cap;
-  for (int64_t j = tid; j < m; j += nt) out[j] = stack[j];
+  for (int64_t j = tid; j < m; j += nt) out[j] = stack[ring_pos(ph->head, ph->cap, j)];
+}
+
+// Deque front operations (Section 4.3).  pop_front: element i of the batch removes pool element i
+// (front first), -1 once the pool is empty.  push_front: element i goes just in front of the
+// previous one, so the last value pushed ends up first.
+__global__ __launch_bounds__(kBlock) void k_pool_pop_front(PoolHeader* ph, const int32_t* __restrict__ stack,
+                                                           int64_t n, int32_t* __restrict__ out,
+                                                           uint8_t* __restrict__ status) {
+  const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t nt = (int64_t)gridDim.x * blockDim.x;
+  const int64_t top0 = ph->top0, head0 = ph->head0, cap = ph->cap;
+  for (int64_t i = tid; i < n; i += nt) {
+    const bool ok = i < top0;
+    if (out) out[i] = ok ? stack[ring_pos(head0, cap, i)] : -1;
+    if (status) status[i] = ok ? 1 : 2;
+  }
+  if (tid == 0) {
+    const int64_t m = n < top0 ? n : top0;
+    ph->head = m ? ring_pos(head0, cap, m) : head0;
+    ph->top = top0 - m;
+    if (n > top0) ph->err |= kErrPool;
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_pool_push_front(PoolHeader* ph, int32_t* __restrict__ stack,
+                                                            const int32_t* __restrict__ in, int64_t n,
+                                                            uint8_t* __restrict__ status) {
+  const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t nt = (int64_t)gridDim.x * blockDim.x;
+  const int64_t top0 = ph->top0, head0 = ph->head0, cap = ph->cap;
+  for (int64_t i = tid; i < n; i += nt) {
+    const bool ok = top0 + i < cap;
+    if (ok) stack[ring_pos(head0, cap, -1 - i)] = in[i];
+    if (status) status[i] = ok ? 1 : 2;
+  }
+  if (tid == 0) {
+    const int64_t room = cap - top0;
+    const int64_t m = n < room ? n : room;
+    ph->head = m ? ring_pos(head0, cap, -m) : head0;
+    ph->top = top0 + m;
+    if (n > room) ph->err |= kErrPool;
+  }
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -2165,6 +2215,24 @@ ct_status ct_pool_pop_batch(ct_pool* p, int64_t n, int32_t* out, uint8_t* status
   if (n == 0) return CT_OK;
   k_pool_snapshot<<<1, 1, 0, S(stream)>>>(p->hdr);
   k_pool_pop<<<flat_blocks(n), kBlock, 0, S(stream)>>>(p->hdr, p->stack, n, out, status);
+  return launched();
+}
+
+ct_status ct_pool_pop_front_batch(ct_pool* p, int64_t n, int32_t* out, uint8_t* status,
+                                  void* stream) {
+  if (!p || n < 0) return CT_E_INVALID;
+  if (n == 0) return CT_OK;
+  k_pool_snapshot<<<1, 1, 0, S(stream)>>>(p->hdr);
+  k_pool_pop_front<<<flat_blocks(n), kBlock, 0, S(stream)>>>(p->hdr, p->stack, n, out, status);
+  return launched();
+}
+
+ct_status ct_pool_push_front_batch(ct_pool* p, const int32_t* in, int64_t n, uint8_t* status,
+                                   void* stream) {
+  if (!p || n < 0 || (n > 0 && !in)) return CT_E_INVALID;
+  if (n == 0) return CT_OK;
+  k_pool_snapshot<<<1, 1, 0, S(stream)>>>(p->hdr);
+  k_pool_push_front<<<flat_blocks(n), kBlock, 0, S(stream)>>>(p->hdr, p->stack, in, n, status);
   return launched();
 }
 

@@ -75,6 +75,8 @@ SIGNATURES = {
     "ct_pool_destroy": (C.c_int, [_P]),
     "ct_pool_pop_batch": (C.c_int, [_P, _I64, _P, _P, _P]),
     "ct_pool_push_batch": (C.c_int, [_P, _P, _I64, _P, _P]),
+    "ct_pool_pop_front_batch": (C.c_int, [_P, _I64, _P, _P, _P]),
+    "ct_pool_push_front_batch": (C.c_int, [_P, _P, _I64, _P, _P]),
     "ct_pool_size": (C.c_int, [_P, _PI64, _P]),
     "ct_pool_dump": (C.c_int, [_P, _P, _I64, _PI64, _P]),
     "ct_pool_get_error": (C.c_int, [_P, C.POINTER(C.c_uint32), _P]),
@@ -154,7 +156,8 @@ _VAL_DTYPE = {VAL_U32: torch.int32, VAL_U64: torch.int64}
 
 
 class Pool:
-    """Device index pool: a fixed-capacity int32 stack (vector/deque back operations)."""
+    """Device index pool: a fixed-capacity int32 deque (back operations: the stack that feeds
+    insert_alloc; front operations: pop_front / push_front)."""
 
     def __init__(self, capacity: int, device="cuda"):
         self.device = torch.device(device)
@@ -186,6 +189,22 @@ class Pool:
         st = torch.empty(values.numel(), dtype=torch.uint8, device=self.device)
         _check(lib().ct_pool_push_batch(self._h, _ptr(values), values.numel(), _ptr(st),
                                         _stream(self.device)), "ct_pool_push_batch")
+        return st
+
+    def pop_front(self, n: int):
+        """pop_front n times (deque front operation): (values or -1, statuses)."""
+        out = torch.empty(int(n), dtype=torch.int32, device=self.device)
+        st = torch.empty(int(n), dtype=torch.uint8, device=self.device)
+        _check(lib().ct_pool_pop_front_batch(self._h, int(n), _ptr(out), _ptr(st),
+                                             _stream(self.device)), "ct_pool_pop_front_batch")
+        return out, st
+
+    def push_front(self, values: torch.Tensor):
+        """push_front each value in order (the last ends up first): statuses."""
+        _need(values, torch.int32, None, "values", self.device)
+        st = torch.empty(values.numel(), dtype=torch.uint8, device=self.device)
+        _check(lib().ct_pool_push_front_batch(self._h, _ptr(values), values.numel(), _ptr(st),
+                                              _stream(self.device)), "ct_pool_push_front_batch")
         return st
 
     def size(self) -> int:

@@ -323,6 +323,56 @@ def test_pool_stack(dev):
     assert gp.error() & ct.ERR_POOL
 
 
+@pytest.mark.parametrize("pcap", [1, 1000, 70_001])
+def test_pool_deque_front_and_back(dev, pcap):
+    """The pool's four deque operations (Section 4.3) in random batches, each compared with the
+    oracle pool (values, statuses, size, front-to-back contents, the sticky error).  Front
+    operations move the ring's head, so later back operations and the table's pool-valued insert
+    and release wrap around the end of the buffer; used as a FIFO free list (pop_front, then
+    push_back of released values) the pool keeps matching."""
+    rng = rng_for(43, pcap)
+    gp = ct.Pool(pcap, device=dev)
+    op = oracle.OraclePool(pcap)
+
+    def same():
+        assert gp.size() == op.size()
+        np.testing.assert_array_equal(gp.dump().cpu().numpy(), op.dump())
+
+    failed = False   # the sticky pool error follows the oracle's refused elements
+    for step in range(24):
+        kind = rng.choice(["pop", "push", "pop_front", "push_front"])
+        n = int(rng.integers(0, max(2, pcap // 3)))
+        if kind in ("pop", "pop_front"):
+            out, st = gp.pop(n) if kind == "pop" else gp.pop_front(n)
+            eo, es = op.pop(n) if kind == "pop" else op.pop_front(n)
+            np.testing.assert_array_equal(out.cpu().numpy(), eo)
+        else:
+            vals = rng.integers(0, 1 << 31, size=n, dtype=np.int64).astype(np.int32)
+            g = torch.from_numpy(vals).to(dev)
+            st = gp.push(g) if kind == "push" else gp.push_front(g)
+            es = op.push(vals) if kind == "push" else op.push_front(vals)
+        np.testing.assert_array_equal(st.cpu().numpy(), es)
+        failed |= bool((es == 2).any())
+        same()
+    assert bool(gp.error() & ct.ERR_POOL) == failed
+    # the pool under a table, after its head has moved: insert_alloc pops the back, erase_release
+    # pushes it, both through the ring
+    if pcap >= 1000:
+        p = Pair(dev, pcap, 32, pool=pcap)
+        out, st = p.gp.pop_front(pcap // 3)
+        eo, es = p.op.pop_front(pcap // 3)
+        np.testing.assert_array_equal(out.cpu().numpy(), eo)
+        keys = distinct_u64(rng, pcap // 2)
+        p.insert_alloc(keys)
+        p.erase_release(keys[::2])
+        st = p.gp.push(out[: pcap // 6].contiguous())     # FIFO reuse: released at the back
+        np.testing.assert_array_equal(st.cpu().numpy(), p.op.push(eo[: pcap // 6]))
+        p.insert_alloc(distinct_u64(rng, pcap // 2, exclude=keys))
+        p.same_state()
+        assert p.gp.size() == p.op.size()
+        np.testing.assert_array_equal(p.gp.dump().cpu().numpy(), p.op.dump())
+
+
 @pytest.mark.parametrize("chunk", [1 << 16, 1 << 18])
 def test_skewed_batches_fold_repeats_per_tile(dev, chunk):
     """Zipf(1.1) batches repeat their hottest keys thousands of times per chunk and overflow the
