@@ -74,6 +74,7 @@ def lib():
             "or_pool_pop": (None, [P, I64, P, P]),
             "or_pool_push": (None, [P, P, I64, P]),
             "or_pool_pop_front": (None, [P, I64, P, P]),
+            "or_select": (I64, [P, C.c_int, C.c_uint64, C.c_uint64, P, P, P, P, I64]),
             "or_pool_push_front": (None, [P, P, I64, P]),
             "or_insert_alloc": (None, [P, P, P, I64, P, P]),
             "or_erase_release": (None, [P, P, P, I64, P]),
@@ -284,6 +285,26 @@ class OracleTable:
         ks = np.empty(n, dtype=np.uint64)
         vs = np.empty(n, dtype=np.uint64)
         lib().or_dump(self._h, _ptr(ks), _ptr(vs), n)
+        if self.value_bits == 32:
+            vs = vs.astype(np.uint32)
+        return ks, vs
+
+    def select_key_range(self, lo: int, hi: int):
+        """Live (keys, values) with lo <= key < hi, sorted by key (range selection, Section 3.6)."""
+        return self._select(0, lo, hi, (0, 0, 0), (0, 0, 0))
+
+    def select_voxel_box(self, lo3, hi3):
+        """Live (keys, values) whose packed block coordinates lie in the box [lo3, hi3] (bounds
+        included), sorted by key."""
+        return self._select(1, 0, 0, lo3, hi3)
+
+    def _select(self, kind, lo, hi, lo3, hi3):
+        l3 = np.ascontiguousarray(lo3, dtype=np.int32)
+        h3 = np.ascontiguousarray(hi3, dtype=np.int32)
+        n = int(lib().or_select(self._h, kind, int(lo), int(hi), _ptr(l3), _ptr(h3), None, None, 0))
+        ks = np.empty(n, dtype=np.uint64)
+        vs = np.empty(n, dtype=np.uint64)
+        lib().or_select(self._h, kind, int(lo), int(hi), _ptr(l3), _ptr(h3), _ptr(ks), _ptr(vs), n)
         if self.value_bits == 32:
             vs = vs.astype(np.uint32)
         return ks, vs

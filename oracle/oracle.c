@@ -383,6 +383,50 @@ int64_t or_dump(const or_table *t, uint64_t *keys_out, uint64_t *vals_out, int64
 }
 
 /*
+ * Range selection (Section 3.6: a range of the container turned into a vector with a copy_if):
+ * the live pairs whose key a predicate accepts, sorted by key.  Returns the number selected;
+ * at most `cap` pairs are written.
+ *   kind 0 (key range) : lo <= key < hi, unsigned.
+ *   kind 1 (voxel box) : the key packs three signed 21-bit block coordinates (x bits 0-20, y 21-41,
+ *                        z 42-62, bit 63 clear) and each lies in [lo3[d], hi3[d]], bounds included.
+ *                        A key with bit 63 set packs no block and is never selected.
+ */
+static int64_t sign21(uint64_t f) { return (f & 0x100000u) ? (int64_t)f - 0x200000 : (int64_t)f; }
+
+static int select_accepts(int kind, uint64_t key, uint64_t lo, uint64_t hi, const int32_t *lo3,
+                          const int32_t *hi3)
+{
+    if (kind == 0) return key >= lo && key < hi;
+    if (key >> 63) return 0;
+    for (int d = 0; d < 3; ++d) {
+        int64_t c = sign21((key >> (21 * d)) & 0x1FFFFFu);
+        if (c < lo3[d] || c > hi3[d]) return 0;
+    }
+    return 1;
+}
+
+int64_t or_select(const or_table *t, int kind, uint64_t lo, uint64_t hi, const int32_t *lo3,
+                  const int32_t *hi3, uint64_t *keys_out, uint64_t *vals_out, int64_t cap)
+{
+    uint64_t *pairs = (uint64_t *)malloc(sizeof(uint64_t) * 2 * (size_t)(t->size > 0 ? t->size : 1));
+    int64_t m = 0;
+    for (int64_t b = 0; b < t->nbuckets; ++b)
+        for (int64_t e = t->head[b]; e >= 0; e = t->next[e]) {
+            if (!select_accepts(kind, t->key[e], lo, hi, lo3, hi3)) continue;
+            pairs[2 * m] = t->key[e];
+            pairs[2 * m + 1] = t->val[e];
+            ++m;
+        }
+    qsort(pairs, (size_t)m, 2 * sizeof(uint64_t), cmp_pair);
+    for (int64_t j = 0; j < m && j < cap; ++j) {
+        if (keys_out) keys_out[j] = pairs[2 * j];
+        if (vals_out) vals_out[j] = pairs[2 * j + 1];
+    }
+    free(pairs);
+    return m;
+}
+
+/*
  * Count invariant violations; `what` (nullable) receives a bit per failed invariant:
  *   1  size equals the number of entries reachable from the buckets, and size <= capacity
  *   2  no key occurs twice

@@ -150,6 +150,53 @@ def test_pool_deque_matches_collections_deque(pcap, ops):
         assert p.dump().tolist() == list(d)
 
 
+@settings(max_examples=150, deadline=None, suppress_health_check=[HealthCheck.too_slow])
+@given(ops=st.lists(st.tuples(st.sampled_from(["insert", "erase"]),
+                              st.lists(st.sampled_from(UNIVERSE), min_size=0, max_size=12)),
+                    max_size=6),
+       lo=st.sampled_from(UNIVERSE), hi=st.sampled_from(UNIVERSE + [U64MAX]))
+def test_key_range_selection_matches_bruteforce(ops, lo, hi):
+    """Range selection (Section 3.6) by key interval: the brute-force table's pairs filtered by
+    lo <= key < hi and sorted, after generated insert/erase batches."""
+    t = OracleTable(8, 64, HASH_MIX64, 3)
+    b = BruteTable(8, 64)
+    for kind, keys in ops:
+        ks = np.array(keys, dtype=np.uint64)
+        if kind == "insert":
+            t.insert(ks, ks + np.uint64(1))
+            b.insert([int(k) for k in keys], [int(k) + 1 & U64MAX for k in keys])
+        else:
+            t.erase(ks)
+            b.erase([int(k) for k in keys])
+    got_k, got_v = t.select_key_range(lo, hi)
+    want = sorted((k, v) for k, v in b.pairs if lo <= k < hi)
+    assert list(zip(got_k.tolist(), got_v.tolist())) == want
+
+
+def test_voxel_box_selection_closed_form():
+    """Selection by block box on packed coordinates: the blocks of a 9 x 9 x 9 grid around the
+    origin (negative coordinates included) and four far blocks; a box selects exactly the grid
+    points inside it, counted from the coordinates themselves, and keys with bit 63 set (which
+    pack no block) never match."""
+    g = np.arange(-4, 5)
+    X, Y, Z = np.meshgrid(g, g, g, indexing="ij")
+    far = np.array([[1048575, 0, 0], [-1048576, 3, 3], [0, 0, 2000], [5, -5, -700]])
+    cx = np.concatenate([X.ravel(), far[:, 0]])
+    cy = np.concatenate([Y.ravel(), far[:, 1]])
+    cz = np.concatenate([Z.ravel(), far[:, 2]])
+    keys = pack_int3(cx, cy, cz)
+    t = OracleTable(2000, 64, HASH_VOXEL21, 1 << 21)
+    t.insert(keys, np.arange(keys.size, dtype=np.uint64))
+    t.insert(np.array([U64MAX, 1 << 63], dtype=np.uint64), np.array([7, 8], dtype=np.uint64))
+    for lo3, hi3 in [((-1, -2, 0), (2, 1, 4)), ((-4, -4, -4), (4, 4, 4)), ((3, 3, 3), (2, 9, 9)),
+                     ((0, 0, 0), (0, 0, 0)), ((-1048576, -1048576, -1048576), (1048575, 1048575, 1048575))]:
+        inside = ((cx >= lo3[0]) & (cx <= hi3[0]) & (cy >= lo3[1]) & (cy <= hi3[1]) &
+                  (cz >= lo3[2]) & (cz <= hi3[2]))
+        k, v = t.select_voxel_box(lo3, hi3)
+        assert k.tolist() == sorted(keys[inside].tolist())
+        assert v.tolist() == [int(np.flatnonzero(keys == x)[0]) for x in k]
+
+
 def test_fifo_free_list_closed_form():
     """pop_front of a fresh pool of capacity c returns c-1, c-2, ...; used as a first-in
     first-out free list (pop_front, push_back) released values come back after every older one."""
