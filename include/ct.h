@@ -156,6 +156,21 @@ ct_status ct_clear(ct_table *t, void *stream);
 ct_status ct_dump(ct_table *t, uint64_t *keys_out, uint64_t *vals_out, int64_t cap,
                   int64_t *h_count, void *stream);
 
+/* Range selection (Section 3.6: a range of the container turned into a vector with a copy_if):
+   copy the live (key, value) pairs whose key the predicate accepts into keys_out / vals_out
+   (device, `cap` entries; vals_out nullable, ignored for sets; values as u64), in unspecified
+   order, and return the number selected in *h_count (only `cap` pairs are written).
+   Synchronises.
+   ct_select_key_range: lo <= key < hi, unsigned.
+   ct_select_voxel_box: the key packs signed 21-bit block coordinates (x bits 0-20, y 21-41,
+   z 42-62, bit 63 clear) and each lies in [h_lo3[d], h_hi3[d]] (host arrays of 3, bounds
+   included); a key with bit 63 set packs no block and is never selected. */
+ct_status ct_select_key_range(ct_table *t, uint64_t lo, uint64_t hi, uint64_t *keys_out,
+                              uint64_t *vals_out, int64_t cap, int64_t *h_count, void *stream);
+ct_status ct_select_voxel_box(ct_table *t, const int32_t *h_lo3, const int32_t *h_hi3,
+                              uint64_t *keys_out, uint64_t *vals_out, int64_t cap,
+                              int64_t *h_count, void *stream);
+
 /* Check the layout invariants on the device: every live key is reachable from its home bucket,
    the live count equals the size counter.  *h_violations = number of failures.  Synchronises. */
 ct_status ct_check_invariants(ct_table *t, int64_t *h_violations, void *stream);

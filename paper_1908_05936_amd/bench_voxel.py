@@ -58,6 +58,24 @@ def run(repeats: int = 3, seed: int = 2, log=print) -> dict:
                 n_find += q.numel()
                 n_ins += miss.numel()
     size = t.size()
+    # range selection (select_blocks-style copy_if): the blocks in the octant x, y, z >= 0 of the
+    # final table; the kernel streams every bucket once
+    import ctypes as C
+    sk = torch.empty(size, dtype=torch.int64, device=dev)
+    sv = torch.empty(size, dtype=torch.int64, device=dev)
+    lo = (C.c_int32 * 3)(0, 0, 0)
+    hi = (C.c_int32 * 3)(2047, 2047, 2047)
+    cnt = C.c_int64(0)
+    sel = []
+    for _ in range(5):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        ct._check(ct.lib().ct_select_voxel_box(t._h, lo, hi, ct._ptr(sk), ct._ptr(sv), size,
+                                               C.byref(cnt), ct._stream(dev)), "select")
+        e1.record()
+        torch.cuda.synchronize()
+        sel.append(e0.elapsed_time(e1) * 1e-3)
+    sel_s = float(np.median(sel))
     out = {
         "workload": (f"voxel blocks: {w['residents'].size} residents, 2^21 buckets, spatial hash, "
                      f"{len(frames)} frames of find 2^18 (90% hits) + insert_alloc of the misses"),
@@ -67,7 +85,13 @@ def run(repeats: int = 3, seed: int = 2, log=print) -> dict:
         "find_Mkeys_s": n_find / find_s / 1e6,
         "insert_alloc_Mkeys_s": n_ins / ins_s / 1e6,
         "final_size": size,
+        "select_box": {"selected": int(cnt.value), "ms": sel_s * 1e3,
+                       "table_GB_s": nb * 128 / sel_s / 1e9,
+                       "note": "octant x, y, z >= 0 of the final table; the call's time, its "
+                               "count read-back included"},
     }
+    log(f"[voxel] select box: {out['select_box']['selected']} blocks in "
+        f"{out['select_box']['ms']:.3f} ms ({out['select_box']['table_GB_s']:.0f} GB/s of table)")
     log(f"[voxel] p50 {out['frame_p50_ms']:.3f} ms p99 {out['frame_p99_ms']:.3f} ms, find "
         f"{out['find_Mkeys_s']:.0f} Mkeys/s, insert_alloc {out['insert_alloc_Mkeys_s']:.0f} Mkeys/s")
     return out

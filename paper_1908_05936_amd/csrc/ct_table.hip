@@ -840,8 +840,26 @@ __device__ __forceinline__ int64_t insert_range(const TableView& t, const uint64
                         &mystep);
       const uint32_t want = fast ? (A & ~found & freeb) : 0u;
       if (want) {
-        const uint64_t pos = claim_group(t, key, want, sub, myfb, myc, myexp, mystep);
-        if ((want >> sub) & 1) mypos = pos;
+        // every lane claims for its own key: one CAS instruction for the whole group
+        int won = 0;
+        if ((want >> sub) & 1) {
+          uint64_t expected = myexp;
+          won = cas64(&t.bk[myfb].s[myc].key, expected, key) ? 1 : 0;
+        }
+        if (won) mypos = myfb * kSlots + (uint64_t)myc;
+        const uint32_t retry = want & ~group_bits(__ballot(won));
+        if (retry) {  // lost a race for the slot to another key: scan on, one key at a time
+          const int gb = group_base();
+#pragma unroll
+          for (int u = 0; u < kSlots; ++u) {
+            if (!((retry >> u) & 1)) continue;
+            const uint64_t ku = __shfl(key, gb + u, 64);
+            const uint64_t fbu = __shfl(myfb, gb + u, 64);
+            const uint64_t stu = __shfl(mystep, gb + u, 64);
+            const uint64_t pos = claim(t, ku, fbu, stu, sub);
+            if (sub == u) mypos = pos;
+          }
+        }
       }
       if ((A >> sub) & 1) {
         if ((found >> sub) & 1) {
@@ -1264,37 +1282,136 @@ __global__ __launch_bounds__(kBlock) void k_find(TableView t, const uint64_t* __
                  (int64_t)gridDim.x * kBlock);
 }
 
-__global__ void k_dump_begin(TableView t) { t.hdr->dump_count = 0; }
-
-__global__ __launch_bounds__(kBlock) void k_dump(TableView t, uint64_t* __restrict__ kout,
-                                                 uint64_t* __restrict__ vout, int64_t cap) {
-  const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t nt = (int64_t)gridDim.x * blockDim.x;
-  const int64_t nslots = (int64_t)t.nb * kSlots;
-  // trip count equal for all lanes of a wave so the wave-wide append stays converged
-  const int64_t span = ((nslots + nt - 1) / nt) * nt;
-  uint32_t* cnt32 = reinterpret_cast<uint32_t*>(&t.hdr->dump_count);
-  for (int64_t j = tid; j < span; j += nt) {
-    Slot s;
-    bool live = false;
-    if (j < nslots) {
-      s = t.bk[j >> 3].s[j & 7];
-      live = s.key != kEmpty && s.key != kTomb;
+// Range selection (Section 3.6: a range of the container becomes a vector through a copy_if),
+// and the dump, which selects every live pair.  Appending through one shared counter serialises
+// (every append is an atomic on the same address), so block b owns a contiguous slot range:
+// k_sel_count writes its count to bcnt[b], k_sel_scan turns the counts into offsets (and the
+// total, out-of-band keys included, into dump_count), and k_sel_write reads the range again and
+// writes each accepted pair at its block's offset plus its rank in the block.  The out-of-band
+// keys go last.  Predicates see the key only.
+struct AllKeys {
+  __device__ bool operator()(uint64_t) const { return true; }
+};
+struct KeyRange {
+  uint64_t lo, hi;  // lo <= key < hi, unsigned
+  __device__ bool operator()(uint64_t key) const { return key >= lo && key < hi; }
+};
+struct VoxelBox {
+  int32_t lo[3], hi[3];  // packed block coordinates in [lo, hi], bounds included
+  __device__ bool operator()(uint64_t key) const {
+    if (key >> 63) return false;  // packs no block
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      const uint32_t f = (uint32_t)(key >> (21 * d)) & 0x1FFFFFu;
+      const int32_t c = (int32_t)(f << 11) >> 11;  // sign-extend the 21-bit field
+      if (c < lo[d] || c > hi[d]) return false;
     }
-    const uint32_t p = wave_append(live, cnt32);
-    if (live && (int64_t)p < cap) {
-      kout[p] = s.key;
-      if (vout) vout[p] = s.val;
-    }
+    return true;
   }
-  if (tid == 0) {
-    for (int s = 0; s < 2; ++s) {
-      if (!t.hdr->spec_live[s]) continue;
-      const uint32_t p = aadd32(cnt32, 1u);
-      if ((int64_t)p < cap) {
-        kout[p] = kTomb + (uint64_t)s;
-        if (vout) vout[p] = t.hdr->spec_val[s];
+};
+
+constexpr int kSelPer = 8;                       // slots per thread and round
+constexpr int64_t kSelRound = (int64_t)kBlock * kSelPer;
+
+template <class Pred>
+__device__ __forceinline__ uint32_t sel_round(const TableView& t, const Pred& pred, int64_t r0,
+                                              int64_t hi, Slot (&sl)[kSelPer]) {
+  uint32_t take = 0;
+#pragma unroll
+  for (int e = 0; e < kSelPer; ++e) {   // loads first (clamped), then the tests
+    const int64_t j = min(r0 + e * kBlock + (int64_t)threadIdx.x, hi - 1);
+    sl[e] = t.bk[j >> 3].s[j & 7];
+  }
+#pragma unroll
+  for (int e = 0; e < kSelPer; ++e) {
+    const int64_t j = r0 + e * kBlock + (int64_t)threadIdx.x;
+    if (j < hi && sl[e].key != kEmpty && sl[e].key != kTomb && pred(sl[e].key)) take |= 1u << e;
+  }
+  return take;
+}
+
+template <class Pred>
+__global__ __launch_bounds__(kBlock) void k_sel_count(TableView t, Pred pred, int64_t per) {
+  const int64_t nslots = (int64_t)t.nb * kSlots;
+  const int64_t lo = (int64_t)blockIdx.x * per;
+  const int64_t hi = min(lo + per, nslots);
+  int64_t c = 0;
+  Slot sl[kSelPer];
+  for (int64_t r0 = lo; r0 < hi; r0 += kSelRound) c += __builtin_popcount(sel_round(t, pred, r0, hi, sl));
+  const int64_t tot = block_sum(c);
+  if (threadIdx.x == 0) t.bcnt[blockIdx.x] = tot;
+}
+
+template <class Pred>
+__global__ __launch_bounds__(1024) void k_sel_scan(TableView t, Pred pred, int nblocks) {
+  __shared__ int64_t wsum[16];
+  const int per = (nblocks + 1023) / 1024;
+  const int b0 = (int)threadIdx.x * per;
+  int64_t loc = 0;
+  for (int j = 0; j < per; ++j)
+    if (b0 + j < nblocks) loc += t.bcnt[b0 + j];
+  const int lane = wave_lane();
+  int64_t x = loc;
+  for (int off = 1; off < 64; off <<= 1) {
+    const int64_t y = __shfl_up(x, off, 64);
+    if (lane >= off) x += y;
+  }
+  if (lane == 63) wsum[threadIdx.x >> 6] = x;
+  __syncthreads();
+  int64_t before = 0, total = 0;
+  for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
+    if (w < (int)(threadIdx.x >> 6)) before += wsum[w];
+    total += wsum[w];
+  }
+  int64_t run = before + x - loc;
+  for (int j = 0; j < per; ++j) {
+    if (b0 + j >= nblocks) break;
+    const int64_t c = t.bcnt[b0 + j];
+    t.bcnt[b0 + j] = run;
+    run += c;
+  }
+  if (threadIdx.x == 0) {
+    for (int sp = 0; sp < 2; ++sp)
+      if (t.hdr->spec_live[sp] && pred(kTomb + (uint64_t)sp)) ++total;
+    t.hdr->dump_count = (uint64_t)total;
+  }
+}
+
+template <class Pred>
+__global__ __launch_bounds__(kBlock) void k_sel_write(TableView t, Pred pred, int64_t per,
+                                                      uint64_t* __restrict__ kout,
+                                                      uint64_t* __restrict__ vout, int64_t cap) {
+  const int64_t nslots = (int64_t)t.nb * kSlots;
+  const int64_t lo = (int64_t)blockIdx.x * per;
+  const int64_t hi = min(lo + per, nslots);
+  int64_t off = t.bcnt[blockIdx.x];
+  Slot sl[kSelPer];
+  for (int64_t r0 = lo; r0 < hi; r0 += kSelRound) {
+    const uint32_t take = sel_round(t, pred, r0, hi, sl);
+    uint32_t total;
+    uint32_t p = block_exclusive_scan((uint32_t)__builtin_popcount(take), &total);
+#pragma unroll
+    for (int e = 0; e < kSelPer; ++e) {
+      if (!((take >> e) & 1u)) continue;
+      const int64_t at = off + p++;
+      if (at < cap) {
+        kout[at] = sl[e].key;
+        if (vout) vout[at] = sl[e].val;
       }
+    }
+    off += total;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {  // the out-of-band keys, after every bucket's
+    int64_t at = (int64_t)t.hdr->dump_count;
+    for (int sp = 0; sp < 2; ++sp)
+      if (t.hdr->spec_live[sp] && pred(kTomb + (uint64_t)sp)) --at;
+    for (int sp = 0; sp < 2; ++sp) {
+      if (!t.hdr->spec_live[sp] || !pred(kTomb + (uint64_t)sp)) continue;
+      if (at < cap) {
+        kout[at] = kTomb + (uint64_t)sp;
+        if (vout) vout[at] = t.hdr->spec_val[sp];
+      }
+      ++at;
     }
   }
 }
@@ -1931,6 +2048,30 @@ ct_status check_batch(const ct_table* t, const void* keys, int64_t n) {
 
 }  // namespace
 
+namespace {
+template <class Pred>
+ct_status select_into(ct_table* t, const Pred& pred, uint64_t* keys_out, uint64_t* vals_out,
+                      int64_t cap, int64_t* h_count, void* stream) {
+  if (!t || !h_count || cap < 0 || (cap > 0 && !keys_out)) return CT_E_INVALID;
+  if (t->desc.val_kind == CT_VAL_NONE) vals_out = nullptr;
+  hipStream_t s = S(stream);
+  const int64_t nslots = (int64_t)t->v.nb * kSlots;
+  const int64_t rounds = (nslots + kSelRound - 1) / kSelRound;
+  const int64_t g0 = std::max<int64_t>(1, std::min<int64_t>(rounds, kMaxGroupBlocks));
+  const int64_t per = ((rounds + g0 - 1) / g0) * kSelRound;   // whole rounds per block
+  const int grid = (int)((nslots + per - 1) / per);
+  k_sel_count<Pred><<<grid, kBlock, 0, s>>>(t->v, pred, per);
+  k_sel_scan<Pred><<<1, 1024, 0, s>>>(t->v, pred, grid);
+  k_sel_write<Pred><<<grid, kBlock, 0, s>>>(t->v, pred, per, keys_out, vals_out, cap);
+  if (launched() != CT_OK) return CT_E_HIP;
+  uint64_t c = 0;
+  ct_status r = read_back(&t->v.hdr->dump_count, &c, s);
+  if (r != CT_OK) return r;
+  *h_count = (int64_t)c;
+  return CT_OK;
+}
+}  // namespace
+
 extern "C" {
 
 const char* ct_status_str(ct_status s) {
@@ -2128,16 +2269,24 @@ ct_status ct_table_rehash(ct_table* src, ct_table* dst, void* stream) {
 
 ct_status ct_dump(ct_table* t, uint64_t* keys_out, uint64_t* vals_out, int64_t cap,
                   int64_t* h_count, void* stream) {
-  if (!t || !h_count || cap < 0 || (cap > 0 && !keys_out)) return CT_E_INVALID;
-  if (t->desc.val_kind == CT_VAL_NONE) vals_out = nullptr;
-  k_dump_begin<<<1, 1, 0, S(stream)>>>(t->v);
-  k_dump<<<flat_blocks((int64_t)t->v.nb * kSlots), kBlock, 0, S(stream)>>>(t->v, keys_out, vals_out, cap);
-  if (launched() != CT_OK) return CT_E_HIP;
-  uint64_t c = 0;
-  ct_status r = read_back(&t->v.hdr->dump_count, &c, S(stream));
-  if (r != CT_OK) return r;
-  *h_count = (int64_t)(c & 0xFFFFFFFFull);
-  return CT_OK;
+  return select_into(t, AllKeys{}, keys_out, vals_out, cap, h_count, stream);
+}
+
+ct_status ct_select_key_range(ct_table* t, uint64_t lo, uint64_t hi, uint64_t* keys_out,
+                              uint64_t* vals_out, int64_t cap, int64_t* h_count, void* stream) {
+  return select_into(t, KeyRange{lo, hi}, keys_out, vals_out, cap, h_count, stream);
+}
+
+ct_status ct_select_voxel_box(ct_table* t, const int32_t* h_lo3, const int32_t* h_hi3,
+                              uint64_t* keys_out, uint64_t* vals_out, int64_t cap, int64_t* h_count,
+                              void* stream) {
+  if (!h_lo3 || !h_hi3) return CT_E_INVALID;
+  VoxelBox box;
+  for (int d = 0; d < 3; ++d) {
+    box.lo[d] = h_lo3[d];
+    box.hi[d] = h_hi3[d];
+  }
+  return select_into(t, box, keys_out, vals_out, cap, h_count, stream);
 }
 
 ct_status ct_check_invariants(ct_table* t, int64_t* h_violations, void* stream) {

@@ -70,6 +70,9 @@ SIGNATURES = {
     "ct_get_error": (C.c_int, [_P, C.POINTER(C.c_uint32), _P]),
     "ct_table_dedup_skewed": (C.c_int, [_P, C.POINTER(C.c_int32), _P]),
     "ct_table_rehash": (C.c_int, [_P, _P, _P]),
+    "ct_select_key_range": (C.c_int, [_P, C.c_uint64, C.c_uint64, _P, _P, _I64, _PI64, _P]),
+    "ct_select_voxel_box": (C.c_int, [_P, C.POINTER(C.c_int32), C.POINTER(C.c_int32), _P, _P,
+                                      _I64, _PI64, _P]),
     "ct_pool_bytes": (C.c_int, [_I64, _PI64]),
     "ct_pool_init": (C.c_int, [_P, _I64, _I64, _P, C.POINTER(_P)]),
     "ct_pool_destroy": (C.c_int, [_P]),
@@ -329,6 +332,28 @@ class Table:
         _check(lib().ct_dump(self._h, _ptr(k), _ptr(v), n, C.byref(cnt), _stream(self.device)),
                "ct_dump")
         m = cnt.value
+        return k[:m], v[:m]
+
+    def select_key_range(self, lo: int, hi: int):
+        """Live (keys, values) with lo <= key < hi (unsigned), in unspecified order."""
+        return self._select(lambda k, v, cap, cnt: lib().ct_select_key_range(
+            self._h, int(lo) & (2**64 - 1), int(hi) & (2**64 - 1), k, v, cap, cnt,
+            _stream(self.device)), "ct_select_key_range")
+
+    def select_voxel_box(self, lo3, hi3):
+        """Live (keys, values) whose packed block coordinates lie in [lo3, hi3] (inclusive)."""
+        lo = (C.c_int32 * 3)(*[int(x) for x in lo3])
+        hi = (C.c_int32 * 3)(*[int(x) for x in hi3])
+        return self._select(lambda k, v, cap, cnt: lib().ct_select_voxel_box(
+            self._h, lo, hi, k, v, cap, cnt, _stream(self.device)), "ct_select_voxel_box")
+
+    def _select(self, call, what):
+        cap = self.size()
+        k = torch.empty(max(cap, 1), dtype=torch.int64, device=self.device)
+        v = torch.empty(max(cap, 1), dtype=torch.int64, device=self.device)
+        cnt = C.c_int64(0)
+        _check(call(_ptr(k), _ptr(v), cap, C.byref(cnt)), what)
+        m = min(cnt.value, cap)
         return k[:m], v[:m]
 
     def rehash_into(self, dst: "Table"):

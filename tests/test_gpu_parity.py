@@ -10,7 +10,7 @@ import torch
 
 import oracle
 from paper_1908_05936_amd import ct
-from paper_1908_05936_amd.workloads import distinct_u64, plain_table, rng_for
+from paper_1908_05936_amd.workloads import distinct_u64, pack_int3, plain_table, rng_for
 
 pytestmark = pytest.mark.gpu
 
@@ -321,6 +321,52 @@ def test_pool_stack(dev):
     np.testing.assert_array_equal(st.cpu().numpy(), es)
     assert gp.size() == op.size() == 0
     assert gp.error() & ct.ERR_POOL
+
+
+def _sorted_pairs(k, v, bits):
+    k = npu(k)
+    v = npu(v) if bits == 64 else npu(v).astype(np.uint32)
+    o = np.argsort(k, kind="stable")
+    return k[o], v[o]
+
+
+def test_range_selection(dev):
+    """Range selection (Section 3.6): live pairs by key interval on a mix64 map and by block box
+    on a voxel21 map, in unspecified order, compared as sorted sets with the oracle's selection;
+    the out-of-band keys take part, and a short output buffer gets the full count and a subset."""
+    rng = rng_for(47)
+    p = Pair(dev, 200_000, 64)
+    keys = distinct_u64(rng, 150_000)
+    keys[:5] = RESERVED
+    p.insert(keys, rng.integers(0, 1 << 62, size=keys.size, dtype=np.uint64))
+    p.erase(keys[::4])
+    q = np.sort(keys)
+    for lo, hi in [(0, U64MAX), (int(q[1000]), int(q[90_000])), (int(q[5]), int(q[5]) + 1),
+                   (U64MAX - 2, U64MAX), (0, 1), (1 << 63, U64MAX), (7, 7)]:
+        gk, gv = p.g.select_key_range(lo, hi)
+        ek, ev = p.o.select_key_range(lo, hi)
+        k, v = _sorted_pairs(gk, gv, 64)
+        np.testing.assert_array_equal(k, ek)
+        np.testing.assert_array_equal(v, ev)
+    L = ct.lib()
+    kout = torch.empty(100, dtype=torch.int64, device=dev)
+    cnt = ct.C.c_int64(0)
+    ct._check(L.ct_select_key_range(p.g._h, 0, U64MAX, ct._ptr(kout), None, 100, ct.C.byref(cnt),
+                                    ct._stream(dev)), "select")
+    assert cnt.value == p.o.size() - (1 if p.o.find(np.array([U64MAX], np.uint64))[1][0] else 0)
+    assert set(npu(kout).tolist()) <= set(keys.tolist())
+    vox = Pair(dev, 300_000, 32, hash_kind=ct.HASH_VOXEL21, bucket_count=1 << 16)
+    c = rng.integers(-300, 300, size=(250_000, 3))
+    vk = np.unique(pack_int3(c[:, 0], c[:, 1], c[:, 2]))
+    vox.insert(vk, np.arange(vk.size, dtype=np.uint32))
+    vox.insert(np.array([U64MAX, 1 << 63], dtype=np.uint64), np.array([1, 2], dtype=np.uint32))
+    for lo3, hi3 in [((-50, -60, -70), (40, 30, 20)), ((-300, -300, -300), (300, 300, 300)),
+                     ((0, 0, 0), (0, 0, 0)), ((10, 10, 10), (5, 50, 50)), ((-1, -1, -1), (-1, -1, -1))]:
+        gk, gv = vox.g.select_voxel_box(lo3, hi3)
+        ek, ev = vox.o.select_voxel_box(lo3, hi3)
+        k, v = _sorted_pairs(gk, gv, 32)
+        np.testing.assert_array_equal(k, ek)
+        np.testing.assert_array_equal(v, ev)
 
 
 @pytest.mark.parametrize("pcap", [1, 1000, 70_001])
