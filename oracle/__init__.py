@@ -75,6 +75,7 @@ def lib():
             "or_pool_push": (None, [P, P, I64, P]),
             "or_pool_pop_front": (None, [P, I64, P, P]),
             "or_select": (I64, [P, C.c_int, C.c_uint64, C.c_uint64, P, P, P, P, I64]),
+            "or_voxel_neighbour_keys": (I64, [P, I64, C.c_int, P]),
             "or_pool_push_front": (None, [P, P, I64, P]),
             "or_insert_alloc": (None, [P, P, P, I64, P, P]),
             "or_erase_release": (None, [P, P, P, I64, P]),
@@ -197,6 +198,17 @@ class OraclePool:
         st = np.empty(v.size, dtype=np.uint8)
         lib().or_pool_push_front(self._h, _ptr(v), v.size, _ptr(st))
         return st
+
+
+def voxel_neighbour_keys(blocks, ndirs: int = 6) -> np.ndarray:
+    """The 6 face (or all 26) neighbour keys of each packed voxel block, block by block in a fixed
+    direction order; coordinates wrap in their 21-bit fields."""
+    b = _u64(blocks)
+    out = np.empty(b.size * ndirs, dtype=np.uint64)
+    m = int(lib().or_voxel_neighbour_keys(_ptr(b), b.size, int(ndirs), _ptr(out)))
+    if m < 0:
+        raise ValueError("ndirs must be 6 or 26")
+    return out
 
 
 class OracleTable:

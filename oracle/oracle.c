@@ -383,6 +383,36 @@ int64_t or_dump(const or_table *t, uint64_t *keys_out, uint64_t *vals_out, int64
 }
 
 /*
+ * Neighbour keys of voxel blocks (the allocation step of the reconstruction workload behind the
+ * voxel-block example of Section 4.1): for block i, in direction order d = 0 .. 26 (offsets
+ * dx = d mod 3 - 1, dy = (d / 3) mod 3 - 1, dz = d / 9 - 1, the zero offset skipped, and with
+ * ndirs 6 only the offsets along one axis), out[i * ndirs + j] is the j-th neighbour's key.  Each
+ * coordinate is the block's signed 21-bit field plus the offset, taken modulo 2^21 when packed.
+ * Returns the number of keys written (n * ndirs), or -1 for an ndirs other than 6 or 26.
+ */
+static int64_t sign21(uint64_t f) { return (f & 0x100000u) ? (int64_t)f - 0x200000 : (int64_t)f; }
+
+int64_t or_voxel_neighbour_keys(const uint64_t *blocks, int64_t n, int ndirs, uint64_t *out)
+{
+    if (ndirs != 6 && ndirs != 26) return -1;
+    int64_t m = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        int64_t c[3];
+        for (int a = 0; a < 3; ++a) c[a] = sign21((blocks[i] >> (21 * a)) & 0x1FFFFFu);
+        for (int d = 0; d < 27; ++d) {
+            int64_t o[3] = {d % 3 - 1, (d / 3) % 3 - 1, d / 9 - 1};
+            int nz = (o[0] != 0) + (o[1] != 0) + (o[2] != 0);
+            if (nz == 0 || (ndirs == 6 && nz != 1)) continue;
+            uint64_t k = 0;
+            for (int a = 0; a < 3; ++a)
+                k |= ((uint64_t)(c[a] + o[a]) & 0x1FFFFFu) << (21 * a);
+            out[m++] = k;
+        }
+    }
+    return m;
+}
+
+/*
  * Range selection (Section 3.6: a range of the container turned into a vector with a copy_if):
  * the live pairs whose key a predicate accepts, sorted by key.  Returns the number selected;
  * at most `cap` pairs are written.
@@ -391,7 +421,6 @@ int64_t or_dump(const or_table *t, uint64_t *keys_out, uint64_t *vals_out, int64
  *                        z 42-62, bit 63 clear) and each lies in [lo3[d], hi3[d]], bounds included.
  *                        A key with bit 63 set packs no block and is never selected.
  */
-static int64_t sign21(uint64_t f) { return (f & 0x100000u) ? (int64_t)f - 0x200000 : (int64_t)f; }
 
 static int select_accepts(int kind, uint64_t key, uint64_t lo, uint64_t hi, const int32_t *lo3,
                           const int32_t *hi3)

@@ -197,6 +197,29 @@ def test_voxel_box_selection_closed_form():
         assert v.tolist() == [int(np.flatnonzero(keys == x)[0]) for x in k]
 
 
+def test_voxel_neighbour_keys_closed_form():
+    """Neighbours of packed blocks: the origin's 6 face neighbours are the unit offsets along each
+    axis; 26 neighbours are every offset in {-1, 0, 1}^3 but zero, each once; a block at the edge
+    of the 21-bit range wraps to the other end (packing takes each coordinate modulo 2^21)."""
+    six = oracle.voxel_neighbour_keys(pack_int3([0], [0], [0]), 6)
+    want = pack_int3([-1, 1, 0, 0, 0, 0], [0, 0, -1, 1, 0, 0], [0, 0, 0, 0, -1, 1])
+    assert sorted(six.tolist()) == sorted(want.tolist())
+    blk = pack_int3([5], [-7], [1048575])
+    all26 = oracle.voxel_neighbour_keys(blk, 26)
+    offs = [(dx, dy, dz) for dx in (-1, 0, 1) for dy in (-1, 0, 1) for dz in (-1, 0, 1)
+            if (dx, dy, dz) != (0, 0, 0)]
+    exp = pack_int3([5 + o[0] for o in offs], [-7 + o[1] for o in offs],
+                    [1048575 + o[2] for o in offs])
+    assert sorted(all26.tolist()) == sorted(exp.tolist()) and len(set(all26.tolist())) == 26
+    # +1 on z = 2^20 - 1 wraps to -2^20
+    assert int(pack_int3([5], [-7], [-1048576])[0]) in all26.tolist()
+    two = oracle.voxel_neighbour_keys(pack_int3([0, 10], [0, 10], [0, 10]), 6)
+    assert two.size == 12 and two[6:].tolist() == oracle.voxel_neighbour_keys(
+        pack_int3([10], [10], [10]), 6).tolist()
+    with pytest.raises(ValueError):
+        oracle.voxel_neighbour_keys(blk, 7)
+
+
 def test_fifo_free_list_closed_form():
     """pop_front of a fresh pool of capacity c returns c-1, c-2, ...; used as a first-in
     first-out free list (pop_front, push_back) released values come back after every older one."""
