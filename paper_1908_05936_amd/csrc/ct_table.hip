@@ -22,11 +22,13 @@
 #include <algorithm>
 #include <cstdint>
 #include <cstdlib>
+#include <cstring>
 #include <new>
 #include <vector>
 
 #include "ct.h"
 #include "ct_device.h"
+#include "ct_dev_api.h"
 
 using namespace ct;
 
@@ -1416,6 +1418,58 @@ __global__ __launch_bounds__(kBlock) void k_sel_write(TableView t, Pred pred, in
   }
 }
 
+// Per-thread operations through the device-side API (ct_dev_api.h): element i is handled by one
+// thread, all concurrently and in no particular order.  The reference user kernel, and what the
+// tests drive the device API with.
+__global__ __launch_bounds__(kBlock) void k_dev_apply(DevView v, int32_t op, const uint64_t* __restrict__ keys,
+                                                      const void* __restrict__ vals, int32_t vk,
+                                                      int64_t n, void* __restrict__ vout,
+                                                      uint8_t* __restrict__ status) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const uint64_t key = keys[i];
+    if (op == CT_OP_INSERT) {
+      const uint64_t val = vk == 2 ? static_cast<const uint64_t*>(vals)[i]
+                           : vk == 1 ? (uint64_t)static_cast<const uint32_t*>(vals)[i] : 0ull;
+      const uint8_t st = dev_insert(v, key, val);
+      if (status) status[i] = st;
+    } else if (op == CT_OP_ERASE) {
+      const bool hit = dev_erase(v, key);
+      if (status) status[i] = hit ? 1 : 0;
+    } else {
+      uint64_t val = 0;
+      const bool hit = dev_find(v, key, &val);
+      if (status) status[i] = hit ? 1 : 0;
+      if (vout) {
+        if (vk == 2) static_cast<uint64_t*>(vout)[i] = hit ? val : ~0ull;
+        else if (vk == 1) static_cast<uint32_t*>(vout)[i] = hit ? (uint32_t)val : ~0u;
+      }
+    }
+  }
+}
+
+// The neighbour update of a block map (the allocation step of the reconstruction workload behind
+// Section 4.1's voxel-block example): every block of `blocks` makes sure that its 6 face
+// neighbours (ndirs 6) or all 26 neighbours (ndirs 26) are in the table, each new one with the
+// index of a block that asked for it as its value.  Coordinates wrap in their 21-bit fields.
+__global__ __launch_bounds__(kBlock) void k_voxel_neighbours(DevView v, const uint64_t* __restrict__ blocks,
+                                                             int64_t n, int32_t ndirs) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const uint64_t b = blocks[i];
+    const int32_t x = sfield21(b), y = sfield21(b >> 21), z = sfield21(b >> 42);
+    for (int d = 0; d < 27; ++d) {
+      const int dx = d % 3 - 1, dy = (d / 3) % 3 - 1, dz = d / 9 - 1;
+      const int nz = (dx != 0) + (dy != 0) + (dz != 0);
+      if (nz == 0 || (ndirs == 6 && nz != 1)) continue;
+      const uint64_t k = ((uint64_t)(uint32_t)(x + dx) & 0x1FFFFFull) |
+                         (((uint64_t)(uint32_t)(y + dy) & 0x1FFFFFull) << 21) |
+                         (((uint64_t)(uint32_t)(z + dz) & 0x1FFFFFull) << 42);
+      if (!dev_contains(v, k)) dev_insert(v, k, (uint64_t)(uint32_t)i);
+    }
+  }
+}
+
 __global__ void k_check_begin(TableView t) {
   t.hdr->live_count = 0;
   t.hdr->violations = 0;
@@ -2248,6 +2302,48 @@ ct_status ct_clear(ct_table* t, void* stream) {
   if (!t) return CT_E_INVALID;
   launch(t, CT_KERNEL_CLEAR, S(stream), [&] { k_table_reset<<<flat_blocks((int64_t)t->v.nb * kSlots), kBlock, 0, S(stream)>>>(t->v, 0); });
   t->size_ub = 0;
+  return launched();
+}
+
+ct_status ct_table_device_view(ct_table* t, int32_t mode, void* out, int64_t bytes) {
+  if (!t || !out || bytes < (int64_t)sizeof(DevView) || mode < kDevRead || mode > kDevErase)
+    return CT_E_INVALID;
+  DevView v{};
+  v.t = t->v;
+  v.mode = mode;
+  std::memcpy(out, &v, sizeof(v));
+  // device inserts grow the table behind the host's back
+  if (mode == kDevInsert) t->size_ub = (uint64_t)t->desc.capacity;
+  return CT_OK;
+}
+
+ct_status ct_dev_apply(ct_table* t, int32_t op, const uint64_t* keys, const void* vals, int64_t n,
+                       void* vals_out, uint8_t* status, void* stream) {
+  if (!t || n < 0 || (n > 0 && !keys)) return CT_E_INVALID;
+  if (op != CT_OP_INSERT && op != CT_OP_FIND && op != CT_OP_ERASE) return CT_E_INVALID;
+  const int32_t vk = t->desc.val_kind;
+  if (op == CT_OP_INSERT && vk != CT_VAL_NONE && n > 0 && !vals) return CT_E_INVALID;
+  if (n == 0) return CT_OK;
+  DevView v{};
+  v.t = t->v;
+  v.mode = op == CT_OP_INSERT ? kDevInsert : op == CT_OP_ERASE ? kDevErase : kDevRead;
+  if (op == CT_OP_INSERT)
+    t->size_ub = std::min<uint64_t>(t->size_ub + (uint64_t)n, (uint64_t)t->desc.capacity);
+  k_dev_apply<<<flat_blocks(n), kBlock, 0, S(stream)>>>(v, op, keys, vals, vk, n, vals_out, status);
+  return launched();
+}
+
+ct_status ct_voxel_insert_neighbours(ct_table* t, const uint64_t* blocks, int64_t n, int32_t ndirs,
+                                     void* stream) {
+  if (!t || n < 0 || (n > 0 && !blocks) || (ndirs != 6 && ndirs != 26)) return CT_E_INVALID;
+  if (t->desc.val_kind == CT_VAL_NONE) return CT_E_INVALID;
+  if (n == 0) return CT_OK;
+  DevView v{};
+  v.t = t->v;
+  v.mode = kDevInsert;
+  t->size_ub = std::min<uint64_t>(t->size_ub + (uint64_t)n * (uint64_t)ndirs,
+                                  (uint64_t)t->desc.capacity);
+  k_voxel_neighbours<<<flat_blocks(n), kBlock, 0, S(stream)>>>(v, blocks, n, ndirs);
   return launched();
 }
 

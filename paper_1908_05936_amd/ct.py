@@ -70,6 +70,9 @@ SIGNATURES = {
     "ct_get_error": (C.c_int, [_P, C.POINTER(C.c_uint32), _P]),
     "ct_table_dedup_skewed": (C.c_int, [_P, C.POINTER(C.c_int32), _P]),
     "ct_table_rehash": (C.c_int, [_P, _P, _P]),
+    "ct_table_device_view": (C.c_int, [_P, _I32, _P, _I64]),
+    "ct_dev_apply": (C.c_int, [_P, _I32, _P, _P, _I64, _P, _P, _P]),
+    "ct_voxel_insert_neighbours": (C.c_int, [_P, _P, _I64, _I32, _P]),
     "ct_select_key_range": (C.c_int, [_P, C.c_uint64, C.c_uint64, _P, _P, _I64, _PI64, _P]),
     "ct_select_voxel_box": (C.c_int, [_P, C.POINTER(C.c_int32), C.POINTER(C.c_int32), _P, _P,
                                       _I64, _PI64, _P]),
@@ -355,6 +358,31 @@ class Table:
         _check(call(_ptr(k), _ptr(v), cap, C.byref(cnt)), what)
         m = min(cnt.value, cap)
         return k[:m], v[:m]
+
+    def dev_apply(self, op: int, keys: torch.Tensor, vals: torch.Tensor | None = None):
+        """Per-thread operations through the device-side API, all elements concurrently and in
+        no particular order (OP_INSERT / OP_ERASE / OP_FIND).  Returns (status, values or None)."""
+        n = keys.numel()
+        _need(keys, torch.int64, None, "keys", self.device)
+        if op == OP_INSERT and self.value_kind != VAL_NONE:
+            if vals is None:
+                raise CtError("values are required for a map")
+            _need(vals, self.value_dtype, n, "vals", self.device)
+        st = torch.empty(n, dtype=torch.uint8, device=self.device)
+        out = None
+        if op == OP_FIND and self.value_kind != VAL_NONE:
+            out = torch.empty(n, dtype=self.value_dtype, device=self.device)
+        _check(lib().ct_dev_apply(self._h, int(op), _ptr(keys),
+                                  _ptr(vals) if op == OP_INSERT and self.value_kind else None, n,
+                                  _ptr(out), _ptr(st), _stream(self.device)), "ct_dev_apply")
+        return st, out
+
+    def insert_neighbours(self, blocks: torch.Tensor, ndirs: int = 6):
+        """Neighbour update of a voxel-block map through the device-side API."""
+        _need(blocks, torch.int64, None, "blocks", self.device)
+        _check(lib().ct_voxel_insert_neighbours(self._h, _ptr(blocks), blocks.numel(), int(ndirs),
+                                                _stream(self.device)),
+               "ct_voxel_insert_neighbours")
 
     def rehash_into(self, dst: "Table"):
         """Insert every live pair of this table into `dst` (same value kind, room for all of them;

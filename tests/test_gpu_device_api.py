@@ -1,0 +1,169 @@
+"""GPU tests of the device-side per-thread operations (Section 4.1: container functions called
+inside kernels, one element per thread; Section 4: operations running concurrently).
+
+The kernels run every element at once and in no fixed order, so results are checked as sets plus
+the invariants that any order gives: a key repeated across threads is stored once and INSERTED
+by exactly one of them (whose value it keeps), a present key is erased by exactly one thread, the
+final contents equal the oracle's after the same set of changes, and the live count and layout
+invariants hold.  Reads are deterministic and compared element by element.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1908_05936_amd import ct
+from paper_1908_05936_amd.workloads import distinct_u64, pack_int3, rng_for
+
+pytestmark = pytest.mark.gpu
+
+U64MAX = (1 << 64) - 1
+RESERVED = np.array([0, U64MAX, U64MAX - 1, 1 << 63], dtype=np.uint64)
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    ct.lib()
+    return torch.device("cuda", 0)
+
+
+def g64(a, dev):
+    return torch.from_numpy(np.ascontiguousarray(np.asarray(a, dtype=np.uint64)).view(np.int64)).to(dev)
+
+
+def dump_sorted(t, bits):
+    k, v = t.dump()
+    k = k.cpu().numpy().view(np.uint64)
+    v = v.cpu().numpy().view(np.uint64)
+    if bits == 32:
+        v = v.astype(np.uint32)
+    o = np.argsort(k, kind="stable")
+    return k[o], v[o]
+
+
+def same(t, o, bits):
+    assert t.size() == o.size()
+    k, v = dump_sorted(t, bits)
+    ek, ev = o.dump()
+    np.testing.assert_array_equal(k, ek)
+    if bits:
+        np.testing.assert_array_equal(v, ev)
+    assert t.check() == 0
+
+
+@pytest.mark.parametrize("bits", [64, 32, 0])
+def test_concurrent_inserts_of_repeated_keys(dev, bits):
+    """200,000 threads insert keys drawn from 6,000 (some already present, reserved-looking ones
+    included): every new key is stored once and INSERTED by exactly one thread, whose value it
+    keeps; every other thread sees PRESENT."""
+    rng = rng_for(101, bits)
+    vk = {0: ct.VAL_NONE, 32: ct.VAL_U32, 64: ct.VAL_U64}[bits]
+    t = ct.Table(60_000, vk, device=dev)
+    o = oracle.OracleTable(60_000, bits, oracle.HASH_MIX64, 60_000)
+    base = distinct_u64(rng, 20_000)
+    bv = rng.integers(0, 1 << 31, size=base.size, dtype=np.uint64)
+    if bits:
+        t.insert(g64(base, dev), torch.from_numpy(bv.astype(np.int64)).to(dev).to(t.value_dtype))
+    else:
+        t.insert(g64(base, dev))
+    o.insert(base, bv if bits else None)
+    universe = np.concatenate([base[:2000], distinct_u64(rng, 4000, exclude=base), RESERVED])
+    keys = universe[rng.integers(0, universe.size, size=200_000)]
+    vals = rng.integers(0, 1 << 31, size=keys.size, dtype=np.uint64)
+    gv = None
+    if bits:
+        gv = torch.from_numpy(vals.astype(np.int64)).to(dev).to(t.value_dtype)
+    st, _ = t.dev_apply(ct.OP_INSERT, g64(keys, dev), gv)
+    st = st.cpu().numpy()
+    assert not (st == 2).any()
+    present_before = np.isin(keys, base)
+    assert (st[present_before] == 0).all()
+    new = ~present_before
+    ins = np.flatnonzero(st == 1)
+    # exactly one INSERTED per distinct new key
+    assert np.unique(keys[ins]).size == ins.size
+    assert set(keys[ins].tolist()) == set(keys[new].tolist())
+    o.insert(keys[ins], vals[ins] if bits else None)
+    same(t, o, bits)
+
+
+def test_concurrent_erases_and_reads(dev):
+    """Each present key is removed by exactly one of the threads that erase it; finds are
+    element-by-element equal to the oracle's (reads only, so no ordering is involved)."""
+    rng = rng_for(103)
+    t = ct.Table(80_000, ct.VAL_U64, device=dev)
+    o = oracle.OracleTable(80_000, 64, oracle.HASH_MIX64, 80_000)
+    base = np.concatenate([distinct_u64(rng, 50_000), RESERVED[1:3]])
+    bv = rng.integers(0, 1 << 62, size=base.size, dtype=np.uint64)
+    t.insert(g64(base, dev), g64(bv, dev))
+    o.insert(base, bv)
+    q = np.concatenate([base[rng.integers(0, base.size, size=30_000)], distinct_u64(rng, 10_000)])
+    st, v = t.dev_apply(ct.OP_FIND, g64(q, dev))
+    ev, ef = o.find(q)
+    np.testing.assert_array_equal(st.cpu().numpy(), ef)
+    np.testing.assert_array_equal(v.cpu().numpy().view(np.uint64), ev)
+    er = base[rng.integers(0, base.size, size=120_000)]
+    st, _ = t.dev_apply(ct.OP_ERASE, g64(er, dev))
+    st = st.cpu().numpy()
+    hit = np.flatnonzero(st == 1)
+    assert np.unique(er[hit]).size == hit.size
+    assert set(er[hit].tolist()) == set(er.tolist())
+    o.erase(np.unique(er))
+    same(t, o, 64)
+    # the batch path keeps working on a table the device functions changed
+    again = distinct_u64(rng, 5000, exclude=base)
+    t.insert(g64(again, dev), g64(again, dev))
+    o.insert(again, again)
+    same(t, o, 64)
+
+
+def test_concurrent_inserts_at_capacity(dev):
+    """A table 10 keys short of its capacity: of 5,000 new keys inserted at once exactly 10 get
+    in (INSERTED), the rest report FULL, and the live count ends at the capacity."""
+    rng = rng_for(107)
+    cap = 4096
+    t = ct.Table(cap, ct.VAL_U64, device=dev)
+    base = distinct_u64(rng, cap - 10)
+    t.insert(g64(base, dev), g64(base, dev))
+    keys = distinct_u64(rng, 5000, exclude=base)
+    st, _ = t.dev_apply(ct.OP_INSERT, g64(keys, dev), g64(keys, dev))
+    st = st.cpu().numpy()
+    assert (st == 1).sum() == 10 and (st == 2).sum() == keys.size - 10
+    assert t.size() == cap and t.check() == 0
+    k, v = dump_sorted(t, 64)
+    assert set(k.tolist()) == set(base.tolist()) | set(keys[st == 1].tolist())
+    np.testing.assert_array_equal(k, v)
+
+
+@pytest.mark.parametrize("ndirs", [6, 26])
+def test_voxel_neighbour_update(dev, ndirs):
+    """The neighbour update of a block map: blocks of a dense cluster ask for their neighbours at
+    once (most neighbours are asked for by several blocks).  The final key set is the residents
+    plus the oracle's neighbour keys, residents keep their values, and each new block's value
+    names a block whose neighbour it is."""
+    rng = rng_for(109, ndirs)
+    c = rng.integers(-40, 40, size=(30_000, 3))
+    blocks = np.unique(pack_int3(c[:, 0], c[:, 1], c[:, 2]))
+    rng.shuffle(blocks)
+    t = ct.Table(1 << 20, ct.VAL_U32, ct.HASH_VOXEL21, bucket_count=1 << 17, device=dev)
+    resid = blocks[: blocks.size // 2]
+    t.insert(g64(resid, dev), torch.arange(resid.size, dtype=torch.int32, device=dev))
+    t.insert_neighbours(g64(blocks, dev), ndirs)
+    nbrs = oracle.voxel_neighbour_keys(blocks, ndirs)
+    want = set(resid.tolist()) | set(nbrs.tolist())
+    k, v = dump_sorted(t, 32)
+    assert set(k.tolist()) == want and t.size() == len(want) and t.check() == 0
+    pos = {x: i for i, x in enumerate(resid.tolist())}
+    per_block = nbrs.reshape(blocks.size, ndirs)
+    for key, val in zip(k.tolist(), v.tolist()):
+        if key in pos:
+            assert val == pos[key]
+        else:
+            assert 0 <= val < blocks.size and key in per_block[val].tolist()
+    # the sequential definition gives the same key set
+    o = oracle.OracleTable(1 << 20, 32, oracle.HASH_VOXEL21, 1 << 17)
+    o.insert(resid, np.arange(resid.size, dtype=np.uint64))
+    o.insert(nbrs, np.repeat(np.arange(blocks.size, dtype=np.uint64), ndirs))
+    np.testing.assert_array_equal(k, o.dump()[0])
