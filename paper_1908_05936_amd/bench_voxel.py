@@ -25,6 +25,61 @@ def _dev64(a, dev):
     return torch.from_numpy(np.ascontiguousarray(a).view(np.int64)).to(dev)
 
 
+def _neighbour_keys_torch(blocks: torch.Tensor) -> torch.Tensor:
+    """The 6 face neighbours of each packed block (coordinates wrap in their 21-bit fields),
+    block-major: torch integer ops on the device."""
+    m = (1 << 21) - 1
+    f = [(blocks >> (21 * a)) & m for a in range(3)]
+    f = [torch.where(c >= (1 << 20), c - (1 << 21), c) for c in f]
+    out = []
+    for a in range(3):
+        for d in (-1, 1):
+            c = [x.clone() for x in f]
+            c[a] = c[a] + d
+            out.append((c[0] & m) | ((c[1] & m) << 21) | ((c[2] & m) << 42))
+    return torch.stack(out, dim=1).reshape(-1)
+
+
+def neighbour_update(res_keys: torch.Tensor, dev, reps: int = 3) -> dict:
+    """The neighbour update of the resident block map: every resident block makes sure that its 6
+    face neighbours are in the map.  Through the device-side per-thread API (one thread per block,
+    contains then insert for each neighbour), and the same result by a batch insert of the 6
+    neighbour keys of every block (built with torch integer ops, timed apart).  Tables of capacity
+    2^23 start from the residents each run; medians of `reps` runs, HIP events."""
+    n = res_keys.numel()
+    keys = None
+    t_dev, t_keys, t_batch, new = [], [], [], 0
+    for r in range(reps):
+        ta = ct.Table(1 << 23, ct.VAL_U32, ct.HASH_VOXEL21, device=dev)
+        ta.insert(res_keys, torch.arange(n, dtype=torch.int32, device=dev), status=False)
+        tb = ct.Table(1 << 23, ct.VAL_U32, ct.HASH_VOXEL21, device=dev)
+        tb.insert(res_keys, torch.arange(n, dtype=torch.int32, device=dev), status=False)
+        torch.cuda.synchronize()
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(5)]
+        e[0].record()
+        ta.insert_neighbours(res_keys, 6)
+        e[1].record()
+        keys = _neighbour_keys_torch(res_keys)
+        vals = torch.arange(n, dtype=torch.int32, device=dev).repeat_interleave(6)
+        e[2].record()
+        tb.insert(keys, vals, status=False)
+        e[3].record()
+        torch.cuda.synchronize()
+        t_dev.append(e[0].elapsed_time(e[1]) * 1e-3)
+        t_keys.append(e[1].elapsed_time(e[2]) * 1e-3)
+        t_batch.append(e[2].elapsed_time(e[3]) * 1e-3)
+        new = ta.size() - n
+        assert tb.size() == ta.size()
+        del ta, tb
+    req = 6 * n
+    return {"blocks": n, "requests": req, "new_blocks": int(new),
+            "device_api_ms": float(np.median(t_dev)) * 1e3,
+            "device_api_Mreq_s": req / float(np.median(t_dev)) / 1e6,
+            "batch_keys_ms": float(np.median(t_keys)) * 1e3,
+            "batch_insert_ms": float(np.median(t_batch)) * 1e3,
+            "batch_Mreq_s": req / float(np.median(t_batch)) / 1e6}
+
+
 def run(repeats: int = 3, seed: int = 2, log=print) -> dict:
     dev = torch.device("cuda", 0)
     w = voxel_blocks(seed=seed)
@@ -76,6 +131,7 @@ def run(repeats: int = 3, seed: int = 2, log=print) -> dict:
         torch.cuda.synchronize()
         sel.append(e0.elapsed_time(e1) * 1e-3)
     sel_s = float(np.median(sel))
+    nbr = neighbour_update(res_keys, dev)
     out = {
         "workload": (f"voxel blocks: {w['residents'].size} residents, 2^21 buckets, spatial hash, "
                      f"{len(frames)} frames of find 2^18 (90% hits) + insert_alloc of the misses"),
@@ -85,11 +141,15 @@ def run(repeats: int = 3, seed: int = 2, log=print) -> dict:
         "find_Mkeys_s": n_find / find_s / 1e6,
         "insert_alloc_Mkeys_s": n_ins / ins_s / 1e6,
         "final_size": size,
+        "neighbour_update": nbr,
         "select_box": {"selected": int(cnt.value), "ms": sel_s * 1e3,
                        "table_GB_s": nb * 128 / sel_s / 1e9,
                        "note": "octant x, y, z >= 0 of the final table; the call's time, its "
                                "count read-back included"},
     }
+    log(f"[voxel] neighbour update of {nbr['blocks']} blocks ({nbr['new_blocks']} new): device "
+        f"API {nbr['device_api_ms']:.2f} ms ({nbr['device_api_Mreq_s']:.0f} Mreq/s), batch insert "
+        f"{nbr['batch_insert_ms']:.2f} ms + keys {nbr['batch_keys_ms']:.2f} ms")
     log(f"[voxel] select box: {out['select_box']['selected']} blocks in "
         f"{out['select_box']['ms']:.3f} ms ({out['select_box']['table_GB_s']:.0f} GB/s of table)")
     log(f"[voxel] p50 {out['frame_p50_ms']:.3f} ms p99 {out['frame_p99_ms']:.3f} ms, find "

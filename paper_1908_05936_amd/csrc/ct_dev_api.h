@@ -16,9 +16,10 @@
 //               erasers sees true).  An erase leaves an empty slot only where its bucket already
 //               had one, so no probe sequence that passed the bucket is cut short.
 //
-// Inserts and erases never share a kernel.  The live count stays exact throughout: an insert
-// reserves capacity before it claims a slot (one compare-and-swap loop per wave), and gives it
-// back when another thread stored the same key first; FULL means the table held its capacity.
+// Inserts and erases never share a kernel.  The live count stays exact throughout: the thread
+// that stores a new key takes one unit of capacity (one atomic add per wave) after its claim;
+// with none left it takes the key out again (a tombstone) and reports FULL, so FULL means the
+// table held its capacity.  Near capacity, a concurrent thread may see such a key for that moment.
 // Key words are read with agent-scope atomic loads, which see other compute units' claims.
 #pragma once
 
@@ -61,27 +62,25 @@ __device__ __forceinline__ uint64_t dev_probe(const TableView& t, uint64_t key, 
   return kNoPos;
 }
 
-// One compare-and-swap loop per wave over the live count: lanes of the wave that arrive together
-// reserve one unit each, in lane order, while capacity lasts.  Returns whether this lane got one.
+// Capacity for the lanes of the wave that arrive together: one fetch-and-add of their number on
+// the live count (a compare-and-swap loop on that one address made the waves retry each other
+// for seconds), then the leader gives back what lies beyond the capacity.  The adds order all
+// reservations, and lane r of a wave holds position old + r: exactly the positions below the
+// capacity are granted, however the adds and give-backs interleave.
 __device__ __forceinline__ bool dev_reserve(const TableView& t) {
   const uint64_t m = __ballot(1);
   const int leader = __builtin_ctzll(m);
   const uint32_t rank = (uint32_t)__builtin_popcountll(m & ((1ull << wave_lane()) - 1ull));
-  uint64_t granted = 0;
+  uint64_t old = 0;
   if (wave_lane() == leader) {
     const uint64_t want = (uint64_t)__builtin_popcountll(m);
-    uint64_t cur = __hip_atomic_load(&t.hdr->size, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    for (;;) {
-      const uint64_t room = cur < t.cap ? t.cap - cur : 0;
-      granted = want < room ? want : room;
-      if (granted == 0) break;
-      if (__hip_atomic_compare_exchange_strong(&t.hdr->size, &cur, cur + granted, __ATOMIC_RELAXED,
-                                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
-        break;
-    }
+    old = __hip_atomic_fetch_add(&t.hdr->size, want, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const uint64_t room = old < t.cap ? t.cap - old : 0;
+    if (want > room)
+      __hip_atomic_fetch_sub(&t.hdr->size, want - room, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
-  granted = __shfl(granted, leader, 64);
-  return rank < granted;
+  old = __shfl(old, leader, 64);
+  return old + rank < t.cap;
 }
 
 // Every lane that reaches this call takes one from the live count: one atomic per wave.
@@ -92,37 +91,40 @@ __device__ __forceinline__ void dev_uncount(const TableView& t) {
                            __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// kPresent, kInserted or kFull.
+// kPresent, kInserted or kFull.  The slot is claimed first, so only the one thread that stores
+// the key asks for capacity; without it the key is taken out again (the slot becomes a
+// tombstone) and the insert reports FULL.
 __device__ inline uint8_t dev_insert(const DevView& v, uint64_t key, uint64_t val) {
   const TableView& t = v.t;
   if (key >= kTomb) {  // out-of-band keys live in the header
     const int s = (int)(key - kTomb);
-    if (__hip_atomic_load(&t.hdr->spec_live[s], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return kPresent;
-    if (!dev_reserve(t)) return kFull;
     uint32_t expected = 0;
-    if (__hip_atomic_compare_exchange_strong(&t.hdr->spec_live[s], &expected, 1u, __ATOMIC_RELAXED,
-                                             __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
-      t.hdr->spec_val[s] = val;
-      return kInserted;
+    if (!__hip_atomic_compare_exchange_strong(&t.hdr->spec_live[s], &expected, 1u, __ATOMIC_RELAXED,
+                                              __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+      return kPresent;
+    if (!dev_reserve(t)) {
+      __hip_atomic_store(&t.hdr->spec_live[s], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      return kFull;
     }
-    dev_uncount(t);
-    return kPresent;
+    t.hdr->spec_val[s] = val;
+    return kInserted;
   }
   const Seq sq = probe_seq(t, key);
   uint64_t empty;
   if (dev_probe(t, key, sq, sq.home, 0, &empty) != kNoPos) return kPresent;
-  if (empty == kNoPos) return kFull;  // every bucket holds keys or tombstones
-  if (!dev_reserve(t)) return kFull;
   for (;;) {
+    if (empty == kNoPos) return kFull;  // every bucket holds keys or tombstones
+    uint64_t* kw = &t.bk[empty >> 3].s[empty & 7].key;
     uint64_t expected = kEmpty;
-    if (cas64(&t.bk[empty >> 3].s[empty & 7].key, expected, key)) {
+    if (cas64(kw, expected, key)) {
+      if (!dev_reserve(t)) {
+        __hip_atomic_store(kw, kTomb, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        return kFull;
+      }
       t.bk[empty >> 3].s[empty & 7].val = val;
       return kInserted;
     }
-    if (expected == key) {  // another thread stored this key in the same first empty slot
-      dev_uncount(t);
-      return kPresent;
-    }
+    if (expected == key) return kPresent;  // another thread stored it in the same first empty slot
     // another key took the slot: go on from the next slot of the sequence
     uint64_t b = empty >> 3;
     int c = (int)(empty & 7) + 1;
@@ -130,14 +132,7 @@ __device__ inline uint8_t dev_insert(const DevView& v, uint64_t key, uint64_t va
       c = 0;
       b = next_bucket(t, b, sq.step);
     }
-    if (dev_probe(t, key, sq, b, c, &empty) != kNoPos) {
-      dev_uncount(t);
-      return kPresent;
-    }
-    if (empty == kNoPos) {
-      dev_uncount(t);
-      return kFull;
-    }
+    if (dev_probe(t, key, sq, b, c, &empty) != kNoPos) return kPresent;
   }
 }
 
