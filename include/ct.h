@@ -216,6 +216,24 @@ ct_status ct_dev_apply(ct_table *t, int32_t op, const uint64_t *keys, const void
 ct_status ct_voxel_insert_neighbours(ct_table *t, const uint64_t *blocks, int64_t n, int32_t ndirs,
                                      void *stream);
 
+/* The same with the index pool: a new neighbour block takes pop_back() of `p` as its value (the
+   block map of Section 4.1 fed by the free list, as a reconstruction allocates blocks).  A block
+   that finds no capacity or an empty pool is left out (CT_ERR_POOL set when the pool ran out). */
+ct_status ct_voxel_insert_neighbours_alloc(ct_table *t, ct_pool *p, const uint64_t *blocks,
+                                           int64_t n, int32_t ndirs, void *stream);
+
+/* Device-side vector / deque back operations on a pool (Sections 4.2-4.3: push_back / pop_back
+   from threads).  ct_pool_device_view fills the by-value pool view of the device functions
+   dev_push_back / dev_pop_back (paper_1908_05936_amd/csrc/ct_dev_api.h); a kernel either pushes
+   or pops.  ct_dev_pool_apply is their reference kernel: element i by one thread, all
+   concurrently; status[i] 1 done / 2 full or empty; popped values in out[i] (-1 when empty): the
+   pops together take the pool's last min(n, size) entries, in no fixed order. */
+#define CT_DEV_PUSH_BACK 0
+#define CT_DEV_POP_BACK 1
+ct_status ct_pool_device_view(ct_pool *p, void *out, int64_t bytes);
+ct_status ct_dev_pool_apply(ct_pool *p, int32_t op, const int32_t *in, int64_t n, int32_t *out,
+                            uint8_t *status, void *stream);
+
 /* Read and clear the sticky error word (CT_ERR_* bits).  Synchronises. */
 ct_status ct_get_error(ct_table *t, uint32_t *h_err, void *stream);
 

@@ -91,10 +91,13 @@ __device__ __forceinline__ void dev_uncount(const TableView& t) {
                            __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// The insert, with the stored value produced after the claim: `take(&value)` runs once the thread
+// holds the slot and a unit of capacity, and may refuse (then the claim is undone as for FULL).
 // kPresent, kInserted or kFull.  The slot is claimed first, so only the one thread that stores
 // the key asks for capacity; without it the key is taken out again (the slot becomes a
 // tombstone) and the insert reports FULL.
-__device__ inline uint8_t dev_insert(const DevView& v, uint64_t key, uint64_t val) {
+template <class Take>
+__device__ inline uint8_t dev_insert_with(const DevView& v, uint64_t key, Take take) {
   const TableView& t = v.t;
   if (key >= kTomb) {  // out-of-band keys live in the header
     const int s = (int)(key - kTomb);
@@ -102,7 +105,13 @@ __device__ inline uint8_t dev_insert(const DevView& v, uint64_t key, uint64_t va
     if (!__hip_atomic_compare_exchange_strong(&t.hdr->spec_live[s], &expected, 1u, __ATOMIC_RELAXED,
                                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
       return kPresent;
+    uint64_t val = 0;
     if (!dev_reserve(t)) {
+      __hip_atomic_store(&t.hdr->spec_live[s], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      return kFull;
+    }
+    if (!take(&val)) {
+      dev_uncount(t);
       __hip_atomic_store(&t.hdr->spec_live[s], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       return kFull;
     }
@@ -117,7 +126,13 @@ __device__ inline uint8_t dev_insert(const DevView& v, uint64_t key, uint64_t va
     uint64_t* kw = &t.bk[empty >> 3].s[empty & 7].key;
     uint64_t expected = kEmpty;
     if (cas64(kw, expected, key)) {
+      uint64_t val = 0;
       if (!dev_reserve(t)) {
+        __hip_atomic_store(kw, kTomb, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        return kFull;
+      }
+      if (!take(&val)) {
+        dev_uncount(t);
         __hip_atomic_store(kw, kTomb, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         return kFull;
       }
@@ -134,6 +149,13 @@ __device__ inline uint8_t dev_insert(const DevView& v, uint64_t key, uint64_t va
     }
     if (dev_probe(t, key, sq, b, c, &empty) != kNoPos) return kPresent;
   }
+}
+
+__device__ inline uint8_t dev_insert(const DevView& v, uint64_t key, uint64_t val) {
+  return dev_insert_with(v, key, [val](uint64_t* out) {
+    *out = val;
+    return true;
+  });
 }
 
 // Whether the key was present (and is now removed).
@@ -180,6 +202,82 @@ __device__ inline bool dev_find(const DevView& v, uint64_t key, uint64_t* val) {
 
 __device__ inline bool dev_contains(const DevView& v, uint64_t key) {
   return dev_find(v, key, nullptr);
+}
+
+// ---------------------------------------------------------------------------------------------
+// Device-side vector / deque back operations on an index pool (Sections 4.2-4.3: push_back and
+// pop_back called from threads).  A kernel either pushes or pops; each is one atomic per wave on
+// the pool's size.  The adds (or subtractions) order the lanes: lane r of a wave takes position
+// old + r (old - 1 - r for pops), and exactly the positions inside the pool are granted, however
+// the give-backs of the other lanes interleave.  A pushed value is readable once the kernel ends.
+// ---------------------------------------------------------------------------------------------
+struct DevPool {
+  PoolHeader* hdr;
+  int32_t* stack;
+};
+
+// Whether the value was stored (false: the pool was at capacity, CT_ERR_POOL set).
+__device__ inline bool dev_push_back(const DevPool& p, int32_t value) {
+  const uint64_t m = __ballot(1);
+  const int leader = __builtin_ctzll(m);
+  const int64_t rank = (int64_t)__builtin_popcountll(m & ((1ull << wave_lane()) - 1ull));
+  const int64_t cap = p.hdr->cap;
+  int64_t old = 0;
+  if (wave_lane() == leader) {
+    const int64_t want = (int64_t)__builtin_popcountll(m);
+    old = __hip_atomic_fetch_add(&p.hdr->top, want, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const int64_t room = old < cap ? cap - (old < 0 ? 0 : old) : 0;
+    if (want > room) {
+      __hip_atomic_fetch_sub(&p.hdr->top, want - room, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_fetch_or(&p.hdr->err, kErrPool, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+  }
+  old = __shfl(old, leader, 64);
+  const int64_t pos = old + rank;
+  if (old < 0 || pos >= cap) return false;
+  p.stack[ring_pos(p.hdr->head, cap, pos)] = value;
+  return true;
+}
+
+// Whether a value was removed into *value (false: the pool was empty, CT_ERR_POOL set).
+__device__ inline bool dev_pop_back(const DevPool& p, int32_t* value) {
+  const uint64_t m = __ballot(1);
+  const int leader = __builtin_ctzll(m);
+  const int64_t rank = (int64_t)__builtin_popcountll(m & ((1ull << wave_lane()) - 1ull));
+  int64_t old = 0;
+  if (wave_lane() == leader) {
+    const int64_t want = (int64_t)__builtin_popcountll(m);
+    old = __hip_atomic_fetch_sub(&p.hdr->top, want, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const int64_t avail = old > 0 ? old : 0;
+    if (want > avail) {
+      __hip_atomic_fetch_add(&p.hdr->top, want - avail, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_fetch_or(&p.hdr->err, kErrPool, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+  }
+  old = __shfl(old, leader, 64);
+  if (rank >= old) return false;
+  *value = p.stack[ring_pos(p.hdr->head, p.hdr->cap, old - 1 - rank)];
+  return true;
+}
+
+// Insert whose new key takes pop_back() of the pool as its value (the block map of Section 4.1
+// fed by the free list); a present key reports its value.  kPresent / kInserted / kFull (no
+// capacity or an empty pool: the claim is undone).  *out gets the key's value, -1 on FULL.
+__device__ inline uint8_t dev_insert_alloc(const DevView& v, const DevPool& p, uint64_t key,
+                                           int32_t* out) {
+  int32_t got = -1;
+  const uint8_t st = dev_insert_with(v, key, [&](uint64_t* val) {
+    if (!dev_pop_back(p, &got)) return false;
+    *val = (uint64_t)(uint32_t)got;
+    return true;
+  });
+  if (st == kPresent) {
+    uint64_t val = 0;
+    *out = dev_find(v, key, &val) ? (int32_t)(uint32_t)val : -1;
+  } else {
+    *out = st == kInserted ? got : -1;
+  }
+  return st;
 }
 
 }  // namespace ct

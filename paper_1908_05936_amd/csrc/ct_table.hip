@@ -1451,8 +1451,11 @@ __global__ __launch_bounds__(kBlock) void k_dev_apply(DevView v, int32_t op, con
 // The neighbour update of a block map (the allocation step of the reconstruction workload behind
 // Section 4.1's voxel-block example): every block of `blocks` makes sure that its 6 face
 // neighbours (ndirs 6) or all 26 neighbours (ndirs 26) are in the table, each new one with the
-// index of a block that asked for it as its value.  Coordinates wrap in their 21-bit fields.
-__global__ __launch_bounds__(kBlock) void k_voxel_neighbours(DevView v, const uint64_t* __restrict__ blocks,
+// index of a block that asked for it as its value, or (ALLOC) with pop_back() of the index pool,
+// as a reconstruction allocates voxel blocks.  Coordinates wrap in their 21-bit fields.
+template <bool ALLOC>
+__global__ __launch_bounds__(kBlock) void k_voxel_neighbours(DevView v, DevPool pool,
+                                                             const uint64_t* __restrict__ blocks,
                                                              int64_t n, int32_t ndirs) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x) {
@@ -1465,8 +1468,34 @@ __global__ __launch_bounds__(kBlock) void k_voxel_neighbours(DevView v, const ui
       const uint64_t k = ((uint64_t)(uint32_t)(x + dx) & 0x1FFFFFull) |
                          (((uint64_t)(uint32_t)(y + dy) & 0x1FFFFFull) << 21) |
                          (((uint64_t)(uint32_t)(z + dz) & 0x1FFFFFull) << 42);
-      if (!dev_contains(v, k)) dev_insert(v, k, (uint64_t)(uint32_t)i);
+      if (dev_contains(v, k)) continue;
+      if constexpr (ALLOC) {
+        int32_t got;
+        dev_insert_alloc(v, pool, k, &got);
+      } else {
+        dev_insert(v, k, (uint64_t)(uint32_t)i);
+      }
     }
+  }
+}
+
+// Per-thread push_back / pop_back through the device-side API: element i by one thread, all
+// concurrently.
+__global__ __launch_bounds__(kBlock) void k_dev_pool_apply(DevPool p, int32_t op,
+                                                           const int32_t* __restrict__ in, int64_t n,
+                                                           int32_t* __restrict__ out,
+                                                           uint8_t* __restrict__ status) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    bool ok;
+    if (op == CT_DEV_PUSH_BACK) {
+      ok = dev_push_back(p, in[i]);
+    } else {
+      int32_t v = -1;
+      ok = dev_pop_back(p, &v);
+      if (out) out[i] = ok ? v : -1;
+    }
+    if (status) status[i] = ok ? 1 : 2;
   }
 }
 
@@ -2343,7 +2372,39 @@ ct_status ct_voxel_insert_neighbours(ct_table* t, const uint64_t* blocks, int64_
   v.mode = kDevInsert;
   t->size_ub = std::min<uint64_t>(t->size_ub + (uint64_t)n * (uint64_t)ndirs,
                                   (uint64_t)t->desc.capacity);
-  k_voxel_neighbours<<<flat_blocks(n), kBlock, 0, S(stream)>>>(v, blocks, n, ndirs);
+  k_voxel_neighbours<false><<<flat_blocks(n), kBlock, 0, S(stream)>>>(v, DevPool{}, blocks, n, ndirs);
+  return launched();
+}
+
+ct_status ct_voxel_insert_neighbours_alloc(ct_table* t, ct_pool* p, const uint64_t* blocks,
+                                           int64_t n, int32_t ndirs, void* stream) {
+  if (!t || !p || n < 0 || (n > 0 && !blocks) || (ndirs != 6 && ndirs != 26)) return CT_E_INVALID;
+  if (t->desc.val_kind == CT_VAL_NONE) return CT_E_INVALID;
+  if (n == 0) return CT_OK;
+  DevView v{};
+  v.t = t->v;
+  v.mode = kDevInsert;
+  t->size_ub = std::min<uint64_t>(t->size_ub + (uint64_t)n * (uint64_t)ndirs,
+                                  (uint64_t)t->desc.capacity);
+  k_voxel_neighbours<true><<<flat_blocks(n), kBlock, 0, S(stream)>>>(v, DevPool{p->hdr, p->stack},
+                                                                     blocks, n, ndirs);
+  return launched();
+}
+
+ct_status ct_pool_device_view(ct_pool* p, void* out, int64_t bytes) {
+  if (!p || !out || bytes < (int64_t)sizeof(DevPool)) return CT_E_INVALID;
+  const DevPool d{p->hdr, p->stack};
+  std::memcpy(out, &d, sizeof(d));
+  return CT_OK;
+}
+
+ct_status ct_dev_pool_apply(ct_pool* p, int32_t op, const int32_t* in, int64_t n, int32_t* out,
+                            uint8_t* status, void* stream) {
+  if (!p || n < 0 || (op != CT_DEV_PUSH_BACK && op != CT_DEV_POP_BACK)) return CT_E_INVALID;
+  if (op == CT_DEV_PUSH_BACK && n > 0 && !in) return CT_E_INVALID;
+  if (n == 0) return CT_OK;
+  k_dev_pool_apply<<<flat_blocks(n), kBlock, 0, S(stream)>>>(DevPool{p->hdr, p->stack}, op, in, n,
+                                                             out, status);
   return launched();
 }
 

@@ -73,6 +73,9 @@ SIGNATURES = {
     "ct_table_device_view": (C.c_int, [_P, _I32, _P, _I64]),
     "ct_dev_apply": (C.c_int, [_P, _I32, _P, _P, _I64, _P, _P, _P]),
     "ct_voxel_insert_neighbours": (C.c_int, [_P, _P, _I64, _I32, _P]),
+    "ct_voxel_insert_neighbours_alloc": (C.c_int, [_P, _P, _P, _I64, _I32, _P]),
+    "ct_pool_device_view": (C.c_int, [_P, _P, _I64]),
+    "ct_dev_pool_apply": (C.c_int, [_P, _I32, _P, _I64, _P, _P, _P]),
     "ct_select_key_range": (C.c_int, [_P, C.c_uint64, C.c_uint64, _P, _P, _I64, _PI64, _P]),
     "ct_select_voxel_box": (C.c_int, [_P, C.POINTER(C.c_int32), C.POINTER(C.c_int32), _P, _P,
                                       _I64, _PI64, _P]),
@@ -212,6 +215,22 @@ class Pool:
         _check(lib().ct_pool_push_front_batch(self._h, _ptr(values), values.numel(), _ptr(st),
                                               _stream(self.device)), "ct_pool_push_front_batch")
         return st
+
+    def dev_push_back(self, values: torch.Tensor):
+        """push_back of every value by its own thread, concurrently (device-side API)."""
+        _need(values, torch.int32, None, "values", self.device)
+        st = torch.empty(values.numel(), dtype=torch.uint8, device=self.device)
+        _check(lib().ct_dev_pool_apply(self._h, 0, _ptr(values), values.numel(), None, _ptr(st),
+                                       _stream(self.device)), "ct_dev_pool_apply")
+        return st
+
+    def dev_pop_back(self, n: int):
+        """n concurrent pop_back calls (device-side API): (values or -1, statuses)."""
+        out = torch.empty(int(n), dtype=torch.int32, device=self.device)
+        st = torch.empty(int(n), dtype=torch.uint8, device=self.device)
+        _check(lib().ct_dev_pool_apply(self._h, 1, None, int(n), _ptr(out), _ptr(st),
+                                       _stream(self.device)), "ct_dev_pool_apply")
+        return out, st
 
     def size(self) -> int:
         v = C.c_int64(0)
@@ -383,6 +402,14 @@ class Table:
         _check(lib().ct_voxel_insert_neighbours(self._h, _ptr(blocks), blocks.numel(), int(ndirs),
                                                 _stream(self.device)),
                "ct_voxel_insert_neighbours")
+
+    def insert_neighbours_alloc(self, pool: "Pool", blocks: torch.Tensor, ndirs: int = 6):
+        """Neighbour update whose new blocks take pop_back() of `pool` as their value."""
+        _need(blocks, torch.int64, None, "blocks", self.device)
+        _check(lib().ct_voxel_insert_neighbours_alloc(self._h, pool._h, _ptr(blocks),
+                                                      blocks.numel(), int(ndirs),
+                                                      _stream(self.device)),
+               "ct_voxel_insert_neighbours_alloc")
 
     def rehash_into(self, dst: "Table"):
         """Insert every live pair of this table into `dst` (same value kind, room for all of them;

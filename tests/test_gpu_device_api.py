@@ -167,3 +167,61 @@ def test_voxel_neighbour_update(dev, ndirs):
     o.insert(resid, np.arange(resid.size, dtype=np.uint64))
     o.insert(nbrs, np.repeat(np.arange(blocks.size, dtype=np.uint64), ndirs))
     np.testing.assert_array_equal(k, o.dump()[0])
+
+
+def test_device_pool_push_and_pop(dev):
+    """push_back and pop_back from threads (Sections 4.2-4.3) on a pool whose head has moved: the
+    pops together take the pool's last entries (compared as a multiset with the oracle's pops),
+    pushes store every value while there is room (compared as multisets), a push beyond the
+    capacity stores exactly the room and sets the pool error."""
+    rng = rng_for(113)
+    cap = 100_000
+    gp = ct.Pool(cap, device=dev)
+    op = oracle.OraclePool(cap)
+    out, _ = gp.pop_front(12_345)
+    op.pop_front(12_345)
+    got, st = gp.dev_pop_back(30_000)
+    eo, es = op.pop(30_000)
+    assert (st.cpu().numpy() == 1).all()
+    np.testing.assert_array_equal(np.sort(got.cpu().numpy()), np.sort(eo))
+    assert gp.size() == op.size()
+    np.testing.assert_array_equal(gp.dump().cpu().numpy(), op.dump())
+    vals = rng.permutation(np.arange(1_000_000, 1_040_000, dtype=np.int32))
+    st = gp.dev_push_back(torch.from_numpy(vals).to(dev))
+    assert (st.cpu().numpy() == 1).all()
+    op.push(vals)
+    assert gp.size() == op.size()
+    np.testing.assert_array_equal(np.sort(gp.dump().cpu().numpy()), np.sort(op.dump()))
+    room = cap - gp.size()
+    more = np.arange(5_000_000, 5_000_000 + room + 777, dtype=np.int32)
+    st = gp.dev_push_back(torch.from_numpy(more).to(dev)).cpu().numpy()
+    assert (st == 1).sum() == room and (st == 2).sum() == 777
+    assert gp.size() == cap and gp.error() & ct.ERR_POOL
+    stored = set(gp.dump().cpu().numpy().tolist()) & set(more.tolist())
+    assert stored == set(more[st == 1].tolist())
+    got, st = gp.dev_pop_back(cap + 50)
+    st = st.cpu().numpy()
+    assert (st == 1).sum() == cap and gp.size() == 0
+
+
+def test_voxel_neighbour_update_with_pool(dev):
+    """The neighbour update allocating from the index pool: new blocks take pool indices, so the
+    residents' values, the new blocks' values and the pool's remaining entries partition
+    0 .. capacity - 1 exactly, and the key set is the residents plus the oracle's neighbours."""
+    rng = rng_for(127)
+    c = rng.integers(-30, 30, size=(20_000, 3))
+    blocks = np.unique(pack_int3(c[:, 0], c[:, 1], c[:, 2]))
+    rng.shuffle(blocks)
+    cap = 1 << 19
+    t = ct.Table(cap, ct.VAL_U32, ct.HASH_VOXEL21, bucket_count=1 << 16, device=dev)
+    pool = ct.Pool(cap, device=dev)
+    resid = blocks[: blocks.size // 2]
+    t.insert_alloc(pool, g64(resid, dev))
+    t.insert_neighbours_alloc(pool, g64(blocks, dev), 26)
+    want = set(resid.tolist()) | set(oracle.voxel_neighbour_keys(blocks, 26).tolist())
+    k, v = dump_sorted(t, 32)
+    assert set(k.tolist()) == want and t.size() == len(want) and t.check() == 0
+    left = pool.dump().cpu().numpy()
+    allv = np.concatenate([v.astype(np.int64), left.astype(np.int64)])
+    np.testing.assert_array_equal(np.sort(allv), np.arange(cap))
+    assert pool.size() == cap - len(want)
