@@ -99,6 +99,8 @@ def parse():
     ap.add_argument("--serve-warmup", type=int, default=200)
     ap.add_argument("--serve-measured", type=int, default=2000)
     ap.add_argument("--serve-distinct", type=int, default=1000)
+    ap.add_argument("--serve-timeout", type=float, default=300.0,
+                    help="seconds the serving sweep may take before it is stopped")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-ceilings", action="store_true")
     ap.add_argument("--cpu-sample-shift", type=int, default=1,
@@ -349,6 +351,23 @@ def pool_ops(dev, keys, reps=3):
     return out
 
 
+def served_leg(child, timeout: float) -> dict:
+    """Release the waiting serving child (bench_serve, same code path as in-process) and read its
+    JSON line; its log goes to this process's stderr.  An error entry if it fails or does not
+    finish within `timeout` seconds (then it is killed)."""
+    import subprocess
+    try:
+        out, _ = child.communicate("go\n", timeout=timeout)
+    except subprocess.TimeoutExpired:
+        child.kill()
+        child.communicate()
+        log(f"the serving sweep did not finish within {timeout:.0f} s; it was stopped")
+        return {"error": f"the serving sweep did not finish within {timeout:.0f} s"}
+    if child.returncode != 0 or not out.strip():
+        return {"error": f"the serving sweep exited with status {child.returncode}"}
+    return json.loads(out.strip().splitlines()[-1])
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -357,6 +376,17 @@ def main():
               "GPUs, which this library does not do)",
               file=sys.stderr)
         sys.exit(2)
+    # the serving sweep runs in a child process, started here before this process touches the
+    # GPU and held until the rest of the line is measured: if the sweep does not finish within
+    # --serve-timeout seconds, the line is printed without it
+    serve_child = None
+    if not a.no_serve:
+        import subprocess
+        serve_child = subprocess.Popen(
+            [sys.executable, "-u", "-m", "paper_1908_05936_amd.bench_serve", "--wait-stdin",
+             "--footprint-gb", str(a.serve_footprint_gb), "--warmup", str(a.serve_warmup),
+             "--measured", str(a.serve_measured), "--distinct", str(a.serve_distinct)],
+            cwd=ROOT, stdin=subprocess.PIPE, stdout=subprocess.PIPE, text=True)
     import torch
 
     from paper_1908_05936_amd import ct
@@ -537,13 +567,11 @@ def main():
     if not a.no_voxel:
         from paper_1908_05936_amd import bench_voxel
         line["voxel"] = bench_voxel.run(log=log)
-    if not a.no_serve:
+    if serve_child is not None:
         del table, K_fill, V_fill, Q, E, K_re, V_re
         torch.cuda.empty_cache()
-        from paper_1908_05936_amd import bench_serve
-        res = bench_serve.run(a.serve_footprint_gb, a.serve_warmup, a.serve_measured,
-                              a.serve_distinct, log=log)
-        line["served"] = {
+        res = served_leg(serve_child, a.serve_timeout)
+        line["served"] = res if "error" in res else {
             "workload": (f"{res['tables']} tables, {res['resident_entries']} resident u64->u64 "
                          f"entries, {res['table_bytes'] / 1e9:.1f} GB; requests 20/70/10 "
                          "insert/find/erase, 2^8..2^20 keys, Zipf(1.1); Poisson arrivals"),

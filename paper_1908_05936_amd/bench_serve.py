@@ -49,7 +49,11 @@ def main(argv=None):
     ap.add_argument("--max-inflight", type=int, default=64)
     ap.add_argument("--streams", type=int, default=8)
     ap.add_argument("--out", default=None)
+    ap.add_argument("--wait-stdin", action="store_true",
+                    help="start only after a line arrives on stdin (exit at end of input)")
     a = ap.parse_args(argv)
+    if a.wait_stdin and not sys.stdin.readline():
+        return
     res = run(a.footprint_gb, a.warmup, a.measured, a.distinct, a.budget_mb, a.max_inflight,
               a.streams, log=lambda m: print(m, file=sys.stderr, flush=True))
     line = json.dumps(res)
