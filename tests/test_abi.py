@@ -68,6 +68,22 @@ def test_table_bytes_and_argument_checks(lib):
     assert lib.ct_pool_bytes(1000, C.byref(nb)) == ct.CT_OK and nb.value >= 4000
     assert lib.ctr_copy(None, None, 16, None) == ct.CT_E_INVALID
     assert lib.ct_status_str(ct.CT_E_FULL) == b"capacity exhausted"
+    # the resize, selection, deque-front and device-side entry points check their arguments too
+    cnt = C.c_int64(0)
+    assert lib.ct_table_rehash(None, None, None) == ct.CT_E_INVALID
+    assert lib.ct_select_key_range(None, 0, 1, None, None, 0, C.byref(cnt), None) == ct.CT_E_INVALID
+    lo3 = (C.c_int32 * 3)(0, 0, 0)
+    assert lib.ct_select_voxel_box(None, lo3, lo3, None, None, 0, C.byref(cnt), None) == ct.CT_E_INVALID
+    assert lib.ct_pool_pop_front_batch(None, 1, None, None, None) == ct.CT_E_INVALID
+    assert lib.ct_pool_push_front_batch(None, None, 1, None, None) == ct.CT_E_INVALID
+    buf = (C.c_uint8 * 4096)()
+    assert lib.ct_table_device_view(None, 0, buf, 4096) == ct.CT_E_INVALID
+    assert lib.ct_pool_device_view(None, buf, 4096) == ct.CT_E_INVALID
+    assert lib.ct_dev_apply(None, ct.OP_INSERT, None, None, 1, None, None, None) == ct.CT_E_INVALID
+    assert lib.ct_dev_pool_apply(None, 0, None, 1, None, None, None) == ct.CT_E_INVALID
+    assert lib.ct_voxel_insert_neighbours(None, None, 1, 6, None) == ct.CT_E_INVALID
+    assert lib.ct_voxel_insert_neighbours_alloc(None, None, None, 1, 6, None) == ct.CT_E_INVALID
+    assert lib.ct_table_dedup_skewed(None, None, None) == ct.CT_E_INVALID
 
 
 def test_product_path_does_not_reach_the_oracle():
