@@ -80,6 +80,28 @@ def neighbour_update(res_keys: torch.Tensor, dev, reps: int = 3) -> dict:
             "batch_Mreq_s": req / float(np.median(t_batch)) / 1e6}
 
 
+def one_call_frames(t, cap, res_keys, frames, dev, size, reps: int = 2) -> dict:
+    """The same frames as one insert_alloc of the whole query each: a present block reports its
+    value, a missing one takes the next pool index, in query order, which is what find, selecting
+    the misses and insert_alloc of them give (so the final table is the same), with no host round
+    trip for the miss count.  Per-frame wall time after one warm-up pass."""
+    ms = []
+    for rep in range(reps + 1):
+        t.clear()
+        pool = ct.Pool(cap, device=dev)
+        t.insert_alloc(pool, res_keys)
+        torch.cuda.synchronize()
+        for q in frames:
+            w0 = time.perf_counter()
+            t.insert_alloc(pool, q)
+            torch.cuda.synchronize()
+            if rep > 0:
+                ms.append((time.perf_counter() - w0) * 1e3)
+    assert t.size() == size
+    return {"frames_timed": len(ms), "frame_p50_ms": float(np.percentile(ms, 50)),
+            "frame_p99_ms": float(np.percentile(ms, 99))}
+
+
 def run(repeats: int = 3, seed: int = 2, log=print) -> dict:
     dev = torch.device("cuda", 0)
     w = voxel_blocks(seed=seed)
@@ -132,6 +154,7 @@ def run(repeats: int = 3, seed: int = 2, log=print) -> dict:
         sel.append(e0.elapsed_time(e1) * 1e-3)
     sel_s = float(np.median(sel))
     nbr = neighbour_update(res_keys, dev)
+    one = one_call_frames(t, cap, res_keys, frames, dev, size)
     out = {
         "workload": (f"voxel blocks: {w['residents'].size} residents, 2^21 buckets, spatial hash, "
                      f"{len(frames)} frames of find 2^18 (90% hits) + insert_alloc of the misses"),
@@ -142,6 +165,7 @@ def run(repeats: int = 3, seed: int = 2, log=print) -> dict:
         "insert_alloc_Mkeys_s": n_ins / ins_s / 1e6,
         "final_size": size,
         "neighbour_update": nbr,
+        "one_call_frames": one,
         "select_box": {"selected": int(cnt.value), "ms": sel_s * 1e3,
                        "table_GB_s": nb * 128 / sel_s / 1e9,
                        "note": "octant x, y, z >= 0 of the final table; the call's time, its "
@@ -150,6 +174,8 @@ def run(repeats: int = 3, seed: int = 2, log=print) -> dict:
     log(f"[voxel] neighbour update of {nbr['blocks']} blocks ({nbr['new_blocks']} new): device "
         f"API {nbr['device_api_ms']:.2f} ms ({nbr['device_api_Mreq_s']:.0f} Mreq/s), batch insert "
         f"{nbr['batch_insert_ms']:.2f} ms + keys {nbr['batch_keys_ms']:.2f} ms")
+    log(f"[voxel] frames as one insert_alloc each: p50 {one['frame_p50_ms']:.3f} ms p99 "
+        f"{one['frame_p99_ms']:.3f} ms")
     log(f"[voxel] select box: {out['select_box']['selected']} blocks in "
         f"{out['select_box']['ms']:.3f} ms ({out['select_box']['table_GB_s']:.0f} GB/s of table)")
     log(f"[voxel] p50 {out['frame_p50_ms']:.3f} ms p99 {out['frame_p99_ms']:.3f} ms, find "
