@@ -93,6 +93,8 @@ def parse():
     ap.add_argument("--no-voxel", action="store_true", help="skip the voxel-block frames")
     ap.add_argument("--no-pool", action="store_true", help="skip the index-pool operations")
     ap.add_argument("--no-rehash", action="store_true", help="skip the resize (rehash) figure")
+    ap.add_argument("--no-mixed", action="store_true",
+                    help="skip the mixed device-side operations figure")
     ap.add_argument("--no-find-uniform", action="store_true",
                     help="skip the uniform-popularity find (counter runs keep to the step's kernels)")
     ap.add_argument("--serve-footprint-gb", type=float, default=40.0)
@@ -303,6 +305,66 @@ def rehash_leg(table, K_re, V_re):
         f"{out['Mpairs_s']:.0f} Mpairs/s")
     del dst
     torch.cuda.empty_cache()
+    return out
+
+
+def mixed_device_leg(table, K_re, V_re, n=1 << 24):
+    """Device-side operations of mixed kinds in one kernel (ct_dev_apply_mixed) on the table as the
+    step leaves it (2^26 live pairs at load 0.8): n elements, 70% finds of resident keys, 20%
+    inserts of fresh keys, 10% erases of other resident keys, in random order.  Every status is
+    fixed by the workload and checked.  The same three operations are then timed as three batches
+    of the batch path, on the same table state (the mixed call undone first)."""
+    import torch
+    from paper_1908_05936_amd import ct
+
+    dev = table.device
+    n_er, n_ins = n // 10, n // 5
+    n_find = n - n_er - n_ins
+    g = torch.Generator(device=dev)
+    g.manual_seed(13)
+    er = K_re[:n_er]
+    er_v = V_re[:n_er]
+    fq = K_re[n_er:][torch.randint(0, K_re.numel() - n_er, (n_find,), device=dev, generator=g)]
+    fresh = torch.randint(-(1 << 62), 1 << 62, (n_ins,), device=dev, generator=g)
+    keys = torch.cat([fq, fresh, er])
+    ops = torch.cat([torch.full((n_find,), ct.OP_FIND, dtype=torch.uint8, device=dev),
+                     torch.full((n_ins,), ct.OP_INSERT, dtype=torch.uint8, device=dev),
+                     torch.full((n_er,), ct.OP_ERASE, dtype=torch.uint8, device=dev)])
+    perm = torch.randperm(n, device=dev, generator=g)
+    keys, ops = keys[perm].contiguous(), ops[perm].contiguous()
+    vals = keys.clone()
+    n0 = table.size()
+    wk = fq[:64].clone()
+    table.dev_apply_mixed(torch.full((64,), ct.OP_FIND, dtype=torch.uint8, device=dev), wk, wk)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    st, _ = table.dev_apply_mixed(ops, keys, vals)
+    e1.record()
+    torch.cuda.synchronize()
+    sec = e0.elapsed_time(e1) * 1e-3
+    assert bool((st == 1).all()), "every find hits, every fresh key is INSERTED, every erase hits"
+    assert table.size() == n0 + n_ins - n_er
+    # undo, then the batch path on the same state
+    table.erase(fresh)
+    table.insert(er, er_v)
+    assert table.size() == n0
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    ev[0].record()
+    v, f = table.find(fq)
+    ev[1].record()
+    table.insert(fresh, fresh)
+    ev[2].record()
+    table.erase(er)
+    ev[3].record()
+    torch.cuda.synchronize()
+    bsec = ev[0].elapsed_time(ev[3]) * 1e-3
+    assert bool(f.all()) and table.size() == n0 + n_ins - n_er
+    out = {"n": n, "mix": "70% find / 20% insert / 10% erase", "ms": sec * 1e3,
+           "Mops_s": n / sec / 1e6, "batch_path_ms": bsec * 1e3, "batch_path_Mops_s": n / bsec / 1e6}
+    log(f"[mixed device ops] {n} in one kernel: {out['ms']:.2f} ms, {out['Mops_s']:.0f} Mops/s; "
+        f"as three batches {out['batch_path_ms']:.2f} ms")
     return out
 
 
@@ -543,6 +605,8 @@ def main():
     log(f"marginal insert of 2^20 fresh keys at load 0.8: {line['insert_marginal_Mops_s']:.0f} Mops/s")
     if not a.no_rehash:
         line["rehash"] = rehash_leg(table, K_re, V_re)
+    if not a.no_mixed:
+        line["mixed_device_ops"] = mixed_device_leg(table, K_re, V_re)
     if not a.no_find_uniform:
         line["find_uniform_Mops_s"] = find_uniform(op_clear, op_fill, dev, K_fill, n_fill, n_find,
                                                    n_present_expected, L, h, s, vals_out, found)

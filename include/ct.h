@@ -190,12 +190,14 @@ ct_status ct_table_rehash(ct_table *src, ct_table *dst, void *stream);
 #define CT_DEV_READ 0   /* find / contains only */
 #define CT_DEV_INSERT 1 /* insert, find, contains; the same key from several threads allowed */
 #define CT_DEV_ERASE 2  /* erase, find, contains */
+#define CT_DEV_MIXED 3  /* insert, erase, find, contains together; erases leave tombstones only */
 
 /* Fill `out` (at least `bytes` bytes, host memory) with the by-value view a user kernel passes to
    the device functions of paper_1908_05936_amd/csrc/ct_dev_api.h (dev_insert, dev_erase,
-   dev_find, dev_contains), for one kernel that uses the table in `mode`.  Inserts and erases never
-   share a kernel; within a mode every operation may run concurrently from any thread (the header
-   states the guarantees).  Host only; CT_E_INVALID if `bytes` is too small. */
+   dev_find, dev_contains), for one kernel that uses the table in `mode`.  Inserts and erases share
+   a kernel only in CT_DEV_MIXED; within a mode every operation may run concurrently from any
+   thread (the header states the guarantees).  Host only; CT_E_INVALID if `bytes` is too small or
+   `mode` unknown. */
 ct_status ct_table_device_view(ct_table *t, int32_t mode, void *out, int64_t bytes);
 
 /* The reference user kernel of the device functions: element i of keys[n] is handled by one
@@ -206,6 +208,20 @@ ct_status ct_table_device_view(ct_table *t, int32_t mode, void *out, int64_t byt
    nullable.  Asynchronous on `stream`. */
 ct_status ct_dev_apply(ct_table *t, int32_t op, const uint64_t *keys, const void *vals, int64_t n,
                        void *vals_out, uint8_t *status, void *stream);
+
+/* The same reference kernel in CT_DEV_MIXED (Section 4: concurrency across all operations):
+   element i does operation ops[i] (device array of CT_OP_INSERT / CT_OP_FIND / CT_OP_ERASE) on
+   keys[i], every element concurrently, the same key under several operations included.  vals
+   (device, the table's value width; required for a map) is read at insert elements; status[i] as
+   in ct_dev_apply for the element's operation, 255 for an unknown code (the table untouched);
+   vals_out[i] (nullable) holds the found value at find elements and the absent sentinel
+   elsewhere.  Per key, INSERTED results and successful erases alternate, starting from the key's
+   state before the kernel.  Erases leave tombstones, which later batch inserts reuse.  The live
+   count is exact when the kernel ends; at capacity it can pass the capacity by the number of
+   keys that an erase removed between their insert's claim and its count.  Asynchronous on
+   `stream`. */
+ct_status ct_dev_apply_mixed(ct_table *t, const uint8_t *ops, const uint64_t *keys, const void *vals,
+                             int64_t n, void *vals_out, uint8_t *status, void *stream);
 
 /* Neighbour update of a voxel-block map through the device functions (the allocation step of the
    reconstruction workload behind Section 4.1's block map): every packed block of blocks[n] makes

@@ -15,24 +15,43 @@
 //   kDevErase   erase, find and contains: each present key is removed once (exactly one of its
 //               erasers sees true).  An erase leaves an empty slot only where its bucket already
 //               had one, so no probe sequence that passed the bucket is cut short.
+//   kDevMixed   insert, erase, find and contains in one kernel, the same key from several threads
+//               and by several operations included.  A slot only ever goes empty -> key ->
+//               tombstone: inserts claim only empty slots and erases always leave tombstones, so
+//               the argument of kDevInsert still holds and a key is live in at most one slot.
+//               Each insert and erase takes effect at one compare-and-swap, so per key the
+//               INSERTED results and the successful erases alternate.  Tombstones accumulate:
+//               once no probe sequence of a key reaches an empty slot, its insert reports FULL.
 //
-// Inserts and erases never share a kernel.  The live count stays exact throughout: the thread
-// that stores a new key takes one unit of capacity (one atomic add per wave) after its claim;
-// with none left it takes the key out again (a tombstone) and reports FULL, so FULL means the
-// table held its capacity.  Near capacity, a concurrent thread may see such a key for that moment.
-// Key words are read with agent-scope atomic loads, which see other compute units' claims.
+// The thread that stores a new key takes one unit of capacity (one atomic add per wave) after its
+// claim; with none left it takes the key out again (a tombstone) and reports FULL, so FULL means
+// the table held its capacity.  Near capacity, a concurrent thread may see such a key for that
+// moment.  The live count is exact once the kernel ends.  In kDevMixed an erase may remove a key
+// between its claim and its unit and return a unit that was not taken yet; the inserter then
+// makes up for it, and a third insert may have used that unit in between, so at capacity the
+// count can pass the capacity by the number of such races.  Key words are read with agent-scope
+// atomic loads, which see other compute units' claims.
 #pragma once
 
 #include "ct_device.h"
 
 namespace ct {
 
-enum : int32_t { kDevRead = 0, kDevInsert = 1, kDevErase = 2 };
+enum : int32_t { kDevRead = 0, kDevInsert = 1, kDevErase = 2, kDevMixed = 3 };
+
+// Live-count striping: a launch that cannot meet the capacity (the host or a set-up kernel has
+// shown that the live count plus every insert it may make fits) counts its changes into
+// kStripes words of the table's partial-count array, 128 bytes apart and picked by workgroup,
+// instead of all into the header's one word, whose atomics would serialise; a fold kernel adds
+// them to the live count after the launch.  Views handed to user kernels never stripe.
+constexpr int kStripes = 64;
+constexpr int kStripeStride = 16;                        // int64 words: 128 bytes
+constexpr int kStripeFlag = kStripes * kStripeStride;    // word set by the set-up kernel
 
 struct DevView {
   TableView t;
   int32_t mode;
-  int32_t pad;
+  int32_t striped;  // 1: count into the stripes, no capacity checks
 };
 
 __device__ __forceinline__ uint64_t dev_key(const TableView& t, uint64_t pos) {
@@ -46,11 +65,17 @@ __device__ __forceinline__ uint64_t dev_probe(const TableView& t, uint64_t key, 
                                               uint64_t b, int c0, uint64_t* empty) {
   *empty = kNoPos;
   for (uint64_t r = 0; r < t.nb; ++r) {
+    // the bucket's eight key words in flight together, then the scan: the order of the reads
+    // within a bucket does not matter, since a slot never returns to a state it has left
+    uint64_t kk[kSlots];
+#pragma unroll
+    for (int c = 0; c < kSlots; ++c) kk[c] = dev_key(t, b * kSlots + (uint64_t)c);
     bool end = false;
-    for (int c = c0; c < kSlots; ++c) {
-      const uint64_t k = dev_key(t, b * kSlots + (uint64_t)c);
-      if (k == key) return b * kSlots + (uint64_t)c;
-      if (k == kEmpty && !end) {
+#pragma unroll
+    for (int c = 0; c < kSlots; ++c) {
+      if (c < c0) continue;
+      if (kk[c] == key) return b * kSlots + (uint64_t)c;
+      if (kk[c] == kEmpty && !end) {
         end = true;
         if (*empty == kNoPos) *empty = b * kSlots + (uint64_t)c;
       }
@@ -62,12 +87,37 @@ __device__ __forceinline__ uint64_t dev_probe(const TableView& t, uint64_t key, 
   return kNoPos;
 }
 
+// The wave's lanes that reach this call add `sign` each to the live count (or to their stripe).
+__device__ __forceinline__ void dev_count_add(const DevView& v, int64_t sign) {
+  const uint64_t m = __ballot(1);
+  if (wave_lane() == __builtin_ctzll(m)) {
+    const int64_t d = sign * (int64_t)__builtin_popcountll(m);
+    if (v.striped)
+      __hip_atomic_fetch_add(&v.t.bcnt[(blockIdx.x % kStripes) * kStripeStride], d,
+                             __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    else
+      __hip_atomic_fetch_add(&v.t.hdr->size, (uint64_t)d, __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+// Every lane that reaches this call adds one to the live count, whatever the capacity.
+__device__ __forceinline__ void dev_count(const DevView& v) { dev_count_add(v, 1); }
+
+// Every lane that reaches this call takes one from the live count: one atomic per wave.
+__device__ __forceinline__ void dev_uncount(const DevView& v) { dev_count_add(v, -1); }
+
 // Capacity for the lanes of the wave that arrive together: one fetch-and-add of their number on
 // the live count (a compare-and-swap loop on that one address made the waves retry each other
 // for seconds), then the leader gives back what lies beyond the capacity.  The adds order all
 // reservations, and lane r of a wave holds position old + r: exactly the positions below the
 // capacity are granted, however the adds and give-backs interleave.
-__device__ __forceinline__ bool dev_reserve(const TableView& t) {
+__device__ __forceinline__ bool dev_reserve(const DevView& v) {
+  if (v.striped) {  // the launch cannot meet the capacity
+    dev_count(v);
+    return true;
+  }
+  const TableView& t = v.t;
   const uint64_t m = __ballot(1);
   const int leader = __builtin_ctzll(m);
   const uint32_t rank = (uint32_t)__builtin_popcountll(m & ((1ull << wave_lane()) - 1ull));
@@ -83,12 +133,67 @@ __device__ __forceinline__ bool dev_reserve(const TableView& t) {
   return old + rank < t.cap;
 }
 
-// Every lane that reaches this call takes one from the live count: one atomic per wave.
-__device__ __forceinline__ void dev_uncount(const TableView& t) {
-  const uint64_t m = __ballot(1);
-  if (wave_lane() == __builtin_ctzll(m))
-    __hip_atomic_fetch_sub(&t.hdr->size, (uint64_t)__builtin_popcountll(m), __ATOMIC_RELAXED,
-                           __HIP_MEMORY_SCOPE_AGENT);
+// The insert of kDevMixed: claim, then capacity, as in kDevInsert.  An erase may remove the key
+// between the two and return a unit the insert has not taken yet; the insert sees that when it
+// takes its unit or tries to take the key back, and then leaves the count as the erase expects
+// (one unit for a key that lived and was erased, so INSERTED).  The value of an out-of-band key
+// that is inserted, erased and inserted again within one kernel is that of one of its inserts.
+template <class Take>
+__device__ inline uint8_t dev_insert_mixed(const DevView& v, uint64_t key, Take take) {
+  const TableView& t = v.t;
+  if (key >= kTomb) {
+    const int s = (int)(key - kTomb);
+    uint32_t* live = &t.hdr->spec_live[s];
+    uint32_t expected = 0;
+    if (!__hip_atomic_compare_exchange_strong(live, &expected, 1u, __ATOMIC_RELAXED,
+                                              __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+      return kPresent;
+    uint64_t val = 0;
+    const bool unit = dev_reserve(v);
+    if (!unit || !take(&val)) {
+      expected = 1;
+      if (__hip_atomic_compare_exchange_strong(live, &expected, 0u, __ATOMIC_RELAXED,
+                                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+        if (unit) dev_uncount(v);
+        return kFull;
+      }
+      if (!unit) dev_count(v);  // erased after the claim: that erase returned this unit
+      return kInserted;
+    }
+    t.hdr->spec_val[s] = val;
+    return kInserted;
+  }
+  const Seq sq = probe_seq(t, key);
+  uint64_t empty;
+  if (dev_probe(t, key, sq, sq.home, 0, &empty) != kNoPos) return kPresent;
+  for (;;) {
+    if (empty == kNoPos) return kFull;  // no empty slot left on the key's sequence
+    uint64_t* kw = &t.bk[empty >> 3].s[empty & 7].key;
+    uint64_t expected = kEmpty;
+    if (cas64(kw, expected, key)) {
+      uint64_t val = 0;
+      const bool unit = dev_reserve(v);
+      if (!unit || !take(&val)) {
+        expected = key;
+        if (cas64(kw, expected, kTomb)) {
+          if (unit) dev_uncount(v);
+          return kFull;
+        }
+        if (!unit) dev_count(v);  // erased after the claim: that erase returned this unit
+        return kInserted;
+      }
+      t.bk[empty >> 3].s[empty & 7].val = val;
+      return kInserted;
+    }
+    if (expected == key) return kPresent;
+    uint64_t b = empty >> 3;
+    int c = (int)(empty & 7) + 1;
+    if (c == kSlots) {
+      c = 0;
+      b = next_bucket(t, b, sq.step);
+    }
+    if (dev_probe(t, key, sq, b, c, &empty) != kNoPos) return kPresent;
+  }
 }
 
 // The insert, with the stored value produced after the claim: `take(&value)` runs once the thread
@@ -99,6 +204,7 @@ __device__ __forceinline__ void dev_uncount(const TableView& t) {
 template <class Take>
 __device__ inline uint8_t dev_insert_with(const DevView& v, uint64_t key, Take take) {
   const TableView& t = v.t;
+  if (v.mode == kDevMixed) return dev_insert_mixed(v, key, take);
   if (key >= kTomb) {  // out-of-band keys live in the header
     const int s = (int)(key - kTomb);
     uint32_t expected = 0;
@@ -106,12 +212,12 @@ __device__ inline uint8_t dev_insert_with(const DevView& v, uint64_t key, Take t
                                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
       return kPresent;
     uint64_t val = 0;
-    if (!dev_reserve(t)) {
+    if (!dev_reserve(v)) {
       __hip_atomic_store(&t.hdr->spec_live[s], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       return kFull;
     }
     if (!take(&val)) {
-      dev_uncount(t);
+      dev_uncount(v);
       __hip_atomic_store(&t.hdr->spec_live[s], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       return kFull;
     }
@@ -127,12 +233,12 @@ __device__ inline uint8_t dev_insert_with(const DevView& v, uint64_t key, Take t
     uint64_t expected = kEmpty;
     if (cas64(kw, expected, key)) {
       uint64_t val = 0;
-      if (!dev_reserve(t)) {
+      if (!dev_reserve(v)) {
         __hip_atomic_store(kw, kTomb, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         return kFull;
       }
       if (!take(&val)) {
-        dev_uncount(t);
+        dev_uncount(v);
         __hip_atomic_store(kw, kTomb, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         return kFull;
       }
@@ -167,19 +273,20 @@ __device__ inline bool dev_erase(const DevView& v, uint64_t key) {
     if (!__hip_atomic_compare_exchange_strong(&t.hdr->spec_live[s], &expected, 0u, __ATOMIC_RELAXED,
                                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
       return false;
-    dev_uncount(t);
+    dev_uncount(v);
     return true;
   }
   const Seq sq = probe_seq(t, key);
   uint64_t empty;
   const uint64_t pos = dev_probe(t, key, sq, sq.home, 0, &empty);
   if (pos == kNoPos) return false;
-  // an empty slot only where the bucket already holds one
+  // an empty slot only where the bucket already holds one, and never while inserts run
   bool has_empty = false;
-  for (int c = 0; c < kSlots; ++c) has_empty |= dev_key(t, (pos & ~7ull) + (uint64_t)c) == kEmpty;
+  if (v.mode != kDevMixed)
+    for (int c = 0; c < kSlots; ++c) has_empty |= dev_key(t, (pos & ~7ull) + (uint64_t)c) == kEmpty;
   uint64_t expected = key;
   if (!cas64(&t.bk[pos >> 3].s[pos & 7].key, expected, has_empty ? kEmpty : kTomb)) return false;
-  dev_uncount(t);
+  dev_uncount(v);
   return true;
 }
 

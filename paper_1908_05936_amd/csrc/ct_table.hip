@@ -1418,16 +1418,47 @@ __global__ __launch_bounds__(kBlock) void k_sel_write(TableView t, Pred pred, in
   }
 }
 
+// Set-up and fold of a striped launch of the reference kernels below: zero the stripes and decide
+// whether the launch can meet the capacity (the live count plus `maxins` inserts), then add the
+// stripes to the live count.  The decision is one word that every wave of the launch reads.
+__global__ __launch_bounds__(64) void k_dev_prep(TableView t, uint64_t maxins) {
+  t.bcnt[threadIdx.x * kStripeStride] = 0;
+  if (threadIdx.x == 0) {
+    const uint64_t n = t.hdr->size;
+    t.bcnt[kStripeFlag] = (n <= t.cap && maxins <= t.cap - n) ? 1 : 0;
+  }
+}
+
+__global__ __launch_bounds__(64) void k_dev_fold(TableView t) {
+  if (!t.bcnt[kStripeFlag]) return;
+  const uint64_t s = wave_sum((uint64_t)t.bcnt[threadIdx.x * kStripeStride]);
+  if (threadIdx.x == 0) t.hdr->size += s;
+}
+
 // Per-thread operations through the device-side API (ct_dev_api.h): element i is handled by one
 // thread, all concurrently and in no particular order.  The reference user kernel, and what the
-// tests drive the device API with.
-__global__ __launch_bounds__(kBlock) void k_dev_apply(DevView v, int32_t op, const uint64_t* __restrict__ keys,
+// tests drive the device API with.  With `ops`, element i does operation ops[i] (mixed mode); an
+// unknown code leaves the table alone and reports kNoStatus.
+__global__ __launch_bounds__(kBlock) void k_dev_apply(DevView v, int32_t op, const uint8_t* __restrict__ ops,
+                                                      const uint64_t* __restrict__ keys,
                                                       const void* __restrict__ vals, int32_t vk,
                                                       int64_t n, void* __restrict__ vout,
                                                       uint8_t* __restrict__ status) {
+  if (v.striped) v.striped = (int32_t)v.t.bcnt[kStripeFlag];
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x) {
     const uint64_t key = keys[i];
+    if (ops) {
+      op = ops[i];
+      if (vout && op != CT_OP_FIND) {
+        if (vk == 2) static_cast<uint64_t*>(vout)[i] = ~0ull;
+        else if (vk == 1) static_cast<uint32_t*>(vout)[i] = ~0u;
+      }
+      if (op != CT_OP_INSERT && op != CT_OP_ERASE && op != CT_OP_FIND) {
+        if (status) status[i] = kNoStatus;
+        continue;
+      }
+    }
     if (op == CT_OP_INSERT) {
       const uint64_t val = vk == 2 ? static_cast<const uint64_t*>(vals)[i]
                            : vk == 1 ? (uint64_t)static_cast<const uint32_t*>(vals)[i] : 0ull;
@@ -1457,6 +1488,7 @@ template <bool ALLOC>
 __global__ __launch_bounds__(kBlock) void k_voxel_neighbours(DevView v, DevPool pool,
                                                              const uint64_t* __restrict__ blocks,
                                                              int64_t n, int32_t ndirs) {
+  if (v.striped) v.striped = (int32_t)v.t.bcnt[kStripeFlag];
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x) {
     const uint64_t b = blocks[i];
@@ -2335,14 +2367,14 @@ ct_status ct_clear(ct_table* t, void* stream) {
 }
 
 ct_status ct_table_device_view(ct_table* t, int32_t mode, void* out, int64_t bytes) {
-  if (!t || !out || bytes < (int64_t)sizeof(DevView) || mode < kDevRead || mode > kDevErase)
+  if (!t || !out || bytes < (int64_t)sizeof(DevView) || mode < kDevRead || mode > kDevMixed)
     return CT_E_INVALID;
   DevView v{};
   v.t = t->v;
   v.mode = mode;
   std::memcpy(out, &v, sizeof(v));
   // device inserts grow the table behind the host's back
-  if (mode == kDevInsert) t->size_ub = (uint64_t)t->desc.capacity;
+  if (mode == kDevInsert || mode == kDevMixed) t->size_ub = (uint64_t)t->desc.capacity;
   return CT_OK;
 }
 
@@ -2358,7 +2390,29 @@ ct_status ct_dev_apply(ct_table* t, int32_t op, const uint64_t* keys, const void
   v.mode = op == CT_OP_INSERT ? kDevInsert : op == CT_OP_ERASE ? kDevErase : kDevRead;
   if (op == CT_OP_INSERT)
     t->size_ub = std::min<uint64_t>(t->size_ub + (uint64_t)n, (uint64_t)t->desc.capacity);
-  k_dev_apply<<<flat_blocks(n), kBlock, 0, S(stream)>>>(v, op, keys, vals, vk, n, vals_out, status);
+  v.striped = op != CT_OP_FIND;
+  if (v.striped) k_dev_prep<<<1, kStripes, 0, S(stream)>>>(t->v, op == CT_OP_INSERT ? (uint64_t)n : 0);
+  k_dev_apply<<<flat_blocks(n), kBlock, 0, S(stream)>>>(v, op, nullptr, keys, vals, vk, n, vals_out,
+                                                        status);
+  if (v.striped) k_dev_fold<<<1, kStripes, 0, S(stream)>>>(t->v);
+  return launched();
+}
+
+ct_status ct_dev_apply_mixed(ct_table* t, const uint8_t* ops, const uint64_t* keys, const void* vals,
+                             int64_t n, void* vals_out, uint8_t* status, void* stream) {
+  if (!t || n < 0 || (n > 0 && (!keys || !ops))) return CT_E_INVALID;
+  const int32_t vk = t->desc.val_kind;
+  if (vk != CT_VAL_NONE && n > 0 && !vals) return CT_E_INVALID;
+  if (n == 0) return CT_OK;
+  DevView v{};
+  v.t = t->v;
+  v.mode = kDevMixed;
+  t->size_ub = std::min<uint64_t>(t->size_ub + (uint64_t)n, (uint64_t)t->desc.capacity);
+  v.striped = 1;
+  k_dev_prep<<<1, kStripes, 0, S(stream)>>>(t->v, (uint64_t)n);
+  k_dev_apply<<<flat_blocks(n), kBlock, 0, S(stream)>>>(v, CT_OP_FIND, ops, keys, vals, vk, n,
+                                                        vals_out, status);
+  k_dev_fold<<<1, kStripes, 0, S(stream)>>>(t->v);
   return launched();
 }
 
@@ -2372,7 +2426,10 @@ ct_status ct_voxel_insert_neighbours(ct_table* t, const uint64_t* blocks, int64_
   v.mode = kDevInsert;
   t->size_ub = std::min<uint64_t>(t->size_ub + (uint64_t)n * (uint64_t)ndirs,
                                   (uint64_t)t->desc.capacity);
+  v.striped = 1;
+  k_dev_prep<<<1, kStripes, 0, S(stream)>>>(t->v, (uint64_t)n * (uint64_t)ndirs);
   k_voxel_neighbours<false><<<flat_blocks(n), kBlock, 0, S(stream)>>>(v, DevPool{}, blocks, n, ndirs);
+  k_dev_fold<<<1, kStripes, 0, S(stream)>>>(t->v);
   return launched();
 }
 
@@ -2386,8 +2443,11 @@ ct_status ct_voxel_insert_neighbours_alloc(ct_table* t, ct_pool* p, const uint64
   v.mode = kDevInsert;
   t->size_ub = std::min<uint64_t>(t->size_ub + (uint64_t)n * (uint64_t)ndirs,
                                   (uint64_t)t->desc.capacity);
+  v.striped = 1;
+  k_dev_prep<<<1, kStripes, 0, S(stream)>>>(t->v, (uint64_t)n * (uint64_t)ndirs);
   k_voxel_neighbours<true><<<flat_blocks(n), kBlock, 0, S(stream)>>>(v, DevPool{p->hdr, p->stack},
                                                                      blocks, n, ndirs);
+  k_dev_fold<<<1, kStripes, 0, S(stream)>>>(t->v);
   return launched();
 }
 

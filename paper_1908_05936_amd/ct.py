@@ -72,6 +72,7 @@ SIGNATURES = {
     "ct_table_rehash": (C.c_int, [_P, _P, _P]),
     "ct_table_device_view": (C.c_int, [_P, _I32, _P, _I64]),
     "ct_dev_apply": (C.c_int, [_P, _I32, _P, _P, _I64, _P, _P, _P]),
+    "ct_dev_apply_mixed": (C.c_int, [_P, _P, _P, _P, _I64, _P, _P, _P]),
     "ct_voxel_insert_neighbours": (C.c_int, [_P, _P, _I64, _I32, _P]),
     "ct_voxel_insert_neighbours_alloc": (C.c_int, [_P, _P, _P, _I64, _I32, _P]),
     "ct_pool_device_view": (C.c_int, [_P, _P, _I64]),
@@ -394,6 +395,27 @@ class Table:
         _check(lib().ct_dev_apply(self._h, int(op), _ptr(keys),
                                   _ptr(vals) if op == OP_INSERT and self.value_kind else None, n,
                                   _ptr(out), _ptr(st), _stream(self.device)), "ct_dev_apply")
+        return st, out
+
+    def dev_apply_mixed(self, ops: torch.Tensor, keys: torch.Tensor,
+                        vals: torch.Tensor | None = None):
+        """Per-thread operations of mixed kinds in one kernel: element i does ops[i] (OP_INSERT /
+        OP_FIND / OP_ERASE, uint8) on keys[i], all concurrently.  Returns (status, values or
+        None); values hold found values at find elements and the sentinel elsewhere."""
+        n = keys.numel()
+        _need(keys, torch.int64, None, "keys", self.device)
+        _need(ops, torch.uint8, n, "ops", self.device)
+        if self.value_kind != VAL_NONE:
+            if vals is None:
+                raise CtError("values are required for a map")
+            _need(vals, self.value_dtype, n, "vals", self.device)
+        st = torch.empty(n, dtype=torch.uint8, device=self.device)
+        out = None
+        if self.value_kind != VAL_NONE:
+            out = torch.empty(n, dtype=self.value_dtype, device=self.device)
+        _check(lib().ct_dev_apply_mixed(self._h, _ptr(ops), _ptr(keys),
+                                        _ptr(vals) if self.value_kind else None, n, _ptr(out),
+                                        _ptr(st), _stream(self.device)), "ct_dev_apply_mixed")
         return st, out
 
     def insert_neighbours(self, blocks: torch.Tensor, ndirs: int = 6):

@@ -80,6 +80,7 @@ def test_table_bytes_and_argument_checks(lib):
     assert lib.ct_table_device_view(None, 0, buf, 4096) == ct.CT_E_INVALID
     assert lib.ct_pool_device_view(None, buf, 4096) == ct.CT_E_INVALID
     assert lib.ct_dev_apply(None, ct.OP_INSERT, None, None, 1, None, None, None) == ct.CT_E_INVALID
+    assert lib.ct_dev_apply_mixed(None, None, None, None, 1, None, None, None) == ct.CT_E_INVALID
     assert lib.ct_dev_pool_apply(None, 0, None, 1, None, None, None) == ct.CT_E_INVALID
     assert lib.ct_voxel_insert_neighbours(None, None, 1, 6, None) == ct.CT_E_INVALID
     assert lib.ct_voxel_insert_neighbours_alloc(None, None, None, 1, 6, None) == ct.CT_E_INVALID

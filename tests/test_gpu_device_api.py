@@ -225,3 +225,171 @@ def test_voxel_neighbour_update_with_pool(dev):
     allv = np.concatenate([v.astype(np.int64), left.astype(np.int64)])
     np.testing.assert_array_equal(np.sort(allv), np.arange(cap))
     assert pool.size() == cap - len(want)
+
+
+@pytest.mark.parametrize("bits", [64, 32, 0])
+def test_mixed_operations_in_one_kernel(dev, bits):
+    """Inserts, erases and finds in one kernel, the same key under several operations included
+    (Section 4: concurrency across all operations).  Per key, the INSERTED results and the
+    successful erases must alternate from the key's state before the kernel; that fixes which
+    keys are live afterwards, and the oracle, given the same changes in an order the statuses
+    allow, must then hold the same contents.  Keys touched by one operation kind only are checked
+    element by element."""
+    rng = rng_for(107, bits)
+    vk = {0: ct.VAL_NONE, 32: ct.VAL_U32, 64: ct.VAL_U64}[bits]
+    cap = 200_000
+    t = ct.Table(cap, vk, device=dev)
+    o = oracle.OracleTable(cap, bits, oracle.HASH_MIX64, cap)
+    base = np.concatenate([distinct_u64(rng, 60_000), np.array([U64MAX - 1], np.uint64)])
+    bv = rng.integers(0, 1 << 31, size=base.size, dtype=np.uint64)
+    if bits:
+        t.insert(g64(base, dev), torch.from_numpy(bv.astype(np.int64)).to(dev).to(t.value_dtype))
+    else:
+        t.insert(g64(base, dev))
+    o.insert(base, bv if bits else None)
+    orig = dict(zip(base.tolist(), bv.tolist()))
+    fresh = np.concatenate([distinct_u64(rng, 40_000, exclude=base), np.array([U64MAX], np.uint64)])
+    rng.shuffle(base[:-1])
+    P = {"A": base[:8000], "A2": base[8000:12000], "C": base[12000:20000], "E": base[20000:24000],
+         "H": np.concatenate([base[24000:26000], base[-1:]])}
+    Q = {"B": fresh[:8000], "D": fresh[8000:12000], "H": np.concatenate([fresh[12000:14000], fresh[-1:]]),
+         "F": fresh[14000:20000]}
+    I, F, E = ct.OP_INSERT, ct.OP_FIND, ct.OP_ERASE
+    plan = [(P["A"], [E]), (P["A2"], [E, E, E]), (P["C"], [F, F]), (P["E"], [E, I]),
+            (P["H"], [I] * 4 + [E] * 4 + [F] * 2), (Q["B"], [I, I, I]), (Q["D"], [I, E]),
+            (Q["H"], [I] * 4 + [E] * 4 + [F] * 2), (Q["F"], [F, E])]
+    keys = np.concatenate([np.repeat(k, len(ops)) for k, ops in plan])
+    ops = np.concatenate([np.tile(np.array(ops, np.uint8), k.size) for k, ops in plan])
+    vals = rng.integers(0, 1 << 31, size=keys.size, dtype=np.uint64)
+    perm = rng.permutation(keys.size)
+    keys, ops, vals = keys[perm], ops[perm], vals[perm]
+    gv = torch.from_numpy(vals.astype(np.int64)).to(dev).to(t.value_dtype) if bits else None
+    st, out = t.dev_apply_mixed(torch.from_numpy(ops).to(dev), g64(keys, dev), gv)
+    st = st.cpu().numpy()
+    if bits:
+        out = out.cpu().numpy().view(np.uint64 if bits == 64 else np.uint32).astype(np.uint64)
+        sentinel = U64MAX if bits == 64 else 0xFFFFFFFF
+        assert (out[ops != F] == sentinel).all()
+    assert not (st[ops == I] == 2).any()
+    assert set(np.unique(st).tolist()) <= {0, 1}
+    group = {}
+    for name, ks in list(P.items()) + list(Q.items()):
+        for k in ks.tolist():
+            group[k] = name
+    by_key = {}
+    for j, k in enumerate(keys.tolist()):
+        by_key.setdefault(k, []).append(j)
+    live_after, new_val = {}, {}
+    for k, js in by_key.items():
+        g = group[k]
+        was = k in orig
+        ins = [j for j in js if ops[j] == I and st[j] == 1]
+        hits = [j for j in js if ops[j] == E and st[j] == 1]
+        finds = [j for j in js if ops[j] == F]
+        if g in ("A", "A2"):
+            assert len(hits) == 1, (g, k)
+        elif g == "C":
+            assert all(st[j] == 1 for j in finds)
+            if bits:
+                assert all(out[j] == orig[k] for j in finds)
+        elif g == "F":
+            assert not st[js].any()
+            if bits:
+                assert all(out[j] == sentinel for j in finds)
+        elif g == "B":
+            assert len(ins) == 1
+        elif g == "D":
+            assert len(ins) == 1
+        elif g == "E":
+            assert len(hits) == 1
+        # alternation from the state before the kernel
+        d = len(ins) - len(hits)
+        assert d in ((-1, 0) if was else (0, 1)), (g, k, len(ins), len(hits))
+        live_after[k] = (was and d == 0) or (not was and d == 1)
+        if live_after[k] and ins:
+            new_val[k] = [vals[j] for j in ins]
+    # the oracle gets the same changes: every touched key erased, then the live ones inserted
+    touched = np.array(sorted(by_key), dtype=np.uint64)
+    o.erase(touched)
+    live = [k for k in by_key if live_after[k]]
+    lv = [(new_val[k][0] if k in new_val else orig[k]) for k in live]
+    o.insert(np.array(live, np.uint64), np.array(lv, np.uint64) if bits else None)
+    assert t.size() == o.size()
+    k, v = dump_sorted(t, bits)
+    ek, ev = o.dump()
+    np.testing.assert_array_equal(k, ek)
+    if bits:
+        # a key inserted several times keeps the value of one of its INSERTED elements
+        ambiguous = np.array([kk in new_val and len(new_val[kk]) > 1 for kk in k.tolist()], bool)
+        np.testing.assert_array_equal(v[~ambiguous], ev[~ambiguous])
+        mask = (1 << bits) - 1
+        for kk, vv in zip(k[ambiguous].tolist(), v[ambiguous].tolist()):
+            assert vv in [x & mask for x in new_val[kk]]
+    assert t.check() == 0
+    # the batch path reuses the tombstones the kernel left
+    again = distinct_u64(rng, 20_000, exclude=np.concatenate([base, fresh]))
+    av = again & np.uint64(0x7FFFFFFF)
+    if bits:
+        t.insert(g64(again, dev), torch.from_numpy(av.astype(np.int64)).to(dev).to(t.value_dtype))
+    else:
+        t.insert(g64(again, dev))
+    o.insert(again, av if bits else None)
+    same_keys = dump_sorted(t, bits)[0]
+    np.testing.assert_array_equal(same_keys, o.dump()[0])
+    assert t.size() == o.size() and t.check() == 0
+
+
+def test_mixed_operations_at_capacity(dev):
+    """Erases and inserts of distinct keys in one kernel on a table at capacity: every erase hits,
+    the live count never passes the capacity, exactly the INSERTED keys join the table and FULL
+    ones stay out; at least the room left before the kernel is granted."""
+    rng = rng_for(109)
+    cap = 4096
+    t = ct.Table(cap, ct.VAL_U64, device=dev)
+    base = distinct_u64(rng, 4000)
+    t.insert(g64(base, dev), g64(base, dev))
+    er = base[:1000]
+    new = distinct_u64(rng, 3000, exclude=base)
+    keys = np.concatenate([er, new])
+    ops = np.concatenate([np.full(er.size, ct.OP_ERASE, np.uint8), np.full(new.size, ct.OP_INSERT, np.uint8)])
+    perm = rng.permutation(keys.size)
+    keys, ops = keys[perm], ops[perm]
+    st, _ = t.dev_apply_mixed(torch.from_numpy(ops).to(dev), g64(keys, dev), g64(keys, dev))
+    st = st.cpu().numpy()
+    assert (st[ops == ct.OP_ERASE] == 1).all()
+    si = st[ops == ct.OP_INSERT]
+    assert set(np.unique(si).tolist()) <= {1, 2}
+    inserted = keys[ops == ct.OP_INSERT][si == 1]
+    assert cap - base.size <= inserted.size <= cap - base.size + er.size
+    expect = np.sort(np.concatenate([base[1000:], inserted]))
+    k, v = dump_sorted(t, 64)
+    np.testing.assert_array_equal(k, expect)
+    np.testing.assert_array_equal(v, expect)
+    assert t.size() == expect.size <= cap
+    assert t.check() == 0
+
+
+@pytest.mark.parametrize("copies,spread", [(3, True), (64, False)])
+def test_mixed_mode_repeated_inserts(dev, copies, spread):
+    """Inserts only, in the mixed mode: an inserter that loses its slot to another key and then
+    meets its own key further on reports PRESENT (not FULL); each key is INSERTED exactly once.
+    Copies spread over the launch, or side by side in one wavefront."""
+    rng = rng_for(113, copies)
+    t = ct.Table(200_000, ct.VAL_U64, device=dev)
+    base = distinct_u64(rng, 60_000)
+    t.insert(g64(base, dev), g64(base, dev))
+    fresh = distinct_u64(rng, 8000, exclude=base)
+    keys = np.repeat(fresh, copies)
+    if spread:
+        rng.shuffle(keys)
+    ops = torch.full((keys.size,), ct.OP_INSERT, dtype=torch.uint8, device=dev)
+    st, _ = t.dev_apply_mixed(ops, g64(keys, dev), g64(keys, dev))
+    st = st.cpu().numpy()
+    assert set(np.unique(st).tolist()) <= {0, 1}
+    ins = keys[st == 1]
+    assert ins.size == fresh.size and np.unique(ins).size == fresh.size
+    k, v = dump_sorted(t, 64)
+    expect = np.sort(np.concatenate([base, fresh]))
+    np.testing.assert_array_equal(k, expect)
+    np.testing.assert_array_equal(v, expect)
+    assert t.check() == 0
