@@ -313,7 +313,8 @@ def mixed_device_leg(table, K_re, V_re, n=1 << 24):
     step leaves it (2^26 live pairs at load 0.8): n elements, 70% finds of resident keys, 20%
     inserts of fresh keys, 10% erases of other resident keys, in random order.  Every status is
     fixed by the workload and checked.  The same three operations are then timed as three batches
-    of the batch path, on the same table state (the mixed call undone first)."""
+    of the batch path, on the same table state (the mixed call undone first), and the finds alone
+    through a read-only device-side launch."""
     import torch
     from paper_1908_05936_amd import ct
 
@@ -324,7 +325,8 @@ def mixed_device_leg(table, K_re, V_re, n=1 << 24):
     g.manual_seed(13)
     er = K_re[:n_er]
     er_v = V_re[:n_er]
-    fq = K_re[n_er:][torch.randint(0, K_re.numel() - n_er, (n_find,), device=dev, generator=g)]
+    fidx = torch.randint(0, K_re.numel() - n_er, (n_find,), device=dev, generator=g)
+    fq, fv = K_re[n_er:][fidx], V_re[n_er:][fidx]
     fresh = torch.randint(-(1 << 62), 1 << 62, (n_ins,), device=dev, generator=g)
     keys = torch.cat([fq, fresh, er])
     ops = torch.cat([torch.full((n_find,), ct.OP_FIND, dtype=torch.uint8, device=dev),
@@ -350,6 +352,13 @@ def mixed_device_leg(table, K_re, V_re, n=1 << 24):
     table.insert(er, er_v)
     assert table.size() == n0
     torch.cuda.synchronize()
+    # the finds alone through a read-only device-side launch
+    e0.record()
+    rst, rv = table.dev_apply(ct.OP_FIND, fq)
+    e1.record()
+    torch.cuda.synchronize()
+    rsec = e0.elapsed_time(e1) * 1e-3
+    assert bool((rst == 1).all()) and bool((rv == fv).all())
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
     ev[0].record()
     v, f = table.find(fq)
@@ -360,11 +369,14 @@ def mixed_device_leg(table, K_re, V_re, n=1 << 24):
     ev[3].record()
     torch.cuda.synchronize()
     bsec = ev[0].elapsed_time(ev[3]) * 1e-3
-    assert bool(f.all()) and table.size() == n0 + n_ins - n_er
+    assert bool(f.all()) and bool((v == fv).all()) and table.size() == n0 + n_ins - n_er
+    fsec = ev[0].elapsed_time(ev[1]) * 1e-3
     out = {"n": n, "mix": "70% find / 20% insert / 10% erase", "ms": sec * 1e3,
-           "Mops_s": n / sec / 1e6, "batch_path_ms": bsec * 1e3, "batch_path_Mops_s": n / bsec / 1e6}
+           "Mops_s": n / sec / 1e6, "batch_path_ms": bsec * 1e3, "batch_path_Mops_s": n / bsec / 1e6,
+           "finds": n_find, "read_only_find_ms": rsec * 1e3, "batch_find_ms": fsec * 1e3}
     log(f"[mixed device ops] {n} in one kernel: {out['ms']:.2f} ms, {out['Mops_s']:.0f} Mops/s; "
-        f"as three batches {out['batch_path_ms']:.2f} ms")
+        f"as three batches {out['batch_path_ms']:.2f} ms; the {n_find} finds alone: read-only "
+        f"device launch {out['read_only_find_ms']:.2f} ms, batch {out['batch_find_ms']:.2f} ms")
     return out
 
 

@@ -393,3 +393,26 @@ def test_mixed_mode_repeated_inserts(dev, copies, spread):
     np.testing.assert_array_equal(k, expect)
     np.testing.assert_array_equal(v, expect)
     assert t.check() == 0
+
+
+def test_mixed_mode_unknown_op_codes(dev):
+    """An element whose operation code is none of insert / find / erase reports 255 and leaves the
+    table alone; the other elements of the same launch run as usual."""
+    rng = rng_for(127)
+    t = ct.Table(10_000, ct.VAL_U64, device=dev)
+    base = distinct_u64(rng, 3000)
+    t.insert(g64(base, dev), g64(base, dev))
+    keys = np.concatenate([base[:1000], distinct_u64(rng, 1000, exclude=base)])
+    ops = np.full(keys.size, 7, np.uint8)
+    ops[::2] = ct.OP_FIND
+    st, out = t.dev_apply_mixed(torch.from_numpy(ops).to(dev), g64(keys, dev), g64(keys, dev))
+    st = st.cpu().numpy()
+    out = out.cpu().numpy().view(np.uint64)
+    assert (st[ops == 7] == 255).all()
+    found = np.isin(keys, base)
+    np.testing.assert_array_equal(st[ops == ct.OP_FIND], found[ops == ct.OP_FIND].astype(np.uint8))
+    hit = (ops == ct.OP_FIND) & found
+    np.testing.assert_array_equal(out[hit], keys[hit])
+    assert (out[~hit] == U64MAX).all()
+    assert t.size() == base.size and t.check() == 0
+    np.testing.assert_array_equal(dump_sorted(t, 64)[0], np.sort(base))
