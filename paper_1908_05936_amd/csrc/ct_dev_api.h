@@ -87,6 +87,72 @@ __device__ __forceinline__ uint64_t dev_probe(const TableView& t, uint64_t key, 
   return kNoPos;
 }
 
+// The same probe from the home bucket for a wave whose 64 lanes all call it together.  In step
+// r (0..7) lane v reads slot v & 7 of the bucket that owner lane 8r + (v >> 3) probes next, so
+// eight lanes read one 128-byte line together and a step of the wave makes 64 line requests
+// instead of 512.  Ballots hand each owner the eight comparisons of its bucket.  Owners whose
+// probe has ended read nothing useful (their lanes still read for the others), and the loop ends
+// when every owner has ended, after at most nb buckets each.
+__device__ __forceinline__ uint64_t dev_probe_wave(const TableView& t, uint64_t key, const Seq& sq,
+                                                   uint64_t* empty) {
+  const int lane = (int)wave_lane();
+  const int me_round = lane >> 3;        // the step in which this lane's bucket is read
+  const int me_shift = 8 * (lane & 7);   // and the ballot bits that hold its slots
+  uint64_t b = sq.home;
+  uint64_t res = kNoPos;
+  uint64_t seen = 0;
+  bool pending = true;
+  *empty = kNoPos;
+  for (;;) {
+    const uint64_t pm = __ballot(pending);
+    if (!pm) break;
+    uint64_t kk[kSlots];
+#pragma unroll
+    for (int r = 0; r < kSlots; ++r) {
+      const int o = 8 * r + (lane >> 3);
+      const uint64_t bo = __shfl(b, o, 64);
+      const bool po = (pm >> o) & 1ull;
+      // an ended owner's lanes read slot v & 7 of bucket 0: a load every lane makes, in bounds
+      kk[r] = dev_key(t, (po ? bo : 0ull) * kSlots + (uint64_t)(lane & 7));
+    }
+    uint32_t my_eq = 0, my_em = 0;
+#pragma unroll
+    for (int r = 0; r < kSlots; ++r) {
+      const int o = 8 * r + (lane >> 3);
+      const uint64_t ko = __shfl(key, o, 64);
+      const uint64_t eq = __ballot(kk[r] == ko);
+      const uint64_t em = __ballot(kk[r] == kEmpty);
+      if (r == me_round) {
+        my_eq = (uint32_t)(eq >> me_shift) & 0xFFu;
+        my_em = (uint32_t)(em >> me_shift) & 0xFFu;
+      }
+    }
+    if (pending) {
+      if (my_eq) {
+        res = b * kSlots + (uint64_t)__builtin_ctz(my_eq);
+        if (my_em && (uint32_t)__builtin_ctz(my_em) < (uint32_t)__builtin_ctz(my_eq))
+          *empty = b * kSlots + (uint64_t)__builtin_ctz(my_em);
+        pending = false;
+      } else if (my_em) {
+        *empty = b * kSlots + (uint64_t)__builtin_ctz(my_em);
+        pending = false;
+      } else if (++seen >= t.nb) {
+        pending = false;
+      } else {
+        b = next_bucket(t, b, sq.step);
+      }
+    }
+  }
+  return res;
+}
+
+// The probe from the home bucket: the whole wave together where it can, else lane by lane.
+__device__ __forceinline__ uint64_t dev_probe_home(const TableView& t, uint64_t key, const Seq& sq,
+                                                   uint64_t* empty) {
+  if (__ballot(1) == ~0ull) return dev_probe_wave(t, key, sq, empty);
+  return dev_probe(t, key, sq, sq.home, 0, empty);
+}
+
 // The wave's lanes that reach this call add `sign` each to the live count (or to their stripe).
 __device__ __forceinline__ void dev_count_add(const DevView& v, int64_t sign) {
   const uint64_t m = __ballot(1);
@@ -165,7 +231,7 @@ __device__ inline uint8_t dev_insert_mixed(const DevView& v, uint64_t key, Take 
   }
   const Seq sq = probe_seq(t, key);
   uint64_t empty;
-  if (dev_probe(t, key, sq, sq.home, 0, &empty) != kNoPos) return kPresent;
+  if (dev_probe_home(t, key, sq, &empty) != kNoPos) return kPresent;
   for (;;) {
     if (empty == kNoPos) return kFull;  // no empty slot left on the key's sequence
     uint64_t* kw = &t.bk[empty >> 3].s[empty & 7].key;
@@ -226,7 +292,7 @@ __device__ inline uint8_t dev_insert_with(const DevView& v, uint64_t key, Take t
   }
   const Seq sq = probe_seq(t, key);
   uint64_t empty;
-  if (dev_probe(t, key, sq, sq.home, 0, &empty) != kNoPos) return kPresent;
+  if (dev_probe_home(t, key, sq, &empty) != kNoPos) return kPresent;
   for (;;) {
     if (empty == kNoPos) return kFull;  // every bucket holds keys or tombstones
     uint64_t* kw = &t.bk[empty >> 3].s[empty & 7].key;
@@ -278,7 +344,7 @@ __device__ inline bool dev_erase(const DevView& v, uint64_t key) {
   }
   const Seq sq = probe_seq(t, key);
   uint64_t empty;
-  const uint64_t pos = dev_probe(t, key, sq, sq.home, 0, &empty);
+  const uint64_t pos = dev_probe_home(t, key, sq, &empty);
   if (pos == kNoPos) return false;
   // an empty slot only where the bucket already holds one, and never while inserts run
   bool has_empty = false;
@@ -301,7 +367,7 @@ __device__ inline bool dev_find(const DevView& v, uint64_t key, uint64_t* val) {
   }
   const Seq sq = probe_seq(t, key);
   uint64_t empty;
-  const uint64_t pos = dev_probe(t, key, sq, sq.home, 0, &empty);
+  const uint64_t pos = dev_probe_home(t, key, sq, &empty);
   if (pos == kNoPos) return false;
   if (val) *val = t.bk[pos >> 3].s[pos & 7].val;
   return true;

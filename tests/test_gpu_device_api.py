@@ -416,3 +416,36 @@ def test_mixed_mode_unknown_op_codes(dev):
     assert (out[~hit] == U64MAX).all()
     assert t.size() == base.size and t.check() == 0
     np.testing.assert_array_equal(dump_sorted(t, 64)[0], np.sort(base))
+
+
+@pytest.mark.parametrize("n", [1 << 17, (1 << 17) + 37])
+def test_device_finds_at_full_load(dev, n):
+    """Finds through the device functions on a table filled to capacity (load 0.8, so many probes
+    run past their home bucket), element by element against the oracle.  Whole wavefronts probe
+    together; a ragged tail probes lane by lane."""
+    rng = rng_for(131, n)
+    cap = 100_000
+    t = ct.Table(cap, ct.VAL_U64, device=dev)
+    o = oracle.OracleTable(cap, 64, oracle.HASH_MIX64, cap)
+    base = distinct_u64(rng, cap)
+    bv = rng.integers(0, 1 << 63, size=cap, dtype=np.uint64)
+    t.insert(g64(base, dev), g64(bv, dev))
+    o.insert(base, bv)
+    assert t.size() == cap
+    q = np.concatenate([base[rng.integers(0, cap, size=n - n // 4)],
+                        distinct_u64(rng, n // 4, exclude=base)])
+    rng.shuffle(q)
+    st, v = t.dev_apply(ct.OP_FIND, g64(q, dev))
+    ev, ef = o.find(q)
+    np.testing.assert_array_equal(st.cpu().numpy(), ef)
+    np.testing.assert_array_equal(v.cpu().numpy().view(np.uint64), ev)
+    # erases of half the keys through the device functions, then the finds again
+    er = base[: cap // 2]
+    est, _ = t.dev_apply(ct.OP_ERASE, g64(er, dev))
+    assert (est.cpu().numpy() == 1).all()
+    o.erase(er)
+    st, v = t.dev_apply(ct.OP_FIND, g64(q, dev))
+    ev, ef = o.find(q)
+    np.testing.assert_array_equal(st.cpu().numpy(), ef)
+    np.testing.assert_array_equal(v.cpu().numpy().view(np.uint64), ev)
+    same(t, o, 64)
