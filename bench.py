@@ -13,6 +13,8 @@ The printed JSON line carries:
   roofline     the dominant kernel's algorithmic bytes per launch / its mean duration vs 8 TB/s
   random_access the same kernels against ceilings measured in this run on this chip
   rehash       the table rehashed into one of twice the capacity (host-side resize)
+  mixed_device_ops  finds, inserts and erases in one device-side kernel on the step's table, the
+               same work as three batch calls, and its finds alone in a read-only launch
   pool         the index pool at 2^24 keys: insert_alloc, erase_release, bare pop and push
   voxel        the voxel-block frames: per-frame p50/p99, find and insert_alloc Mkeys/s
   served       the serving sweep on 64 device-resident tables: p50/p99 latency and achieved
@@ -41,6 +43,7 @@ ERASE_BYTES = 8 + 1 + 2 * 128       # key in, flag out; bucket line read and wri
 METRIC = "find & insert Mops/s at load 0.8 (1 GPU); served p50/p99 batch latency"
 PMC_SUMMARY = os.path.join(ROOT, "profiles", "pmc_large_table.md")
 KERNEL_SOURCES = ["include/ct.h", "paper_1908_05936_amd/csrc/ct_device.h",
+                  "paper_1908_05936_amd/csrc/ct_dev_api.h",
                   "paper_1908_05936_amd/csrc/ct_table.hip"]
 
 
