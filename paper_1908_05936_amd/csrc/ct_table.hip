@@ -1435,47 +1435,99 @@ __global__ __launch_bounds__(64) void k_dev_fold(TableView t) {
   if (threadIdx.x == 0) t.hdr->size += s;
 }
 
+// One element of the reference kernels below: operation `op` on keys[i] through the device
+// functions, its status (and found value) written at i.
+__device__ __forceinline__ void dev_apply_one(const DevView& v, int32_t op, int64_t i, uint64_t key,
+                                              const void* __restrict__ vals, int32_t vk,
+                                              void* __restrict__ vout, uint8_t* __restrict__ status) {
+  if (op == CT_OP_INSERT) {
+    const uint64_t val = vk == 2 ? static_cast<const uint64_t*>(vals)[i]
+                         : vk == 1 ? (uint64_t)static_cast<const uint32_t*>(vals)[i] : 0ull;
+    const uint8_t st = dev_insert(v, key, val);
+    if (status) status[i] = st;
+  } else if (op == CT_OP_ERASE) {
+    const bool hit = dev_erase(v, key);
+    if (status) status[i] = hit ? 1 : 0;
+  } else {
+    uint64_t val = 0;
+    const bool hit = dev_find(v, key, &val);
+    if (status) status[i] = hit ? 1 : 0;
+    if (vout) {
+      if (vk == 2) static_cast<uint64_t*>(vout)[i] = hit ? val : ~0ull;
+      else if (vk == 1) static_cast<uint32_t*>(vout)[i] = hit ? (uint32_t)val : ~0u;
+    }
+  }
+}
+
 // Per-thread operations through the device-side API (ct_dev_api.h): element i is handled by one
 // thread, all concurrently and in no particular order.  The reference user kernel, and what the
-// tests drive the device API with.  With `ops`, element i does operation ops[i] (mixed mode); an
-// unknown code leaves the table alone and reports kNoStatus.
-__global__ __launch_bounds__(kBlock) void k_dev_apply(DevView v, int32_t op, const uint8_t* __restrict__ ops,
-                                                      const uint64_t* __restrict__ keys,
+// tests drive the device API with.
+__global__ __launch_bounds__(kBlock) void k_dev_apply(DevView v, int32_t op, const uint64_t* __restrict__ keys,
                                                       const void* __restrict__ vals, int32_t vk,
                                                       int64_t n, void* __restrict__ vout,
                                                       uint8_t* __restrict__ status) {
   if (v.striped) v.striped = (int32_t)v.t.bcnt[kStripeFlag];
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * blockDim.x) {
-    const uint64_t key = keys[i];
-    if (ops) {
-      op = ops[i];
-      if (vout && op != CT_OP_FIND) {
-        if (vk == 2) static_cast<uint64_t*>(vout)[i] = ~0ull;
-        else if (vk == 1) static_cast<uint32_t*>(vout)[i] = ~0u;
+       i += (int64_t)gridDim.x * blockDim.x)
+    dev_apply_one(v, op, i, keys[i], vals, vk, vout, status);
+}
+
+// The mixed-mode reference kernel: element i does operation ops[i], every element concurrently.
+// A workgroup takes a window of kSortWin elements and sorts their indices by operation into LDS
+// queues, then runs each queue on consecutive threads, so most waves call one device function
+// with all 64 lanes and their probes go as a team.  An unknown code leaves the table alone and
+// reports kNoStatus; non-find elements get the absent sentinel as their value.
+constexpr int kSortWin = 4 * kBlock;
+
+__global__ __launch_bounds__(kBlock) void k_dev_apply_sorted(DevView v, const uint8_t* __restrict__ ops,
+                                                             const uint64_t* __restrict__ keys,
+                                                             const void* __restrict__ vals, int32_t vk,
+                                                             int64_t n, void* __restrict__ vout,
+                                                             uint8_t* __restrict__ status) {
+  constexpr int32_t kKind[3] = {CT_OP_FIND, CT_OP_INSERT, CT_OP_ERASE};
+  __shared__ uint16_t q[3][kSortWin];
+  __shared__ uint32_t qn[3];
+  if (v.striped) v.striped = (int32_t)v.t.bcnt[kStripeFlag];
+  const uint64_t below = (1ull << wave_lane()) - 1ull;
+  const int64_t nwin = (n + kSortWin - 1) / kSortWin;
+  for (int64_t w = blockIdx.x; w < nwin; w += gridDim.x) {  // the same trips for the whole block
+    if (threadIdx.x < 3) qn[threadIdx.x] = 0;
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < kSortWin / kBlock; ++r) {
+      const int slot = r * kBlock + (int)threadIdx.x;
+      const int64_t i = w * kSortWin + slot;
+      int kind = -1;
+      if (i < n) {
+        const int32_t op = ops[i];
+        kind = op == CT_OP_FIND ? 0 : op == CT_OP_INSERT ? 1 : op == CT_OP_ERASE ? 2 : -1;
+        if (vout && op != CT_OP_FIND) {
+          if (vk == 2) static_cast<uint64_t*>(vout)[i] = ~0ull;
+          else if (vk == 1) static_cast<uint32_t*>(vout)[i] = ~0u;
+        }
+        if (kind < 0 && status) status[i] = kNoStatus;
       }
-      if (op != CT_OP_INSERT && op != CT_OP_ERASE && op != CT_OP_FIND) {
-        if (status) status[i] = kNoStatus;
-        continue;
+      // one LDS add per wave and kind; order inside the wave by rank among the kind's lanes
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        const uint64_t m = __ballot(kind == k);
+        if (!m) continue;
+        uint32_t base = 0;
+        if (wave_lane() == __builtin_ctzll(m)) base = atomicAdd(&qn[k], (uint32_t)__builtin_popcountll(m));
+        base = __shfl(base, __builtin_ctzll(m), 64);
+        if (kind == k) q[k][base + (uint32_t)__builtin_popcountll(m & below)] = (uint16_t)slot;
       }
     }
-    if (op == CT_OP_INSERT) {
-      const uint64_t val = vk == 2 ? static_cast<const uint64_t*>(vals)[i]
-                           : vk == 1 ? (uint64_t)static_cast<const uint32_t*>(vals)[i] : 0ull;
-      const uint8_t st = dev_insert(v, key, val);
-      if (status) status[i] = st;
-    } else if (op == CT_OP_ERASE) {
-      const bool hit = dev_erase(v, key);
-      if (status) status[i] = hit ? 1 : 0;
-    } else {
-      uint64_t val = 0;
-      const bool hit = dev_find(v, key, &val);
-      if (status) status[i] = hit ? 1 : 0;
-      if (vout) {
-        if (vk == 2) static_cast<uint64_t*>(vout)[i] = hit ? val : ~0ull;
-        else if (vk == 1) static_cast<uint32_t*>(vout)[i] = hit ? (uint32_t)val : ~0u;
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const uint32_t cnt = qn[k];
+      for (uint32_t j = threadIdx.x; j < cnt; j += kBlock) {
+        const int64_t e = w * kSortWin + q[k][j];
+        dev_apply_one(v, kKind[k], e, keys[e], vals, vk, vout, status);
       }
     }
+    __syncthreads();  // the queues are read before the next window refills them
   }
 }
 
@@ -2392,8 +2444,7 @@ ct_status ct_dev_apply(ct_table* t, int32_t op, const uint64_t* keys, const void
     t->size_ub = std::min<uint64_t>(t->size_ub + (uint64_t)n, (uint64_t)t->desc.capacity);
   v.striped = op != CT_OP_FIND;
   if (v.striped) k_dev_prep<<<1, kStripes, 0, S(stream)>>>(t->v, op == CT_OP_INSERT ? (uint64_t)n : 0);
-  k_dev_apply<<<flat_blocks(n), kBlock, 0, S(stream)>>>(v, op, nullptr, keys, vals, vk, n, vals_out,
-                                                        status);
+  k_dev_apply<<<flat_blocks(n), kBlock, 0, S(stream)>>>(v, op, keys, vals, vk, n, vals_out, status);
   if (v.striped) k_dev_fold<<<1, kStripes, 0, S(stream)>>>(t->v);
   return launched();
 }
@@ -2410,8 +2461,9 @@ ct_status ct_dev_apply_mixed(ct_table* t, const uint8_t* ops, const uint64_t* ke
   t->size_ub = std::min<uint64_t>(t->size_ub + (uint64_t)n, (uint64_t)t->desc.capacity);
   v.striped = 1;
   k_dev_prep<<<1, kStripes, 0, S(stream)>>>(t->v, (uint64_t)n);
-  k_dev_apply<<<flat_blocks(n), kBlock, 0, S(stream)>>>(v, CT_OP_FIND, ops, keys, vals, vk, n,
-                                                        vals_out, status);
+  const int sorted_blocks = (int)std::max<int64_t>(1, std::min<int64_t>((n + kSortWin - 1) / kSortWin, 8192));
+  k_dev_apply_sorted<<<sorted_blocks, kBlock, 0, S(stream)>>>(v, ops, keys, vals, vk, n, vals_out,
+                                                               status);
   k_dev_fold<<<1, kStripes, 0, S(stream)>>>(t->v);
   return launched();
 }
