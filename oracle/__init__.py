@@ -81,6 +81,7 @@ def lib():
             "or_erase_release": (None, [P, P, P, I64, P]),
             "or_dump": (I64, [P, P, P, I64]),
             "or_check": (I64, [P, P, I, C.POINTER(C.c_int)]),
+            "or_corrupt": (I, [P, P, I]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -327,3 +328,8 @@ class OracleTable:
         bad = lib().or_check(self._h, pool._h if pool is not None else None, int(values_from_pool),
                              C.byref(w))
         return int(bad), int(w.value)
+
+    def corrupt(self, kind: int, pool: OraclePool | None = None) -> bool:
+        """TEST HOOK: break exactly one invariant (``or_corrupt`` in oracle.c lists the kinds) so a
+        test can show that ``check`` reports it.  False when the state has no room for it."""
+        return lib().or_corrupt(self._h, pool._h if pool is not None else None, int(kind)) == 0

@@ -458,29 +458,45 @@ int64_t or_select(const or_table *t, int kind, uint64_t lo, uint64_t hi, const i
 /*
  * Count invariant violations; `what` (nullable) receives a bit per failed invariant:
  *   1  size equals the number of entries reachable from the buckets, and size <= capacity
- *   2  no key occurs twice
- *   4  every live key is found by lookup with its stored value
+ *   2  no key occurs twice among the reachable entries
+ *   4  every reachable entry's key is found by lookup, with the entry's value
  *   8  every entry lies in the list of its own bucket; links stay in range; lists are acyclic
- *  16  live entries and free-list entries partition {0 .. capacity-1} (no leaked entry)
+ *      and no entry is on two lists
+ *  16  reachable entries and free-list entries partition {0 .. capacity-1}: every entry is in
+ *      exactly one of the two (no leaked entry, no entry both live and free)
  *  32  (with a pool) pool stack entries are in range and distinct; when `values_from_pool`, the
  *      pool stack and the live values partition {0 .. pool capacity - 1}
+ * These are the uniqueness guarantee of Section 4.1 (a key is stored at most once), the fixed
+ * capacity of Section 4 and the contracts of Section 3.3 written out for the chained layout; each
+ * bit is computed from its own evidence, so a single broken invariant sets a single bit (a key
+ * filed under another bucket sets 8 and, since lookup then misses it, 4).
  */
+/* lookup() that stops at a link out of range or after `capacity` steps (a damaged list). */
+static int64_t checked_lookup(const or_table *t, uint64_t key)
+{
+    int64_t steps = 0;
+    for (int64_t e = t->head[or_bucket_of(t, key)]; e >= 0 && e < t->capacity && steps <= t->capacity;
+         e = t->next[e], ++steps)
+        if (t->key[e] == key) return e;
+    return -1;
+}
+
 int64_t or_check(const or_table *t, const or_pool *p, int values_from_pool, int *what)
 {
     int64_t bad = 0;
     int w = 0;
     int64_t C = t->capacity;
     uint8_t *mark = (uint8_t *)calloc((size_t)(C > 0 ? C : 1), 1);
+    uint64_t *ks = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)(C > 0 ? C : 1));
     int64_t reach = 0;
     for (int64_t b = 0; b < t->nbuckets; ++b) {
-        int64_t steps = 0;
         for (int64_t e = t->head[b]; e >= 0; e = t->next[e]) {
-            if (e >= C || ++steps > C) { ++bad; w |= 8; break; }
-            if (mark[e]) { ++bad; w |= 8; break; }
+            if (e >= C) { ++bad; w |= 8; break; }    /* link out of range */
+            if (mark[e]) { ++bad; w |= 8; break; }   /* a cycle, or an entry on two lists */
             mark[e] = 1;
-            ++reach;
+            ks[reach++] = t->key[e];
             if (or_bucket_of(t, t->key[e]) != b) { ++bad; w |= 8; }
-            int64_t f = lookup(t, t->key[e]);
+            int64_t f = checked_lookup(t, t->key[e]);
             if (f < 0 || t->val[f] != t->val[e]) { ++bad; w |= 4; }
         }
     }
@@ -492,16 +508,10 @@ int64_t or_check(const or_table *t, const or_pool *p, int values_from_pool, int 
     }
     for (int64_t e = 0; e < C; ++e)
         if (!mark[e]) { ++bad; w |= 16; }
-    if (t->free_top + t->size != C) { ++bad; w |= 16; }
     free(mark);
 
-    int64_t m = t->size;
-    uint64_t *ks = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)(m > 0 ? m : 1));
-    int64_t k = 0;
-    for (int64_t b = 0; b < t->nbuckets && k < m; ++b)
-        for (int64_t e = t->head[b]; e >= 0 && k < m; e = t->next[e]) ks[k++] = t->key[e];
-    qsort(ks, (size_t)k, sizeof(uint64_t), cmp_pair);  /* cmp_pair reads the first u64 only */
-    for (int64_t j = 1; j < k; ++j)
+    qsort(ks, (size_t)reach, sizeof(uint64_t), cmp_pair);  /* cmp_pair reads the first u64 only */
+    for (int64_t j = 1; j < reach; ++j)
         if (ks[j] == ks[j - 1]) { ++bad; w |= 2; }
     free(ks);
 
@@ -514,12 +524,14 @@ int64_t or_check(const or_table *t, const or_pool *p, int values_from_pool, int 
             pm[v] = 1;
         }
         if (values_from_pool) {
-            for (int64_t b = 0; b < t->nbuckets; ++b)
-                for (int64_t e = t->head[b]; e >= 0; e = t->next[e]) {
+            for (int64_t b = 0; b < t->nbuckets; ++b) {
+                int64_t steps = 0;
+                for (int64_t e = t->head[b]; e >= 0 && e < C && steps <= C; e = t->next[e], ++steps) {
                     int64_t v = (int64_t)(int32_t)(uint32_t)t->val[e];
                     if (v < 0 || v >= P || pm[v]) { ++bad; w |= 32; continue; }
                     pm[v] = 2;
                 }
+            }
             for (int64_t v = 0; v < P; ++v)
                 if (!pm[v]) { ++bad; w |= 32; }
         }
@@ -527,4 +539,86 @@ int64_t or_check(const or_table *t, const or_pool *p, int values_from_pool, int 
     }
     if (what) *what = w;
     return bad;
+}
+
+/*
+ * TEST HOOK, not an operation of the containers: break exactly one invariant of a table (and
+ * pool) so that the tests can show that or_check reports it.  Returns 0 when the corruption was
+ * applied, -1 when the state has no room for it (for example an empty table, or no free entry).
+ *   1  size counter off by one (invariant 1)
+ *   2  a free entry made a second copy of a live key, with the same value, on the same list (2)
+ *   3  a live entry moved to the list of another bucket (8, and 4 through the failed lookup)
+ *   4  a list made cyclic: its last entry links back to its first (8)
+ *   5  a link pointing past the entry array (8)
+ *   6  a free entry dropped from the free list without being linked anywhere (16)
+ *   7  an entry both live and on the free list (16)
+ *   8  (pool) an index duplicated inside the pool stack (32)
+ *   9  (pool, values from the pool) an index dropped from the pool stack (32)
+ */
+static int64_t first_nonempty_bucket(const or_table *t, int64_t from)
+{
+    for (int64_t b = from; b < t->nbuckets; ++b)
+        if (t->head[b] >= 0) return b;
+    return -1;
+}
+
+int or_corrupt(or_table *t, or_pool *p, int kind)
+{
+    int64_t b = first_nonempty_bucket(t, 0);
+    switch (kind) {
+    case 1:
+        t->size += 1;
+        return 0;
+    case 2: {
+        if (b < 0 || t->free_top == 0) return -1;
+        int64_t e = t->head[b];
+        int64_t d = t->free_stack[--t->free_top];
+        t->key[d] = t->key[e];
+        t->val[d] = t->val[e];
+        t->next[d] = t->head[b];
+        t->head[b] = d;
+        t->size += 1;
+        return 0;
+    }
+    case 3: {
+        if (b < 0 || t->nbuckets < 2) return -1;
+        int64_t e = t->head[b];
+        t->head[b] = t->next[e];
+        int64_t o = (b + 1) % t->nbuckets;
+        t->next[e] = t->head[o];
+        t->head[o] = e;
+        return 0;
+    }
+    case 4: {
+        if (b < 0) return -1;
+        int64_t e = t->head[b];
+        while (t->next[e] >= 0) e = t->next[e];
+        t->next[e] = t->head[b];
+        return 0;
+    }
+    case 5: {
+        if (b < 0) return -1;
+        int64_t e = t->head[b];
+        while (t->next[e] >= 0) e = t->next[e];
+        t->next[e] = t->capacity + 5;
+        return 0;
+    }
+    case 6:
+        if (t->free_top == 0) return -1;
+        --t->free_top;
+        return 0;
+    case 7:
+        if (b < 0 || t->free_top == 0) return -1;
+        t->free_stack[0] = t->head[b];
+        return 0;
+    case 8:
+        if (!p || p->top < 2) return -1;
+        p->stack[1] = p->stack[0];
+        return 0;
+    case 9:
+        if (!p || p->top < 1) return -1;
+        --p->top;
+        return 0;
+    }
+    return -1;
 }

@@ -417,3 +417,77 @@ def test_partitioned_baseline_equals_sequential_replay():
         e = keys[rng.integers(0, keys.size, size=9000)]
         np.testing.assert_array_equal(p.erase(e), o.erase(e))
         assert p.size() == o.size()
+
+
+# --------------------------------------------------------------------------------------------
+# the invariant checker itself: each broken invariant must be reported by its own bit
+# --------------------------------------------------------------------------------------------
+# (kind of corruption, bits or_check must report): see or_corrupt / or_check in oracle.c
+CORRUPTIONS = [
+    (1, 1),        # size counter off by one
+    (2, 2),        # a second copy of a live key on the same list
+    (3, 4 | 8),    # an entry filed under another bucket: wrong list, and lookup misses it
+    (4, 8),        # a cyclic list
+    (5, 8),        # a link past the entry array
+    (6, 16),       # a free entry dropped from the free list (leaked)
+    (7, 16),       # an entry both live and free
+]
+
+
+def _populated(hash_kind, nb, cap=64, n=40, seed=0):
+    rng = np.random.default_rng(seed)
+    t = OracleTable(cap, 64, hash_kind, nb)
+    if hash_kind == HASH_VOXEL21:
+        keys = pack_int3(rng.integers(-9, 9, n), rng.integers(-9, 9, n), rng.integers(-9, 9, n))
+    else:
+        keys = rng.integers(0, 1 << 64, size=n, dtype=np.uint64)
+    t.insert(keys, np.arange(n, dtype=np.uint64))
+    return t
+
+
+@pytest.mark.parametrize("hash_kind,nb", [(HASH_MIX64, 7), (HASH_MIX64, 64), (HASH_VOXEL21, 13)])
+@pytest.mark.parametrize("kind,bits", CORRUPTIONS)
+def test_checker_reports_each_broken_invariant(hash_kind, nb, kind, bits):
+    t = _populated(hash_kind, nb)
+    assert t.check() == (0, 0)
+    assert t.corrupt(kind)
+    bad, what = t.check()
+    assert bad > 0 and what == bits, (kind, bad, what)
+
+
+def _pool_valued(cap=32, pcap=48, n=20):
+    t, p = OracleTable(cap, 32), OraclePool(pcap)
+    rng = np.random.default_rng(3)
+    t.insert_alloc(p, rng.integers(0, 1 << 64, size=n, dtype=np.uint64))
+    return t, p
+
+
+@pytest.mark.parametrize("kind", [8, 9])
+def test_checker_reports_broken_pool_conservation(kind):
+    """A duplicated pool index, or one dropped from the pool: the pool stack and the live values
+    no longer partition the pool's indices (bit 32)."""
+    t, p = _pool_valued()
+    assert t.check(p, values_from_pool=True) == (0, 0)
+    assert t.corrupt(kind, p)
+    bad, what = t.check(p, values_from_pool=True)
+    assert bad > 0 and what == 32, (kind, bad, what)
+
+
+def test_checker_reports_a_value_not_taken_from_the_pool():
+    """A live value overwritten with an index the pool still holds: that index is both free and
+    in use (bit 32), while the map's own invariants hold."""
+    t, p = _pool_valued()
+    keys, vals = t.dump()
+    t.erase(keys[:1])
+    top = p.dump()[-1]          # an index still in the pool
+    t.insert(keys[:1], np.array([top], dtype=np.uint64))
+    bad, what = t.check(p, values_from_pool=True)
+    assert what == 32 and bad > 0
+    assert t.check()[1] == 0
+
+
+def test_corruption_needs_room():
+    """An empty table has no live entry to break: the hook says so instead of doing nothing."""
+    t = OracleTable(8, 64, HASH_MIX64, 4)
+    assert not t.corrupt(2) and not t.corrupt(3) and not t.corrupt(4)
+    assert t.check() == (0, 0)
