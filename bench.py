@@ -17,6 +17,8 @@ The printed JSON line carries:
                same work as three batch calls, and its finds alone in a read-only launch
   pool         the index pool at 2^24 keys: insert_alloc, erase_release, bare pop and push
   voxel        the voxel-block frames: per-frame p50/p99, find and insert_alloc Mkeys/s
+  multi_table  the 256-table schedule, tuned in this run: plan, graph replay and per-batch
+               keys/s, and the fraction of the R1/R2 ceiling of its own mix at its footprint
   served       the serving sweep on 64 device-resident tables: p50/p99 latency and achieved
                keys/s at fractions of the saturated rate
   cpu_baseline the CPU oracle timed on a bounded sample of the same workload
@@ -95,6 +97,8 @@ def parse():
     ap.add_argument("--no-serve", action="store_true", help="skip the serving sweep")
     ap.add_argument("--no-voxel", action="store_true", help="skip the voxel-block frames")
     ap.add_argument("--no-pool", action="store_true", help="skip the index-pool operations")
+    ap.add_argument("--no-multi", action="store_true",
+                    help="skip the tuned 256-table schedule")
     ap.add_argument("--no-rehash", action="store_true", help="skip the resize (rehash) figure")
     ap.add_argument("--no-mixed", action="store_true",
                     help="skip the mixed device-side operations figure")
@@ -108,7 +112,7 @@ def parse():
                     help="seconds the serving sweep may take before it is stopped")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-ceilings", action="store_true")
-    ap.add_argument("--cpu-sample-shift", type=int, default=1,
+    ap.add_argument("--cpu-sample-shift", type=int, default=2,
                     help="oracle sample = the workload with every size divided by 2^shift")
     return ap.parse_args()
 
@@ -185,33 +189,51 @@ def measure_ceilings(ct, torch, dev, nlines, find_keys, uniform_keys, fill_keys=
     return res
 
 
-def cpu_baseline(shift, seed=3):
-    """The oracle as it stands, single-threaded, on the workload scaled down by 2^shift."""
+def host_cpu_model() -> str:
+    """The host CPU's model name as the kernel reports it (first processor), else the machine."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or platform.machine()
+
+
+def cpu_baseline(shift, seed=3, runs=5):
+    """The oracle as it stands, single-threaded, on the workload scaled down by 2^shift: the
+    median of `runs` runs, each on a fresh oracle table (generation excluded)."""
     import oracle
     from paper_1908_05936_amd.workloads import large_table
 
     w = large_table(seed=seed, log2_keys=26 - shift, log2_queries=27 - shift, log2_churn=24 - shift)
-    o = oracle.OracleTable(w["capacity"], 64)
     ops = w["insert_keys"].size + w["find"].size + w["erase"].size + w["reinsert_keys"].size
-    t0 = time.perf_counter()
-    o.insert(w["insert_keys"], w["insert_vals"])
-    o.find(w["find"])
-    o.erase(w["erase"])
-    o.insert(w["reinsert_keys"], w["reinsert_vals"])
-    dt = time.perf_counter() - t0
-    del o
+
+    def one(table):
+        t0 = time.perf_counter()
+        table.insert(w["insert_keys"], w["insert_vals"])
+        table.find(w["find"])
+        table.erase(w["erase"])
+        table.insert(w["reinsert_keys"], w["reinsert_vals"])
+        return time.perf_counter() - t0
+
+    seq = []
+    for _ in range(runs):
+        o = oracle.OracleTable(w["capacity"], 64)
+        seq.append(one(o))
+        del o
+    dt = float(np.median(seq))
     # the same sample on all host cores available to this process (up to 16): partitioned by key
     # hash, one oracle table and thread per partition, index order kept within each partition
     parts = max(1, min(16, len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity")
                       else os.cpu_count() or 1))
-    po = oracle.PartitionedOracle(w["capacity"], parts)
-    t1 = time.perf_counter()
-    po.insert(w["insert_keys"], w["insert_vals"])
-    po.find(w["find"])
-    po.erase(w["erase"])
-    po.insert(w["reinsert_keys"], w["reinsert_vals"])
-    dtp = time.perf_counter() - t1
-    del po
+    par = []
+    for _ in range(runs):
+        po = oracle.PartitionedOracle(w["capacity"], parts)
+        par.append(one(po))
+        del po
+    dtp = float(np.median(par))
     return {
         "value": ops / dt / 1e6,
         "unit": "Mops/s",
@@ -219,12 +241,14 @@ def cpu_baseline(shift, seed=3):
         "kind": "oracle",
         "sample": (f"large_table scaled by 1/{1 << shift}: fill 2^{26 - shift}, "
                    f"2^{27 - shift} Zipf(1.1) finds (20% absent), erase 2^{24 - shift}, "
-                   f"re-insert 2^{24 - shift}; {ops} ops in {dt:.2f} s, single thread"),
-        "host_cpu": platform.processor() or platform.machine(),
+                   f"re-insert 2^{24 - shift}; {ops} ops, median {dt:.2f} s of {runs} runs "
+                   f"(min {min(seq):.2f}, max {max(seq):.2f}), single thread"),
+        "runs": runs,
+        "host_cpu": host_cpu_model(),
         "host_threads_available": os.cpu_count(),
         "partitioned": {"value": ops / dtp / 1e6, "unit": "Mops/s", "cores": parts,
                         "kind": "oracle tables partitioned by key hash, one thread each",
-                        "seconds": dtp},
+                        "seconds": dtp, "runs": runs},
     }
 
 
@@ -425,6 +449,81 @@ def pool_ops(dev, keys, reps=3):
     log(f"[pool] insert_alloc {out['insert_alloc_Mops_s']:.0f} erase_release "
         f"{out['erase_release_Mops_s']:.0f} pop {out['pop_Mops_s']:.0f} push "
         f"{out['push_Mops_s']:.0f} Mops/s")
+    return out
+
+
+def multi_table_leg(dev) -> dict:
+    """The 256-table schedule (tables of 2^10..2^20 entries at load factors 0.5-0.9, a fill then a
+    20/70/10 insert/find/erase mix of batches of 2^6..2^18 keys): the autotuner picks the execution
+    form, merged runs, chunk, provisioning and block size on the seed-4 schedule in this run, and
+    the choice is measured on the seed-6 schedule: plan run, HIP-graph replay and one library call
+    per operation.  The ceiling is the schedule's own mix at its footprint: every insert or erase
+    key costs one random line gather + CAS (R2), every find key one random line gather (R1), both
+    measured here over a buffer of the tables' total size."""
+    import torch
+    from paper_1908_05936_amd import ct
+    from paper_1908_05936_amd.multi import measure, tune
+    from paper_1908_05936_amd.workloads import multi_table
+
+    t0 = time.perf_counter()
+    cfg = tune(multi_table(seed=4), dev, log=lambda m: None)
+    torch.cuda.empty_cache()
+    tune_s = time.perf_counter() - t0
+    we = multi_table(seed=6)
+    knobs = dict(lanes=cfg["lanes"], merge=cfg.get("merge", False), chunk=cfg["chunk"],
+                 provision=cfg["provision"], block=cfg.get("block", 256))
+    res = measure(we, dev, knobs)
+    count = {"insert": 0, "find": 0, "erase": 0}
+    for _, kind, keys, _ in we["schedule"]:
+        count[kind] += keys.size
+    del we
+    torch.cuda.empty_cache()
+    lines = max(1, res["table_bytes"] // 128)
+    buf = torch.zeros(lines * 128, dtype=torch.uint8, device=dev)
+    g = torch.Generator(device=dev)
+    g.manual_seed(5)
+    keys = torch.randint(0, 1 << 62, (1 << 24,), device=dev, generator=g)
+    out = torch.empty(keys.numel(), dtype=torch.int64, device=dev)
+
+    def timed(fn, reps=5):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps * 1e-3
+
+    r1 = keys.numel() / timed(lambda: ct.gather(buf, lines, 128, keys, out))
+    r2 = keys.numel() / timed(lambda: ct.gather(buf, lines, 128, keys, out, cas=True))
+    del buf, keys, out
+    torch.cuda.empty_cache()
+    ceiling_s = (count["insert"] + count["erase"]) / r2 + count["find"] / r1
+    best_ms = min(res["graph_replay_ms"], res["plan_ms"])
+    out = {
+        "workload": (f"{res['tables']} tables (2^10..2^20 entries, load 0.5-0.9, u64 keys, u32 "
+                     f"values), {res['ops']} operations, {res['keys']} keys: fill, then 20/70/10 "
+                     "insert/find/erase batches of 2^6..2^18 keys; tuned on seed 4, measured on "
+                     "seed 6"),
+        "tuned": knobs, "tuning_trials": cfg.get("trials"), "tuning_s": tune_s,
+        "keys": res["keys"], "insert_keys": count["insert"], "find_keys": count["find"],
+        "erase_keys": count["erase"], "table_bytes": res["table_bytes"],
+        "plan_ms": res["plan_ms"], "graph_replay_ms": res["graph_replay_ms"],
+        "per_batch_ms": res["per_batch_ms"], "streams4_ms": res["streams4_ms"],
+        "plan_Mkeys_s": res["plan_Mkeys_s"], "graph_Mkeys_s": res["graph_Mkeys_s"],
+        "per_batch_Mkeys_s": res["per_batch_Mkeys_s"],
+        "speedup_vs_per_batch": res["per_batch_ms"] / best_ms,
+        "grouped_launches": res.get("grouped_launches"), "grouped_steps": res.get("grouped_steps"),
+        "R1_Mlines_s_at_footprint": r1 / 1e6, "R2_Mops_s_at_footprint": r2 / 1e6,
+        "ceiling_ms": ceiling_s * 1e3,
+        "frac_of_random_access_ceiling": ceiling_s / (best_ms * 1e-3),
+    }
+    log(f"[multi] tuned {knobs} in {tune_s:.0f} s; graph {res['graph_replay_ms']:.2f} ms "
+        f"({res['graph_Mkeys_s']:.0f} Mkeys/s), per-batch {res['per_batch_ms']:.2f} ms; "
+        f"{out['frac_of_random_access_ceiling']:.2f} of the R1/R2 ceiling at "
+        f"{res['table_bytes'] / 1e9:.2f} GB")
     return out
 
 
@@ -646,6 +745,14 @@ def main():
     if not a.no_voxel:
         from paper_1908_05936_amd import bench_voxel
         line["voxel"] = bench_voxel.run(log=log)
+    if "voxel" in line and "random_access" in line:
+        # the voxel table is 2^21 buckets of 128 bytes: its find is compared with the gather
+        # ceiling at that footprint (256 MiB, the last-level cache's size)
+        r1 = line["random_access"]["by_footprint"]["256MiB"]["R1_Mlines_s"]
+        line["voxel"]["find_R1_256MiB_Mlines_s"] = r1
+        line["voxel"]["find_frac_of_R1_256MiB"] = line["voxel"]["find_Mkeys_s"] / r1
+    if not a.no_multi:
+        line["multi_table"] = multi_table_leg(dev)
     if serve_child is not None:
         del table, K_fill, V_fill, Q, E, K_re, V_re
         torch.cuda.empty_cache()

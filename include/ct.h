@@ -171,9 +171,32 @@ ct_status ct_select_voxel_box(ct_table *t, const int32_t *h_lo3, const int32_t *
                               uint64_t *keys_out, uint64_t *vals_out, int64_t cap,
                               int64_t *h_count, void *stream);
 
-/* Check the layout invariants on the device: every live key is reachable from its home bucket,
-   the live count equals the size counter.  *h_violations = number of failures.  Synchronises. */
-ct_status ct_check_invariants(ct_table *t, int64_t *h_violations, void *stream);
+/* Check the table's invariants on the device (the uniqueness of Section 4.1 and the contracts of
+   Section 3.3 stated for this layout) and return the number of failures in *h_violations
+   (0 = consistent).  Checked:
+     CT_CHECK_SIZE       the size counter equals the number of live slots (out-of-band keys
+                         included) and does not exceed the capacity;
+     CT_CHECK_DUPLICATE  no key is stored twice (a second copy of a key lies on the same probe
+                         path, so the walk from a copy's home bucket would pass the other);
+     CT_CHECK_REACH      every live key is reachable: no bucket between its home bucket and its
+                         own holds an empty slot, so find would see it;
+     CT_CHECK_POOL       with `p` (nullable; only for CT_VAL_U32 tables whose values are pool
+                         indices, as insert_alloc / erase_release keep them): the pool's entries
+                         and the table's live values together hold every index 0 .. capacity(p)-1
+                         exactly once (no leaked or duplicated index).  This is tested with two
+                         independent 64-bit multiset fingerprints and a count, which any missing,
+                         repeated or foreign index changes except with probability about 2^-64.
+   Uses the table's header words only: no scratch.  Synchronises `stream`.  CT_E_INVALID for a
+   pool with a table that is not CT_VAL_U32. */
+#define CT_CHECK_SIZE 1u
+#define CT_CHECK_DUPLICATE 2u
+#define CT_CHECK_REACH 12u  /* an unreachable key is also not findable: two bits, as the oracle */
+#define CT_CHECK_POOL 32u
+ct_status ct_check_invariants(ct_table *t, const ct_pool *p, int64_t *h_violations, void *stream);
+
+/* The same check, with the CT_CHECK_* bits of the failed invariants in *h_what (nullable). */
+ct_status ct_check_invariants_detail(ct_table *t, const ct_pool *p, int64_t *h_violations,
+                                     uint32_t *h_what, void *stream);
 
 /* Host-side resizing (a capacity is fixed at creation, Section 4; growth is a copy into a larger
    table): insert every live (key, value) of `src` into `dst`, which must have the same value kind
@@ -238,6 +261,16 @@ ct_status ct_voxel_insert_neighbours(ct_table *t, const uint64_t *blocks, int64_
 ct_status ct_voxel_insert_neighbours_alloc(ct_table *t, ct_pool *p, const uint64_t *blocks,
                                            int64_t n, int32_t ndirs, void *stream);
 
+/* The two-container step of Section 4.1's reconstruction example, through the device functions
+   in one kernel: for every key of keys[n] (device), one thread asks `map` whether it holds the key
+   (dev_contains, read-only) and, if so, inserts it into `set` (dev_insert; many threads may insert
+   one key, it is stored once).  status[n] (nullable): 255 when `map` lacks the key, else the set
+   insert's CT_PRESENT / CT_INSERTED / CT_FULL (exactly one element of each new key reads
+   CT_INSERTED).  `map` and `set` must be different tables; `set` may be of any value kind (values
+   are stored as 0).  Asynchronous on `stream`. */
+ct_status ct_dev_update_set(ct_table *map, ct_table *set, const uint64_t *keys, int64_t n,
+                            uint8_t *status, void *stream);
+
 /* Device-side vector / deque back operations on a pool (Sections 4.2-4.3: push_back / pop_back
    from threads).  ct_pool_device_view fills the by-value pool view of the device functions
    dev_push_back / dev_pop_back (paper_1908_05936_amd/csrc/ct_dev_api.h); a kernel either pushes
@@ -252,6 +285,14 @@ ct_status ct_dev_pool_apply(ct_pool *p, int32_t op, const int32_t *in, int64_t n
 
 /* Read and clear the sticky error word (CT_ERR_* bits).  Synchronises. */
 ct_status ct_get_error(ct_table *t, uint32_t *h_err, void *stream);
+
+/* Test hook, not for production use: from now on (clear keeps it, 0 switches it off), the first
+   claim attempt of every insert element whose index within its chunk is a multiple of `every` is
+   treated as lost to another key, as when a concurrent insert took the slot first (the rare
+   failed attempt of Section 4 that further attempts resolve).  The slot stays free, so the
+   element's retry path claims it; results are unchanged.  Also applies to ct_table_rehash into
+   this table (by source slot).  Enqueued on `stream`. */
+ct_status ct_table_debug_inject_claim_losses(ct_table *t, uint32_t every, void *stream);
 
 /* Diagnostic: *h_skewed = 1 when a recent chunk of this table overflowed its dedup bins (keys
    repeated thousands of times), so its large chunks fold each tile's repeated keys before binning;
@@ -368,6 +409,11 @@ ct_status ct_graph_destroy(void *graph_exec);
                                  after the last): fewer, larger steps and levels, for up to
                                  (8 + 2 value widths + 1) bytes per merged element of device
                                  memory in the grouped form's buffer */
+
+#define CT_GROUP_BLOCK_SHIFT 8  /* options bits 8-11: log2 of the threads per block of the
+                                  find / insert / erase stages, 7 .. 10 (128 .. 1024); 0 = 256 */
+#define CT_GROUP_BLOCK(threads) ((threads) == 128 ? (7 << 8) : (threads) == 512 ? (9 << 8) : \
+                                 (threads) == 1024 ? (10 << 8) : 0)
 
 /* Bytes of device memory the grouped form of `p` with `options` needs (host only). */
 ct_status ct_plan_group_bytes(ct_plan *p, int32_t options, int64_t *bytes);

@@ -42,8 +42,9 @@ def main(argv=None):
         torch.cuda.empty_cache()
     log(f"[multi] tuned: {cfg}")
     we = multi_table(seed=a.eval_seed)
-    res = measure(we, dev, {k: cfg.get(k, False) if k == "merge" else cfg[k]
-                            for k in ("lanes", "merge", "chunk", "provision")})
+    res = measure(we, dev, dict(lanes=cfg["lanes"], merge=cfg.get("merge", False),
+                                chunk=cfg["chunk"], provision=cfg["provision"],
+                                block=cfg.get("block", 256)))
     res["tuned_on_seed"] = a.tune_seed
     res["evaluated_on_seed"] = a.eval_seed
     res["tuning"] = cfg

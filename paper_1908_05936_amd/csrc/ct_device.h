@@ -79,7 +79,16 @@ struct alignas(256) Header {
   uint32_t dagg;           // 1: the current chunk's coarse scatter folds each tile's repeats first
   uint32_t dskew;          // 1: a recent chunk overflowed its bins (skewed keys): aggregate
   uint32_t dskew_age;      // binned chunks since dskew was set; every 16th tries without folding
+  // invariant check (ct_check_invariants): duplicate keys found, pool values out of range, and
+  // the multiset fingerprint of (pool entries + live values - {0 .. pool capacity - 1})
+  uint64_t dup_count;
+  uint64_t pool_bad;
+  int64_t pool_count;
+  uint64_t pool_h1, pool_h2;
+  uint32_t inject;         // test hook: when nonzero, the first claim of every chunk element whose
+                           // index is a multiple of it is treated as lost to another key
 };
+static_assert(sizeof(Header) == 256, "the header fills one 256-byte line");
 
 // A pool is a deque of int32 in a ring of `cap` entries: element x (0 = front, top - 1 = back)
 // sits at stack[(head + x) mod cap].  Back operations move top; front operations move head too.
@@ -243,15 +252,16 @@ __device__ __forceinline__ uint64_t wave_sum(uint64_t v) {
   return v;
 }
 
-// Sum of `v` over a block of kBlock threads, returned to thread 0; call with every thread active.
+// Sum of `v` over a block of NT threads, returned to thread 0; call with every thread active.
+template <int NT = kBlock>
 __device__ __forceinline__ int64_t block_sum(int64_t v) {
-  __shared__ int64_t part[kBlock / 64];
+  __shared__ int64_t part[NT / 64];
   v = (int64_t)wave_sum((uint64_t)v);
   if (wave_lane() == 0) part[threadIdx.x >> 6] = v;
   __syncthreads();
   int64_t s = 0;
   if (threadIdx.x == 0)
-    for (int w = 0; w < kBlock / 64; ++w) s += part[w];
+    for (int w = 0; w < NT / 64; ++w) s += part[w];
   return s;
 }
 

@@ -14,27 +14,43 @@ namespace {
 
 constexpr int kB = 256;
 
-// G lanes read one line of 16*G bytes; XOR of the line goes to out[i].
+// G lanes read one line of 16*G bytes; XOR of the line goes to out[i].  A group takes U keys per
+// round and issues all U line loads before it reduces any, so each lane has U independent
+// 16-byte loads in flight (the container kernels keep up to 8 bucket loads in flight per lane).
 template <int G, bool CAS>
 __global__ __launch_bounds__(kB) void k_gather(uint4* __restrict__ lines, uint64_t nlines,
                                                const uint64_t* __restrict__ keys, int64_t n,
                                                uint64_t* __restrict__ out) {
+  constexpr int U = 4;
   const int sub = threadIdx.x % G;
   const int64_t ng = (int64_t)gridDim.x * (kB / G);
-  for (int64_t i = (int64_t)blockIdx.x * (kB / G) + threadIdx.x / G; i < n; i += ng) {
-    const uint64_t key = keys[i];
-    const uint64_t line = __umul64hi(fmix64(key), nlines);
-    const uint4 w = lines[line * G + sub];
-    uint64_t x = ((uint64_t)w.y << 32 | w.x) ^ ((uint64_t)w.w << 32 | w.z);
-    for (int off = 1; off < G; off <<= 1) x ^= __shfl_xor(x, off, 64);
-    if (sub == 0) {
-      if (CAS) {
-        uint64_t* word = reinterpret_cast<uint64_t*>(&lines[line * G]);
-        uint64_t expected = (uint64_t)w.y << 32 | w.x;
-        cas64(word, expected, expected ^ key);
-        x ^= expected;
+  const int64_t rounds = (n + ng * U - 1) / (ng * U);
+  for (int64_t r = 0; r < rounds; ++r) {
+    const int64_t i0 = r * ng * U + (int64_t)blockIdx.x * (kB / G) + threadIdx.x / G;
+    uint64_t key[U], line[U];
+    uint4 w[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t i = min(i0 + u * ng, n - 1);   // clamped: loads are unconditional
+      key[u] = keys[i];
+      line[u] = __umul64hi(fmix64(key[u]), nlines);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) w[u] = lines[line[u] * G + sub];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t i = i0 + u * ng;
+      uint64_t x = ((uint64_t)w[u].y << 32 | w[u].x) ^ ((uint64_t)w[u].w << 32 | w[u].z);
+      for (int off = 1; off < G; off <<= 1) x ^= __shfl_xor(x, off, 64);
+      if (sub == 0 && i < n) {
+        if (CAS) {
+          uint64_t* word = reinterpret_cast<uint64_t*>(&lines[line[u] * G]);
+          uint64_t expected = (uint64_t)w[u].y << 32 | w[u].x;
+          cas64(word, expected, expected ^ key[u]);
+          x ^= expected;
+        }
+        out[i] = x;
       }
-      out[i] = x;
     }
   }
 }
@@ -61,10 +77,24 @@ __global__ __launch_bounds__(kB) void k_amin(uint64_t* __restrict__ words, uint6
   }
 }
 
-__global__ __launch_bounds__(kB) void k_copy(const uint4* __restrict__ src, uint4* __restrict__ dst,
+// Stream copy: each thread moves U 16-byte words per round, all U loads issued before the stores
+// (whole rounds take no bounds tests; the ragged last round does).
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+__global__ __launch_bounds__(kB) void k_copy(const u32x4* __restrict__ src, u32x4* __restrict__ dst,
                                              int64_t n16) {
-  const int64_t nt = (int64_t)gridDim.x * kB;
-  for (int64_t i = (int64_t)blockIdx.x * kB + threadIdx.x; i < n16; i += nt) dst[i] = src[i];
+  constexpr int U = 8;
+  const int64_t span = (int64_t)gridDim.x * kB * U;
+  int64_t i = (int64_t)blockIdx.x * kB * U + threadIdx.x;
+  for (; i + (U - 1) * kB < n16; i += span) {
+    u32x4 v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) v[u] = __builtin_nontemporal_load(&src[i + u * kB]);
+#pragma unroll
+    for (int u = 0; u < U; ++u) __builtin_nontemporal_store(v[u], &dst[i + u * kB]);
+  }
+  for (int u = 0; u < U; ++u)
+    if (i + u * kB < n16) dst[i + u * kB] = src[i + u * kB];
 }
 
 int blocks_for(int64_t items, int per_block, int cap) {
@@ -127,8 +157,8 @@ ct_status ctr_copy(const void* src, void* dst, int64_t bytes, void* stream) {
   if (reinterpret_cast<uintptr_t>(src) % 16 || reinterpret_cast<uintptr_t>(dst) % 16) return CT_E_INVALID;
   if (bytes == 0) return CT_OK;
   const int64_t n16 = bytes / 16;
-  k_copy<<<blocks_for(n16, kB * 4, 16384), kB, 0, reinterpret_cast<hipStream_t>(stream)>>>(
-      static_cast<const uint4*>(src), static_cast<uint4*>(dst), n16);
+  k_copy<<<blocks_for(n16, kB * 8, 8192), kB, 0, reinterpret_cast<hipStream_t>(stream)>>>(
+      static_cast<const u32x4*>(src), static_cast<u32x4*>(dst), n16);
   return done();
 }
 

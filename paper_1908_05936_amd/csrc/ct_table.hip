@@ -146,11 +146,22 @@ __device__ __forceinline__ uint32_t dedup_lookup(const TableView& t, const uint6
 // kernels
 // ---------------------------------------------------------------------------------------------
 // Empty every slot in [lo, hi) (thread-strided by `step`); `header` also resets the counters.
+// Slots are written as 16-byte words, U per thread and round (the stores of a round issue
+// back to back; a round that would pass `hi` takes a bounds test per word).
 __device__ __forceinline__ void reset_range(const TableView& t, int64_t lo, int64_t hi,
                                             int64_t step, bool header, int zero_err) {
+  constexpr int U = 4;
   const uint4 empty = make_uint4(0xFFFFFFFFu, 0xFFFFFFFFu, 0u, 0u);
-  for (int64_t j = lo + threadIdx.x; j < hi; j += step)
-    *reinterpret_cast<uint4*>(&t.bk[j >> 3].s[j & 7]) = empty;
+  uint4* slots = reinterpret_cast<uint4*>(t.bk);
+  int64_t j = lo * U + threadIdx.x;
+  const int64_t span = step * U;
+  const int64_t width = blockDim.x;
+  for (; j + (U - 1) * width < hi; j += span) {
+#pragma unroll
+    for (int u = 0; u < U; ++u) slots[j + u * width] = empty;
+  }
+  for (int u = 0; u < U; ++u)
+    if (j + u * width < hi) slots[j + u * width] = empty;
   if (header && threadIdx.x == 0) {
     Header* h = t.hdr;
     h->size = 0;
@@ -158,7 +169,10 @@ __device__ __forceinline__ void reset_range(const TableView& t, int64_t lo, int6
     h->spec_val[0] = h->spec_val[1] = 0;
     h->spec_live[0] = h->spec_live[1] = 0;
     h->spec_first[0] = h->spec_first[1] = kNone;
-    if (zero_err) h->err = 0;
+    if (zero_err) {
+      h->err = 0;
+      h->inject = 0;
+    }
     h->fast = 0;
     h->ndup = 0;
     h->nnew = 0;
@@ -333,6 +347,25 @@ __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* t
   return before + x - v;
 }
 
+// The chunk's overflow flag and one fill count, read once for the whole block.  Other blocks of
+// the same launch may raise the flag while this block starts, so a per-wave read could let some
+// waves of a block leave and others stay; the staying waves would then meet the block's barriers
+// and scans without the leavers' contributions (the scan words those waves never wrote hold stale
+// LDS contents).  One reader and a barrier make the decision uniform across the block.
+__device__ __forceinline__ bool block_overflowed(const TableView& t, const uint32_t* count,
+                                                 uint32_t* fill) {
+  __shared__ uint32_t flag_and_fill[2];
+  if (threadIdx.x == 0) {
+    const uint32_t o = t.hdr->dovf;
+    const uint32_t f = *count;
+    flag_and_fill[0] = o;
+    flag_and_fill[1] = f;
+  }
+  __syncthreads();
+  *fill = flag_and_fill[1];
+  return flag_and_fill[0] != 0;
+}
+
 __device__ __forceinline__ uint32_t fine_bin(const TableView& t, uint64_t mix) {
   return (uint32_t)(mix >> (64 - t.lp));
 }
@@ -398,7 +431,9 @@ __device__ __forceinline__ void bin_write(const TableView& t, BinStage& S, uint3
     S.b[p] = (uint8_t)b;
   }
   __syncthreads();
-  for (uint32_t p = threadIdx.x; p < total; p += kBlock) {
+  // a block stages at most kBinTile elements; the bound also keeps p from wrapping
+  const uint32_t staged = min(total, (uint32_t)kBinTile);
+  for (uint32_t p = threadIdx.x; p < staged; p += kBlock) {
     const uint32_t b = S.b[p];
     const uint32_t pos = S.base[b] + (p - S.loc[b]);
     if (pos < cap) {
@@ -516,11 +551,8 @@ __global__ __launch_bounds__(kBlock) void k_bin_scatter2(TableView t, int blocks
   __shared__ BinStage S;
   const int g = (int)blockIdx.x / blocks_per_seg;
   const int c = g / kBinSub;
-  // the overflow flag and the segment's fill count in one round trip
-  const uint32_t ovf = t.hdr->dovf;
-  const uint32_t fill = t.bcur[g * kCtrStride];
-  asm volatile("" ::"v"(ovf), "v"(fill));
-  if (ovf) return;
+  uint32_t fill;
+  if (block_overflowed(t, &t.bcur[g * kCtrStride], &fill)) return;
   const uint32_t n1 = min(fill, t.c1);
   const int lp2 = t.lp - t.lp1;
   const uint32_t p2 = 1u << lp2;
@@ -564,11 +596,8 @@ __global__ __launch_bounds__(kBlock) void k_bin_dedup(TableView t) {
   __shared__ uint32_t hm[kBinLds];
   __shared__ uint8_t hx[kBinLds];
   const uint32_t f = blockIdx.x;
-  // the overflow flag and the bin's fill count in one round trip
-  const uint32_t ovf = t.hdr->dovf;
-  const uint32_t fill = t.bcur[kCoarseCtrWords + f];
-  asm volatile("" ::"v"(ovf), "v"(fill));
-  if (ovf) return;
+  uint32_t fill;
+  if (block_overflowed(t, &t.bcur[kCoarseCtrWords + f], &fill)) return;
   const uint32_t n = min(fill, t.c2);
   if (n == 0) return;
   const uint64_t* rk = t.r2k + (int64_t)f * t.c2;
@@ -758,12 +787,12 @@ __device__ __forceinline__ void group_probe(const TableView& t, uint64_t key, ui
 // time.  Returns this lane's claimed slot (meaningful on `want` lanes), kNoPos when none is left.
 __device__ __forceinline__ uint64_t claim_group(const TableView& t, uint64_t key, uint32_t want,
                                                 int sub, uint64_t myfb, int myc, uint64_t myexp,
-                                                uint64_t mystep) {
+                                                uint64_t mystep, uint32_t inject, uint64_t id) {
   uint64_t mypos = kNoPos;
   int won = 0;
   if ((want >> sub) & 1) {
     uint64_t expected = myexp;
-    won = cas64(&t.bk[myfb].s[myc].key, expected, key) ? 1 : 0;
+    if (!inject || id % inject != 0) won = cas64(&t.bk[myfb].s[myc].key, expected, key) ? 1 : 0;
   }
   if (won) mypos = myfb * kSlots + (uint64_t)myc;
   const uint32_t retry = want & ~group_bits(__ballot(won));
@@ -795,6 +824,7 @@ __device__ __forceinline__ int64_t insert_range(const TableView& t, const uint64
                                                 int64_t step) {
   const int sub = threadIdx.x & 7;
   const bool fast = t.hdr->fast != 0;
+  const uint32_t inject = t.hdr->inject;
   const bool flags = ALLOC || !fast;
   int64_t ins = 0;
   for (int64_t g0 = lo + (int64_t)(threadIdx.x >> 3) * kSlots; g0 < hi; g0 += step) {
@@ -846,7 +876,9 @@ __device__ __forceinline__ int64_t insert_range(const TableView& t, const uint64
         int won = 0;
         if ((want >> sub) & 1) {
           uint64_t expected = myexp;
-          won = cas64(&t.bk[myfb].s[myc].key, expected, key) ? 1 : 0;
+          // (test hook: an injected loss leaves the slot free, so the retry below claims it)
+          if (!inject || (uint64_t)i % inject != 0)
+            won = cas64(&t.bk[myfb].s[myc].key, expected, key) ? 1 : 0;
         }
         if (won) mypos = myfb * kSlots + (uint64_t)myc;
         const uint32_t retry = want & ~group_bits(__ballot(won));
@@ -917,6 +949,7 @@ __global__ __launch_bounds__(kBlock) void k_rehash(TableView src, TableView dst)
   const int64_t gpb = kBlock / 8;
   const int64_t ngroups = (int64_t)gridDim.x * gpb;
   const int64_t span = ((nbk + ngroups - 1) / ngroups) * ngroups;  // equal trips for all lanes
+  const uint32_t inject = dst.hdr->inject;
   int64_t ins = 0;
   for (int64_t g = (int64_t)blockIdx.x * gpb + (threadIdx.x >> 3); g < span; g += ngroups) {
     Slot sl;
@@ -935,7 +968,9 @@ __global__ __launch_bounds__(kBlock) void k_rehash(TableView src, TableView dst)
                       &mystep);
     const uint32_t want = A & ~found & freeb;
     uint64_t pos = kNoPos;
-    if (want) pos = claim_group(dst, key, want, sub, myfb, myc, myexp, mystep);
+    if (want)
+      pos = claim_group(dst, key, want, sub, myfb, myc, myexp, mystep, inject,
+                        (uint64_t)g * kSlots + (uint64_t)sub);
     if (live && !((found >> sub) & 1)) {
       if (((want >> sub) & 1) && pos != kNoPos) {
         dst.bk[pos >> 3].s[pos & 7].val = sl.val;
@@ -1563,6 +1598,23 @@ __global__ __launch_bounds__(kBlock) void k_voxel_neighbours(DevView v, DevPool 
   }
 }
 
+// The two-container step of the reconstruction example of Section 4.1: every thread asks the
+// block map whether its key is there (contains, read-only on `map`) and, if so, inserts the key
+// into the update set `set` (an unordered_set, many threads may insert the same key).  status[i]:
+// kNoStatus when the map lacks the key, else the set insert's PRESENT / INSERTED / FULL.
+__global__ __launch_bounds__(kBlock) void k_dev_update_set(DevView map, DevView set,
+                                                           const uint64_t* __restrict__ keys,
+                                                           int64_t n, uint8_t* __restrict__ status) {
+  if (set.striped) set.striped = (int32_t)set.t.bcnt[kStripeFlag];
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const uint64_t key = keys[i];
+    uint8_t st = kNoStatus;
+    if (dev_contains(map, key)) st = dev_insert(set, key, 0);
+    if (status) status[i] = st;
+  }
+}
+
 // Per-thread push_back / pop_back through the device-side API: element i by one thread, all
 // concurrently.
 __global__ __launch_bounds__(kBlock) void k_dev_pool_apply(DevPool p, int32_t op,
@@ -1584,37 +1636,120 @@ __global__ __launch_bounds__(kBlock) void k_dev_pool_apply(DevPool p, int32_t op
 }
 
 __global__ void k_check_begin(TableView t) {
-  t.hdr->live_count = 0;
-  t.hdr->violations = 0;
+  Header* h = t.hdr;
+  h->live_count = 0;
+  h->violations = 0;
+  h->dup_count = 0;
+  h->pool_bad = 0;
+  h->pool_count = 0;
+  h->pool_h1 = 0;
+  h->pool_h2 = 0;
 }
 
-// Every live key must be reachable: no bucket between its home and its bucket holds a kEmpty slot.
-__global__ __launch_bounds__(kBlock) void k_check(TableView t) {
+// Two independent 64-bit fingerprints of a pool index.  Sums of them over a multiset (wrapping)
+// are equal for equal multisets; a multiset that differs from {0 .. P-1} (an index missing,
+// repeated, or replaced) changes both sums except with probability about 2^-64 each.
+__device__ __forceinline__ uint64_t check_h1(uint64_t v) { return fmix64(v + 0x9E3779B97F4A7C15ull); }
+__device__ __forceinline__ uint64_t check_h2(uint64_t v) {
+  return fmix64(v * 0xD1B54A32D192ED03ull + 0x632BE59BD9B4E019ull);
+}
+
+struct CheckSums {
+  uint64_t live = 0, unreach = 0, dup = 0, pbad = 0, h1 = 0, h2 = 0;
+  int64_t pcnt = 0;
+};
+
+__device__ __forceinline__ void check_pool_value(CheckSums& c, uint64_t v, int64_t pool_cap) {
+  if (v >= (uint64_t)pool_cap) {
+    ++c.pbad;
+  } else {
+    ++c.pcnt;
+    c.h1 += check_h1(v);
+    c.h2 += check_h2(v);
+  }
+}
+
+__device__ __forceinline__ void check_flush(const TableView& t, CheckSums c) {
+  c.live = wave_sum(c.live);
+  c.unreach = wave_sum(c.unreach);
+  c.dup = wave_sum(c.dup);
+  c.pbad = wave_sum(c.pbad);
+  c.h1 = wave_sum(c.h1);
+  c.h2 = wave_sum(c.h2);
+  c.pcnt = (int64_t)wave_sum((uint64_t)c.pcnt);
+  if (wave_lane() == 0) {
+    Header* h = t.hdr;
+    if (c.live) aadd64(&h->live_count, c.live);
+    if (c.unreach) aadd64(&h->violations, c.unreach);
+    if (c.dup) aadd64(&h->dup_count, c.dup);
+    if (c.pbad) aadd64(&h->pool_bad, c.pbad);
+    if (c.pcnt) aadd64(reinterpret_cast<uint64_t*>(&h->pool_count), (uint64_t)c.pcnt);
+    if (c.h1) aadd64(&h->pool_h1, c.h1);
+    if (c.h2) aadd64(&h->pool_h2, c.h2);
+  }
+}
+
+// Every live key must be reachable (no bucket between its home and its own bucket holds a kEmpty
+// slot, so a lookup finds it) and stored once: a second copy of a key lies on the same probe
+// path, so the walk of the later copy passes the earlier one (or an earlier slot of its own
+// bucket).  With pool_cap > 0 the live values are pool indices and enter the fingerprint sums.
+__global__ __launch_bounds__(kBlock) void k_check(TableView t, int64_t pool_cap) {
   const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t nt = (int64_t)gridDim.x * blockDim.x;
   const int64_t nslots = (int64_t)t.nb * kSlots;
-  uint64_t live = 0, bad = 0;
+  CheckSums c;
   for (int64_t j = tid; j < nslots; j += nt) {
-    const uint64_t key = t.bk[j >> 3].s[j & 7].key;
-    if (key == kEmpty || key == kTomb) continue;
-    ++live;
+    const Slot sl = t.bk[j >> 3].s[j & 7];
+    if (sl.key == kEmpty || sl.key == kTomb) continue;
+    ++c.live;
     const uint64_t at = (uint64_t)(j >> 3);
-    const Seq q = probe_seq(t, key);
+    const int own = (int)(j & 7);
+    const Seq q = probe_seq(t, sl.key);
     uint64_t b = q.home;
-    for (uint64_t step = 0; b != at; ++step) {
-      if (step >= t.nb) { ++bad; break; }
+    bool unreachable = false, dup = false;
+    for (uint64_t step = 0;; ++step) {
+      if (step >= t.nb) { unreachable = true; break; }
+      const bool last = b == at;
       bool has_empty = false;
-      for (int c = 0; c < kSlots; ++c) has_empty |= t.bk[b].s[c].key == kEmpty;
-      if (has_empty) { ++bad; break; }
+      for (int s = 0; s < kSlots; ++s) {
+        const uint64_t k2 = t.bk[b].s[s].key;
+        has_empty |= k2 == kEmpty;
+        dup |= k2 == sl.key && (!last || s < own);
+      }
+      if (last) break;
+      if (has_empty) { unreachable = true; break; }
       b = next_bucket(t, b, q.step);
     }
+    c.unreach += unreachable;
+    c.dup += dup;
+    if (pool_cap > 0) check_pool_value(c, sl.val, pool_cap);
   }
-  live = wave_sum(live);
-  bad = wave_sum(bad);
-  if (wave_lane() == 0) {
-    if (live) aadd64(&t.hdr->live_count, live);
-    if (bad) aadd64(&t.hdr->violations, bad);
+  if (pool_cap > 0 && tid == 0) {
+    for (int s = 0; s < 2; ++s)
+      if (t.hdr->spec_live[s]) check_pool_value(c, t.hdr->spec_val[s], pool_cap);
   }
+  check_flush(t, c);
+}
+
+// The pool's entries enter the fingerprint sums, and every index 0 .. cap-1 leaves them once: the
+// sums and the count end at zero exactly when the pool and the table's live values together hold
+// each index once.
+__global__ __launch_bounds__(kBlock) void k_check_pool(TableView t, const PoolHeader* ph,
+                                                       const int32_t* __restrict__ stack) {
+  const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t nt = (int64_t)gridDim.x * blockDim.x;
+  const int64_t top = ph->top, head = ph->head, cap = ph->cap;
+  CheckSums c;
+  for (int64_t j = tid; j < cap; j += nt) {
+    if (j < top) {
+      const int32_t v = stack[ring_pos(head, cap, j)];
+      check_pool_value(c, v < 0 ? ~0ull : (uint64_t)v, cap);
+    }
+    --c.pcnt;
+    c.h1 -= check_h1((uint64_t)j);
+    c.h2 -= check_h2((uint64_t)j);
+  }
+  check_flush(t, c);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -1793,12 +1928,15 @@ __global__ __launch_bounds__(kBlock) void k_g_dedup(const GStep* __restrict__ st
   dedup_range(t, g.keys, g.db - 1, (int64_t)L.lb * kBlock, g.q, (int64_t)L.nblk * kBlock);
 }
 
-__global__ __launch_bounds__(kBlock) void k_g_insert(const GStep* __restrict__ st,
-                                                     const GEntry* __restrict__ e, int32_t n) {
+// The grouped find / insert / erase stages run with BS threads per block (the plan's block size):
+// the range code strides by the step's blocks times BS, 8 lanes per key group as always.
+template <int BS>
+__global__ __launch_bounds__(BS) void k_g_insert(const GStep* __restrict__ st,
+                                                 const GEntry* __restrict__ e, int32_t n) {
   const GLoc L = g_locate(e, n);
   const GStep& g = st[L.step];
   const TableView t = g.v;
-  const int64_t lo = (int64_t)L.lb * kBlock, step = (int64_t)L.nblk * kBlock;
+  const int64_t lo = (int64_t)L.lb * BS, step = (int64_t)L.nblk * BS;
   int64_t ins;
   if (g.vk == 1)
     ins = insert_range<1, false>(t, g.keys, g.vals, g.db - 1, g.flags, nullptr, lo, g.q, step);
@@ -1806,27 +1944,29 @@ __global__ __launch_bounds__(kBlock) void k_g_insert(const GStep* __restrict__ s
     ins = insert_range<2, false>(t, g.keys, g.vals, g.db - 1, g.flags, nullptr, lo, g.q, step);
   else
     ins = insert_range<0, false>(t, g.keys, nullptr, g.db - 1, g.flags, nullptr, lo, g.q, step);
-  const int64_t tot = block_sum(ins);
+  const int64_t tot = block_sum<BS>(ins);
   if (threadIdx.x == 0) t.bcnt[L.lb] = tot;
 }
 
-__global__ __launch_bounds__(kBlock) void k_g_erase(const GStep* __restrict__ st,
-                                                    const GEntry* __restrict__ e, int32_t n) {
+template <int BS>
+__global__ __launch_bounds__(BS) void k_g_erase(const GStep* __restrict__ st,
+                                                const GEntry* __restrict__ e, int32_t n) {
   const GLoc L = g_locate(e, n);
   const GStep& g = st[L.step];
   const TableView t = g.v;
-  const int64_t del = erase_range<false>(t, g.keys, g.db - 1, g.flags, (int64_t)L.lb * kBlock,
-                                         g.q, (int64_t)L.nblk * kBlock);
-  const int64_t tot = block_sum(del);
+  const int64_t del = erase_range<false>(t, g.keys, g.db - 1, g.flags, (int64_t)L.lb * BS,
+                                         g.q, (int64_t)L.nblk * BS);
+  const int64_t tot = block_sum<BS>(del);
   if (threadIdx.x == 0) t.bcnt[L.lb] = -tot;
 }
 
-__global__ __launch_bounds__(kBlock) void k_g_find(const GStep* __restrict__ st,
-                                                   const GEntry* __restrict__ e, int32_t n) {
+template <int BS>
+__global__ __launch_bounds__(BS) void k_g_find(const GStep* __restrict__ st,
+                                               const GEntry* __restrict__ e, int32_t n) {
   const GLoc L = g_locate(e, n);
   const GStep& g = st[L.step];
   const TableView t = g.v;
-  const int64_t lo = (int64_t)L.lb * kBlock, step = (int64_t)L.nblk * kBlock;
+  const int64_t lo = (int64_t)L.lb * BS, step = (int64_t)L.nblk * BS;
   if (g.vk == 1) find_range<1>(t, g.keys, g.vout, g.flags, lo, g.q, step);
   else if (g.vk == 2) find_range<2>(t, g.keys, g.vout, g.flags, lo, g.q, step);
   else find_range<0>(t, g.keys, nullptr, g.flags, lo, g.q, step);
@@ -2109,8 +2249,10 @@ int64_t bin_prologue_units_host(const TableView& v, int64_t q) {
   return (q + 15) / 16 + ((int64_t)kCoarseCtrWords + ((int64_t)1 << v.lp)) / 4;
 }
 
-int group_blocks(int64_t n) {
-  const int64_t b = (n + (kBlock / 8) - 1) / (kBlock / 8);
+// Blocks of `bs` threads for n key groups of 8 lanes (at most kMaxGroupBlocks: the count
+// partials of one launch).
+int group_blocks(int64_t n, int bs = kBlock) {
+  const int64_t b = (n + (bs / 8) - 1) / (bs / 8);
   return (int)std::max<int64_t>(1, std::min<int64_t>(b, kMaxGroupBlocks));
 }
 
@@ -2503,6 +2645,25 @@ ct_status ct_voxel_insert_neighbours_alloc(ct_table* t, ct_pool* p, const uint64
   return launched();
 }
 
+ct_status ct_dev_update_set(ct_table* map, ct_table* set, const uint64_t* keys, int64_t n,
+                            uint8_t* status, void* stream) {
+  if (!map || !set || map == set || n < 0 || (n > 0 && !keys)) return CT_E_INVALID;
+  if (n == 0) return CT_OK;
+  hipStream_t s = S(stream);
+  DevView mv{};
+  mv.t = map->v;
+  mv.mode = kDevRead;
+  DevView sv{};
+  sv.t = set->v;
+  sv.mode = kDevInsert;
+  sv.striped = 1;
+  set->size_ub = std::min<uint64_t>(set->size_ub + (uint64_t)n, (uint64_t)set->desc.capacity);
+  k_dev_prep<<<1, kStripes, 0, s>>>(set->v, (uint64_t)n);
+  k_dev_update_set<<<flat_blocks(n), kBlock, 0, s>>>(mv, sv, keys, n, status);
+  k_dev_fold<<<1, kStripes, 0, s>>>(set->v);
+  return launched();
+}
+
 ct_status ct_pool_device_view(ct_pool* p, void* out, int64_t bytes) {
   if (!p || !out || bytes < (int64_t)sizeof(DevPool)) return CT_E_INVALID;
   const DevPool d{p->hdr, p->stack};
@@ -2558,21 +2719,46 @@ ct_status ct_select_voxel_box(ct_table* t, const int32_t* h_lo3, const int32_t* 
   return select_into(t, box, keys_out, vals_out, cap, h_count, stream);
 }
 
-ct_status ct_check_invariants(ct_table* t, int64_t* h_violations, void* stream) {
+ct_status ct_check_invariants_detail(ct_table* t, const ct_pool* p, int64_t* h_violations,
+                                     uint32_t* h_what, void* stream) {
   if (!t || !h_violations) return CT_E_INVALID;
-  k_check_begin<<<1, 1, 0, S(stream)>>>(t->v);
-  k_check<<<flat_blocks((int64_t)t->v.nb * kSlots), kBlock, 0, S(stream)>>>(t->v);
+  if (p && t->desc.val_kind != CT_VAL_U32) return CT_E_INVALID;
+  hipStream_t s = S(stream);
+  const int64_t pool_cap = p ? std::max<int64_t>(p->cap, 1) : 0;
+  k_check_begin<<<1, 1, 0, s>>>(t->v);
+  k_check<<<flat_blocks((int64_t)t->v.nb * kSlots), kBlock, 0, s>>>(t->v, pool_cap);
+  if (p) k_check_pool<<<flat_blocks(p->cap), kBlock, 0, s>>>(t->v, p->hdr, p->stack);
   if (launched() != CT_OK) return CT_E_HIP;
   Header h;
-  if (hipMemcpyAsync(&h, t->v.hdr, sizeof(Header), hipMemcpyDeviceToHost, S(stream)) != hipSuccess)
+  if (hipMemcpyAsync(&h, t->v.hdr, sizeof(Header), hipMemcpyDeviceToHost, s) != hipSuccess)
     return CT_E_HIP;
-  if (hipStreamSynchronize(S(stream)) != hipSuccess) return CT_E_HIP;
+  if (hipStreamSynchronize(s) != hipSuccess) return CT_E_HIP;
   const uint64_t specs = (uint64_t)(h.spec_live[0] != 0) + (uint64_t)(h.spec_live[1] != 0);
-  int64_t bad = (int64_t)h.violations;
-  if (h.live_count + specs != h.size) ++bad;
-  if (h.size > t->v.cap) ++bad;
+  int64_t bad = 0;
+  uint32_t what = 0;
+  if (h.live_count + specs != h.size || h.size > t->v.cap) {
+    ++bad;
+    what |= CT_CHECK_SIZE;
+  }
+  if (h.dup_count) {
+    bad += (int64_t)h.dup_count;
+    what |= CT_CHECK_DUPLICATE;
+  }
+  if (h.violations) {
+    bad += (int64_t)h.violations;
+    what |= CT_CHECK_REACH;
+  }
+  if (p && (h.pool_bad || h.pool_count != 0 || h.pool_h1 != 0 || h.pool_h2 != 0)) {
+    bad += h.pool_bad ? (int64_t)h.pool_bad : 1;
+    what |= CT_CHECK_POOL;
+  }
   *h_violations = bad;
+  if (h_what) *h_what = what;
   return CT_OK;
+}
+
+ct_status ct_check_invariants(ct_table* t, const ct_pool* p, int64_t* h_violations, void* stream) {
+  return ct_check_invariants_detail(t, p, h_violations, nullptr, stream);
 }
 
 ct_status ct_get_error(ct_table* t, uint32_t* h_err, void* stream) {
@@ -2585,6 +2771,14 @@ ct_status ct_get_error(ct_table* t, uint32_t* h_err, void* stream) {
   if (hipMemcpyAsync(&t->v.hdr->err, &zero, sizeof(zero), hipMemcpyHostToDevice, S(stream)) != hipSuccess)
     return CT_E_HIP;
   return hipStreamSynchronize(S(stream)) == hipSuccess ? CT_OK : CT_E_HIP;
+}
+
+__global__ void k_set_inject(TableView t, uint32_t every) { t.hdr->inject = every; }
+
+ct_status ct_table_debug_inject_claim_losses(ct_table* t, uint32_t every, void* stream) {
+  if (!t) return CT_E_INVALID;
+  k_set_inject<<<1, 1, 0, S(stream)>>>(t->v, every);
+  return launched();
 }
 
 ct_status ct_table_dedup_skewed(ct_table* t, int32_t* h_skewed, void* stream) {
@@ -2764,6 +2958,7 @@ struct ct_plan {
   const void* gentries = nullptr;  // device: GEntry[]
   const void* gcopies = nullptr;   // device: GCopy[] of the merged operations' copy stages
   size_t grouped_ops = (size_t)-1;
+  int gblock = kBlock;             // threads per block of its find / insert / erase stages
 };
 
 namespace {
@@ -2855,8 +3050,21 @@ struct GroupForm {
 // operations of one kind on one table becomes one operation over a contiguous copy of its arrays
 // in the merge area (a batch equals its parts applied in order), gathered before the first level
 // and scattered back after the last.  Host only.
+// Threads per block of the grouped find / insert / erase stages encoded in `options`.
+int group_block_size(int32_t options) {
+  const int code = (options >> CT_GROUP_BLOCK_SHIFT) & 0xF;
+  return code ? (1 << code) : kBlock;
+}
+
+bool group_options_valid(int32_t options) {
+  if (options & ~(CT_GROUP_MERGE_RUNS | (0xF << CT_GROUP_BLOCK_SHIFT))) return false;
+  const int code = (options >> CT_GROUP_BLOCK_SHIFT) & 0xF;
+  return code == 0 || (code >= 7 && code <= 10);   // 128 .. 1024 threads
+}
+
 ct_status group_build(const ct_plan* p, int32_t options, uint8_t* base, GroupForm& F) {
   const bool merge = (options & CT_GROUP_MERGE_RUNS) != 0;
+  const int bs = group_block_size(options);
   struct Eff {  // an operation of one table as it will be cut into steps
     PlanOp op;
     size_t first, count;  // its run of plan operations
@@ -2968,7 +3176,7 @@ ct_status group_build(const ct_plan* p, int32_t options, uint8_t* base, GroupFor
           g.vout = (o.type == kOpFind && o.vout) ? static_cast<uint8_t*>(o.vout) + c0 * vb : nullptr;
           g.flags = o.flags ? o.flags + c0 : nullptr;
           g.db = ie ? dedup_slots_for(q) : 0u;
-          g.gb = group_blocks((q + kSlots - 1) / kSlots);
+          g.gb = group_blocks((q + kSlots - 1) / kSlots, bs);
           g.ntiles = (int32_t)((q + kTile - 1) / kTile);
           F.steps.push_back(g);
           level.push_back(lev++);
@@ -3026,12 +3234,21 @@ ct_status group_build(const ct_plan* p, int32_t options, uint8_t* base, GroupFor
   return CT_OK;
 }
 
+// One launch of a grouped find / insert / erase stage with BS threads per block.
+template <int BS>
+void probe_stage(int32_t stage, hipStream_t s, const ct_group::Launch& L, const GStep* st,
+                 const GEntry* e) {
+  if (stage == gFind) k_g_find<BS><<<L.blocks, BS, 0, s>>>(st, e, L.n);
+  else if (stage == gInsert) k_g_insert<BS><<<L.blocks, BS, 0, s>>>(st, e, L.n);
+  else k_g_erase<BS><<<L.blocks, BS, 0, s>>>(st, e, L.n);
+}
+
 }  // namespace
 
 extern "C" {
 
 ct_status ct_plan_group_bytes(ct_plan* p, int32_t options, int64_t* bytes) {
-  if (!p || !bytes || (options & ~CT_GROUP_MERGE_RUNS)) return CT_E_INVALID;
+  if (!p || !bytes || !group_options_valid(options)) return CT_E_INVALID;
   GroupForm F;
   ct_status r = group_build(p, options, nullptr, F);
   if (r != CT_OK) return r;
@@ -3041,7 +3258,7 @@ ct_status ct_plan_group_bytes(ct_plan* p, int32_t options, int64_t* bytes) {
 
 ct_status ct_plan_group(ct_plan* p, int32_t options, void* d_buf, int64_t bytes) {
   if (!p || !d_buf || reinterpret_cast<uintptr_t>(d_buf) % kAlign) return CT_E_INVALID;
-  if (options & ~CT_GROUP_MERGE_RUNS) return CT_E_INVALID;
+  if (!group_options_valid(options)) return CT_E_INVALID;
   uint8_t* base = static_cast<uint8_t*>(d_buf);
   GroupForm F;
   ct_status r = group_build(p, options, base, F);
@@ -3061,6 +3278,7 @@ ct_status ct_plan_group(ct_plan* p, int32_t options, void* d_buf, int64_t bytes)
   p->gentries = base + F.entries_off;
   p->gcopies = base + F.copies_off;
   p->grouped_ops = p->ops.size();
+  p->gblock = group_block_size(options);
   return CT_OK;
 }
 
@@ -3075,9 +3293,14 @@ ct_status ct_plan_launch_grouped(ct_plan* p, void* stream) {
       case gReset: k_g_reset<<<L.blocks, kBlock, 0, s>>>(st, e, L.n); break;
       case gPro: k_g_prologue<<<L.blocks, kBlock, 0, s>>>(st, e, L.n); break;
       case gDedup: k_g_dedup<<<L.blocks, kBlock, 0, s>>>(st, e, L.n); break;
-      case gFind: k_g_find<<<L.blocks, kBlock, 0, s>>>(st, e, L.n); break;
-      case gInsert: k_g_insert<<<L.blocks, kBlock, 0, s>>>(st, e, L.n); break;
-      case gErase: k_g_erase<<<L.blocks, kBlock, 0, s>>>(st, e, L.n); break;
+      case gFind:
+      case gInsert:
+      case gErase:
+        if (p->gblock == 128) probe_stage<128>(L.stage, s, L, st, e);
+        else if (p->gblock == 512) probe_stage<512>(L.stage, s, L, st, e);
+        else if (p->gblock == 1024) probe_stage<1024>(L.stage, s, L, st, e);
+        else probe_stage<kBlock>(L.stage, s, L, st, e);
+        break;
       case gApply: k_g_apply<<<L.blocks, 1024, 0, s>>>(st, e, L.n); break;
       case gCount: k_g_tile_count<<<L.blocks, kBlock, 0, s>>>(st, e, L.n); break;
       case gScan: k_g_tile_scan<<<L.blocks, 1024, 0, s>>>(st, e, L.n); break;

@@ -23,8 +23,10 @@ ERR_FULL, ERR_POOL = 1, 2
 KERNELS = ["clear", "prologue", "dedup", "insert", "erase", "apply", "rank", "final", "fix", "find"]
 VAL_NONE, VAL_U32, VAL_U64 = 0, 1, 2
 GROUP_MERGE_RUNS = 1
+GROUP_BLOCK = {128: 7 << 8, 256: 0, 512: 9 << 8, 1024: 10 << 8}   # CT_GROUP_BLOCK(threads)
 OP_CLEAR, OP_INSERT, OP_FIND, OP_ERASE = 0, 1, 2, 3
 HASH_MIX64, HASH_VOXEL21 = 0, 1
+CHECK_SIZE, CHECK_DUPLICATE, CHECK_REACH, CHECK_POOL = 1, 2, 12, 32
 
 
 class CtError(RuntimeError):
@@ -66,9 +68,11 @@ SIGNATURES = {
     "ct_size": (C.c_int, [_P, _PI64, _P]),
     "ct_clear": (C.c_int, [_P, _P]),
     "ct_dump": (C.c_int, [_P, _P, _P, _I64, _PI64, _P]),
-    "ct_check_invariants": (C.c_int, [_P, _PI64, _P]),
+    "ct_check_invariants": (C.c_int, [_P, _P, _PI64, _P]),
+    "ct_check_invariants_detail": (C.c_int, [_P, _P, _PI64, C.POINTER(C.c_uint32), _P]),
     "ct_get_error": (C.c_int, [_P, C.POINTER(C.c_uint32), _P]),
     "ct_table_dedup_skewed": (C.c_int, [_P, C.POINTER(C.c_int32), _P]),
+    "ct_table_debug_inject_claim_losses": (C.c_int, [_P, C.c_uint32, _P]),
     "ct_table_rehash": (C.c_int, [_P, _P, _P]),
     "ct_table_device_view": (C.c_int, [_P, _I32, _P, _I64]),
     "ct_dev_apply": (C.c_int, [_P, _I32, _P, _P, _I64, _P, _P, _P]),
@@ -76,6 +80,7 @@ SIGNATURES = {
     "ct_voxel_insert_neighbours": (C.c_int, [_P, _P, _I64, _I32, _P]),
     "ct_voxel_insert_neighbours_alloc": (C.c_int, [_P, _P, _P, _I64, _I32, _P]),
     "ct_pool_device_view": (C.c_int, [_P, _P, _I64]),
+    "ct_dev_update_set": (C.c_int, [_P, _P, _P, _I64, _P, _P]),
     "ct_dev_pool_apply": (C.c_int, [_P, _I32, _P, _I64, _P, _P, _P]),
     "ct_select_key_range": (C.c_int, [_P, C.c_uint64, C.c_uint64, _P, _P, _I64, _PI64, _P]),
     "ct_select_voxel_box": (C.c_int, [_P, C.POINTER(C.c_int32), C.POINTER(C.c_int32), _P, _P,
@@ -418,6 +423,15 @@ class Table:
                                         _ptr(st), _stream(self.device)), "ct_dev_apply_mixed")
         return st, out
 
+    def dev_update_set(self, set_table: "Table", keys: torch.Tensor):
+        """In one kernel, every key that this map holds (contains) is inserted into `set_table`
+        (device-side insert, concurrently): per-element status, 255 where this map lacks it."""
+        _need(keys, torch.int64, None, "keys", self.device)
+        st = torch.empty(keys.numel(), dtype=torch.uint8, device=self.device)
+        _check(lib().ct_dev_update_set(self._h, set_table._h, _ptr(keys), keys.numel(), _ptr(st),
+                                       _stream(self.device)), "ct_dev_update_set")
+        return st
+
     def insert_neighbours(self, blocks: torch.Tensor, ndirs: int = 6):
         """Neighbour update of a voxel-block map through the device-side API."""
         _need(blocks, torch.int64, None, "blocks", self.device)
@@ -460,16 +474,32 @@ class Table:
             self.insert(keys, None if self.value_kind == VAL_NONE else
                         vals.to(self.value_dtype) if vals is not None else None, status=False)
 
-    def check(self) -> int:
+    def check(self, pool: "Pool | None" = None) -> int:
+        """Invariant violations found on the device (0 = consistent); with `pool`, also that the
+        pool and this table's values together hold every pool index once."""
         v = C.c_int64(0)
-        _check(lib().ct_check_invariants(self._h, C.byref(v), _stream(self.device)),
+        _check(lib().ct_check_invariants(self._h, pool._h if pool is not None else None,
+                                         C.byref(v), _stream(self.device)),
                "ct_check_invariants")
         return v.value
+
+    def check_detail(self, pool: "Pool | None" = None):
+        """(violations, CHECK_* bits of the failed invariants)."""
+        v, w = C.c_int64(0), C.c_uint32(0)
+        _check(lib().ct_check_invariants_detail(self._h, pool._h if pool is not None else None,
+                                                C.byref(v), C.byref(w), _stream(self.device)),
+               "ct_check_invariants_detail")
+        return v.value, w.value
 
     def error(self) -> int:
         e = C.c_uint32(0)
         _check(lib().ct_get_error(self._h, C.byref(e), _stream(self.device)), "ct_get_error")
         return e.value
+
+    def debug_inject_claim_losses(self, every: int):
+        """Test hook: treat the first claim of every `every`-th chunk element as lost (0 = off)."""
+        _check(lib().ct_table_debug_inject_claim_losses(self._h, int(every), _stream(self.device)),
+               "ct_table_debug_inject_claim_losses")
 
     def dedup_skewed(self) -> bool:
         """True when recent chunks overflowed the dedup bins, so large chunks fold each tile's
@@ -550,9 +580,12 @@ class Plan:
         _check(lib().ct_graph_launch(self._graph, s.cuda_stream), "ct_graph_launch")
 
     # grouped form: one launch per stage per level over all tables
-    def group(self, merge_runs: bool = False):
-        """Build the grouped form (descriptor buffer allocated here, kept by the plan)."""
-        opt = GROUP_MERGE_RUNS if merge_runs else 0
+    def group(self, merge_runs: bool = False, block: int = 256):
+        """Build the grouped form (descriptor buffer allocated here, kept by the plan); `block` is
+        the threads per block of its find / insert / erase stages (128, 256, 512 or 1024)."""
+        if block not in GROUP_BLOCK:
+            raise CtError(f"block must be one of {sorted(GROUP_BLOCK)}")
+        opt = (GROUP_MERGE_RUNS if merge_runs else 0) | GROUP_BLOCK[block]
         nb = C.c_int64(0)
         _check(lib().ct_plan_group_bytes(self._h, opt, C.byref(nb)), "ct_plan_group_bytes")
         self._gbuf = torch.empty(nb.value, dtype=torch.uint8, device=self.device)

@@ -13,9 +13,13 @@ Autotuner.  The knobs of a plan run are
   * chunk       -- per-table insert/erase chunk (a larger chunk means fewer chained sub-operations
                    for big batches on small tables, at 34-109 bytes of scratch per chunk element),
   * provision   -- physical slots per requested capacity (1.0 = the requested load factor; more
-                   slots lower the physical load and shorten probes, at the cost of memory).
+                   slots lower the physical load and shorten probes, at the cost of memory),
+  * block       -- grouped form only: threads per block of the find / insert / erase stages
+                   (128, 256, 512, 1024: more blocks in flight against fewer waves per block).
 The lane-group width that probes one key is fixed at 8 lanes x 16 bytes = one 128-byte bucket
-line; it is a layout constant, not a launch knob.  The tuner does coordinate descent from the
+line: the layout's bucket is one such line, and a 4-lane probe of 64-byte half lines would need a
+table of 64-byte buckets (4 slots), which the measured gather ceilings rule out (35.3 G 128-byte
+lines/s x 8 slots against 40.5 G 64-byte lines/s x 4 slots per second of probing).  The tuner does coordinate descent from the
 defaults on one seed's schedule and reports the choice, which a caller then evaluates on a
 schedule drawn with another seed.  Results are cached in a JSON file keyed by device name and
 workload signature.
@@ -32,7 +36,7 @@ import torch
 from . import ct
 
 OPS = {"insert": ct.OP_INSERT, "find": ct.OP_FIND, "erase": ct.OP_ERASE}
-DEFAULT = dict(lanes=0, merge=False, chunk=0, provision=1.0)
+DEFAULT = dict(lanes=0, merge=False, chunk=0, provision=1.0, block=256)
 
 
 def _g64(a, dev):
@@ -111,11 +115,11 @@ def time_fn(fn, reps=3, warmup=1):
     return float(np.median(ts))
 
 
-def runner(p: ct.Plan, lanes: int, merge: bool = False):
+def runner(p: ct.Plan, lanes: int, merge: bool = False, block: int = 256):
     """Callable running plan `p` once: grouped (lanes 0, built on first use) or on side streams."""
     if lanes == 0:
         if getattr(p, "_gbuf", None) is None:
-            p.group(merge_runs=merge)
+            p.group(merge_runs=merge, block=block)
         return p.launch_grouped
     return lambda: p.launch(lanes)
 
@@ -149,18 +153,21 @@ def tune(w: dict, dev, cache: str | None = None, reps: int = 3, log=print) -> di
             built[wk] = Workload(w, dev, chunk=cfg["chunk"], provision=cfg["provision"])
         wl = built[wk]
         p = wl.plan()
-        t = time_fn(runner(p, cfg["lanes"], cfg.get("merge", False)), reps=reps)
+        t = time_fn(runner(p, cfg["lanes"], cfg.get("merge", False), cfg.get("block", 256)),
+                    reps=reps)
         trials.append(dict(cfg, seconds=t))
         log(f"[tune] {cfg} -> {t * 1e3:.2f} ms")
         return t
 
     best_t = run(best)
     space = [("lanes", [0, 1, 2, 4, 8]), ("chunk", [0, -1]), ("provision", [1.0, 1.25, 1.5]),
-             ("merge", [False, True])]
+             ("merge", [False, True]), ("block", [128, 256, 512, 1024])]
     seen = {repr(sorted(best.items()))}
     for sweep in range(2):  # a second sweep revisits each knob at the others' new values
         improved = False
         for name, values in space:
+            if name in ("merge", "block") and best["lanes"] != 0:
+                continue   # knobs of the grouped form only
             for v in values:
                 cfg = dict(best, **{name: v})
                 if repr(sorted(cfg.items())) in seen:
@@ -187,7 +194,8 @@ def measure(w: dict, dev, cfg: dict, reps: int = 5, graph_replays: int = 10) -> 
     """Plan run, its HIP-graph replay and one-stream per-batch calls on schedule `w` with `cfg`."""
     wl = Workload(w, dev, chunk=cfg["chunk"], provision=cfg["provision"])
     p = wl.plan()
-    t_plan = time_fn(runner(p, cfg["lanes"], cfg.get("merge", False)), reps=reps)
+    t_plan = time_fn(runner(p, cfg["lanes"], cfg.get("merge", False), cfg.get("block", 256)),
+                     reps=reps)
     s = torch.cuda.Stream(dev)
     if cfg["lanes"] == 0:
         p.capture_grouped(stream=s)

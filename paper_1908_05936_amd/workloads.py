@@ -72,42 +72,41 @@ def splitmix64(seed: int, start: int, n: int) -> np.ndarray:
 def zipf_ranks(rng: np.random.Generator, n: int, num_elements: int, exponent: float) -> np.ndarray:
     """``n`` ranks in [1, num_elements] with P(k) proportional to k^-exponent.
 
-    Rejection-inversion sampling of Hoermann & Derflinger (1996), "Rejection-inversion to generate
-    variates from monotone discrete distributions", vectorised: propose by inverting the integral of
-    the continuous envelope x^-s, accept by the squeeze test or the exact integral bound.
+    Rejection-inversion (Hoermann & Derflinger 1996, "Rejection-inversion to generate variates
+    from monotone discrete distributions"): the continuous hat g(x) = x^-s dominates the
+    probabilities in the sense that the mass g gives to [k - 1/2, k + 1/2] is at least k^-s (g is
+    convex).  With G an antiderivative of g, a point u drawn uniformly from [G(1/2), G(N + 1/2)]
+    is inverted to x = G^-1(u) and rounded to the nearest rank k; the point is kept when it falls
+    into the last k^-s of the slice [G(k - 1/2), G(k + 1/2)] that maps to k, so each rank is kept
+    with probability proportional to k^-s, and the rest are drawn again.
     """
     s = float(exponent)
+    if s <= 0.0:
+        raise ValueError("the exponent must be positive")
     N = float(num_elements)
+    a = 1.0 - s
 
-    def h(x):
-        return np.exp(-s * np.log(x))
+    def g(x):
+        return np.power(x, -s)
 
-    def helper1(x):  # log1p(x)/x, continuous at 0
-        return np.where(np.abs(x) > 1e-8, np.log1p(x) / np.where(x == 0, 1.0, x), 1.0 - x * (0.5 - x / 3.0))
+    if a == 0.0:   # s == 1: G = log
+        G, Ginv = np.log, np.exp
+    else:          # G(x) = (x^a - 1) / a, written with expm1 / log1p to keep small a exact
+        def G(x):
+            return np.expm1(a * np.log(x)) / a
 
-    def helper2(x):  # expm1(x)/x, continuous at 0
-        return np.where(np.abs(x) > 1e-8, np.expm1(x) / np.where(x == 0, 1.0, x), 1.0 + x * 0.5 * (1.0 + x / 3.0))
+        def Ginv(u):
+            return np.exp(np.log1p(a * u) / a)
 
-    def H(x):
-        lx = np.log(x)
-        return helper2((1.0 - s) * lx) * lx
-
-    def Hinv(x):
-        t = np.maximum(x * (1.0 - s), -1.0)
-        return np.exp(helper1(t) * x)
-
-    h_x1 = H(np.float64(1.5)) - 1.0
-    h_n = H(np.float64(N + 0.5))
-    sq = 2.0 - Hinv(H(np.float64(2.5)) - h(np.float64(2.0)))
+    lo, hi = G(np.float64(0.5)), G(np.float64(N + 0.5))
     out = np.empty(int(n), dtype=np.int64)
     todo = np.arange(int(n))
     while todo.size:
-        u = h_n + rng.random(todo.size) * (h_x1 - h_n)
-        x = Hinv(u)
-        k = np.clip(np.floor(x + 0.5), 1, N)
-        ok = (k - x <= sq) | (u >= H(k + 0.5) - h(k))
-        out[todo[ok]] = k[ok].astype(np.int64)
-        todo = todo[~ok]
+        u = lo + rng.random(todo.size) * (hi - lo)
+        k = np.clip(np.floor(Ginv(u) + 0.5), 1.0, N)
+        keep = u >= G(k + 0.5) - g(k)
+        out[todo[keep]] = k[keep].astype(np.int64)
+        todo = todo[~keep]
     return out
 
 

@@ -85,6 +85,18 @@ def test_table_bytes_and_argument_checks(lib):
     assert lib.ct_voxel_insert_neighbours(None, None, 1, 6, None) == ct.CT_E_INVALID
     assert lib.ct_voxel_insert_neighbours_alloc(None, None, None, 1, 6, None) == ct.CT_E_INVALID
     assert lib.ct_table_dedup_skewed(None, None, None) == ct.CT_E_INVALID
+    assert lib.ct_check_invariants(None, None, C.byref(cnt), None) == ct.CT_E_INVALID
+    assert lib.ct_dev_update_set(None, None, None, 1, None, None) == ct.CT_E_INVALID
+    assert lib.ct_table_debug_inject_claim_losses(None, 1, None) == ct.CT_E_INVALID
+    # grouped-plan options: merge runs and the block sizes 128 .. 1024 are known, others refused
+    plan = C.c_void_p()
+    assert lib.ct_plan_create(C.byref(plan)) == ct.CT_OK
+    nb = C.c_int64(0)
+    for opt in (0, ct.GROUP_MERGE_RUNS, ct.GROUP_BLOCK[128], ct.GROUP_BLOCK[1024] | 1):
+        assert lib.ct_plan_group_bytes(plan, opt, C.byref(nb)) == ct.CT_OK, opt
+    for opt in (4, 5 << 8, 11 << 8, 1 << 12):
+        assert lib.ct_plan_group_bytes(plan, opt, C.byref(nb)) == ct.CT_E_INVALID, opt
+    assert lib.ct_plan_destroy(plan) == ct.CT_OK
 
 
 def test_product_path_does_not_reach_the_oracle():

@@ -449,3 +449,42 @@ def test_device_finds_at_full_load(dev, n):
     np.testing.assert_array_equal(st.cpu().numpy(), ef)
     np.testing.assert_array_equal(v.cpu().numpy().view(np.uint64), ev)
     same(t, o, 64)
+
+
+@pytest.mark.parametrize("set_bits", [0, 64])
+def test_two_container_update_set(dev, set_bits):
+    """The two-container step of Section 4.1's reconstruction example in one kernel: each thread
+    asks the block map whether its key is there and inserts it into the update set.  Threads
+    repeat keys; some keys are in the set already; out-of-band bit patterns included.  The set
+    must end as its old keys plus the queried keys the map holds, each new key INSERTED by
+    exactly one of its elements, elements of keys the map lacks reporting 255."""
+    rng = rng_for(77)
+    resident = np.concatenate([RESERVED[:3], distinct_u64(rng, 20000)])
+    absent = distinct_u64(rng, 5000, exclude=resident)
+    q = np.concatenate([resident[rng.integers(0, resident.size, 150000)],
+                        absent[rng.integers(0, absent.size, 50000)], RESERVED])
+    q = q[rng.permutation(q.size)]
+    pre = np.concatenate([resident[:3000:3], absent[:100]])     # already in the set
+    vk = ct.VAL_NONE if set_bits == 0 else ct.VAL_U64
+    a = ct.Table(1 << 15, ct.VAL_U32, ct.HASH_MIX64, device=dev)
+    a.insert(g64(resident, dev), torch.arange(resident.size, dtype=torch.int32, device=dev))
+    b = ct.Table(1 << 15, vk, ct.HASH_MIX64, device=dev)
+    b.insert(g64(pre, dev), None if vk == ct.VAL_NONE else g64(np.zeros(pre.size, np.uint64), dev))
+    st = a.dev_update_set(b, g64(q, dev)).cpu().numpy()
+    oa = oracle.OracleTable(1 << 15, 32)
+    oa.insert(resident, np.arange(resident.size, dtype=np.uint32))
+    _, in_map = oa.find(q)
+    np.testing.assert_array_equal(st == 255, in_map == 0)
+    ob = oracle.OracleTable(1 << 15, set_bits)
+    ob.insert(pre, None if set_bits == 0 else np.zeros(pre.size, np.uint64))
+    new_keys = np.setdiff1d(np.unique(q[in_map == 1]), pre)
+    for key in np.unique(q[in_map == 1]):
+        s = st[q == key]
+        if key in new_keys:
+            assert (s == ct.INSERTED).sum() == 1 and (s == ct.PRESENT).sum() == s.size - 1, key
+        else:
+            assert (s == ct.PRESENT).all(), key
+    ob.insert(np.unique(q[in_map == 1]), None if set_bits == 0 else
+              np.zeros(np.unique(q[in_map == 1]).size, np.uint64))
+    same(b, ob, set_bits)
+    assert a.check() == 0

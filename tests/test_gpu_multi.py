@@ -157,16 +157,19 @@ def test_plan_full_size(dev):
         assert t.size() == o.size()
 
 
-@pytest.mark.parametrize("chunk,merge", [(0, False), (1024, False), (0, True), (1024, True)])
-def test_grouped_matches_oracle(dev, chunk, merge):
+@pytest.mark.parametrize("chunk,merge,block", [(0, False, 256), (1024, False, 256), (0, True, 256),
+                                               (1024, True, 256), (1024, False, 128),
+                                               (0, True, 512), (1024, True, 1024)])
+def test_grouped_matches_oracle(dev, chunk, merge, block):
     """Grouped form: one launch per stage per level over all tables; chunk 1024 cuts the larger
     batches into several steps (levels) per operation; merged runs turn each table's consecutive
-    same-kind operations into one operation over gathered copies of their arrays."""
+    same-kind operations into one operation over gathered copies of their arrays; the find /
+    insert / erase stages run with `block` threads per block (the tuner's block-size knob)."""
     w = small()
     exp, tabs = expected(w)
     r = Run(w, dev, chunk=chunk)
     p = r.plan(dev)
-    p.group(merge_runs=merge)
+    p.group(merge_runs=merge, block=block)
     nl, ns = p.group_info()
     assert nl > 0 and ns > 0
     if not merge:   # merging runs gives fewer steps than operations

@@ -1,5 +1,6 @@
 """The seeded input generators produce what they promise (no GPU, no container arithmetic)."""
 import numpy as np
+import pytest
 
 from paper_1908_05936_amd.workloads import large_table, pack_int3, plain_table, splitmix64, zipf_ranks, rng_for
 
@@ -11,16 +12,30 @@ def test_splitmix64_published_vector():
     assert splitmix64(1234567, 2, 1).tolist() == [9817491932198370423]
 
 
-def test_zipf_rank_frequencies():
+@pytest.mark.parametrize("N,s", [(1000, 1.1), (40, 1.0), (7, 2.5), (1 << 26, 1.1)])
+def test_zipf_rank_frequencies(N, s):
+    """Rank frequencies against the exact probabilities k^-s / H(N, s): every one of the top ranks
+    and the mass of the rest within 5 standard errors; the extreme ranks occur."""
     rng = rng_for(5)
-    N, s = 1000, 1.1
-    r = zipf_ranks(rng, 400000, N, s)
+    n = 400000
+    r = zipf_ranks(rng, n, N, s)
     assert r.min() >= 1 and r.max() <= N
-    p = np.arange(1, N + 1, dtype=np.float64) ** -s
-    p /= p.sum()
-    freq = np.bincount(r, minlength=N + 1)[1:] / r.size
-    for k in (1, 2, 3, 10, 100):
-        assert abs(freq[k - 1] - p[k - 1]) < 5 * np.sqrt(p[k - 1] / r.size) + 1e-4, k
+    top = min(N, 50)
+    k = np.arange(1, top + 1, dtype=np.float64)
+    if N <= 10**6:
+        H = (np.arange(1, N + 1, dtype=np.float64) ** -s).sum()
+    else:   # the head summed exactly, the tail by the Euler-Maclaurin integral
+        m = 10**6
+        H = (np.arange(1, m + 1, dtype=np.float64) ** -s).sum()
+        H += ((N + 0.5) ** (1 - s) - (m + 0.5) ** (1 - s)) / (1 - s)
+    p = k ** -s / H
+    freq = np.bincount(r, minlength=top + 1)[1:top + 1] / n
+    assert np.all(np.abs(freq - p) < 5 * np.sqrt(p * (1 - p) / n) + 1e-5)
+    rest = 1.0 - p.sum()
+    if rest > 0:
+        assert abs((r > top).mean() - rest) < 5 * np.sqrt(rest * (1 - rest) / n) + 1e-5
+    if N <= 50:
+        assert r.max() == N
 
 
 def test_plain_table_shape():
