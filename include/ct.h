@@ -198,6 +198,21 @@ ct_status ct_check_invariants(ct_table *t, const ct_pool *p, int64_t *h_violatio
 ct_status ct_check_invariants_detail(ct_table *t, const ct_pool *p, int64_t *h_violations,
                                      uint32_t *h_what, void *stream);
 
+/* Table health: *h_closed (nullable) = buckets without an empty slot, *h_tombstones (nullable) =
+   slots holding a tombstone.  An erase leaves a tombstone where its bucket holds no empty slot;
+   inserts reuse tombstones, but nothing else turns them back into empty slots, so after long
+   churn near full load more buckets close, and a lookup of an absent key walks past closed
+   buckets until it meets an open one (every bucket when none is open).  Synchronises. */
+ct_status ct_table_health(ct_table *t, int64_t *h_closed, int64_t *h_tombstones, void *stream);
+
+/* Reopen buckets in place: every bucket that no live key's probe path passes (no live key lies
+   further along a path that runs through it) gets its tombstones turned into empty slots.  Keys,
+   values, size and every result are unchanged; lookups of absent keys and inserts stop earlier
+   afterwards.  Uses the table's per-batch scratch as a bitmap of buckets (several passes over the
+   slots when that scratch holds fewer bits than buckets).  Asynchronous on `stream`; must not
+   overlap other calls on the table. */
+ct_status ct_table_purge(ct_table *t, void *stream);
+
 /* Host-side resizing (a capacity is fixed at creation, Section 4; growth is a copy into a larger
    table): insert every live (key, value) of `src` into `dst`, which must have the same value kind
    and room for all of them (capacity(dst) >= size(dst) + size(src), else CT_E_FULL and nothing

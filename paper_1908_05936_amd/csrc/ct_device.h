@@ -87,6 +87,8 @@ struct alignas(256) Header {
   uint64_t pool_h1, pool_h2;
   uint32_t inject;         // test hook: when nonzero, the first claim of every chunk element whose
                            // index is a multiple of it is treated as lost to another key
+  uint64_t closed_count;   // health scan: buckets without an empty slot
+  uint64_t tomb_count;     //              tombstone slots
 };
 static_assert(sizeof(Header) == 256, "the header fills one 256-byte line");
 

@@ -1753,6 +1753,81 @@ __global__ __launch_bounds__(kBlock) void k_check_pool(TableView t, const PoolHe
 }
 
 // ---------------------------------------------------------------------------------------------
+// table health and purge.  An erase leaves a tombstone where its bucket holds no empty slot, and
+// inserts turn tombstones back into keys; nothing turns a tombstone back into an empty slot, so
+// under long churn the buckets without an empty slot grow in number, and lookups of absent keys
+// walk past more of them.  The purge reopens every bucket that no live key's probe path passes:
+// its tombstones become empty slots.  A bucket that some live key passes (one before that key's
+// own bucket on its path) keeps its tombstones, so every live key stays reachable.
+// ---------------------------------------------------------------------------------------------
+// Buckets without an empty slot, and tombstones; 8 lanes per bucket.
+__global__ __launch_bounds__(kBlock) void k_health(TableView t) {
+  const int sub = threadIdx.x & 7;
+  const int64_t ngroups = (int64_t)gridDim.x * (kBlock / 8);
+  uint64_t closed = 0, tombs = 0;
+  const int64_t nbk = (int64_t)t.nb;
+  const int64_t span = ((nbk + ngroups - 1) / ngroups) * ngroups;   // equal trips: ballots below
+  for (int64_t b = (int64_t)blockIdx.x * (kBlock / 8) + (threadIdx.x >> 3); b < span; b += ngroups) {
+    const uint64_t key = b < nbk ? t.bk[b].s[sub].key : 0;
+    const uint32_t e = group_bits(__ballot(b < nbk && key == kEmpty));
+    if (b < nbk && sub == 0 && !e) ++closed;
+    if (b < nbk && key == kTomb) ++tombs;
+  }
+  closed = wave_sum(closed);
+  tombs = wave_sum(tombs);
+  if (wave_lane() == 0) {
+    if (closed) aadd64(&t.hdr->closed_count, closed);
+    if (tombs) aadd64(&t.hdr->tomb_count, tombs);
+  }
+}
+
+__global__ void k_health_begin(TableView t) {
+  t.hdr->closed_count = 0;
+  t.hdr->tomb_count = 0;
+}
+
+__global__ __launch_bounds__(kBlock) void k_purge_clear(uint32_t* __restrict__ bits, int64_t words) {
+  for (int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x; j < words;
+       j += (int64_t)gridDim.x * kBlock)
+    bits[j] = 0;
+}
+
+// Bit (b - w0) for every bucket b in [w0, w1) that a live key's probe path passes before the
+// key's own bucket.
+__global__ __launch_bounds__(kBlock) void k_purge_mark(TableView t, uint32_t* __restrict__ bits,
+                                                       int64_t w0, int64_t w1) {
+  const int64_t nslots = (int64_t)t.nb * kSlots;
+  for (int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x; j < nslots;
+       j += (int64_t)gridDim.x * kBlock) {
+    const uint64_t key = t.bk[j >> 3].s[j & 7].key;
+    if (key == kEmpty || key == kTomb) continue;
+    const uint64_t at = (uint64_t)(j >> 3);
+    const Seq q = probe_seq(t, key);
+    uint64_t b = q.home;
+    for (uint64_t step = 0; b != at && step < t.nb; ++step) {
+      if ((int64_t)b >= w0 && (int64_t)b < w1) {
+        const uint64_t r = b - (uint64_t)w0;
+        atomicOr(&bits[r >> 5], 1u << (r & 31));
+      }
+      b = next_bucket(t, b, q.step);
+    }
+  }
+}
+
+// Every bucket of [w0, w1) that no live key passes: its tombstones become empty slots.
+__global__ __launch_bounds__(kBlock) void k_purge_reopen(TableView t, const uint32_t* __restrict__ bits,
+                                                         int64_t w0, int64_t w1) {
+  const int64_t nslots = (w1 - w0) * kSlots;
+  for (int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x; j < nslots;
+       j += (int64_t)gridDim.x * kBlock) {
+    const uint64_t r = (uint64_t)(j >> 3);
+    if ((bits[r >> 5] >> (r & 31)) & 1u) continue;
+    uint64_t* k = &t.bk[(uint64_t)w0 + r].s[j & 7].key;
+    if (*k == kTomb) *k = kEmpty;
+  }
+}
+
+// ---------------------------------------------------------------------------------------------
 // pool kernels
 // ---------------------------------------------------------------------------------------------
 __global__ __launch_bounds__(kBlock) void k_pool_init(PoolHeader* ph, int32_t* stack, int64_t cap) {
@@ -2086,6 +2161,7 @@ struct ct_table {
   TableView v;
   int64_t chunk;      // Q: elements per chunk (power of two)
   uint64_t size_ub;   // upper bound of the live count known to the host
+  int64_t dd_bytes;   // bytes of the dedup scratch region at v.dd (the purge's bitmap)
 };
 
 struct ct_pool {
@@ -2276,10 +2352,10 @@ ct_status read_back(const T* dev, T* host, hipStream_t s) {
 // insert / erase drivers
 // ---------------------------------------------------------------------------------------------
 // Resolve the repeated keys of one chunk: binned for large chunks, dd otherwise.
-void dedup_chunk(ct_table* t, PoolHeader* pool, const uint64_t* kc, int64_t q, hipStream_t s) {
+void dedup_chunk(ct_table* t, const TableView& v, PoolHeader* pool, const uint64_t* kc, int64_t q,
+                 hipStream_t s) {
   const uint32_t db = dedup_slots_for(q);
-  if (t->v.r1k && q >= kBinMinChunk) {
-    const TableView& v = t->v;
+  if (v.r1k && q >= kBinMinChunk) {
     // blocks per coarse segment: enough for its expected fill (about c1 / 2) in one tile each
     const int blocks_per_seg = (int)std::max<int64_t>(1, (v.c1 / 2 + kBinTile - 1) / kBinTile);
     const int nfine = 1 << v.lp;
@@ -2290,39 +2366,47 @@ void dedup_chunk(ct_table* t, PoolHeader* pool, const uint64_t* kc, int64_t q, h
     launch(t, CT_KERNEL_DEDUP, s, [&] { k_bin_fallback_clear<<<flat_blocks(db / 2), kBlock, 0, s>>>(v, db); });
     launch(t, CT_KERNEL_DEDUP, s, [&] { k_bin_fallback_dedup<<<flat_blocks(q), kBlock, 0, s>>>(v, kc, q, db - 1); });
   } else {
-    launch(t, CT_KERNEL_PROLOGUE, s, [&] { k_prologue<<<flat_blocks(db / 2), kBlock, 0, s>>>(t->v, pool, db, q); });
-    launch(t, CT_KERNEL_DEDUP, s, [&] { k_dedup<<<flat_blocks(q), kBlock, 0, s>>>(t->v, kc, q, db - 1); });
+    launch(t, CT_KERNEL_PROLOGUE, s, [&] { k_prologue<<<flat_blocks(db / 2), kBlock, 0, s>>>(v, pool, db, q); });
+    launch(t, CT_KERNEL_DEDUP, s, [&] { k_dedup<<<flat_blocks(q), kBlock, 0, s>>>(v, kc, q, db - 1); });
   }
 }
 
+// Insert of n keys in chunks of at most `chunk`, with the per-chunk scratch that view `v` names
+// (the table's own, or another region holding the same arrays).
 template <int VK>
-ct_status insert_chunks(ct_table* t, const uint64_t* keys, const void* vals, int64_t n,
-                        uint8_t* status, hipStream_t s) {
+ct_status insert_chunks(ct_table* t, const TableView& v, int64_t chunk, const uint64_t* keys,
+                        const void* vals, int64_t n, uint8_t* status, hipStream_t s) {
   const int vb = VK == 1 ? 4 : 8;
-  for (int64_t c0 = 0; c0 < n; c0 += t->chunk) {
-    const int64_t q = std::min<int64_t>(t->chunk, n - c0);
+  for (int64_t c0 = 0; c0 < n; c0 += chunk) {
+    const int64_t q = std::min<int64_t>(chunk, n - c0);
     const uint32_t db = dedup_slots_for(q);
     const uint64_t* kc = keys + c0;
     const void* vc = VK ? static_cast<const void*>(static_cast<const uint8_t*>(vals) + c0 * vb) : nullptr;
     uint8_t* sc = status ? status + c0 : nullptr;
     const int gb = group_blocks((q + kSlots - 1) / kSlots);
     const int ntiles = (int)((q + kTile - 1) / kTile);
-    dedup_chunk(t, nullptr, kc, q, s);
-    launch(t, CT_KERNEL_INSERT, s, [&] { k_insert<VK, false><<<gb, kBlock, 0, s>>>(t->v, kc, vc, q, db - 1, sc, nullptr); });
-    launch(t, CT_KERNEL_APPLY, s, [&] { k_apply_count<<<1, 1024, 0, s>>>(t->v, gb); });
+    dedup_chunk(t, v, nullptr, kc, q, s);
+    launch(t, CT_KERNEL_INSERT, s, [&] { k_insert<VK, false><<<gb, kBlock, 0, s>>>(v, kc, vc, q, db - 1, sc, nullptr); });
+    launch(t, CT_KERNEL_APPLY, s, [&] { k_apply_count<<<1, 1024, 0, s>>>(v, gb); });
     // the host bound proves that no element can meet FULL: the rank pass is not needed
     const bool surely_fast = t->size_ub + (uint64_t)q <= (uint64_t)t->desc.capacity;
     if (!surely_fast) {
-      launch(t, CT_KERNEL_RANK, s, [&] { k_tile_count<<<ntiles, kBlock, 0, s>>>(t->v, q, 1); });
-      launch(t, CT_KERNEL_RANK, s, [&] { k_tile_scan<<<1, 1024, 0, s>>>(t->v, nullptr, ntiles, 0); });
-      launch(t, CT_KERNEL_FINAL, s, [&] { k_final<VK, 0><<<ntiles, kBlock, 0, s>>>(t->v, nullptr, nullptr, kc, vc, q, sc, nullptr); });
+      launch(t, CT_KERNEL_RANK, s, [&] { k_tile_count<<<ntiles, kBlock, 0, s>>>(v, q, 1); });
+      launch(t, CT_KERNEL_RANK, s, [&] { k_tile_scan<<<1, 1024, 0, s>>>(v, nullptr, ntiles, 0); });
+      launch(t, CT_KERNEL_FINAL, s, [&] { k_final<VK, 0><<<ntiles, kBlock, 0, s>>>(v, nullptr, nullptr, kc, vc, q, sc, nullptr); });
     }
-    if (sc) launch(t, CT_KERNEL_FIX, s, [&] { k_fix<<<flat_blocks(q), kBlock, 0, s>>>(t->v, sc, nullptr); });
+    if (sc) launch(t, CT_KERNEL_FIX, s, [&] { k_fix<<<flat_blocks(q), kBlock, 0, s>>>(v, sc, nullptr); });
     t->size_ub = std::min<uint64_t>(t->size_ub + (uint64_t)q, (uint64_t)t->desc.capacity);
     ct_status r = launched();
     if (r != CT_OK) return r;
   }
   return CT_OK;
+}
+
+template <int VK>
+ct_status insert_chunks(ct_table* t, const uint64_t* keys, const void* vals, int64_t n,
+                        uint8_t* status, hipStream_t s) {
+  return insert_chunks<VK>(t, t->v, t->chunk, keys, vals, n, status, s);
 }
 
 template <bool RELEASE>
@@ -2335,7 +2419,7 @@ ct_status erase_chunks(ct_table* t, ct_pool* p, const uint64_t* keys, int64_t n,
     uint8_t* ec = erased ? erased + c0 : nullptr;
     const int gb = group_blocks((q + kSlots - 1) / kSlots);
     const int ntiles = (int)((q + kTile - 1) / kTile);
-    dedup_chunk(t, RELEASE ? p->hdr : nullptr, kc, q, s);
+    dedup_chunk(t, t->v, RELEASE ? p->hdr : nullptr, kc, q, s);
     launch(t, CT_KERNEL_ERASE, s, [&] { k_erase<RELEASE><<<gb, kBlock, 0, s>>>(t->v, kc, q, db - 1, ec); });
     launch(t, CT_KERNEL_APPLY, s, [&] { k_apply_count<<<1, 1024, 0, s>>>(t->v, gb); });
     if (RELEASE) {
@@ -2417,6 +2501,7 @@ ct_status ct_table_init(void* d_buf, int64_t bytes, const ct_table_desc* d, void
   t->bytes = bytes;
   t->chunk = L.chunk;
   t->size_ub = 0;
+  t->dd_bytes = L.bins ? (int64_t)kBinCoarse * kBinSub * L.c1 * 8 : L.dslots * 8;
   TableView& v = t->v;
   v.hdr = reinterpret_cast<Header*>(base);
   v.bk = reinterpret_cast<Bucket*>(base + L.off_bk);
@@ -2761,6 +2846,38 @@ ct_status ct_check_invariants(ct_table* t, const ct_pool* p, int64_t* h_violatio
   return ct_check_invariants_detail(t, p, h_violations, nullptr, stream);
 }
 
+ct_status ct_table_health(ct_table* t, int64_t* h_closed, int64_t* h_tombstones, void* stream) {
+  if (!t || (!h_closed && !h_tombstones)) return CT_E_INVALID;
+  hipStream_t s = S(stream);
+  k_health_begin<<<1, 1, 0, s>>>(t->v);
+  k_health<<<group_blocks((int64_t)t->v.nb), kBlock, 0, s>>>(t->v);
+  if (launched() != CT_OK) return CT_E_HIP;
+  Header h;
+  if (hipMemcpyAsync(&h, t->v.hdr, sizeof(Header), hipMemcpyDeviceToHost, s) != hipSuccess)
+    return CT_E_HIP;
+  if (hipStreamSynchronize(s) != hipSuccess) return CT_E_HIP;
+  if (h_closed) *h_closed = (int64_t)h.closed_count;
+  if (h_tombstones) *h_tombstones = (int64_t)h.tomb_count;
+  return CT_OK;
+}
+
+ct_status ct_table_purge(ct_table* t, void* stream) {
+  if (!t) return CT_E_INVALID;
+  hipStream_t s = S(stream);
+  uint32_t* bits = reinterpret_cast<uint32_t*>(t->v.dd);
+  const int64_t window = t->dd_bytes / 4 * 32;   // buckets per pass: one bit each
+  const int64_t nb = (int64_t)t->v.nb;
+  for (int64_t w0 = 0; w0 < nb; w0 += window) {
+    const int64_t w1 = std::min(nb, w0 + window);
+    const int64_t words = (w1 - w0 + 31) / 32;
+    k_purge_clear<<<flat_blocks(words), kBlock, 0, s>>>(bits, words);
+    k_purge_mark<<<flat_blocks(nb * kSlots), kBlock, 0, s>>>(t->v, bits, w0, w1);
+    k_purge_reopen<<<flat_blocks((w1 - w0) * kSlots), kBlock, 0, s>>>(t->v, bits, w0, w1);
+    if (launched() != CT_OK) return CT_E_HIP;
+  }
+  return CT_OK;
+}
+
 ct_status ct_get_error(ct_table* t, uint32_t* h_err, void* stream) {
   if (!t || !h_err) return CT_E_INVALID;
   uint32_t e = 0;
@@ -2896,7 +3013,7 @@ ct_status ct_insert_alloc_batch(ct_table* t, ct_pool* p, const uint64_t* keys, i
     int32_t* vc = vals_out ? vals_out + c0 : nullptr;
     const int gb = group_blocks((q + kSlots - 1) / kSlots);
     const int ntiles = (int)((q + kTile - 1) / kTile);
-    dedup_chunk(t, p->hdr, kc, q, s);
+    dedup_chunk(t, t->v, p->hdr, kc, q, s);
     launch(t, CT_KERNEL_INSERT, s, [&] { k_insert<1, true><<<gb, kBlock, 0, s>>>(t->v, kc, nullptr, q, db - 1, sc, vc); });
     launch(t, CT_KERNEL_RANK, s, [&] { k_tile_count<<<ntiles, kBlock, 0, s>>>(t->v, q, 0); });
     launch(t, CT_KERNEL_RANK, s, [&] { k_tile_scan<<<1, 1024, 0, s>>>(t->v, p->hdr, ntiles, 1); });

@@ -74,6 +74,8 @@ SIGNATURES = {
     "ct_table_dedup_skewed": (C.c_int, [_P, C.POINTER(C.c_int32), _P]),
     "ct_table_debug_inject_claim_losses": (C.c_int, [_P, C.c_uint32, _P]),
     "ct_table_rehash": (C.c_int, [_P, _P, _P]),
+    "ct_table_health": (C.c_int, [_P, _PI64, _PI64, _P]),
+    "ct_table_purge": (C.c_int, [_P, _P]),
     "ct_table_device_view": (C.c_int, [_P, _I32, _P, _I64]),
     "ct_dev_apply": (C.c_int, [_P, _I32, _P, _P, _I64, _P, _P, _P]),
     "ct_dev_apply_mixed": (C.c_int, [_P, _P, _P, _P, _I64, _P, _P, _P]),
@@ -500,6 +502,17 @@ class Table:
         """Test hook: treat the first claim of every `every`-th chunk element as lost (0 = off)."""
         _check(lib().ct_table_debug_inject_claim_losses(self._h, int(every), _stream(self.device)),
                "ct_table_debug_inject_claim_losses")
+
+    def health(self):
+        """(buckets without an empty slot, tombstone slots)."""
+        c, tb = C.c_int64(0), C.c_int64(0)
+        _check(lib().ct_table_health(self._h, C.byref(c), C.byref(tb), _stream(self.device)),
+               "ct_table_health")
+        return c.value, tb.value
+
+    def purge(self):
+        """Turn the tombstones of every bucket no live key passes into empty slots."""
+        _check(lib().ct_table_purge(self._h, _stream(self.device)), "ct_table_purge")
 
     def dedup_skewed(self) -> bool:
         """True when recent chunks overflowed the dedup bins, so large chunks fold each tile's

@@ -88,6 +88,8 @@ def test_table_bytes_and_argument_checks(lib):
     assert lib.ct_check_invariants(None, None, C.byref(cnt), None) == ct.CT_E_INVALID
     assert lib.ct_dev_update_set(None, None, None, 1, None, None) == ct.CT_E_INVALID
     assert lib.ct_table_debug_inject_claim_losses(None, 1, None) == ct.CT_E_INVALID
+    assert lib.ct_table_health(None, C.byref(cnt), None, None) == ct.CT_E_INVALID
+    assert lib.ct_table_purge(None, None) == ct.CT_E_INVALID
     # grouped-plan options: merge runs and the block sizes 128 .. 1024 are known, others refused
     plan = C.c_void_p()
     assert lib.ct_plan_create(C.byref(plan)) == ct.CT_OK
