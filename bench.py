@@ -102,6 +102,8 @@ def parse():
     ap.add_argument("--no-rehash", action="store_true", help="skip the resize (rehash) figure")
     ap.add_argument("--no-mixed", action="store_true",
                     help="skip the mixed device-side operations figure")
+    ap.add_argument("--insert-path", choices=["auto", "resolve-first"], default="auto",
+                    help="how insert chunks resolve repeated keys (ct_table_set_insert_path)")
     ap.add_argument("--no-find-uniform", action="store_true",
                     help="skip the uniform-popularity find (counter runs keep to the step's kernels)")
     ap.add_argument("--serve-footprint-gb", type=float, default=40.0)
@@ -586,6 +588,7 @@ def main():
     del w
 
     table = ct.Table(cap, ct.VAL_U64, ct.HASH_MIX64, chunk=a.chunk, device=dev)
+    table.set_insert_path(ct.INSERT_AUTO if a.insert_path == "auto" else ct.INSERT_RESOLVE_FIRST)
     st_fill = torch.empty(n_fill, dtype=torch.uint8, device=dev)
     vals_out = torch.empty(n_find, dtype=torch.int64, device=dev)
     found = torch.empty(n_find, dtype=torch.uint8, device=dev)
@@ -708,6 +711,7 @@ def main():
             "capacity": cap,
             "bucket_count": table.bucket_count,
             "chunk": table.chunk,
+            "insert_path": a.insert_path,
             "ops_per_step": total_ops,
             "wall_Mops_s": total_ops * a.steps / wall / 1e6,
         },

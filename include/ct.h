@@ -22,10 +22,12 @@
  *  * Every 2^64 key value is a legal key: occupancy is kept without reserving key values
  *    (the indicator principle of Section 5.1).
  *  * Memory order: inside a batch, slots are claimed with relaxed compare-and-swap at device
- *    (agent) scope; a claim only has to be unique, since equal keys of one batch are resolved to
- *    their lowest index before any claim.  Batches are ordered by the stream: the outputs of a
- *    call, and the table state it leaves, are visible to work enqueued after it on the same
- *    stream (or after an event that follows it); the host sees them after synchronising.
+ *    (agent) scope; a claim only has to be unique.  Equal keys of one batch are resolved to their
+ *    lowest index either before any claim, or (speculative inserts, ct_table_set_insert_path)
+ *    after the claiming kernel has ended, from the copies that met their key; in both cases the
+ *    order comes from kernel boundaries, not from fences.  Batches are ordered by the stream: the
+ *    outputs of a call, and the table state it leaves, are visible to work enqueued after it on
+ *    the same stream (or after an event that follows it); the host sees them after synchronising.
  *
  * Batch semantics
  * ---------------
@@ -313,6 +315,18 @@ ct_status ct_table_debug_inject_claim_losses(ct_table *t, uint32_t every, void *
    repeated thousands of times), so its large chunks fold each tile's repeated keys before binning;
    0 otherwise.  Results never depend on it.  Synchronises. */
 ct_status ct_table_dedup_skewed(ct_table *t, int32_t *h_skewed, void *stream);
+
+/* How insert chunks resolve repeated keys (the index order of the batch semantics above).
+   CT_INSERT_AUTO (the default): a chunk that the host can prove cannot reach capacity is inserted
+   speculatively: every element probes and claims for itself, and only the elements that met their
+   key in the table (or lost a claim to a copy of it) are resolved afterwards, by lowest index.  A
+   batch of distinct keys absent from the table then needs no resolution pass at all.  Other
+   chunks resolve repeated keys first.  CT_INSERT_RESOLVE_FIRST: every chunk resolves repeated keys
+   before it touches the table.  Results are identical on both paths.  Host only: applies to
+   insert calls enqueued afterwards (ct_insert_alloc_batch always resolves first). */
+#define CT_INSERT_AUTO 0
+#define CT_INSERT_RESOLVE_FIRST 1
+ct_status ct_table_set_insert_path(ct_table *t, int32_t path);
 
 /* --- index pool: vector/deque of int32 used as a LIFO free list (Sections 4.2, 4.3) -------- */
 

@@ -1074,6 +1074,300 @@ __global__ __launch_bounds__(1024) void k_apply_count(TableView t, int nblocks) 
   apply_count_block(t, nblocks);
 }
 
+// ---------------------------------------------------------------------------------------------
+// Speculative insert: repeated keys resolved after the table update instead of before it.
+//
+// When the host can prove that a chunk cannot reach capacity, no element can meet FULL and the
+// index order matters only among copies of one key.  Every element then probes and claims for
+// itself.  Claims only turn free slots into keys during the kernel, and every copy of a key takes
+// the first free slot of the same probe sequence, so a key is stored at most once: a copy either
+// claims the slot, sees the key in a bucket, or loses its CAS to the key (the rescan after a lost
+// CAS looks for the key as well as for free slots).  The claimer is whichever copy got there
+// first, not necessarily the lowest index, and a copy that sees the key cannot tell whether it
+// was there before the chunk.  Such elements are "ambiguous": they report PRESENT and are listed.
+// After the kernel, the listed keys get their lowest listed index in dd, and every claimer looks
+// its key up there: when a listed copy has a lower index, that copy becomes the inserter (its
+// value goes into the slot, the statuses swap).  A listed key that no element claimed was present
+// before the chunk, so PRESENT was right.  The out-of-band keys are always listed and resolved
+// by one thread.  With distinct keys absent from the table nothing is listed and the resolution
+// kernels return at once.
+// ---------------------------------------------------------------------------------------------
+// Claim for an absent key from bucket b on (the retry after a lost CAS), watching for the key
+// itself: *seen is set when a copy of the key holds a slot on the way.  Returns the claimed slot,
+// or kNoPos (also when seen).
+__device__ __forceinline__ uint64_t claim_watch(const TableView& t, uint64_t key, uint64_t b,
+                                                uint64_t stride, int sub, bool* seen) {
+  for (uint64_t step = 0; step < t.nb; ++step) {
+    const uint64_t cur = t.bk[b].s[sub].key;
+    if (group_bits(__ballot(cur == key))) {
+      *seen = true;
+      return kNoPos;
+    }
+    uint32_t f = group_bits(__ballot(cur == kEmpty || cur == kTomb));
+    while (f) {
+      const int c = lowest(f);
+      int won = 0, same = 0;
+      if (sub == c) {
+        uint64_t expected = cur;
+        won = cas64(&t.bk[b].s[c].key, expected, key) ? 1 : 0;
+        same = !won && expected == key;
+      }
+      if (group_bits(__ballot(won))) return b * kSlots + (uint64_t)c;
+      if (group_bits(__ballot(same))) {
+        *seen = true;
+        return kNoPos;
+      }
+      f &= f - 1;
+    }
+    b = next_bucket(t, b, stride);
+  }
+  return kNoPos;
+}
+
+template <int VK>
+__device__ __forceinline__ int64_t insert_spec_range(const TableView& t,
+                                                     const uint64_t* __restrict__ keys,
+                                                     const void* __restrict__ vals,
+                                                     uint8_t* __restrict__ status, int64_t lo,
+                                                     int64_t hi, int64_t step) {
+  const int sub = threadIdx.x & 7;
+  const uint32_t inject = t.hdr->inject;
+  int64_t ins = 0;
+  for (int64_t g0 = lo + (int64_t)(threadIdx.x >> 3) * kSlots; g0 < hi; g0 += step) {
+    const int64_t i = g0 + sub;
+    const bool valid = i < hi;
+    const uint64_t key = valid ? keys[i] : kEmpty;
+    const uint64_t val = valid ? load_val<VK>(vals, i) : 0;
+    bool amb = valid && key >= kTomb;  // out-of-band keys: resolved after the kernel
+    uint8_t st = kPresent;
+    uint8_t claimed = 0;
+    const uint32_t A = group_bits(__ballot(valid && key < kTomb));
+    if (A) {
+      uint32_t found, hadE, freeb;
+      uint64_t mypos = kNoPos, myval = 0, myfb = 0, myexp = 0;
+      int myc = 0;
+      uint64_t mystep = 0;
+      group_probe<true>(t, key, A, sub, &found, &hadE, &freeb, &mypos, &myval, &myfb, &myc, &myexp,
+                        &mystep);
+      const uint32_t want = A & ~found & freeb;
+      bool seen = false;
+      if (want) {
+        int won = 0;
+        if ((want >> sub) & 1) {
+          uint64_t expected = myexp;
+          // (test hook: an injected loss leaves the slot free, so the retry below claims it)
+          if (!inject || (uint64_t)i % inject != 0) {
+            won = cas64(&t.bk[myfb].s[myc].key, expected, key) ? 1 : 0;
+            seen = !won && expected == key;
+          }
+        }
+        if (won) mypos = myfb * kSlots + (uint64_t)myc;
+        const uint32_t retry = want & ~group_bits(__ballot(won || seen));
+        if (retry) {  // lost the slot to another key: scan on, one key at a time
+          const int gb = group_base();
+#pragma unroll
+          for (int u = 0; u < kSlots; ++u) {
+            if (!((retry >> u) & 1)) continue;
+            const uint64_t ku = __shfl(key, gb + u, 64);
+            const uint64_t fbu = __shfl(myfb, gb + u, 64);
+            const uint64_t stu = __shfl(mystep, gb + u, 64);
+            bool su = false;
+            const uint64_t pos = claim_watch(t, ku, fbu, stu, sub, &su);
+            if (sub == u) {
+              mypos = pos;
+              seen = su;
+            }
+          }
+        }
+      }
+      if ((A >> sub) & 1) {
+        if (((found >> sub) & 1) || seen) {
+          amb = true;
+        } else if (!((want >> sub) & 1) || mypos == kNoPos) {
+          st = kFull;  // no free slot anywhere: cannot happen while size + chunk <= capacity
+          aor32(&t.hdr->err, kErrFull);
+        } else {
+          if (VK) t.bk[mypos >> 3].s[mypos & 7].val = val;
+          st = kInserted;
+          claimed = 1;
+          ++ins;
+        }
+      }
+    }
+    const uint32_t slot = wave_append(amb, &t.hdr->ndup);
+    if (amb) t.dup[slot] = make_uint2((uint32_t)i, 0u);
+    if (valid) {
+      t.flag[i] = claimed;
+      if (status) status[i] = st;
+    }
+  }
+  return ins;
+}
+
+template <int VK>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(VK == 0 ? 1 : 5))) void k_insert_spec(TableView t, const uint64_t* __restrict__ keys,
+                                                        const void* __restrict__ vals, int64_t q,
+                                                        uint8_t* __restrict__ status) {
+  const int64_t ins = insert_spec_range<VK>(t, keys, vals, status, (int64_t)blockIdx.x * kBlock, q,
+                                            (int64_t)gridDim.x * kBlock);
+  const int64_t tot = block_sum(ins);
+  if (threadIdx.x == 0) t.bcnt[blockIdx.x] = tot;
+}
+
+// Chunk header of a speculative chunk: snapshot, empty list, no out-of-band copy seen yet.
+// The host's size bound has proved that the chunk cannot reach capacity; a live count that
+// says otherwise is a library bug and raises kErrInternal.
+__global__ void k_spec_prologue(TableView t, int64_t q) {
+  if (threadIdx.x == 0) {
+    Header* h = t.hdr;
+    h->size0 = h->size;
+    h->spec_first[0] = h->spec_first[1] = kNone;
+    h->ndup = 0;
+    h->nnew = 0;
+    h->fast = 1u;
+    h->dmode = 0u;
+    if (h->size + (uint64_t)q > t.cap) h->err |= kErrInternal;
+  }
+}
+
+// dd entries the resolution of `nd` listed elements uses: a power of two >= 2 nd.
+__device__ __forceinline__ uint32_t spec_slots(uint32_t nd) {
+  uint32_t p = 2;
+  while (p < 2 * nd) p <<= 1;
+  return p;
+}
+
+// Block 0 adds the insert kernel's partials to the live count (`nblocks` of them); every block
+// then clears the dd entries the listed elements need (none when nothing is listed).
+__global__ __launch_bounds__(kBlock) void k_spec_clear(TableView t, int nblocks) {
+  if (blockIdx.x == 0) apply_count_block(t, nblocks);
+  const uint32_t nd = t.hdr->ndup;
+  if (nd == 0) return;
+  const int64_t units = spec_slots(nd) / 2;
+  const uint4 empty = make_uint4(0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu);
+  for (int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x; j < units; j += (int64_t)gridDim.x * kBlock)
+    reinterpret_cast<uint4*>(t.dd)[j] = empty;
+}
+
+// Lowest listed index per key, in dd.  Windows of 256 listed elements first resolve their keys
+// in LDS, so a key listed many times costs one global operation per window; the window's lowest
+// copy enters dd with one CAS, or lowers the held index with an atomic min (skipped when the held
+// index is already lower).  Out-of-band keys take an atomic min on their header word.
+__global__ __launch_bounds__(kBlock) void k_spec_amb(TableView t, const uint64_t* __restrict__ keys) {
+  const uint32_t nd = t.hdr->ndup;
+  if (nd == 0) return;
+  const uint32_t dmask = spec_slots(nd) - 1;
+  constexpr uint32_t kW = 2 * kBlock;
+  __shared__ unsigned long long wk[kW];
+  __shared__ uint32_t wmin[kW];
+  for (int64_t b0 = (int64_t)blockIdx.x * kBlock; b0 < nd; b0 += (int64_t)gridDim.x * kBlock) {
+    for (uint32_t j = threadIdx.x; j < kW; j += kBlock) {
+      wk[j] = kEmpty;
+      wmin[j] = kNone;
+    }
+    __syncthreads();
+    const int64_t j = b0 + threadIdx.x;
+    const bool valid = j < nd;
+    const uint32_t i = valid ? t.dup[j].x : 0u;
+    const uint64_t key = valid ? keys[i] : kEmpty;
+    const bool normal = valid && key < kTomb;
+    if (valid && !normal) amin32(&t.hdr->spec_first[key - kTomb], i);
+    const uint64_t mix = dedup_mix(key);
+    uint32_t s = (uint32_t)(mix >> 32) & (kW - 1);
+    if (normal) {
+      for (;;) {  // at most kBlock keys in kW slots: a free or matching slot exists
+        const unsigned long long old = atomicCAS(&wk[s], (unsigned long long)kEmpty,
+                                                 (unsigned long long)key);
+        if (old == kEmpty || old == key) break;
+        s = (s + 1) & (kW - 1);
+      }
+      atomicMin(&wmin[s], i);
+    }
+    __syncthreads();
+    if (normal && wmin[s] == i) {
+      const uint64_t tag = mix & 0xFFFFFFFF00000000ull;
+      const uint64_t mine = tag | (uint64_t)i;
+      uint32_t h = (uint32_t)mix & dmask;
+      for (uint32_t probe = 0; probe <= dmask; ++probe) {
+        uint64_t e = t.dd[h];
+        if (e == kEmpty) {
+          uint64_t expected = kEmpty;
+          if (cas64(&t.dd[h], expected, mine)) break;
+          e = expected;
+        }
+        if ((e & 0xFFFFFFFF00000000ull) == tag && keys[(uint32_t)e] == key) {
+          if (i < (uint32_t)e) amin64(&t.dd[h], mine);
+          break;
+        }
+        h = (h + 1) & dmask;
+      }
+    }
+    __syncthreads();  // the window's LDS table is reused by the next window
+  }
+}
+
+// Slot of a key that is known to be stored (one lane alone, eight key loads per bucket).
+__device__ __forceinline__ uint64_t lane_slot_of(const TableView& t, uint64_t key) {
+  const Seq q = probe_seq(t, key);
+  uint64_t b = q.home;
+  for (uint64_t step = 0; step < t.nb; ++step) {
+    for (int c = 0; c < kSlots; ++c)
+      if (t.bk[b].s[c].key == key) return b * kSlots + (uint64_t)c;
+    b = next_bucket(t, b, q.step);
+  }
+  return kNoPos;
+}
+
+// Every claimer whose key has a lower listed copy hands the insert to that copy.  Thread 0 of
+// block 0 inserts each out-of-band key for its lowest copy when it was absent.
+template <int VK>
+__global__ __launch_bounds__(kBlock) void k_spec_claimers(TableView t, const uint64_t* __restrict__ keys,
+                                                          const void* __restrict__ vals, int64_t q,
+                                                          uint8_t* __restrict__ status) {
+  const uint32_t nd = t.hdr->ndup;
+  if (nd == 0) return;
+  const uint32_t dmask = spec_slots(nd) - 1;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    Header* h = t.hdr;
+    for (int s = 0; s < 2; ++s) {
+      const uint32_t m = h->spec_first[s];
+      if (m == kNone || h->spec_live[s]) continue;
+      h->spec_live[s] = 1;
+      h->spec_val[s] = load_val<VK>(vals, m);
+      h->size += 1;
+      if (status) status[m] = kInserted;
+    }
+  }
+  for (int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x; c < q; c += (int64_t)gridDim.x * kBlock) {
+    if (!t.flag[c]) continue;
+    const uint64_t key = keys[c];
+    const uint64_t mix = dedup_mix(key);
+    const uint64_t tag = mix & 0xFFFFFFFF00000000ull;
+    uint32_t h = (uint32_t)mix & dmask;
+    for (uint32_t probe = 0; probe <= dmask; ++probe) {
+      const uint64_t e = t.dd[h];
+      if (e == kEmpty) break;
+      if ((e & 0xFFFFFFFF00000000ull) == tag && keys[(uint32_t)e] == key) {
+        const uint32_t m = (uint32_t)e;
+        if (m < (uint32_t)c) {
+          const uint64_t pos = lane_slot_of(t, key);
+          if (pos == kNoPos) {
+            aor32(&t.hdr->err, kErrInternal);
+          } else {
+            if (VK) t.bk[pos >> 3].s[pos & 7].val = load_val<VK>(vals, m);
+            if (status) {
+              status[m] = kInserted;
+              status[c] = kPresent;
+            }
+          }
+        }
+        break;
+      }
+      h = (h + 1) & dmask;
+    }
+  }
+}
+
 // Flagged count per tile of kTile elements.
 __global__ __launch_bounds__(kBlock) void k_tile_count(TableView t, int64_t q, int only_slow) {
   if (only_slow && t.hdr->fast) return;
@@ -2162,6 +2456,7 @@ struct ct_table {
   int64_t chunk;      // Q: elements per chunk (power of two)
   uint64_t size_ub;   // upper bound of the live count known to the host
   int64_t dd_bytes;   // bytes of the dedup scratch region at v.dd (the purge's bitmap)
+  int32_t insert_path = CT_INSERT_AUTO;  // how insert chunks resolve repeated keys
 };
 
 struct ct_pool {
@@ -2385,11 +2680,23 @@ ct_status insert_chunks(ct_table* t, const TableView& v, int64_t chunk, const ui
     uint8_t* sc = status ? status + c0 : nullptr;
     const int gb = group_blocks((q + kSlots - 1) / kSlots);
     const int ntiles = (int)((q + kTile - 1) / kTile);
+    // the host bound proves that no element can meet FULL: the rank pass is not needed
+    const bool surely_fast = t->size_ub + (uint64_t)q <= (uint64_t)t->desc.capacity;
+    if (surely_fast && t->insert_path == CT_INSERT_AUTO) {
+      // speculative: insert first, then resolve the copies of keys listed as ambiguous
+      launch(t, CT_KERNEL_PROLOGUE, s, [&] { k_spec_prologue<<<1, 64, 0, s>>>(v, q); });
+      launch(t, CT_KERNEL_INSERT, s, [&] { k_insert_spec<VK><<<gb, kBlock, 0, s>>>(v, kc, vc, q, sc); });
+      launch(t, CT_KERNEL_APPLY, s, [&] { k_spec_clear<<<flat_blocks(db / 2), kBlock, 0, s>>>(v, gb); });
+      launch(t, CT_KERNEL_DEDUP, s, [&] { k_spec_amb<<<flat_blocks(q), kBlock, 0, s>>>(v, kc); });
+      launch(t, CT_KERNEL_FIX, s, [&] { k_spec_claimers<VK><<<flat_blocks(q), kBlock, 0, s>>>(v, kc, vc, q, sc); });
+      t->size_ub = std::min<uint64_t>(t->size_ub + (uint64_t)q, (uint64_t)t->desc.capacity);
+      ct_status r = launched();
+      if (r != CT_OK) return r;
+      continue;
+    }
     dedup_chunk(t, v, nullptr, kc, q, s);
     launch(t, CT_KERNEL_INSERT, s, [&] { k_insert<VK, false><<<gb, kBlock, 0, s>>>(v, kc, vc, q, db - 1, sc, nullptr); });
     launch(t, CT_KERNEL_APPLY, s, [&] { k_apply_count<<<1, 1024, 0, s>>>(v, gb); });
-    // the host bound proves that no element can meet FULL: the rank pass is not needed
-    const bool surely_fast = t->size_ub + (uint64_t)q <= (uint64_t)t->desc.capacity;
     if (!surely_fast) {
       launch(t, CT_KERNEL_RANK, s, [&] { k_tile_count<<<ntiles, kBlock, 0, s>>>(v, q, 1); });
       launch(t, CT_KERNEL_RANK, s, [&] { k_tile_scan<<<1, 1024, 0, s>>>(v, nullptr, ntiles, 0); });
@@ -2904,6 +3211,12 @@ ct_status ct_table_dedup_skewed(ct_table* t, int32_t* h_skewed, void* stream) {
   ct_status r = read_back(&t->v.hdr->dskew, &v, S(stream));
   if (r != CT_OK) return r;
   *h_skewed = v ? 1 : 0;
+  return CT_OK;
+}
+
+ct_status ct_table_set_insert_path(ct_table* t, int32_t path) {
+  if (!t || (path != CT_INSERT_AUTO && path != CT_INSERT_RESOLVE_FIRST)) return CT_E_INVALID;
+  t->insert_path = path;
   return CT_OK;
 }
 

@@ -26,6 +26,7 @@ GROUP_MERGE_RUNS = 1
 GROUP_BLOCK = {128: 7 << 8, 256: 0, 512: 9 << 8, 1024: 10 << 8}   # CT_GROUP_BLOCK(threads)
 OP_CLEAR, OP_INSERT, OP_FIND, OP_ERASE = 0, 1, 2, 3
 HASH_MIX64, HASH_VOXEL21 = 0, 1
+INSERT_AUTO, INSERT_RESOLVE_FIRST = 0, 1  # ct_table_set_insert_path
 CHECK_SIZE, CHECK_DUPLICATE, CHECK_REACH, CHECK_POOL = 1, 2, 12, 32
 
 
@@ -72,6 +73,7 @@ SIGNATURES = {
     "ct_check_invariants_detail": (C.c_int, [_P, _P, _PI64, C.POINTER(C.c_uint32), _P]),
     "ct_get_error": (C.c_int, [_P, C.POINTER(C.c_uint32), _P]),
     "ct_table_dedup_skewed": (C.c_int, [_P, C.POINTER(C.c_int32), _P]),
+    "ct_table_set_insert_path": (C.c_int, [_P, _I32]),
     "ct_table_debug_inject_claim_losses": (C.c_int, [_P, C.c_uint32, _P]),
     "ct_table_rehash": (C.c_int, [_P, _P, _P]),
     "ct_table_health": (C.c_int, [_P, _PI64, _PI64, _P]),
@@ -521,6 +523,10 @@ class Table:
         _check(lib().ct_table_dedup_skewed(self._h, C.byref(v), _stream(self.device)),
                "ct_table_dedup_skewed")
         return bool(v.value)
+
+    def set_insert_path(self, path: int):
+        """INSERT_AUTO (speculative where no element can meet FULL) or INSERT_RESOLVE_FIRST."""
+        _check(lib().ct_table_set_insert_path(self._h, int(path)), "ct_table_set_insert_path")
 
     def profiling(self, enable: bool = True):
         _check(lib().ct_table_set_profiling(self._h, int(enable)), "ct_table_set_profiling")
