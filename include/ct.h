@@ -134,6 +134,19 @@ ct_status ct_table_value_bytes(const ct_table *t, int32_t *bytes);
 ct_status ct_insert_batch(ct_table *t, const uint64_t *keys, const void *vals, int64_t n,
                           uint8_t *status, void *stream);
 
+/* ct_insert_batch for callers that cannot allocate device memory, or must not do so while they
+   run (code under HIP graph capture, tight serving loops, harnesses that forbid allocation).  Same
+   arguments, same results and the same table as ct_insert_batch, but the per-chunk scratch
+   (repeated-key table, marks, lists, rank sums, count partials: about 1.2 MiB) lives in one static
+   device array per GPU instead of the table buffer, and no call allocates anything.  The batch
+   runs in chunks of at most 2^15 elements, the largest the array holds, so every batch size is
+   accepted.  Every call on one GPU shares that GPU's array: calls that overlap on one GPU (other
+   streams, other threads, other tables) race on it and must be serialised by the caller.  The
+   array keeps the last call's contents; each chunk clears what it needs itself.  CT_E_HIP when
+   the array's device address cannot be obtained. */
+ct_status ct_insert_batch_noalloc(ct_table *t, const uint64_t *keys, const void *vals, int64_t n,
+                                  uint8_t *status, void *stream);
+
 /* find / contains (Section 4.1) for an array.  vals_out[n] (nullable; u32 or u64 by value kind;
    not allowed for sets) receives the mapped value, or all-ones of the value width when the key is
    absent; found[n] (nullable) receives 1 when present, else 0.  Read-only and lock-free. */

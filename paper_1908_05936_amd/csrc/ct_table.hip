@@ -23,6 +23,7 @@
 #include <cstdint>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -3865,6 +3866,122 @@ ct_status ct_graph_launch(void* graph_exec, void* stream) {
 ct_status ct_graph_destroy(void* graph_exec) {
   if (!graph_exec) return CT_E_INVALID;
   return hipGraphExecDestroy(static_cast<hipGraphExec_t>(graph_exec)) == hipSuccess ? CT_OK : CT_E_HIP;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------------------------
+// Allocation-free insert: the per-chunk scratch lives in a static device array, not in the
+// table's buffer.  One array per GPU (each device holds its own copy), shared by every call on
+// that GPU: calls that overlap on one GPU race on it.  Every kernel that needs part of it cleared
+// clears it itself at the start of each chunk (the prologue kernels), so a call never depends on
+// what the previous call left there.
+// ---------------------------------------------------------------------------------------------
+namespace {
+
+constexpr int64_t kStaticChunk = 1 << 15;  // elements per chunk: below the binned-dedup size
+
+struct StaticScratch {
+  int64_t dd, dmark, dup, flag, ref, tsum, bcnt, total;
+};
+
+constexpr StaticScratch static_scratch_layout() {
+  StaticScratch L{};
+  int64_t off = 0;
+  L.dd = off;
+  off += 2 * kStaticChunk * 8;
+  L.dmark = off;
+  off += kStaticChunk;
+  L.dup = off;
+  off += kStaticChunk * 8;
+  L.flag = off;
+  off += kStaticChunk;
+  L.ref = off;
+  off += kStaticChunk * 8;
+  L.tsum = off;
+  off += 256;  // kStaticChunk / kTile tile sums, 4 bytes each
+  L.bcnt = off;
+  off += (int64_t)kMaxGroupBlocks * 8;
+  L.total = off;
+  return L;
+}
+
+constexpr StaticScratch kStaticLayout = static_scratch_layout();
+static_assert(kStaticChunk / kTile * 4 <= 256, "tile sums fit their region");
+static_assert(kStaticLayout.dd % 256 == 0 && kStaticLayout.dmark % 256 == 0 &&
+                  kStaticLayout.dup % 256 == 0 && kStaticLayout.flag % 256 == 0 &&
+                  kStaticLayout.ref % 256 == 0 && kStaticLayout.tsum % 256 == 0 &&
+                  kStaticLayout.bcnt % 256 == 0,
+              "every region starts on a 256-byte boundary");
+
+}  // namespace
+
+static __device__ __align__(256) uint8_t scratch[kStaticLayout.total];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+uint8_t* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on the device that runs `s`, looked up once per device with that
+// device current.  The array's name is a host-side stand-in and never reaches a kernel.
+ct_status scratch_for_stream(hipStream_t s, uint8_t** out) {
+  int dev = -1;
+  if (s) {
+    if (hipStreamGetDevice(s, &dev) != hipSuccess) return CT_E_HIP;
+  } else if (hipGetDevice(&dev) != hipSuccess) {
+    return CT_E_HIP;
+  }
+  if (dev < 0 || dev >= kMaxDevices) return CT_E_INVALID;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    int prev = -1;
+    if (hipGetDevice(&prev) != hipSuccess) return CT_E_HIP;
+    if (prev != dev && hipSetDevice(dev) != hipSuccess) return CT_E_HIP;
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (prev != dev) (void)hipSetDevice(prev);
+    if (e != hipSuccess || !p) return CT_E_HIP;
+    g_scratch_ptr[dev] = static_cast<uint8_t*>(p);
+  }
+  *out = g_scratch_ptr[dev];
+  return CT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+ct_status ct_insert_batch_noalloc(ct_table* t, const uint64_t* keys, const void* vals, int64_t n,
+                                  uint8_t* status, void* stream) {
+  ct_status r = check_batch(t, keys, n);
+  if (r != CT_OK) return r;
+  const int vk = t->desc.val_kind;
+  if (vk != CT_VAL_NONE && !vals) return CT_E_INVALID;
+  if (n == 0) return CT_OK;
+  hipStream_t s = S(stream);
+  uint8_t* base = nullptr;
+  r = scratch_for_stream(s, &base);
+  if (r != CT_OK) return r;
+  TableView w = t->v;  // the table's slots and header, the static array's scratch
+  w.dd = reinterpret_cast<uint64_t*>(base + kStaticLayout.dd);
+  w.dmark = base + kStaticLayout.dmark;
+  w.dup = reinterpret_cast<uint2*>(base + kStaticLayout.dup);
+  w.flag = base + kStaticLayout.flag;
+  w.ref = reinterpret_cast<uint64_t*>(base + kStaticLayout.ref);
+  w.tsum = reinterpret_cast<uint32_t*>(base + kStaticLayout.tsum);
+  w.bcnt = reinterpret_cast<int64_t*>(base + kStaticLayout.bcnt);
+  w.r1k = nullptr;  // chunks below the binned size resolve repeats through dd
+  w.r1i = nullptr;
+  w.r2k = nullptr;
+  w.r2i = nullptr;
+  w.bcur = nullptr;
+  w.dfirst = nullptr;
+  const int64_t chunk = std::min<int64_t>(t->chunk, kStaticChunk);
+  if (vk == CT_VAL_U32) return insert_chunks<1>(t, w, chunk, keys, vals, n, status, s);
+  if (vk == CT_VAL_U64) return insert_chunks<2>(t, w, chunk, keys, vals, n, status, s);
+  return insert_chunks<0>(t, w, chunk, keys, nullptr, n, status, s);
 }
 
 }  // extern "C"

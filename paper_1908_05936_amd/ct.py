@@ -64,6 +64,7 @@ SIGNATURES = {
     "ct_table_profile": (C.c_int, [_P, C.c_int32, C.POINTER(C.c_double), _PI64]),
     "ct_table_profile_reset": (C.c_int, [_P]),
     "ct_insert_batch": (C.c_int, [_P, _P, _P, _I64, _P, _P]),
+    "ct_insert_batch_noalloc": (C.c_int, [_P, _P, _P, _I64, _P, _P]),
     "ct_find_batch": (C.c_int, [_P, _P, _I64, _P, _P, _P]),
     "ct_erase_batch": (C.c_int, [_P, _P, _I64, _P, _P]),
     "ct_size": (C.c_int, [_P, _PI64, _P]),
