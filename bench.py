@@ -44,6 +44,7 @@ INSERT_BYTES = 8 + 8 + 1 + 2 * 128  # key, value in, status out; bucket line rea
 ERASE_BYTES = 8 + 1 + 2 * 128       # key in, flag out; bucket line read and written back
 METRIC = "find & insert Mops/s at load 0.8 (1 GPU); served p50/p99 batch latency"
 PMC_SUMMARY = os.path.join(ROOT, "profiles", "pmc_large_table.md")
+INSERT_PATHS = {"auto": 0, "resolve-first": 1, "speculative": 2}   # ct_table_set_insert_path
 KERNEL_SOURCES = ["include/ct.h", "paper_1908_05936_amd/csrc/ct_device.h",
                   "paper_1908_05936_amd/csrc/ct_dev_api.h",
                   "paper_1908_05936_amd/csrc/ct_table.hip"]
@@ -102,7 +103,7 @@ def parse():
     ap.add_argument("--no-rehash", action="store_true", help="skip the resize (rehash) figure")
     ap.add_argument("--no-mixed", action="store_true",
                     help="skip the mixed device-side operations figure")
-    ap.add_argument("--insert-path", choices=["auto", "resolve-first"], default="auto",
+    ap.add_argument("--insert-path", choices=["auto", "resolve-first", "speculative"], default="auto",
                     help="how insert chunks resolve repeated keys (ct_table_set_insert_path)")
     ap.add_argument("--no-find-uniform", action="store_true",
                     help="skip the uniform-popularity find (counter runs keep to the step's kernels)")
@@ -588,7 +589,7 @@ def main():
     del w
 
     table = ct.Table(cap, ct.VAL_U64, ct.HASH_MIX64, chunk=a.chunk, device=dev)
-    table.set_insert_path(ct.INSERT_AUTO if a.insert_path == "auto" else ct.INSERT_RESOLVE_FIRST)
+    table.set_insert_path(INSERT_PATHS[a.insert_path])
     st_fill = torch.empty(n_fill, dtype=torch.uint8, device=dev)
     vals_out = torch.empty(n_find, dtype=torch.int64, device=dev)
     found = torch.empty(n_find, dtype=torch.uint8, device=dev)

@@ -49,6 +49,9 @@ constexpr int kBinFineCap = 3072;       // entries of a fine bin (3 x the mean; 
 constexpr int kBinLds = 2048;           // LDS hash slots of the fine-bin dedup: distinct keys of a
                                         // bin must be fewer (else the chunk takes the fallback)
 constexpr int kMaxFinePerCoarse = 256;  // fine bins per coarse bin at the largest chunk (2^24)
+constexpr int kMaxGroupBlocks = 16384;  // blocks of one insert/erase launch: its count partials
+constexpr int kStripeRegion = 4096;     // behind the partials: the speculative insert's listed
+                                        // counts, 32 words on separate 128-byte lines
 
 enum : uint8_t { kPresent = 0, kInserted = 1, kFull = 2, kNoStatus = 0xFF };
 enum : uint32_t { kErrFull = 1u, kErrPool = 2u, kErrInternal = 0x80000000u };
@@ -137,6 +140,8 @@ struct TableView {
   uint32_t* dfirst; // per repeated element: index of its key's first occurrence
   uint32_t c1, c2;  // capacities of a coarse segment and of a fine bin
   int lp1, lp;      // log2 of P1 and of P
+  uint64_t* fb;     // host-mapped word (or null): (keys << 32 | keys newly stored) of the table's
+                    // last insert chunk, which the host reads to pick the next chunk's path
   int hash;         // 0 mix64, 1 voxel21
   int nb_pow2;
   int step_mode;    // probe step between buckets: 0 linear (1), 1 odd (nb a power of two),

@@ -1056,23 +1056,36 @@ __global__ __launch_bounds__(kBlock) void k_erase(TableView t, const uint64_t* _
 }
 
 // Add the per-block partials of the preceding insert/erase kernel to the live count.
-__device__ __forceinline__ void apply_count_block(const TableView& t, int nparts) {
+// Returns the change (valid on thread 0).
+__device__ __forceinline__ int64_t apply_count_block(const TableView& t, int nparts) {
   int64_t v = 0;
   for (int j = threadIdx.x; j < nparts; j += blockDim.x) v += t.bcnt[j];
   v = (int64_t)wave_sum((uint64_t)v);
   __shared__ int64_t part[16];
   if (wave_lane() == 0) part[threadIdx.x >> 6] = v;
   __syncthreads();
+  int64_t s = 0;
   if (threadIdx.x == 0) {
-    int64_t s = 0;
     for (int w = 0; w < (int)(blockDim.x >> 6); ++w) s += part[w];
     if (s) t.hdr->size = (uint64_t)((int64_t)t.hdr->size + s);
   }
   __syncthreads();
+  return s;
 }
 
-__global__ __launch_bounds__(1024) void k_apply_count(TableView t, int nblocks) {
-  apply_count_block(t, nblocks);
+// The host's view of how an insert chunk of q keys went: q and the keys it stored, one 64-bit
+// store to host-mapped memory (read without synchronising; a stale or torn read only changes
+// which path the next chunk takes, never a result).
+__device__ __forceinline__ void insert_feedback(const TableView& t, int64_t q, int64_t stored) {
+  if (!t.fb || q <= 0) return;
+  const uint64_t w = ((uint64_t)q << 32) | (uint64_t)(uint32_t)(stored < 0 ? 0 : stored);
+  __hip_atomic_store(t.fb, w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+// fb_q > 0: the partials are the stored keys of an insert chunk of fb_q keys (report them).
+__global__ __launch_bounds__(1024) void k_apply_count(TableView t, int nblocks, int64_t fb_q) {
+  const int64_t s = apply_count_block(t, nblocks);
+  if (threadIdx.x == 0 && fb_q) insert_feedback(t, fb_q, s);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -1085,14 +1098,35 @@ __global__ __launch_bounds__(1024) void k_apply_count(TableView t, int nblocks) 
 // claims the slot, sees the key in a bucket, or loses its CAS to the key (the rescan after a lost
 // CAS looks for the key as well as for free slots).  The claimer is whichever copy got there
 // first, not necessarily the lowest index, and a copy that sees the key cannot tell whether it
-// was there before the chunk.  Such elements are "ambiguous": they report PRESENT and are listed.
-// After the kernel, the listed keys get their lowest listed index in dd, and every claimer looks
-// its key up there: when a listed copy has a lower index, that copy becomes the inserter (its
-// value goes into the slot, the statuses swap).  A listed key that no element claimed was present
-// before the chunk, so PRESENT was right.  The out-of-band keys are always listed and resolved
-// by one thread.  With distinct keys absent from the table nothing is listed and the resolution
-// kernels return at once.
+// was there before the chunk.  Such elements are "listed" (flag 2; claimers have flag 1): they
+// report PRESENT.  After the kernel, a key needs a fix only when it has a claimer and a listed
+// copy of lower index; that copy becomes the inserter (its value goes into the slot, the statuses
+// swap).  A listed key without a claimer was present before the chunk, so PRESENT was right.
+//
+// The resolution pairs claimers with listed copies through the dd table, in the direction that
+// puts fewer keys into it: with few listed elements (a batch of mostly new keys), the listed keys
+// enter dd with their lowest index and the claimers look themselves up; with mostly listed
+// elements (keys that are mostly present already), the claimers enter dd and each listed copy
+// lowers the index beside its claimer's entry, which the claimer checks afterwards.  The
+// out-of-band keys are always listed and resolved by one thread.  With distinct keys absent from
+// the table nothing is listed, and the resolution kernels return at once.
 // ---------------------------------------------------------------------------------------------
+constexpr int kListStripes = 32;          // listed-count stripes, one per 128-byte line
+constexpr int kListStripeWords = 32;      // u32 words between stripes
+enum : uint8_t { kFlagNone = 0, kFlagClaimed = 1, kFlagListed = 2 };
+
+// The listed-count stripes sit behind the block partials of the table's bcnt region.
+__device__ __forceinline__ uint32_t* list_stripes(const TableView& t) {
+  return reinterpret_cast<uint32_t*>(t.bcnt + kMaxGroupBlocks);
+}
+
+__device__ __forceinline__ uint32_t listed_total(const TableView& t) {
+  const uint32_t* st = list_stripes(t);
+  uint32_t n = 0;
+  for (int j = 0; j < kListStripes; ++j) n += st[j * kListStripeWords];
+  return n;
+}
+
 // Claim for an absent key from bucket b on (the retry after a lost CAS), watching for the key
 // itself: *seen is set when a copy of the key holds a slot on the way.  Returns the claimed slot,
 // or kNoPos (also when seen).
@@ -1125,15 +1159,16 @@ __device__ __forceinline__ uint64_t claim_watch(const TableView& t, uint64_t key
   return kNoPos;
 }
 
+// Elements [lo, hi) of a chunk, 8 per group.  Returns this thread's (stored, listed) counts.
 template <int VK>
-__device__ __forceinline__ int64_t insert_spec_range(const TableView& t,
-                                                     const uint64_t* __restrict__ keys,
-                                                     const void* __restrict__ vals,
-                                                     uint8_t* __restrict__ status, int64_t lo,
-                                                     int64_t hi, int64_t step) {
+__device__ __forceinline__ uint2 insert_spec_range(const TableView& t,
+                                                   const uint64_t* __restrict__ keys,
+                                                   const void* __restrict__ vals,
+                                                   uint8_t* __restrict__ status, int64_t lo,
+                                                   int64_t hi, int64_t step) {
   const int sub = threadIdx.x & 7;
   const uint32_t inject = t.hdr->inject;
-  int64_t ins = 0;
+  uint32_t ins = 0, listed = 0;
   for (int64_t g0 = lo + (int64_t)(threadIdx.x >> 3) * kSlots; g0 < hi; g0 += step) {
     const int64_t i = g0 + sub;
     const bool valid = i < hi;
@@ -1195,30 +1230,35 @@ __device__ __forceinline__ int64_t insert_spec_range(const TableView& t,
         }
       }
     }
-    const uint32_t slot = wave_append(amb, &t.hdr->ndup);
-    if (amb) t.dup[slot] = make_uint2((uint32_t)i, 0u);
     if (valid) {
-      t.flag[i] = claimed;
+      t.flag[i] = claimed ? kFlagClaimed : (amb ? kFlagListed : kFlagNone);
       if (status) status[i] = st;
+      listed += amb ? 1u : 0u;
     }
   }
-  return ins;
+  return make_uint2(ins, listed);
 }
 
 template <int VK>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(VK == 0 ? 1 : 5))) void k_insert_spec(TableView t, const uint64_t* __restrict__ keys,
                                                         const void* __restrict__ vals, int64_t q,
                                                         uint8_t* __restrict__ status) {
-  const int64_t ins = insert_spec_range<VK>(t, keys, vals, status, (int64_t)blockIdx.x * kBlock, q,
-                                            (int64_t)gridDim.x * kBlock);
-  const int64_t tot = block_sum(ins);
-  if (threadIdx.x == 0) t.bcnt[blockIdx.x] = tot;
+  const uint2 c = insert_spec_range<VK>(t, keys, vals, status, (int64_t)blockIdx.x * kBlock, q,
+                                        (int64_t)gridDim.x * kBlock);
+  // both counts in one reduction: stored in the low half, listed in the high half
+  const int64_t tot = block_sum((int64_t)c.x + ((int64_t)c.y << 32));
+  if (threadIdx.x == 0) {
+    t.bcnt[blockIdx.x] = tot & 0xFFFFFFFFll;
+    const uint32_t nl = (uint32_t)(tot >> 32);
+    // one atomic per block with listed elements, spread over the stripes
+    if (nl) aadd32(&list_stripes(t)[(blockIdx.x % kListStripes) * kListStripeWords], nl);
+  }
 }
 
-// Chunk header of a speculative chunk: snapshot, empty list, no out-of-band copy seen yet.
 // The host's size bound has proved that the chunk cannot reach capacity; a live count that
-// says otherwise is a library bug and raises kErrInternal.
+// says otherwise is a library bug and raises kErrInternal.  Also zeroes the listed counts.
 __global__ void k_spec_prologue(TableView t, int64_t q) {
+  if (threadIdx.x < kListStripes) list_stripes(t)[threadIdx.x * kListStripeWords] = 0;
   if (threadIdx.x == 0) {
     Header* h = t.hdr;
     h->size0 = h->size;
@@ -1231,49 +1271,112 @@ __global__ void k_spec_prologue(TableView t, int64_t q) {
   }
 }
 
-// dd entries the resolution of `nd` listed elements uses: a power of two >= 2 nd.
-__device__ __forceinline__ uint32_t spec_slots(uint32_t nd) {
-  uint32_t p = 2;
-  while (p < 2 * nd) p <<= 1;
+// Resolution direction and dd entries for `nd` listed elements of a q-element chunk.
+struct SpecPlan {
+  bool by_claimers;  // claimers enter dd (mostly listed elements)
+  uint32_t slots;    // dd entries in use: a power of two >= 2 x the keys entering dd
+};
+
+__device__ __forceinline__ SpecPlan spec_plan(uint32_t nd, int64_t q) {
+  SpecPlan p;
+  p.by_claimers = 2 * (int64_t)nd > q;
+  const uint32_t enter = p.by_claimers ? (uint32_t)(q - nd) : nd;
+  uint32_t s = 2;
+  while (s < 2 * enter) s <<= 1;
+  p.slots = s;
   return p;
 }
 
-// Block 0 adds the insert kernel's partials to the live count (`nblocks` of them); every block
-// then clears the dd entries the listed elements need (none when nothing is listed).
-__global__ __launch_bounds__(kBlock) void k_spec_clear(TableView t, int nblocks) {
-  if (blockIdx.x == 0) apply_count_block(t, nblocks);
-  const uint32_t nd = t.hdr->ndup;
-  if (nd == 0) return;
-  const int64_t units = spec_slots(nd) / 2;
-  const uint4 empty = make_uint4(0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu);
-  for (int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x; j < units; j += (int64_t)gridDim.x * kBlock)
-    reinterpret_cast<uint4*>(t.dd)[j] = empty;
+// In the claimer direction, the lowest listed index per claimer entry sits behind the entries.
+__device__ __forceinline__ uint32_t* spec_low(const TableView& t, const SpecPlan& p) {
+  return reinterpret_cast<uint32_t*>(t.dd + p.slots);
 }
 
-// Lowest listed index per key, in dd.  Windows of 256 listed elements first resolve their keys
-// in LDS, so a key listed many times costs one global operation per window; the window's lowest
-// copy enters dd with one CAS, or lowers the held index with an atomic min (skipped when the held
-// index is already lower).  Out-of-band keys take an atomic min on their header word.
-__global__ __launch_bounds__(kBlock) void k_spec_amb(TableView t, const uint64_t* __restrict__ keys) {
-  const uint32_t nd = t.hdr->ndup;
+// Block 0 adds the stored keys to the live count (`nblocks` partials); every block clears the dd
+// entries (and, in the claimer direction, the lowest-index words) the resolution uses.
+__global__ __launch_bounds__(kBlock) void k_spec_clear(TableView t, int nblocks, int64_t q) {
+  if (blockIdx.x == 0) {
+    const int64_t stored = apply_count_block(t, nblocks);
+    if (threadIdx.x == 0) insert_feedback(t, q, stored);
+  }
+  __shared__ uint32_t snd;
+  if (threadIdx.x == 0) {
+    snd = listed_total(t);
+    if (blockIdx.x == 0) t.hdr->ndup = snd;  // for the kernels that follow
+  }
+  __syncthreads();
+  const uint32_t nd = snd;
   if (nd == 0) return;
-  const uint32_t dmask = spec_slots(nd) - 1;
+  const SpecPlan p = spec_plan(nd, q);
+  const int64_t units = p.slots / 2;
+  const uint4 ones = make_uint4(0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu);
+  for (int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x; j < units; j += (int64_t)gridDim.x * kBlock) {
+    reinterpret_cast<uint4*>(t.dd)[j] = ones;
+    if (p.by_claimers && j < units / 2) reinterpret_cast<uint4*>(spec_low(t, p))[j] = ones;
+  }
+  if (p.by_claimers && units == 1 && blockIdx.x == 0 && threadIdx.x == 0) {
+    spec_low(t, p)[0] = kNone;
+    spec_low(t, p)[1] = kNone;
+  }
+}
+
+// dd slot of `key` among entries (tag | chunk index); kNone when absent.
+__device__ __forceinline__ uint32_t dd_find(const TableView& t, const uint64_t* keys, uint64_t key,
+                                           uint32_t dmask, uint32_t* idx) {
+  const uint64_t mix = dedup_mix(key);
+  const uint64_t tag = mix & 0xFFFFFFFF00000000ull;
+  uint32_t h = (uint32_t)mix & dmask;
+  for (uint32_t probe = 0; probe <= dmask; ++probe) {
+    const uint64_t e = t.dd[h];
+    if (e == kEmpty) return kNone;
+    if ((e & 0xFFFFFFFF00000000ull) == tag && keys[(uint32_t)e] == key) {
+      *idx = (uint32_t)e;
+      return h;
+    }
+    h = (h + 1) & dmask;
+  }
+  return kNone;
+}
+
+// Build: the keys that enter dd.  Listed direction: windows of 256 elements first resolve their
+// listed keys in LDS, so a key listed many times costs one CAS or atomic min per window (skipped
+// when the held index is already lower).  Claimer direction: every claimer's key is distinct, so
+// each takes an empty entry with one CAS.  Out-of-band listed copies take an atomic min on their
+// header word in both directions.
+__global__ __launch_bounds__(kBlock) void k_spec_build(TableView t, const uint64_t* __restrict__ keys,
+                                                       int64_t q) {
+  const uint32_t nd = t.hdr->ndup;  // written by k_spec_clear
+  if (nd == 0) return;
+  const SpecPlan p = spec_plan(nd, q);
+  const uint32_t dmask = p.slots - 1;
   constexpr uint32_t kW = 2 * kBlock;
   __shared__ unsigned long long wk[kW];
   __shared__ uint32_t wmin[kW];
-  for (int64_t b0 = (int64_t)blockIdx.x * kBlock; b0 < nd; b0 += (int64_t)gridDim.x * kBlock) {
+  for (int64_t b0 = (int64_t)blockIdx.x * kBlock; b0 < q; b0 += (int64_t)gridDim.x * kBlock) {
+    const int64_t i = b0 + threadIdx.x;
+    const uint8_t f = i < q ? t.flag[i] : kFlagNone;
+    const uint64_t key = f != kFlagNone ? keys[i] : kEmpty;
+    if (f == kFlagListed && key >= kTomb) amin32(&t.hdr->spec_first[key - kTomb], (uint32_t)i);
+    const uint64_t mix = dedup_mix(key);
+    const uint64_t tag = mix & 0xFFFFFFFF00000000ull;
+    if (p.by_claimers) {
+      if (f == kFlagClaimed) {
+        uint32_t h = (uint32_t)mix & dmask;
+        for (uint32_t probe = 0; probe <= dmask; ++probe) {
+          uint64_t expected = kEmpty;
+          if (cas64(&t.dd[h], expected, tag | (uint64_t)i)) break;
+          h = (h + 1) & dmask;
+        }
+      }
+      continue;
+    }
+    // listed direction (uniform per block: p depends only on nd and q)
     for (uint32_t j = threadIdx.x; j < kW; j += kBlock) {
       wk[j] = kEmpty;
       wmin[j] = kNone;
     }
     __syncthreads();
-    const int64_t j = b0 + threadIdx.x;
-    const bool valid = j < nd;
-    const uint32_t i = valid ? t.dup[j].x : 0u;
-    const uint64_t key = valid ? keys[i] : kEmpty;
-    const bool normal = valid && key < kTomb;
-    if (valid && !normal) amin32(&t.hdr->spec_first[key - kTomb], i);
-    const uint64_t mix = dedup_mix(key);
+    const bool normal = f == kFlagListed && key < kTomb;
     uint32_t s = (uint32_t)(mix >> 32) & (kW - 1);
     if (normal) {
       for (;;) {  // at most kBlock keys in kW slots: a free or matching slot exists
@@ -1282,11 +1385,10 @@ __global__ __launch_bounds__(kBlock) void k_spec_amb(TableView t, const uint64_t
         if (old == kEmpty || old == key) break;
         s = (s + 1) & (kW - 1);
       }
-      atomicMin(&wmin[s], i);
+      atomicMin(&wmin[s], (uint32_t)i);
     }
     __syncthreads();
-    if (normal && wmin[s] == i) {
-      const uint64_t tag = mix & 0xFFFFFFFF00000000ull;
+    if (normal && wmin[s] == (uint32_t)i) {
       const uint64_t mine = tag | (uint64_t)i;
       uint32_t h = (uint32_t)mix & dmask;
       for (uint32_t probe = 0; probe <= dmask; ++probe) {
@@ -1297,7 +1399,7 @@ __global__ __launch_bounds__(kBlock) void k_spec_amb(TableView t, const uint64_t
           e = expected;
         }
         if ((e & 0xFFFFFFFF00000000ull) == tag && keys[(uint32_t)e] == key) {
-          if (i < (uint32_t)e) amin64(&t.dd[h], mine);
+          if ((uint32_t)i < (uint32_t)e) amin64(&t.dd[h], mine);
           break;
         }
         h = (h + 1) & dmask;
@@ -1319,15 +1421,88 @@ __device__ __forceinline__ uint64_t lane_slot_of(const TableView& t, uint64_t ke
   return kNoPos;
 }
 
-// Every claimer whose key has a lower listed copy hands the insert to that copy.  Thread 0 of
-// block 0 inserts each out-of-band key for its lowest copy when it was absent.
+// Claimer c hands the insert of its key to listed copy m < c: m's value into the slot, statuses
+// swapped.
 template <int VK>
-__global__ __launch_bounds__(kBlock) void k_spec_claimers(TableView t, const uint64_t* __restrict__ keys,
-                                                          const void* __restrict__ vals, int64_t q,
-                                                          uint8_t* __restrict__ status) {
-  const uint32_t nd = t.hdr->ndup;
+__device__ __forceinline__ void hand_over(const TableView& t, const void* __restrict__ vals,
+                                          uint8_t* __restrict__ status, uint64_t key, uint32_t c,
+                                          uint32_t m) {
+  const uint64_t pos = lane_slot_of(t, key);
+  if (pos == kNoPos) {
+    aor32(&t.hdr->err, kErrInternal);
+    return;
+  }
+  if (VK) t.bk[pos >> 3].s[pos & 7].val = load_val<VK>(vals, m);
+  if (status) {
+    status[m] = kInserted;
+    status[c] = kPresent;
+  }
+}
+
+// Probe: listed direction: every claimer looks its key up and hands over to a lower listed copy.
+// Claimer direction: every listed copy of a claimed key lowers the index word beside the entry
+// (windows of 256 elements combine copies of one entry in LDS first; skipped when the word is
+// already lower).
+template <int VK>
+__global__ __launch_bounds__(kBlock) void k_spec_probe(TableView t, const uint64_t* __restrict__ keys,
+                                                       const void* __restrict__ vals, int64_t q,
+                                                       uint8_t* __restrict__ status) {
+  const uint32_t nd = t.hdr->ndup;  // written by k_spec_clear
   if (nd == 0) return;
-  const uint32_t dmask = spec_slots(nd) - 1;
+  const SpecPlan p = spec_plan(nd, q);
+  const uint32_t dmask = p.slots - 1;
+  uint32_t* low = spec_low(t, p);
+  constexpr uint32_t kW = 2 * kBlock;
+  __shared__ uint32_t wh[kW], wmin[kW];
+  for (int64_t b0 = (int64_t)blockIdx.x * kBlock; b0 < q; b0 += (int64_t)gridDim.x * kBlock) {
+    const int64_t i = b0 + threadIdx.x;
+    const uint8_t f = i < q ? t.flag[i] : kFlagNone;
+    if (!p.by_claimers) {
+      if (f == kFlagClaimed) {
+        const uint64_t key = keys[i];
+        uint32_t m = 0;
+        if (dd_find(t, keys, key, dmask, &m) != kNone && m < (uint32_t)i)
+          hand_over<VK>(t, vals, status, key, (uint32_t)i, m);
+      }
+      continue;
+    }
+    for (uint32_t j = threadIdx.x; j < kW; j += kBlock) {
+      wh[j] = kNone;
+      wmin[j] = kNone;
+    }
+    __syncthreads();
+    uint32_t h = kNone, s = 0;
+    if (f == kFlagListed) {
+      const uint64_t key = keys[i];
+      uint32_t c = 0;
+      if (key < kTomb) {
+        h = dd_find(t, keys, key, dmask, &c);
+        if (h != kNone && (uint32_t)i > c) h = kNone;  // the claimer is lower: nothing to do
+      }
+    }
+    if (h != kNone) {
+      s = (h * 2654435761u) & (kW - 1);
+      for (;;) {  // at most kBlock entries in kW slots
+        const uint32_t old = atomicCAS(&wh[s], kNone, h);
+        if (old == kNone || old == h) break;
+        s = (s + 1) & (kW - 1);
+      }
+      atomicMin(&wmin[s], (uint32_t)i);
+    }
+    __syncthreads();
+    if (h != kNone && wmin[s] == (uint32_t)i && (uint32_t)i < low[h]) amin32(&low[h], (uint32_t)i);
+    __syncthreads();
+  }
+}
+
+// Swap (claimer direction): a claimer whose entry holds a lower listed index hands over.  Thread
+// 0 of block 0 inserts each out-of-band key for its lowest copy when it was absent.
+template <int VK>
+__global__ __launch_bounds__(kBlock) void k_spec_swap(TableView t, const uint64_t* __restrict__ keys,
+                                                      const void* __restrict__ vals, int64_t q,
+                                                      uint8_t* __restrict__ status) {
+  const uint32_t nd = t.hdr->ndup;  // written by k_spec_clear
+  if (nd == 0) return;
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     Header* h = t.hdr;
     for (int s = 0; s < 2; ++s) {
@@ -1339,33 +1514,21 @@ __global__ __launch_bounds__(kBlock) void k_spec_claimers(TableView t, const uin
       if (status) status[m] = kInserted;
     }
   }
+  const SpecPlan p = spec_plan(nd, q);
+  if (!p.by_claimers) return;
+  const uint32_t dmask = p.slots - 1;
+  const uint32_t* low = spec_low(t, p);
   for (int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x; c < q; c += (int64_t)gridDim.x * kBlock) {
-    if (!t.flag[c]) continue;
+    if (t.flag[c] != kFlagClaimed) continue;
     const uint64_t key = keys[c];
-    const uint64_t mix = dedup_mix(key);
-    const uint64_t tag = mix & 0xFFFFFFFF00000000ull;
-    uint32_t h = (uint32_t)mix & dmask;
-    for (uint32_t probe = 0; probe <= dmask; ++probe) {
-      const uint64_t e = t.dd[h];
-      if (e == kEmpty) break;
-      if ((e & 0xFFFFFFFF00000000ull) == tag && keys[(uint32_t)e] == key) {
-        const uint32_t m = (uint32_t)e;
-        if (m < (uint32_t)c) {
-          const uint64_t pos = lane_slot_of(t, key);
-          if (pos == kNoPos) {
-            aor32(&t.hdr->err, kErrInternal);
-          } else {
-            if (VK) t.bk[pos >> 3].s[pos & 7].val = load_val<VK>(vals, m);
-            if (status) {
-              status[m] = kInserted;
-              status[c] = kPresent;
-            }
-          }
-        }
-        break;
-      }
-      h = (h + 1) & dmask;
+    uint32_t self = 0;
+    const uint32_t h = dd_find(t, keys, key, dmask, &self);
+    if (h == kNone) {
+      aor32(&t.hdr->err, kErrInternal);
+      continue;
     }
+    const uint32_t m = low[h];
+    if (m < (uint32_t)c) hand_over<VK>(t, vals, status, key, (uint32_t)c, m);
   }
 }
 
@@ -2458,6 +2621,7 @@ struct ct_table {
   uint64_t size_ub;   // upper bound of the live count known to the host
   int64_t dd_bytes;   // bytes of the dedup scratch region at v.dd (the purge's bitmap)
   int32_t insert_path = CT_INSERT_AUTO;  // how insert chunks resolve repeated keys
+  uint64_t* fb_host = nullptr;           // host side of v.fb (pinned, mapped), or null
 };
 
 struct ct_pool {
@@ -2470,7 +2634,6 @@ struct ct_pool {
 namespace {
 
 constexpr int64_t kAlign = 256;
-constexpr int kMaxGroupBlocks = 16384;
 
 int64_t align_up(int64_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
@@ -2572,7 +2735,7 @@ bool make_layout(const ct_table_desc* d, Layout* L) {
   L->off_tsum = off;
   off = align_up(off + L->ntiles * 4);
   L->off_bcnt = off;
-  off = align_up(off + kMaxGroupBlocks * 8);
+  off = align_up(off + kMaxGroupBlocks * 8 + kStripeRegion);
   L->total = off;
   return true;
 }
@@ -2667,6 +2830,18 @@ void dedup_chunk(ct_table* t, const TableView& v, PoolHeader* pool, const uint64
   }
 }
 
+// Whether a chunk that cannot reach capacity is inserted speculatively.  AUTO follows the
+// table's last insert chunk (reported through the mapped feedback word, possibly stale): keys
+// mostly new -> speculative; mostly present or repeated -> repeated keys resolved first, where
+// only one copy of each key probes the table.
+bool use_speculation(const ct_table* t) {
+  if (t->insert_path == CT_INSERT_RESOLVE_FIRST) return false;
+  if (t->insert_path == CT_INSERT_SPECULATIVE || !t->fb_host) return true;
+  const uint64_t f = __atomic_load_n(t->fb_host, __ATOMIC_RELAXED);
+  const uint64_t fq = f >> 32, stored = f & 0xFFFFFFFFull;
+  return fq == 0 || 2 * stored >= fq;
+}
+
 // Insert of n keys in chunks of at most `chunk`, with the per-chunk scratch that view `v` names
 // (the table's own, or another region holding the same arrays).
 template <int VK>
@@ -2683,13 +2858,14 @@ ct_status insert_chunks(ct_table* t, const TableView& v, int64_t chunk, const ui
     const int ntiles = (int)((q + kTile - 1) / kTile);
     // the host bound proves that no element can meet FULL: the rank pass is not needed
     const bool surely_fast = t->size_ub + (uint64_t)q <= (uint64_t)t->desc.capacity;
-    if (surely_fast && t->insert_path == CT_INSERT_AUTO) {
+    if (surely_fast && use_speculation(t)) {
       // speculative: insert first, then resolve the copies of keys listed as ambiguous
       launch(t, CT_KERNEL_PROLOGUE, s, [&] { k_spec_prologue<<<1, 64, 0, s>>>(v, q); });
       launch(t, CT_KERNEL_INSERT, s, [&] { k_insert_spec<VK><<<gb, kBlock, 0, s>>>(v, kc, vc, q, sc); });
-      launch(t, CT_KERNEL_APPLY, s, [&] { k_spec_clear<<<flat_blocks(db / 2), kBlock, 0, s>>>(v, gb); });
-      launch(t, CT_KERNEL_DEDUP, s, [&] { k_spec_amb<<<flat_blocks(q), kBlock, 0, s>>>(v, kc); });
-      launch(t, CT_KERNEL_FIX, s, [&] { k_spec_claimers<VK><<<flat_blocks(q), kBlock, 0, s>>>(v, kc, vc, q, sc); });
+      launch(t, CT_KERNEL_APPLY, s, [&] { k_spec_clear<<<flat_blocks(db / 2), kBlock, 0, s>>>(v, gb, q); });
+      launch(t, CT_KERNEL_DEDUP, s, [&] { k_spec_build<<<flat_blocks(q), kBlock, 0, s>>>(v, kc, q); });
+      launch(t, CT_KERNEL_FIX, s, [&] { k_spec_probe<VK><<<flat_blocks(q), kBlock, 0, s>>>(v, kc, vc, q, sc); });
+      launch(t, CT_KERNEL_FIX, s, [&] { k_spec_swap<VK><<<flat_blocks(q), kBlock, 0, s>>>(v, kc, vc, q, sc); });
       t->size_ub = std::min<uint64_t>(t->size_ub + (uint64_t)q, (uint64_t)t->desc.capacity);
       ct_status r = launched();
       if (r != CT_OK) return r;
@@ -2697,7 +2873,8 @@ ct_status insert_chunks(ct_table* t, const TableView& v, int64_t chunk, const ui
     }
     dedup_chunk(t, v, nullptr, kc, q, s);
     launch(t, CT_KERNEL_INSERT, s, [&] { k_insert<VK, false><<<gb, kBlock, 0, s>>>(v, kc, vc, q, db - 1, sc, nullptr); });
-    launch(t, CT_KERNEL_APPLY, s, [&] { k_apply_count<<<1, 1024, 0, s>>>(v, gb); });
+    // a chunk that may meet capacity stores more keys in its ranked pass: no report
+    launch(t, CT_KERNEL_APPLY, s, [&] { k_apply_count<<<1, 1024, 0, s>>>(v, gb, surely_fast ? q : 0); });
     if (!surely_fast) {
       launch(t, CT_KERNEL_RANK, s, [&] { k_tile_count<<<ntiles, kBlock, 0, s>>>(v, q, 1); });
       launch(t, CT_KERNEL_RANK, s, [&] { k_tile_scan<<<1, 1024, 0, s>>>(v, nullptr, ntiles, 0); });
@@ -2729,7 +2906,7 @@ ct_status erase_chunks(ct_table* t, ct_pool* p, const uint64_t* keys, int64_t n,
     const int ntiles = (int)((q + kTile - 1) / kTile);
     dedup_chunk(t, t->v, RELEASE ? p->hdr : nullptr, kc, q, s);
     launch(t, CT_KERNEL_ERASE, s, [&] { k_erase<RELEASE><<<gb, kBlock, 0, s>>>(t->v, kc, q, db - 1, ec); });
-    launch(t, CT_KERNEL_APPLY, s, [&] { k_apply_count<<<1, 1024, 0, s>>>(t->v, gb); });
+    launch(t, CT_KERNEL_APPLY, s, [&] { k_apply_count<<<1, 1024, 0, s>>>(t->v, gb, 0); });
     if (RELEASE) {
       launch(t, CT_KERNEL_RANK, s, [&] { k_tile_count<<<ntiles, kBlock, 0, s>>>(t->v, q, 0); });
       launch(t, CT_KERNEL_RANK, s, [&] { k_tile_scan<<<1, 1024, 0, s>>>(t->v, p->hdr, ntiles, 2); });
@@ -2835,8 +3012,23 @@ ct_status ct_table_init(void* d_buf, int64_t bytes, const ct_table_desc* d, void
   v.hash = d->hash_kind;
   v.nb_pow2 = (L.nb & (L.nb - 1)) == 0;
   v.step_mode = v.nb_pow2 ? 1 : (is_prime(L.nb) ? 2 : 0);
+  // the insert-path feedback word; without it every provable chunk is speculative
+  v.fb = nullptr;
+  void* fbh = nullptr;
+  if (hipHostMalloc(&fbh, 64, hipHostMallocMapped) == hipSuccess) {
+    void* fbd = nullptr;
+    if (hipHostGetDevicePointer(&fbd, fbh, 0) == hipSuccess) {
+      t->fb_host = static_cast<uint64_t*>(fbh);
+      *t->fb_host = 0;
+      v.fb = static_cast<uint64_t*>(fbd);
+    } else {
+      (void)hipHostFree(fbh);
+    }
+  }
+  (void)hipGetLastError();  // a failed pinned allocation only disables the feedback
   k_table_reset<<<flat_blocks(L.nb * kSlots), kBlock, 0, S(stream)>>>(v, 1);
   if (launched() != CT_OK) {
+    if (t->fb_host) (void)hipHostFree(t->fb_host);
     delete t;
     return CT_E_HIP;
   }
@@ -2847,6 +3039,7 @@ ct_status ct_table_init(void* d_buf, int64_t bytes, const ct_table_desc* d, void
 ct_status ct_table_destroy(ct_table* t) {
   if (!t) return CT_E_INVALID;
   for (hipEvent_t e : t->prof.events) (void)hipEventDestroy(e);
+  if (t->fb_host) (void)hipHostFree(t->fb_host);
   delete t;
   return CT_OK;
 }
@@ -3085,7 +3278,7 @@ ct_status ct_table_rehash(ct_table* src, ct_table* dst, void* stream) {
   const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(((int64_t)src->v.nb + kBlock / 8 - 1) / (kBlock / 8), kMaxGroupBlocks));
   hipStream_t s = S(stream);
   launch(dst, CT_KERNEL_INSERT, s, [&] { k_rehash<<<grid, kBlock, 0, s>>>(src->v, dst->v); });
-  launch(dst, CT_KERNEL_APPLY, s, [&] { k_apply_count<<<1, 1024, 0, s>>>(dst->v, grid); });
+  launch(dst, CT_KERNEL_APPLY, s, [&] { k_apply_count<<<1, 1024, 0, s>>>(dst->v, grid, 0); });
   dst->size_ub = (uint64_t)(nd + ns);
   return launched();
 }
@@ -3216,7 +3409,7 @@ ct_status ct_table_dedup_skewed(ct_table* t, int32_t* h_skewed, void* stream) {
 }
 
 ct_status ct_table_set_insert_path(ct_table* t, int32_t path) {
-  if (!t || (path != CT_INSERT_AUTO && path != CT_INSERT_RESOLVE_FIRST)) return CT_E_INVALID;
+  if (!t || path < CT_INSERT_AUTO || path > CT_INSERT_SPECULATIVE) return CT_E_INVALID;
   t->insert_path = path;
   return CT_OK;
 }
@@ -3901,7 +4094,7 @@ constexpr StaticScratch static_scratch_layout() {
   L.tsum = off;
   off += 256;  // kStaticChunk / kTile tile sums, 4 bytes each
   L.bcnt = off;
-  off += (int64_t)kMaxGroupBlocks * 8;
+  off += (int64_t)kMaxGroupBlocks * 8 + kStripeRegion;
   L.total = off;
   return L;
 }

@@ -26,7 +26,7 @@ GROUP_MERGE_RUNS = 1
 GROUP_BLOCK = {128: 7 << 8, 256: 0, 512: 9 << 8, 1024: 10 << 8}   # CT_GROUP_BLOCK(threads)
 OP_CLEAR, OP_INSERT, OP_FIND, OP_ERASE = 0, 1, 2, 3
 HASH_MIX64, HASH_VOXEL21 = 0, 1
-INSERT_AUTO, INSERT_RESOLVE_FIRST = 0, 1  # ct_table_set_insert_path
+INSERT_AUTO, INSERT_RESOLVE_FIRST, INSERT_SPECULATIVE = 0, 1, 2  # ct_table_set_insert_path
 CHECK_SIZE, CHECK_DUPLICATE, CHECK_REACH, CHECK_POOL = 1, 2, 12, 32
 
 
@@ -526,7 +526,7 @@ class Table:
         return bool(v.value)
 
     def set_insert_path(self, path: int):
-        """INSERT_AUTO (speculative where no element can meet FULL) or INSERT_RESOLVE_FIRST."""
+        """INSERT_AUTO (the default), INSERT_RESOLVE_FIRST or INSERT_SPECULATIVE."""
         _check(lib().ct_table_set_insert_path(self._h, int(path)), "ct_table_set_insert_path")
 
     def profiling(self, enable: bool = True):

@@ -120,7 +120,7 @@ def test_plain_table_workload(dev):
     p.same_state()
 
 
-PATHS = [ct.INSERT_AUTO, ct.INSERT_RESOLVE_FIRST]
+PATHS = [ct.INSERT_SPECULATIVE, ct.INSERT_RESOLVE_FIRST]
 
 
 @pytest.mark.parametrize("path", PATHS)
@@ -585,7 +585,7 @@ def test_speculative_insert_ambiguous_copies(dev, bits, chunk):
     value must still be the lowest copy's).  Every output and the final contents equal the
     oracle's."""
     rng = rng_for(307, bits + chunk)
-    p = Pair(dev, 1 << 18, bits, chunk=chunk)
+    p = Pair(dev, 1 << 18, bits, chunk=chunk, path=ct.INSERT_SPECULATIVE)
     base = distinct_u64(rng, 60000)
 
     def v(n):
@@ -621,4 +621,31 @@ def test_speculative_insert_ambiguous_copies(dev, bits, chunk):
     else:
         p.g.insert(g64(keys, dev), g64(vals, dev), status=False)
     p.o.insert(keys, vals)
+    p.same_state()
+
+
+def test_auto_path_follows_the_last_chunk(dev):
+    """The default path inserts a chunk speculatively while the table's last insert chunk stored
+    at least half of its keys, and resolves repeated keys first otherwise (the table reports each
+    chunk through a pinned host word).  The path shows in the launches of the repeated-key kernels:
+    one per speculative chunk, five per binned resolve-first chunk.  Results equal the oracle's on
+    every chunk, whichever path ran."""
+    rng = rng_for(331)
+    chunk = 1 << 16
+    p = Pair(dev, 1 << 20, 64, chunk=chunk)
+    keys = distinct_u64(rng, 3 * chunk)
+    a, b, c = keys[:chunk], keys[chunk:2 * chunk], keys[2 * chunk:]
+    p.g.profiling(True)
+
+    def dedup_launches(batch):
+        p.g.profile_reset()
+        p.insert(batch, rng.integers(0, 1 << 62, size=batch.size, dtype=np.uint64))
+        return p.g.profile()["dedup"][1]
+
+    assert dedup_launches(a) == 1      # nothing reported yet: speculative
+    assert dedup_launches(a) == 1      # the last chunk stored every key: speculative (stores none)
+    assert dedup_launches(a) == 5      # the last chunk stored none: repeated keys first
+    assert dedup_launches(b) == 5      # still after a chunk that stored none (this one stores all)
+    assert dedup_launches(c) == 1      # speculative again
+    p.g.profiling(False)
     p.same_state()

@@ -8,8 +8,10 @@ which thread takes the next step, so a bucket "read" by a thread may mix slot st
 and after other threads' claims.  Each thread probes, claims the first free slot it saw, and on a
 lost claim either stops (the winner holds its own key) or scans on while watching for its key.
 
-After all threads end, the listed (ambiguous) elements give each key its lowest listed index, and
-a claimer whose key has a lower listed copy hands the insert to it.  The test checks, over many
+After all threads end, a claimer whose key has a listed (ambiguous) copy of lower index hands the
+insert to the lowest such copy; the model finds that copy both ways the kernels can (listed keys
+into a table that claimers look up, or claimers into a table that listed copies lower) and
+checks that they agree.  The test checks, over many
 random schedules, tables with tombstones, and batches full of repeated and present keys, that
 
 * no key is ever stored twice (the uniqueness of Section 4.1);
@@ -149,22 +151,43 @@ def run_chunk(t, keys, vals, rng, watch=True):
             del pending[i]
             if stop.value[0] == "claimed":
                 t.vals[stop.value[1]] = vals[i]
-    # resolution: lowest listed index per key, then claimers hand over to a lower listed copy
+    for kind, _ in outcome.values():
+        if kind == "full":
+            raise AssertionError("FULL in a chunk that fits")
+    a = resolve_by_listed(outcome, keys)
+    b = resolve_by_claimers(outcome, keys)
+    assert a == b, "the two resolution directions disagree"
     status = [PRESENT] * len(keys)
+    for c, (kind, _) in outcome.items():
+        if kind == "claimed":
+            status[c] = INSERTED
+    for c, m in a.items():
+        t.vals[outcome[c][1]] = vals[m]
+        status[m], status[c] = INSERTED, PRESENT
+    return status
+
+
+def resolve_by_listed(outcome, keys):
+    """Listed keys enter the table with their lowest listed index; each claimer looks itself up.
+    Returns {claimer: listed copy that takes the insert over}."""
     low = {}
     for i, (kind, _) in outcome.items():
         if kind == "amb":
             low[keys[i]] = min(low.get(keys[i], i), i)
-        elif kind == "claimed":
-            status[i] = INSERTED
-        else:
-            raise AssertionError("FULL in a chunk that fits")
-    for c, (kind, slot) in outcome.items():
-        if kind == "claimed" and keys[c] in low and low[keys[c]] < c:
-            m = low[keys[c]]
-            t.vals[slot] = vals[m]
-            status[m], status[c] = INSERTED, PRESENT
-    return status
+    return {c: low[keys[c]] for c, (kind, _) in outcome.items()
+            if kind == "claimed" and keys[c] in low and low[keys[c]] < c}
+
+
+def resolve_by_claimers(outcome, keys):
+    """Claimers enter the table; each listed copy below its key's claimer lowers the claimer's
+    word, which the claimer checks afterwards."""
+    entry = {keys[c]: c for c, (kind, _) in outcome.items() if kind == "claimed"}
+    word = {}
+    for i, (kind, _) in outcome.items():
+        if kind == "amb" and keys[i] in entry and i < entry[keys[i]]:
+            c = entry[keys[i]]
+            word[c] = min(word.get(c, i), i)
+    return word
 
 
 def contents(t):
