@@ -157,6 +157,8 @@ def measure_ceilings(ct, torch, dev, nlines, find_keys, uniform_keys, fill_keys=
     res["R1_gather64_Mlines_s"] = n / t / 1e6
     t = timed(lambda: ct.gather(buf, nlines, 128, uniform_keys, out, cas=True))
     res["R2_gather128_cas_Mops_s"] = n / t / 1e6
+    t = timed(lambda: ct.gather(buf, nlines, 128, uniform_keys, out, cas=True, store=True))
+    res["R6_gather128_cas_store_Mops_s"] = n / t / 1e6
     t = timed(lambda: ct.cas_words(buf, nlines * 16, uniform_keys))
     res["R3_cas_Mops_s"] = n / t / 1e6
     nb = min(buf.numel(), 1 << 30)
@@ -637,8 +639,6 @@ def main():
         assert int(erased.sum()) == n_er and int((st_re == 1).sum()) == n_re
         assert table.size() == n_fill
     per = {name: 0.0 for name, _ in ops}
-    table.profiling(True)
-    table.profile_reset()
     torch.cuda.synchronize()
     w0 = time.perf_counter()
     for _ in range(a.steps):
@@ -648,6 +648,13 @@ def main():
             per[name] += ev[j].elapsed_time(ev[j + 1]) * 1e-3
     torch.cuda.synchronize()
     wall = time.perf_counter() - w0
+    # per-kernel times: the same number of steps again, with the library's event profiler on (it
+    # records two events around every launch, so it stays out of the timed steps above)
+    table.profiling(True)
+    table.profile_reset()
+    for _ in range(a.steps):
+        step(False)
+    torch.cuda.synchronize()
     total_ops = n_fill + n_find + n_er + n_re
     dev_time = sum(per.values())
     ms_step = wall / a.steps * 1e3
@@ -741,6 +748,7 @@ def main():
         ceil["find_frac_of_R5"] = f_mops / ceil["R5_find_stream_Mlines_s"]
         ceil["insert_frac_of_R2"] = i_mops / ceil["R2_gather128_cas_Mops_s"]
         ceil["insert_frac_of_R5"] = i_mops / ceil["R5_insert_stream_Mops_s"]
+        ceil["insert_frac_of_R6"] = i_mops / ceil["R6_gather128_cas_store_Mops_s"]
         if "find_uniform_Mops_s" in line:
             ceil["find_uniform_frac_of_R1"] = (line["find_uniform_Mops_s"]
                                                / ceil["R1_gather128_Mlines_s"])

@@ -329,18 +329,22 @@ ct_status ct_table_debug_inject_claim_losses(ct_table *t, uint32_t every, void *
    0 otherwise.  Results never depend on it.  Synchronises. */
 ct_status ct_table_dedup_skewed(ct_table *t, int32_t *h_skewed, void *stream);
 
-/* How insert chunks resolve repeated keys (the index order of the batch semantics above).  Only
-   chunks that the host can prove cannot reach capacity have a choice; the others, and
-   ct_insert_alloc_batch, always resolve repeated keys first.
-   CT_INSERT_SPECULATIVE: every element probes and claims for itself, and only the elements that
-   met their key in the table (or lost a claim to a copy of it) are resolved afterwards, by lowest
-   index.  A batch of distinct keys absent from the table then needs no resolution pass at all.
+/* How insert and erase chunks resolve repeated keys (the index order of the batch semantics
+   above).  For inserts, only chunks that the host can prove cannot reach capacity have a choice;
+   the others, ct_insert_alloc_batch and ct_erase_release_batch always resolve repeated keys
+   first.
+   CT_INSERT_SPECULATIVE: every element acts for itself (an insert claims a slot with one CAS, an
+   erase removes the key it finds with one CAS), and only the elements that met their key in the
+   table, lost that CAS to a copy of their key, or (erase) found nothing are resolved afterwards,
+   by lowest index.  A batch of distinct new keys to insert, or of distinct present keys to erase,
+   then needs no resolution pass at all.
    CT_INSERT_RESOLVE_FIRST: repeated keys are resolved before the table is touched, so only one
-   copy of each key probes it (cheaper when most keys are present or repeated).
-   CT_INSERT_AUTO (the default): speculative while the table's last insert chunk stored at least
-   half of its keys, else resolve first; the table reports each chunk through a word of pinned
-   host memory that the host reads without synchronising.  Results are identical on every path.
-   Host only: applies to insert calls enqueued afterwards. */
+   copy of each key probes it (cheaper when most keys are present or repeated, or absent from an
+   erase).
+   CT_INSERT_AUTO (the default): speculative while the table's last chunk of the same operation
+   stored (erase: removed) at least half of its keys, else resolve first; the table reports each
+   chunk through a word of pinned host memory that the host reads without synchronising.  Results
+   are identical on every path.  Host only: applies to calls enqueued afterwards. */
 #define CT_INSERT_AUTO 0
 #define CT_INSERT_RESOLVE_FIRST 1
 #define CT_INSERT_SPECULATIVE 2

@@ -17,7 +17,9 @@ constexpr int kB = 256;
 // G lanes read one line of 16*G bytes; XOR of the line goes to out[i].  A group takes U keys per
 // round and issues all U line loads before it reduces any, so each lane has U independent
 // 16-byte loads in flight (the container kernels keep up to 8 bucket loads in flight per lane).
-template <int G, bool CAS>
+// CAS: one 64-bit compare-and-swap on the line's first word; STORE: then an 8-byte store to the
+// word after it (an insert's claim and value store into one slot).
+template <int G, bool CAS, bool STORE = false>
 __global__ __launch_bounds__(kB) void k_gather(uint4* __restrict__ lines, uint64_t nlines,
                                                const uint64_t* __restrict__ keys, int64_t n,
                                                uint64_t* __restrict__ out) {
@@ -48,6 +50,7 @@ __global__ __launch_bounds__(kB) void k_gather(uint4* __restrict__ lines, uint64
           uint64_t expected = (uint64_t)w[u].y << 32 | w[u].x;
           cas64(word, expected, expected ^ key[u]);
           x ^= expected;
+          if (STORE) word[1] = x;
         }
         out[i] = x;
       }
@@ -104,7 +107,7 @@ int blocks_for(int64_t items, int per_block, int cap) {
 
 ct_status done() { return hipGetLastError() == hipSuccess ? CT_OK : CT_E_HIP; }
 
-template <bool CAS>
+template <bool CAS, bool STORE = false>
 ct_status gather(void* lines, int64_t nlines, int32_t line_bytes, const uint64_t* keys, int64_t n,
                  uint64_t* out, void* stream) {
   if (!lines || nlines <= 0 || n < 0 || (n > 0 && (!keys || !out))) return CT_E_INVALID;
@@ -114,9 +117,9 @@ ct_status gather(void* lines, int64_t nlines, int32_t line_bytes, const uint64_t
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   uint4* L = static_cast<uint4*>(lines);
   if (line_bytes == 128)
-    k_gather<8, CAS><<<blocks_for(n, kB / 8, 16384), kB, 0, s>>>(L, (uint64_t)nlines, keys, n, out);
+    k_gather<8, CAS, STORE><<<blocks_for(n, kB / 8, 16384), kB, 0, s>>>(L, (uint64_t)nlines, keys, n, out);
   else
-    k_gather<4, CAS><<<blocks_for(n, kB / 4, 16384), kB, 0, s>>>(L, (uint64_t)nlines, keys, n, out);
+    k_gather<4, CAS, STORE><<<blocks_for(n, kB / 4, 16384), kB, 0, s>>>(L, (uint64_t)nlines, keys, n, out);
   return done();
 }
 
@@ -132,6 +135,11 @@ ct_status ctr_gather(const void* lines, int64_t nlines, int32_t line_bytes, cons
 ct_status ctr_gather_cas(void* lines, int64_t nlines, int32_t line_bytes, const uint64_t* keys,
                          int64_t n, uint64_t* out, void* stream) {
   return gather<true>(lines, nlines, line_bytes, keys, n, out, stream);
+}
+
+ct_status ctr_gather_cas_store(void* lines, int64_t nlines, int32_t line_bytes,
+                               const uint64_t* keys, int64_t n, uint64_t* out, void* stream) {
+  return gather<true, true>(lines, nlines, line_bytes, keys, n, out, stream);
 }
 
 ct_status ctr_cas(void* words, int64_t nwords, const uint64_t* keys, int64_t n, void* stream) {

@@ -1076,16 +1076,20 @@ __device__ __forceinline__ int64_t apply_count_block(const TableView& t, int npa
 // The host's view of how an insert chunk of q keys went: q and the keys it stored, one 64-bit
 // store to host-mapped memory (read without synchronising; a stale or torn read only changes
 // which path the next chunk takes, never a result).
-__device__ __forceinline__ void insert_feedback(const TableView& t, int64_t q, int64_t stored) {
+// Word 0 reports insert chunks (keys stored), word 1 erase chunks (keys removed).
+__device__ __forceinline__ void chunk_feedback(const TableView& t, int word, int64_t q,
+                                               int64_t changed) {
   if (!t.fb || q <= 0) return;
-  const uint64_t w = ((uint64_t)q << 32) | (uint64_t)(uint32_t)(stored < 0 ? 0 : stored);
-  __hip_atomic_store(t.fb, w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+  const uint64_t w = ((uint64_t)q << 32) | (uint64_t)(uint32_t)(changed < 0 ? 0 : changed);
+  __hip_atomic_store(t.fb + word, w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
-// fb_q > 0: the partials are the stored keys of an insert chunk of fb_q keys (report them).
-__global__ __launch_bounds__(1024) void k_apply_count(TableView t, int nblocks, int64_t fb_q) {
+// fb_q > 0: the partials are the count changes of an insert (fb_word 0) or erase (fb_word 1)
+// chunk of fb_q keys: report how many keys the chunk stored or removed.
+__global__ __launch_bounds__(1024) void k_apply_count(TableView t, int nblocks, int64_t fb_q,
+                                                      int fb_word) {
   const int64_t s = apply_count_block(t, nblocks);
-  if (threadIdx.x == 0 && fb_q) insert_feedback(t, fb_q, s);
+  if (threadIdx.x == 0 && fb_q) chunk_feedback(t, fb_word, fb_q, fb_word ? -s : s);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -1255,9 +1259,67 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(VK == 0 
   }
 }
 
+// Speculative erase: every element probes; a found key is removed with one CAS (key -> kEmpty
+// where its bucket holds an empty slot, else kTomb), so of several copies exactly one removes it
+// (flag 1, reports 1).  A copy that loses that CAS or finds no key is listed (flag 2, reports 0):
+// afterwards the lowest listed copy takes the removal over from a higher remover.  A copy cannot
+// miss a key that is still there: an erase writes kEmpty only into buckets that already hold one,
+// so no probe sequence is cut short.  Out-of-band keys are always listed.
+__device__ __forceinline__ uint2 erase_spec_range(const TableView& t, const uint64_t* __restrict__ keys,
+                                                  uint8_t* __restrict__ erased, int64_t lo,
+                                                  int64_t hi, int64_t step) {
+  const int sub = threadIdx.x & 7;
+  uint32_t del = 0, listed = 0;
+  for (int64_t g0 = lo + (int64_t)(threadIdx.x >> 3) * kSlots; g0 < hi; g0 += step) {
+    const int64_t i = g0 + sub;
+    const bool valid = i < hi;
+    const uint64_t key = valid ? keys[i] : kEmpty;
+    bool amb = valid && key >= kTomb;
+    uint8_t hit = 0;
+    const uint32_t A = group_bits(__ballot(valid && key < kTomb));
+    if (A) {
+      uint32_t found, hadE, freeb;
+      uint64_t mypos = kNoPos, myval = 0, myfb = 0, myexp = 0;
+      int myc = 0;
+      uint64_t mystep = 0;
+      group_probe<false>(t, key, A, sub, &found, &hadE, &freeb, &mypos, &myval, &myfb, &myc, &myexp,
+                         &mystep);
+      if ((A >> sub) & 1) {
+        if ((found >> sub) & 1) {
+          uint64_t expected = key;
+          const uint64_t gone = ((hadE >> sub) & 1) ? kEmpty : kTomb;
+          if (cas64(&t.bk[mypos >> 3].s[mypos & 7].key, expected, gone)) hit = 1;
+          else amb = true;
+        } else {
+          amb = true;
+        }
+      }
+    }
+    if (valid) {
+      t.flag[i] = hit ? kFlagClaimed : (amb ? kFlagListed : kFlagNone);
+      if (erased) erased[i] = hit;
+      del += hit;
+      listed += amb ? 1u : 0u;
+    }
+  }
+  return make_uint2(del, listed);
+}
+
+__global__ __launch_bounds__(kBlock) void k_erase_spec(TableView t, const uint64_t* __restrict__ keys,
+                                                       int64_t q, uint8_t* __restrict__ erased) {
+  const uint2 c = erase_spec_range(t, keys, erased, (int64_t)blockIdx.x * kBlock, q,
+                                   (int64_t)gridDim.x * kBlock);
+  const int64_t tot = block_sum((int64_t)c.x + ((int64_t)c.y << 32));
+  if (threadIdx.x == 0) {
+    t.bcnt[blockIdx.x] = -(tot & 0xFFFFFFFFll);
+    const uint32_t nl = (uint32_t)(tot >> 32);
+    if (nl) aadd32(&list_stripes(t)[(blockIdx.x % kListStripes) * kListStripeWords], nl);
+  }
+}
+
 // The host's size bound has proved that the chunk cannot reach capacity; a live count that
 // says otherwise is a library bug and raises kErrInternal.  Also zeroes the listed counts.
-__global__ void k_spec_prologue(TableView t, int64_t q) {
+__global__ void k_spec_prologue(TableView t, int64_t q, int insert) {
   if (threadIdx.x < kListStripes) list_stripes(t)[threadIdx.x * kListStripeWords] = 0;
   if (threadIdx.x == 0) {
     Header* h = t.hdr;
@@ -1267,7 +1329,7 @@ __global__ void k_spec_prologue(TableView t, int64_t q) {
     h->nnew = 0;
     h->fast = 1u;
     h->dmode = 0u;
-    if (h->size + (uint64_t)q > t.cap) h->err |= kErrInternal;
+    if (insert && h->size + (uint64_t)q > t.cap) h->err |= kErrInternal;
   }
 }
 
@@ -1292,20 +1354,21 @@ __device__ __forceinline__ uint32_t* spec_low(const TableView& t, const SpecPlan
   return reinterpret_cast<uint32_t*>(t.dd + p.slots);
 }
 
-// Block 0 adds the stored keys to the live count (`nblocks` partials); every block clears the dd
-// entries (and, in the claimer direction, the lowest-index words) the resolution uses.
-__global__ __launch_bounds__(kBlock) void k_spec_clear(TableView t, int nblocks, int64_t q) {
-  if (blockIdx.x == 0) {
-    const int64_t stored = apply_count_block(t, nblocks);
-    if (threadIdx.x == 0) insert_feedback(t, q, stored);
-  }
-  __shared__ uint32_t snd;
+// One block: the count change of the insert or erase kernel (`nblocks` partials) goes into the
+// live count and the feedback word; the listed counts are summed into the header for the
+// kernels that follow.
+__global__ __launch_bounds__(1024) void k_spec_sum(TableView t, int nblocks, int64_t q, int erase) {
+  const int64_t change = apply_count_block(t, nblocks);
   if (threadIdx.x == 0) {
-    snd = listed_total(t);
-    if (blockIdx.x == 0) t.hdr->ndup = snd;  // for the kernels that follow
+    chunk_feedback(t, erase, q, erase ? -change : change);
+    t.hdr->ndup = listed_total(t);
   }
-  __syncthreads();
-  const uint32_t nd = snd;
+}
+
+// Clears the dd entries (and, in the claimer direction, the lowest-index words) the resolution
+// uses; nothing when no element is listed.
+__global__ __launch_bounds__(kBlock) void k_spec_clear(TableView t, int64_t q) {
+  const uint32_t nd = t.hdr->ndup;
   if (nd == 0) return;
   const SpecPlan p = spec_plan(nd, q);
   const int64_t units = p.slots / 2;
@@ -1345,7 +1408,7 @@ __device__ __forceinline__ uint32_t dd_find(const TableView& t, const uint64_t* 
 // header word in both directions.
 __global__ __launch_bounds__(kBlock) void k_spec_build(TableView t, const uint64_t* __restrict__ keys,
                                                        int64_t q) {
-  const uint32_t nd = t.hdr->ndup;  // written by k_spec_clear
+  const uint32_t nd = t.hdr->ndup;  // written by k_spec_sum
   if (nd == 0) return;
   const SpecPlan p = spec_plan(nd, q);
   const uint32_t dmask = p.slots - 1;
@@ -1423,10 +1486,19 @@ __device__ __forceinline__ uint64_t lane_slot_of(const TableView& t, uint64_t ke
 
 // Claimer c hands the insert of its key to listed copy m < c: m's value into the slot, statuses
 // swapped.
-template <int VK>
+// An erase only moves the outcome: m reports the removal, c reports none (both statuses are the
+// insert's INSERTED / PRESENT values, 1 / 0).
+template <int VK, bool ERASE>
 __device__ __forceinline__ void hand_over(const TableView& t, const void* __restrict__ vals,
                                           uint8_t* __restrict__ status, uint64_t key, uint32_t c,
                                           uint32_t m) {
+  if (ERASE) {
+    if (status) {
+      status[m] = 1;
+      status[c] = 0;
+    }
+    return;
+  }
   const uint64_t pos = lane_slot_of(t, key);
   if (pos == kNoPos) {
     aor32(&t.hdr->err, kErrInternal);
@@ -1443,11 +1515,11 @@ __device__ __forceinline__ void hand_over(const TableView& t, const void* __rest
 // Claimer direction: every listed copy of a claimed key lowers the index word beside the entry
 // (windows of 256 elements combine copies of one entry in LDS first; skipped when the word is
 // already lower).
-template <int VK>
+template <int VK, bool ERASE>
 __global__ __launch_bounds__(kBlock) void k_spec_probe(TableView t, const uint64_t* __restrict__ keys,
                                                        const void* __restrict__ vals, int64_t q,
                                                        uint8_t* __restrict__ status) {
-  const uint32_t nd = t.hdr->ndup;  // written by k_spec_clear
+  const uint32_t nd = t.hdr->ndup;  // written by k_spec_sum
   if (nd == 0) return;
   const SpecPlan p = spec_plan(nd, q);
   const uint32_t dmask = p.slots - 1;
@@ -1462,7 +1534,7 @@ __global__ __launch_bounds__(kBlock) void k_spec_probe(TableView t, const uint64
         const uint64_t key = keys[i];
         uint32_t m = 0;
         if (dd_find(t, keys, key, dmask, &m) != kNone && m < (uint32_t)i)
-          hand_over<VK>(t, vals, status, key, (uint32_t)i, m);
+          hand_over<VK, ERASE>(t, vals, status, key, (uint32_t)i, m);
       }
       continue;
     }
@@ -1497,21 +1569,29 @@ __global__ __launch_bounds__(kBlock) void k_spec_probe(TableView t, const uint64
 
 // Swap (claimer direction): a claimer whose entry holds a lower listed index hands over.  Thread
 // 0 of block 0 inserts each out-of-band key for its lowest copy when it was absent.
-template <int VK>
+template <int VK, bool ERASE>
 __global__ __launch_bounds__(kBlock) void k_spec_swap(TableView t, const uint64_t* __restrict__ keys,
                                                       const void* __restrict__ vals, int64_t q,
                                                       uint8_t* __restrict__ status) {
-  const uint32_t nd = t.hdr->ndup;  // written by k_spec_clear
+  const uint32_t nd = t.hdr->ndup;  // written by k_spec_sum
   if (nd == 0) return;
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     Header* h = t.hdr;
     for (int s = 0; s < 2; ++s) {
       const uint32_t m = h->spec_first[s];
-      if (m == kNone || h->spec_live[s]) continue;
-      h->spec_live[s] = 1;
-      h->spec_val[s] = load_val<VK>(vals, m);
-      h->size += 1;
-      if (status) status[m] = kInserted;
+      if (m == kNone) continue;
+      if (ERASE) {  // the lowest copy removes the key when it was there
+        if (!h->spec_live[s]) continue;
+        h->spec_live[s] = 0;
+        h->size -= 1;
+        if (status) status[m] = 1;
+      } else {      // the lowest copy stores the key when it was absent
+        if (h->spec_live[s]) continue;
+        h->spec_live[s] = 1;
+        h->spec_val[s] = load_val<VK>(vals, m);
+        h->size += 1;
+        if (status) status[m] = kInserted;
+      }
     }
   }
   const SpecPlan p = spec_plan(nd, q);
@@ -1528,7 +1608,7 @@ __global__ __launch_bounds__(kBlock) void k_spec_swap(TableView t, const uint64_
       continue;
     }
     const uint32_t m = low[h];
-    if (m < (uint32_t)c) hand_over<VK>(t, vals, status, key, (uint32_t)c, m);
+    if (m < (uint32_t)c) hand_over<VK, ERASE>(t, vals, status, key, (uint32_t)c, m);
   }
 }
 
@@ -2834,12 +2914,28 @@ void dedup_chunk(ct_table* t, const TableView& v, PoolHeader* pool, const uint64
 // table's last insert chunk (reported through the mapped feedback word, possibly stale): keys
 // mostly new -> speculative; mostly present or repeated -> repeated keys resolved first, where
 // only one copy of each key probes the table.
-bool use_speculation(const ct_table* t) {
+bool use_speculation(const ct_table* t, int word) {
   if (t->insert_path == CT_INSERT_RESOLVE_FIRST) return false;
   if (t->insert_path == CT_INSERT_SPECULATIVE || !t->fb_host) return true;
-  const uint64_t f = __atomic_load_n(t->fb_host, __ATOMIC_RELAXED);
-  const uint64_t fq = f >> 32, stored = f & 0xFFFFFFFFull;
-  return fq == 0 || 2 * stored >= fq;
+  const uint64_t f = __atomic_load_n(t->fb_host + word, __ATOMIC_RELAXED);
+  const uint64_t fq = f >> 32, changed = f & 0xFFFFFFFFull;
+  return fq == 0 || 2 * changed >= fq;
+}
+
+// The resolution kernels of a speculative chunk (after its insert or erase kernel).
+// The resolution kernels stride over their elements with at most kSpecGrid blocks: they read one
+// header word and leave when nothing is listed, and a small grid keeps that cheap.
+constexpr int kSpecGrid = 1024;
+
+template <int VK, bool ERASE>
+void spec_resolve(ct_table* t, const TableView& v, const uint64_t* kc, const void* vc, int64_t q,
+                  uint8_t* sc, int gb, uint32_t db, hipStream_t s) {
+  const int g = std::min(flat_blocks(q), kSpecGrid);
+  launch(t, CT_KERNEL_APPLY, s, [&] { k_spec_sum<<<1, 1024, 0, s>>>(v, gb, q, ERASE ? 1 : 0); });
+  launch(t, CT_KERNEL_APPLY, s, [&] { k_spec_clear<<<std::min(flat_blocks(db / 2), kSpecGrid), kBlock, 0, s>>>(v, q); });
+  launch(t, CT_KERNEL_DEDUP, s, [&] { k_spec_build<<<g, kBlock, 0, s>>>(v, kc, q); });
+  launch(t, CT_KERNEL_FIX, s, [&] { k_spec_probe<VK, ERASE><<<g, kBlock, 0, s>>>(v, kc, vc, q, sc); });
+  launch(t, CT_KERNEL_FIX, s, [&] { k_spec_swap<VK, ERASE><<<g, kBlock, 0, s>>>(v, kc, vc, q, sc); });
 }
 
 // Insert of n keys in chunks of at most `chunk`, with the per-chunk scratch that view `v` names
@@ -2858,14 +2954,11 @@ ct_status insert_chunks(ct_table* t, const TableView& v, int64_t chunk, const ui
     const int ntiles = (int)((q + kTile - 1) / kTile);
     // the host bound proves that no element can meet FULL: the rank pass is not needed
     const bool surely_fast = t->size_ub + (uint64_t)q <= (uint64_t)t->desc.capacity;
-    if (surely_fast && use_speculation(t)) {
+    if (surely_fast && use_speculation(t, 0)) {
       // speculative: insert first, then resolve the copies of keys listed as ambiguous
-      launch(t, CT_KERNEL_PROLOGUE, s, [&] { k_spec_prologue<<<1, 64, 0, s>>>(v, q); });
+      launch(t, CT_KERNEL_PROLOGUE, s, [&] { k_spec_prologue<<<1, 64, 0, s>>>(v, q, 1); });
       launch(t, CT_KERNEL_INSERT, s, [&] { k_insert_spec<VK><<<gb, kBlock, 0, s>>>(v, kc, vc, q, sc); });
-      launch(t, CT_KERNEL_APPLY, s, [&] { k_spec_clear<<<flat_blocks(db / 2), kBlock, 0, s>>>(v, gb, q); });
-      launch(t, CT_KERNEL_DEDUP, s, [&] { k_spec_build<<<flat_blocks(q), kBlock, 0, s>>>(v, kc, q); });
-      launch(t, CT_KERNEL_FIX, s, [&] { k_spec_probe<VK><<<flat_blocks(q), kBlock, 0, s>>>(v, kc, vc, q, sc); });
-      launch(t, CT_KERNEL_FIX, s, [&] { k_spec_swap<VK><<<flat_blocks(q), kBlock, 0, s>>>(v, kc, vc, q, sc); });
+      spec_resolve<VK, false>(t, v, kc, vc, q, sc, gb, db, s);
       t->size_ub = std::min<uint64_t>(t->size_ub + (uint64_t)q, (uint64_t)t->desc.capacity);
       ct_status r = launched();
       if (r != CT_OK) return r;
@@ -2874,7 +2967,7 @@ ct_status insert_chunks(ct_table* t, const TableView& v, int64_t chunk, const ui
     dedup_chunk(t, v, nullptr, kc, q, s);
     launch(t, CT_KERNEL_INSERT, s, [&] { k_insert<VK, false><<<gb, kBlock, 0, s>>>(v, kc, vc, q, db - 1, sc, nullptr); });
     // a chunk that may meet capacity stores more keys in its ranked pass: no report
-    launch(t, CT_KERNEL_APPLY, s, [&] { k_apply_count<<<1, 1024, 0, s>>>(v, gb, surely_fast ? q : 0); });
+    launch(t, CT_KERNEL_APPLY, s, [&] { k_apply_count<<<1, 1024, 0, s>>>(v, gb, surely_fast ? q : 0, 0); });
     if (!surely_fast) {
       launch(t, CT_KERNEL_RANK, s, [&] { k_tile_count<<<ntiles, kBlock, 0, s>>>(v, q, 1); });
       launch(t, CT_KERNEL_RANK, s, [&] { k_tile_scan<<<1, 1024, 0, s>>>(v, nullptr, ntiles, 0); });
@@ -2904,9 +2997,18 @@ ct_status erase_chunks(ct_table* t, ct_pool* p, const uint64_t* keys, int64_t n,
     uint8_t* ec = erased ? erased + c0 : nullptr;
     const int gb = group_blocks((q + kSlots - 1) / kSlots);
     const int ntiles = (int)((q + kTile - 1) / kTile);
+    if (!RELEASE && use_speculation(t, 1)) {
+      // speculative: remove first, then move each removal to the lowest copy of its key
+      launch(t, CT_KERNEL_PROLOGUE, s, [&] { k_spec_prologue<<<1, 64, 0, s>>>(t->v, q, 0); });
+      launch(t, CT_KERNEL_ERASE, s, [&] { k_erase_spec<<<gb, kBlock, 0, s>>>(t->v, kc, q, ec); });
+      spec_resolve<0, true>(t, t->v, kc, nullptr, q, ec, gb, db, s);
+      ct_status r = launched();
+      if (r != CT_OK) return r;
+      continue;
+    }
     dedup_chunk(t, t->v, RELEASE ? p->hdr : nullptr, kc, q, s);
     launch(t, CT_KERNEL_ERASE, s, [&] { k_erase<RELEASE><<<gb, kBlock, 0, s>>>(t->v, kc, q, db - 1, ec); });
-    launch(t, CT_KERNEL_APPLY, s, [&] { k_apply_count<<<1, 1024, 0, s>>>(t->v, gb, 0); });
+    launch(t, CT_KERNEL_APPLY, s, [&] { k_apply_count<<<1, 1024, 0, s>>>(t->v, gb, RELEASE ? 0 : q, 1); });
     if (RELEASE) {
       launch(t, CT_KERNEL_RANK, s, [&] { k_tile_count<<<ntiles, kBlock, 0, s>>>(t->v, q, 0); });
       launch(t, CT_KERNEL_RANK, s, [&] { k_tile_scan<<<1, 1024, 0, s>>>(t->v, p->hdr, ntiles, 2); });
@@ -3278,7 +3380,7 @@ ct_status ct_table_rehash(ct_table* src, ct_table* dst, void* stream) {
   const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(((int64_t)src->v.nb + kBlock / 8 - 1) / (kBlock / 8), kMaxGroupBlocks));
   hipStream_t s = S(stream);
   launch(dst, CT_KERNEL_INSERT, s, [&] { k_rehash<<<grid, kBlock, 0, s>>>(src->v, dst->v); });
-  launch(dst, CT_KERNEL_APPLY, s, [&] { k_apply_count<<<1, 1024, 0, s>>>(dst->v, grid, 0); });
+  launch(dst, CT_KERNEL_APPLY, s, [&] { k_apply_count<<<1, 1024, 0, s>>>(dst->v, grid, 0, 0); });
   dst->size_ub = (uint64_t)(nd + ns);
   return launched();
 }

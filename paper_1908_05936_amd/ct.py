@@ -126,6 +126,7 @@ SIGNATURES = {
     "ct_server_destroy": (C.c_int, [_P]),
     "ctr_gather": (C.c_int, [_P, _I64, _I32, _P, _I64, _P, _P]),
     "ctr_gather_cas": (C.c_int, [_P, _I64, _I32, _P, _I64, _P, _P]),
+    "ctr_gather_cas_store": (C.c_int, [_P, _I64, _I32, _P, _I64, _P, _P]),
     "ctr_cas": (C.c_int, [_P, _I64, _P, _I64, _P]),
     "ctr_amin": (C.c_int, [_P, _I64, _P, _I64, _P]),
     "ctr_copy": (C.c_int, [_P, _P, _I64, _P]),
@@ -709,8 +710,9 @@ class NativeServer:
 
 # --- measured ceilings (include/ct_roofline.h) ------------------------------------------------
 def gather(lines: torch.Tensor, nlines: int, line_bytes: int, keys: torch.Tensor, out: torch.Tensor,
-           cas: bool = False):
-    f = lib().ctr_gather_cas if cas else lib().ctr_gather
+           cas: bool = False, store: bool = False):
+    """ctr_gather, ctr_gather_cas (cas) or ctr_gather_cas_store (cas and store)."""
+    f = (lib().ctr_gather_cas_store if store else lib().ctr_gather_cas) if cas else lib().ctr_gather
     _check(f(_ptr(lines), int(nlines), int(line_bytes), _ptr(keys), keys.numel(), _ptr(out),
              _stream(keys.device)), "ctr_gather")
 

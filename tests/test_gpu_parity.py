@@ -649,3 +649,33 @@ def test_auto_path_follows_the_last_chunk(dev):
     assert dedup_launches(c) == 1      # speculative again
     p.g.profiling(False)
     p.same_state()
+
+
+@pytest.mark.parametrize("chunk", [1024, 1 << 16])
+def test_speculative_erase_repeated_and_absent(dev, chunk):
+    """A speculative erase removes a found key with one compare-and-swap, so exactly one copy
+    removes it; copies that lose that CAS or find nothing are listed, and the lowest listed copy
+    takes the removal over from a higher remover.  Batches mix keys present once, present keys
+    repeated many times, absent keys (repeated too) and the reserved-looking keys, on a table with
+    tombstones; the erase flags and the contents equal the oracle's after every batch, also
+    without a flag array."""
+    rng = rng_for(347, chunk)
+    p = Pair(dev, 1 << 18, 64, chunk=chunk, path=ct.INSERT_SPECULATIVE)
+    base = distinct_u64(rng, 80000)
+    p.insert(np.concatenate([base[:50000], RESERVED[:3]]), rng.integers(0, 1 << 62, size=50003, dtype=np.uint64))
+    for rep in range(4):
+        n = [3000, 1 << 16, 70001, 17][rep]
+        pools = [base[:50000], base[:200], base[50000:], RESERVED]
+        which = rng.integers(0, 4, size=n)
+        keys = np.empty(n, dtype=np.uint64)
+        for j in range(4):
+            pick = pools[j][rng.integers(0, pools[j].size, size=n)]
+            keys[which == j] = pick[which == j]
+        p.erase(keys)
+        p.same_state()
+        p.insert(keys[: n // 2], rng.integers(0, 1 << 62, size=n // 2, dtype=np.uint64))
+        p.same_state()
+    keys = base[rng.integers(0, 80000, size=40000)]
+    p.g.erase(g64(keys, dev), status=False)
+    p.o.erase(keys)
+    p.same_state()
