@@ -1,5 +1,6 @@
 """Scheduling logic of the native request server, built for the host against a HIP stand-in and a
-reference table (tests/native), run plainly and under ThreadSanitizer: results equal a sequential
+reference table (tests/native), run plainly, under ThreadSanitizer, and under AddressSanitizer with
+UndefinedBehaviorSanitizer: results equal a sequential
 replay in submission order, caps hold, every ticket completes once, nothing leaks."""
 import os
 import shutil
@@ -35,3 +36,7 @@ def test_server_scheduling_on_host(tmp_path):
 
 def test_server_scheduling_under_thread_sanitizer(tmp_path):
     _build_and_run(tmp_path, ["-fsanitize=thread"])
+
+
+def test_server_scheduling_under_address_and_undefined_sanitizers(tmp_path):
+    _build_and_run(tmp_path, ["-fsanitize=address,undefined", "-fno-sanitize-recover=all"])
