@@ -402,6 +402,16 @@ ct_status ct_pool_get_error(ct_pool *p, uint32_t *h_err, void *stream);
 ct_status ct_insert_alloc_batch(ct_table *t, ct_pool *p, const uint64_t *keys, int64_t n,
                                 int32_t *vals_out, uint8_t *status, void *stream);
 
+/* ct_insert_alloc_batch of the elements i with skip[i] == 0 only (skip[n], device, required):
+   the same results as ct_insert_alloc_batch of those keys gathered in index order, written back to
+   their positions; vals_out[i] and status[i] of skipped elements are left untouched.  Passing the
+   `found` array of a ct_find_batch of the same keys inserts the keys the find missed (the
+   allocation step of the reconstruction use of Section 4.1), with no host round trip to count
+   or compact them. */
+ct_status ct_insert_alloc_batch_masked(ct_table *t, ct_pool *p, const uint64_t *keys,
+                                       const uint8_t *skip, int64_t n, int32_t *vals_out,
+                                       uint8_t *status, void *stream);
+
 /* Erase of an array where each removed key's value is pushed back to `p`, in batch order.
    erased[n] nullable as for ct_erase_batch. */
 ct_status ct_erase_release_batch(ct_table *t, ct_pool *p, const uint64_t *keys, int64_t n,

@@ -2,8 +2,10 @@
 
 2^20 resident blocks (packed int3 keys, values popped from the index pool) in a table of 2^21
 buckets, then 100 frames of find(2^18 keys, 90 % hits) followed by insert_alloc of the frame's
-misses.  Reports per-frame wall time p50/p99 (find, selecting the misses, insert_alloc, with the
-results on the device) and find / insert_alloc Mkeys/s from HIP events on the launching stream.
+misses, passed to the table as the find's flags (ct_insert_alloc_batch_masked).  Reports per-frame
+wall time p50/p99 (find and insert of the misses, results on the device) and find / insert
+Mkeys/s from HIP events on the launching stream; the same frames with the misses compacted on the
+host, and as one insert_alloc of the whole query, for comparison.
 
     python -m paper_1908_05936_amd.bench_voxel [--repeats 3]
 """
@@ -102,6 +104,28 @@ def one_call_frames(t, cap, res_keys, frames, dev, size, reps: int = 2) -> dict:
             "frame_p99_ms": float(np.percentile(ms, 99))}
 
 
+def compacted_frames(t, cap, res_keys, frames, dev, size, reps: int = 2) -> dict:
+    """The same frames with the misses compacted first (a boolean-mask gather, which reads the
+    miss count back to the host) and passed to insert_alloc.  Per-frame wall time after one
+    warm-up pass; the final table is the same."""
+    ms = []
+    for rep in range(reps + 1):
+        t.clear()
+        pool = ct.Pool(cap, device=dev)
+        t.insert_alloc(pool, res_keys)
+        torch.cuda.synchronize()
+        for q in frames:
+            w0 = time.perf_counter()
+            _, found = t.find(q, values=True)
+            t.insert_alloc(pool, q[found == 0])
+            torch.cuda.synchronize()
+            if rep > 0:
+                ms.append((time.perf_counter() - w0) * 1e3)
+    assert t.size() == size
+    return {"frames_timed": len(ms), "frame_p50_ms": float(np.percentile(ms, 50)),
+            "frame_p99_ms": float(np.percentile(ms, 99))}
+
+
 def run(repeats: int = 3, seed: int = 2, log=print) -> dict:
     dev = torch.device("cuda", 0)
     w = voxel_blocks(seed=seed)
@@ -111,30 +135,32 @@ def run(repeats: int = 3, seed: int = 2, log=print) -> dict:
     t = ct.Table(cap, ct.VAL_U32, ct.HASH_VOXEL21, bucket_count=nb, device=dev)
     pool = ct.Pool(cap, device=dev)
     frame_ms, find_s, ins_s, n_find, n_ins = [], 0.0, 0.0, 0, 0
+    vout = torch.empty(1 << 18, dtype=torch.int32, device=dev)
+    sout = torch.empty(1 << 18, dtype=torch.uint8, device=dev)
     for rep in range(repeats):
         t.clear()
         pool = ct.Pool(cap, device=dev)   # a fresh free list: pops 0, 1, 2, ... again
         t.insert_alloc(pool, res_keys)
         torch.cuda.synchronize()
         for q in frames:
-            e = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+            e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
             w0 = time.perf_counter()
             e[0].record()
             _, found = t.find(q, values=True)
             e[1].record()
-            miss = q[found == 0]
+            # the misses go in through the find's flags: no host round trip to count them
+            t.insert_alloc_masked(pool, q, found, vout[:q.numel()], sout[:q.numel()])
             e[2].record()
-            t.insert_alloc(pool, miss)
-            e[3].record()
             torch.cuda.synchronize()
             wall = time.perf_counter() - w0
             if rep > 0:   # the first pass warms up
                 frame_ms.append(wall * 1e3)
                 find_s += e[0].elapsed_time(e[1]) * 1e-3
-                ins_s += e[2].elapsed_time(e[3]) * 1e-3
+                ins_s += e[1].elapsed_time(e[2]) * 1e-3
                 n_find += q.numel()
-                n_ins += miss.numel()
+                n_ins += int(q.numel() - found.sum())
     size = t.size()
+    compacted = compacted_frames(t, cap, res_keys, frames, dev, size)
     # range selection (select_blocks-style copy_if): the blocks in the octant x, y, z >= 0 of the
     # final table; the kernel streams every bucket once
     import ctypes as C
@@ -157,7 +183,8 @@ def run(repeats: int = 3, seed: int = 2, log=print) -> dict:
     one = one_call_frames(t, cap, res_keys, frames, dev, size)
     out = {
         "workload": (f"voxel blocks: {w['residents'].size} residents, 2^21 buckets, spatial hash, "
-                     f"{len(frames)} frames of find 2^18 (90% hits) + insert_alloc of the misses"),
+                     f"{len(frames)} frames of find 2^18 (90% hits) + insert_alloc of the misses "
+                     "(through the find's flags)"),
         "frames_timed": len(frame_ms),
         "frame_p50_ms": float(np.percentile(frame_ms, 50)),
         "frame_p99_ms": float(np.percentile(frame_ms, 99)),
@@ -166,6 +193,7 @@ def run(repeats: int = 3, seed: int = 2, log=print) -> dict:
         "final_size": size,
         "neighbour_update": nbr,
         "one_call_frames": one,
+        "compacted_frames": compacted,
         "select_box": {"selected": int(cnt.value), "ms": sel_s * 1e3,
                        "table_GB_s": nb * 128 / sel_s / 1e9,
                        "note": "octant x, y, z >= 0 of the final table; the call's time, its "
@@ -176,6 +204,8 @@ def run(repeats: int = 3, seed: int = 2, log=print) -> dict:
         f"{nbr['batch_insert_ms']:.2f} ms + keys {nbr['batch_keys_ms']:.2f} ms")
     log(f"[voxel] frames as one insert_alloc each: p50 {one['frame_p50_ms']:.3f} ms p99 "
         f"{one['frame_p99_ms']:.3f} ms")
+    log(f"[voxel] frames with the misses compacted on the host: p50 "
+        f"{compacted['frame_p50_ms']:.3f} ms p99 {compacted['frame_p99_ms']:.3f} ms")
     log(f"[voxel] select box: {out['select_box']['selected']} blocks in "
         f"{out['select_box']['ms']:.3f} ms ({out['select_box']['table_GB_s']:.0f} GB/s of table)")
     log(f"[voxel] p50 {out['frame_p50_ms']:.3f} ms p99 {out['frame_p99_ms']:.3f} ms, find "

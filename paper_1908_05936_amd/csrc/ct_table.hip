@@ -253,8 +253,10 @@ __global__ __launch_bounds__(kBlock) void k_prologue(TableView t, PoolHeader* po
 // indices held by one entry belong to one key, so the fingerprint plus one look at that
 // element's key identifies the entry exactly.  A key repeated many times therefore costs one
 // global operation per window, not per copy.  Needs blockDim.x == kBlock.
+// `skip` (nullable): elements with a nonzero byte there take no part (a masked insert).
 __device__ __forceinline__ void dedup_range(const TableView& t, const uint64_t* __restrict__ keys,
-                                            uint32_t dmask, int64_t lo, int64_t hi, int64_t step) {
+                                            const uint8_t* __restrict__ skip, uint32_t dmask,
+                                            int64_t lo, int64_t hi, int64_t step) {
   constexpr uint32_t kW = 2 * kBlock;  // LDS slots of a window's table
   __shared__ unsigned long long wk[kW];
   __shared__ uint32_t wmin[kW], wcnt[kW];
@@ -266,7 +268,7 @@ __device__ __forceinline__ void dedup_range(const TableView& t, const uint64_t* 
     }
     __syncthreads();
     const int64_t i = b0 + threadIdx.x;
-    const bool valid = i < hi;
+    const bool valid = i < hi && !(skip && skip[i]);
     const uint64_t key = valid ? keys[i] : kEmpty;
     const bool normal = valid && key < kTomb;
     if (valid && !normal) amin32(&t.hdr->spec_first[key - kTomb], (uint32_t)i);
@@ -313,8 +315,9 @@ __device__ __forceinline__ void dedup_range(const TableView& t, const uint64_t* 
 }
 
 __global__ __launch_bounds__(kBlock) void k_dedup(TableView t, const uint64_t* __restrict__ keys,
-                                                  int64_t q, uint32_t dmask) {
-  dedup_range(t, keys, dmask, (int64_t)blockIdx.x * kBlock, q, (int64_t)gridDim.x * kBlock);
+                                                  const uint8_t* __restrict__ skip, int64_t q,
+                                                  uint32_t dmask) {
+  dedup_range(t, keys, skip, dmask, (int64_t)blockIdx.x * kBlock, q, (int64_t)gridDim.x * kBlock);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -689,7 +692,7 @@ __global__ __launch_bounds__(kBlock) void k_bin_fallback_dedup(TableView t,
                                                                const uint64_t* __restrict__ keys,
                                                                int64_t q, uint32_t dmask) {
   if (!t.hdr->dovf) return;
-  dedup_range(t, keys, dmask, (int64_t)blockIdx.x * kBlock, q, (int64_t)gridDim.x * kBlock);
+  dedup_range(t, keys, nullptr, dmask, (int64_t)blockIdx.x * kBlock, q, (int64_t)gridDim.x * kBlock);
 }
 
 // Index-order role of this lane's element: its own index when it is the first copy of its key in
@@ -816,9 +819,11 @@ __device__ __forceinline__ uint64_t claim_group(const TableView& t, uint64_t key
 // new key (all CASes of the group in flight together; a lost race retries one key at a time).
 // Otherwise (or with a pool) flag new keys for the ranked completion.
 // Elements [lo, hi) of a chunk, 8 per group, the block's groups striding by `step` elements.
+// `skip` (nullable): elements with a nonzero byte there take no part and keep their outputs.
 // Returns this thread's count of stored keys.
 template <int VK, bool ALLOC>
 __device__ __forceinline__ int64_t insert_range(const TableView& t, const uint64_t* __restrict__ keys,
+                                                const uint8_t* __restrict__ skip,
                                                 const void* __restrict__ vals, uint32_t dmask,
                                                 uint8_t* __restrict__ status,
                                                 int32_t* __restrict__ vout, int64_t lo, int64_t hi,
@@ -836,9 +841,10 @@ __device__ __forceinline__ int64_t insert_range(const TableView& t, const uint64
     const uint64_t val = (!ALLOC && valid) ? load_val<VK>(vals, i) : 0;
     const uint32_t mark = t.dmark[min(i, hi - 1)];
     asm volatile("" ::"v"(mark));  // keep the load here, issued with the key's
-    const uint32_t first = valid ? first_copy(t, keys, key, i, dmask, mark) : 0u;
-    const bool actor = valid && first == (uint32_t)i;
-    const bool dup = valid && !actor;
+    const bool active = valid && !(skip && skip[i]);
+    const uint32_t first = active ? first_copy(t, keys, key, i, dmask, mark) : 0u;
+    const bool actor = active && first == (uint32_t)i;
+    const bool dup = active && !actor;
     const uint32_t slot = wave_append(dup, &t.hdr->ndup);
     if (dup) t.dup[slot] = make_uint2((uint32_t)i, first);
 
@@ -930,8 +936,9 @@ template <int VK, bool ALLOC>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu((ALLOC || VK == 0) ? 1 : 5))) void k_insert(TableView t, const uint64_t* __restrict__ keys,
                                                    const void* __restrict__ vals, int64_t q,
                                                    uint32_t dmask, uint8_t* __restrict__ status,
-                                                   int32_t* __restrict__ vout) {
-  const int64_t ins = insert_range<VK, ALLOC>(t, keys, vals, dmask, status, vout,
+                                                   int32_t* __restrict__ vout,
+                                                   const uint8_t* __restrict__ skip) {
+  const int64_t ins = insert_range<VK, ALLOC>(t, keys, skip, vals, dmask, status, vout,
                                               (int64_t)blockIdx.x * kBlock, q,
                                               (int64_t)gridDim.x * kBlock);
   // one partial per block, summed by k_apply_count: no same-address atomics across the grid
@@ -2538,7 +2545,7 @@ __global__ __launch_bounds__(kBlock) void k_g_dedup(const GStep* __restrict__ st
   const GLoc L = g_locate(e, n);
   const GStep& g = st[L.step];
   const TableView t = g.v;
-  dedup_range(t, g.keys, g.db - 1, (int64_t)L.lb * kBlock, g.q, (int64_t)L.nblk * kBlock);
+  dedup_range(t, g.keys, nullptr, g.db - 1, (int64_t)L.lb * kBlock, g.q, (int64_t)L.nblk * kBlock);
 }
 
 // The grouped find / insert / erase stages run with BS threads per block (the plan's block size):
@@ -2552,11 +2559,11 @@ __global__ __launch_bounds__(BS) void k_g_insert(const GStep* __restrict__ st,
   const int64_t lo = (int64_t)L.lb * BS, step = (int64_t)L.nblk * BS;
   int64_t ins;
   if (g.vk == 1)
-    ins = insert_range<1, false>(t, g.keys, g.vals, g.db - 1, g.flags, nullptr, lo, g.q, step);
+    ins = insert_range<1, false>(t, g.keys, nullptr, g.vals, g.db - 1, g.flags, nullptr, lo, g.q, step);
   else if (g.vk == 2)
-    ins = insert_range<2, false>(t, g.keys, g.vals, g.db - 1, g.flags, nullptr, lo, g.q, step);
+    ins = insert_range<2, false>(t, g.keys, nullptr, g.vals, g.db - 1, g.flags, nullptr, lo, g.q, step);
   else
-    ins = insert_range<0, false>(t, g.keys, nullptr, g.db - 1, g.flags, nullptr, lo, g.q, step);
+    ins = insert_range<0, false>(t, g.keys, nullptr, nullptr, g.db - 1, g.flags, nullptr, lo, g.q, step);
   const int64_t tot = block_sum<BS>(ins);
   if (threadIdx.x == 0) t.bcnt[L.lb] = tot;
 }
@@ -2906,7 +2913,7 @@ void dedup_chunk(ct_table* t, const TableView& v, PoolHeader* pool, const uint64
     launch(t, CT_KERNEL_DEDUP, s, [&] { k_bin_fallback_dedup<<<flat_blocks(q), kBlock, 0, s>>>(v, kc, q, db - 1); });
   } else {
     launch(t, CT_KERNEL_PROLOGUE, s, [&] { k_prologue<<<flat_blocks(db / 2), kBlock, 0, s>>>(v, pool, db, q); });
-    launch(t, CT_KERNEL_DEDUP, s, [&] { k_dedup<<<flat_blocks(q), kBlock, 0, s>>>(v, kc, q, db - 1); });
+    launch(t, CT_KERNEL_DEDUP, s, [&] { k_dedup<<<flat_blocks(q), kBlock, 0, s>>>(v, kc, nullptr, q, db - 1); });
   }
 }
 
@@ -2965,7 +2972,7 @@ ct_status insert_chunks(ct_table* t, const TableView& v, int64_t chunk, const ui
       continue;
     }
     dedup_chunk(t, v, nullptr, kc, q, s);
-    launch(t, CT_KERNEL_INSERT, s, [&] { k_insert<VK, false><<<gb, kBlock, 0, s>>>(v, kc, vc, q, db - 1, sc, nullptr); });
+    launch(t, CT_KERNEL_INSERT, s, [&] { k_insert<VK, false><<<gb, kBlock, 0, s>>>(v, kc, vc, q, db - 1, sc, nullptr, nullptr); });
     // a chunk that may meet capacity stores more keys in its ranked pass: no report
     launch(t, CT_KERNEL_APPLY, s, [&] { k_apply_count<<<1, 1024, 0, s>>>(v, gb, surely_fast ? q : 0, 0); });
     if (!surely_fast) {
@@ -3607,23 +3614,32 @@ ct_status ct_pool_get_error(ct_pool* p, uint32_t* h_err, void* stream) {
   return hipStreamSynchronize(S(stream)) == hipSuccess ? CT_OK : CT_E_HIP;
 }
 
-ct_status ct_insert_alloc_batch(ct_table* t, ct_pool* p, const uint64_t* keys, int64_t n,
-                                int32_t* vals_out, uint8_t* status, void* stream) {
-  ct_status r = check_batch(t, keys, n);
-  if (r != CT_OK || !p) return CT_E_INVALID;
-  if (t->desc.val_kind != CT_VAL_U32) return CT_E_INVALID;
-  if (n == 0) return CT_OK;
-  hipStream_t s = S(stream);
+}  // extern "C"
+
+namespace {
+
+// Pool-valued insert of n keys; with `skip`, only the elements whose byte there is zero take part,
+// in index order among themselves (masked batches are sparse: their repeated keys are resolved
+// through dd, whatever the chunk size).
+ct_status insert_alloc_chunks(ct_table* t, ct_pool* p, const uint64_t* keys, const uint8_t* skip,
+                              int64_t n, int32_t* vals_out, uint8_t* status, hipStream_t s) {
+  ct_status r = CT_OK;
   for (int64_t c0 = 0; c0 < n; c0 += t->chunk) {
     const int64_t q = std::min<int64_t>(t->chunk, n - c0);
     const uint32_t db = dedup_slots_for(q);
     const uint64_t* kc = keys + c0;
+    const uint8_t* mc = skip ? skip + c0 : nullptr;
     uint8_t* sc = status ? status + c0 : nullptr;
     int32_t* vc = vals_out ? vals_out + c0 : nullptr;
     const int gb = group_blocks((q + kSlots - 1) / kSlots);
     const int ntiles = (int)((q + kTile - 1) / kTile);
-    dedup_chunk(t, t->v, p->hdr, kc, q, s);
-    launch(t, CT_KERNEL_INSERT, s, [&] { k_insert<1, true><<<gb, kBlock, 0, s>>>(t->v, kc, nullptr, q, db - 1, sc, vc); });
+    if (mc) {
+      launch(t, CT_KERNEL_PROLOGUE, s, [&] { k_prologue<<<flat_blocks(db / 2), kBlock, 0, s>>>(t->v, p->hdr, db, q); });
+      launch(t, CT_KERNEL_DEDUP, s, [&] { k_dedup<<<flat_blocks(q), kBlock, 0, s>>>(t->v, kc, mc, q, db - 1); });
+    } else {
+      dedup_chunk(t, t->v, p->hdr, kc, q, s);
+    }
+    launch(t, CT_KERNEL_INSERT, s, [&] { k_insert<1, true><<<gb, kBlock, 0, s>>>(t->v, kc, nullptr, q, db - 1, sc, vc, mc); });
     launch(t, CT_KERNEL_RANK, s, [&] { k_tile_count<<<ntiles, kBlock, 0, s>>>(t->v, q, 0); });
     launch(t, CT_KERNEL_RANK, s, [&] { k_tile_scan<<<1, 1024, 0, s>>>(t->v, p->hdr, ntiles, 1); });
     launch(t, CT_KERNEL_FINAL, s, [&] { k_final<1, 1><<<ntiles, kBlock, 0, s>>>(t->v, p->hdr, p->stack, kc, nullptr, q, sc, vc); });
@@ -3633,6 +3649,29 @@ ct_status ct_insert_alloc_batch(ct_table* t, ct_pool* p, const uint64_t* keys, i
     if (r != CT_OK) return r;
   }
   return CT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+ct_status ct_insert_alloc_batch(ct_table* t, ct_pool* p, const uint64_t* keys, int64_t n,
+                                int32_t* vals_out, uint8_t* status, void* stream) {
+  ct_status r = check_batch(t, keys, n);
+  if (r != CT_OK || !p) return CT_E_INVALID;
+  if (t->desc.val_kind != CT_VAL_U32) return CT_E_INVALID;
+  if (n == 0) return CT_OK;
+  return insert_alloc_chunks(t, p, keys, nullptr, n, vals_out, status, S(stream));
+}
+
+ct_status ct_insert_alloc_batch_masked(ct_table* t, ct_pool* p, const uint64_t* keys,
+                                       const uint8_t* skip, int64_t n, int32_t* vals_out,
+                                       uint8_t* status, void* stream) {
+  ct_status r = check_batch(t, keys, n);
+  if (r != CT_OK || !p || (n > 0 && !skip)) return CT_E_INVALID;
+  if (t->desc.val_kind != CT_VAL_U32) return CT_E_INVALID;
+  if (n == 0) return CT_OK;
+  return insert_alloc_chunks(t, p, keys, skip, n, vals_out, status, S(stream));
 }
 
 ct_status ct_erase_release_batch(ct_table* t, ct_pool* p, const uint64_t* keys, int64_t n,

@@ -66,8 +66,12 @@ def test_large_table_full_size(dev):
     assert t.check() == 0
 
 
-def test_voxel_frames_full_size(dev):
-    print("voxel: generating", flush=True)
+@pytest.mark.parametrize("misses", ["compacted", "masked"])
+def test_voxel_frames_full_size(dev, misses):
+    """100 frames of find + insert_alloc of the misses on the full voxel workload, bit-exact
+    against the oracle.  The misses reach the table either compacted on the host (the find's flags
+    select them) or through ct_insert_alloc_batch_masked with the find's flags as the mask."""
+    print(f"voxel ({misses}): generating", flush=True)
     w = voxel_blocks(seed=2)
     nb = w["bucket_count"]
     pool_cap = w["pool_capacity"]
@@ -86,10 +90,17 @@ def test_voxel_frames_full_size(dev):
         np.testing.assert_array_equal(fd.cpu().numpy(), ef)
         np.testing.assert_array_equal(v.cpu().numpy().view(np.uint32), ev)
         miss = q[ef == 0]
-        v, st = t.insert_alloc(gp, g64(miss, dev))
         ev, es = o.insert_alloc(op, miss)
-        np.testing.assert_array_equal(st.cpu().numpy(), es)
-        np.testing.assert_array_equal(v.cpu().numpy(), ev)
+        if misses == "compacted":
+            v, st = t.insert_alloc(gp, g64(miss, dev))
+            np.testing.assert_array_equal(st.cpu().numpy(), es)
+            np.testing.assert_array_equal(v.cpu().numpy(), ev)
+        else:
+            v, st = t.insert_alloc_masked(gp, qd, fd)
+            v, st = v.cpu().numpy(), st.cpu().numpy()
+            np.testing.assert_array_equal(st[ef == 0], es)
+            np.testing.assert_array_equal(v[ef == 0], ev)
+            assert (st[ef == 1] == 0xFF).all() and (v[ef == 1] == -1).all()
         if f % 25 == 0:
             print(f"voxel: frame {f} ok", flush=True)
     assert t.size() == o.size() == 3669976

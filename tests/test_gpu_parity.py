@@ -679,3 +679,38 @@ def test_speculative_erase_repeated_and_absent(dev, chunk):
     p.g.erase(g64(keys, dev), status=False)
     p.o.erase(keys)
     p.same_state()
+
+
+@pytest.mark.parametrize("chunk", [1024, 1 << 16])
+def test_masked_insert_alloc(dev, chunk):
+    """ct_insert_alloc_batch_masked inserts only the elements whose skip byte is 0, with the same
+    results as ct_insert_alloc_batch of those keys gathered in index order; skipped elements keep
+    their outputs.  Masks: a find's flags (insert the misses), random masks, all-skipped and
+    none-skipped; keys repeat and include the reserved-looking ones; the pool runs out in the last
+    batch."""
+    rng = rng_for(359, chunk)
+    pcap = 60000
+    p = Pair(dev, 1 << 17, 32, chunk=chunk, pool=pcap)
+    universe = np.concatenate([distinct_u64(rng, 90000), RESERVED])
+    for rep in range(5):
+        n = [20000, 70001, 5000, 3, 90000][rep]
+        keys = universe[rng.integers(0, universe.size, size=n)]
+        kd = g64(keys, dev)
+        if rep == 0 or rep == 4:
+            _, f = p.g.find(kd)
+            skip = f
+        elif rep == 1:
+            skip = torch.from_numpy((rng.random(n) < 0.7).astype(np.uint8)).to(dev)
+        elif rep == 2:
+            skip = torch.ones(n, dtype=torch.uint8, device=dev)
+        else:
+            skip = torch.zeros(n, dtype=torch.uint8, device=dev)
+        m = skip.cpu().numpy() == 0
+        v, st = p.g.insert_alloc_masked(p.gp, kd, skip)
+        ev, es = p.o.insert_alloc(p.op, keys[m])
+        v, st = v.cpu().numpy(), st.cpu().numpy()
+        np.testing.assert_array_equal(st[m], es)
+        np.testing.assert_array_equal(v[m], ev)
+        assert (st[~m] == 0xFF).all() and (v[~m] == -1).all()
+        p.same_state()
+    assert (es == 2).any()   # the pool ran out in the last batch
