@@ -101,6 +101,7 @@ SIGNATURES = {
     "ct_pool_dump": (C.c_int, [_P, _P, _I64, _PI64, _P]),
     "ct_pool_get_error": (C.c_int, [_P, C.POINTER(C.c_uint32), _P]),
     "ct_insert_alloc_batch": (C.c_int, [_P, _P, _P, _I64, _P, _P, _P]),
+    "ct_insert_alloc_batch_masked": (C.c_int, [_P, _P, _P, _P, _I64, _P, _P, _P]),
     "ct_erase_release_batch": (C.c_int, [_P, _P, _P, _I64, _P, _P]),
     "ct_plan_create": (C.c_int, [C.POINTER(_P)]),
     "ct_plan_destroy": (C.c_int, [_P]),
@@ -337,6 +338,22 @@ class Table:
         _check(lib().ct_insert_alloc_batch(self._h, pool._h, _ptr(keys), n, _ptr(out), _ptr(st),
                                            _stream(self.device)), "ct_insert_alloc_batch")
         return out, st
+
+    def insert_alloc_masked(self, pool: Pool, keys: torch.Tensor, skip: torch.Tensor,
+                            out: torch.Tensor | None = None, status: torch.Tensor | None = None):
+        """insert_alloc of the keys whose skip byte is 0 (e.g. the found flags of a find of the
+        same keys); the outputs of skipped elements are left as they are in `out` / `status`."""
+        n = keys.numel()
+        _need(keys, torch.int64, None, "keys", self.device)
+        _need(skip, torch.uint8, n, "skip", self.device)
+        if out is None:
+            out = torch.full((n,), -1, dtype=torch.int32, device=self.device)
+        if status is None:
+            status = torch.full((n,), 0xFF, dtype=torch.uint8, device=self.device)
+        _check(lib().ct_insert_alloc_batch_masked(self._h, pool._h, _ptr(keys), _ptr(skip), n,
+                                                  _ptr(out), _ptr(status), _stream(self.device)),
+               "ct_insert_alloc_batch_masked")
+        return out, status
 
     def erase_release(self, pool: Pool, keys: torch.Tensor):
         n = keys.numel()
