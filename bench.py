@@ -521,6 +521,8 @@ def multi_table_leg(dev) -> dict:
         "per_batch_Mkeys_s": res["per_batch_Mkeys_s"],
         "speedup_vs_per_batch": res["per_batch_ms"] / best_ms,
         "grouped_launches": res.get("grouped_launches"), "grouped_steps": res.get("grouped_steps"),
+        "single_launch_ms": res.get("single_launch_ms"),
+        "single_launch_Mkeys_s": res.get("single_launch_Mkeys_s"),
         "R1_Mlines_s_at_footprint": r1 / 1e6, "R2_Mops_s_at_footprint": r2 / 1e6,
         "ceiling_ms": ceiling_s * 1e3,
         "frac_of_random_access_ceiling": ceiling_s / (best_ms * 1e-3),

@@ -495,6 +495,16 @@ ct_status ct_plan_launch_grouped(ct_plan *p, void *stream);
    graph, replayed with ct_graph_launch and freed with ct_graph_destroy. */
 ct_status ct_plan_capture_grouped(ct_plan *p, void *stream, void **graph_exec);
 
+/* The grouped form of `p` as ONE kernel launch (a cooperative launch: every workgroup of its grid
+   is resident at once).  The grid runs the stage launches of ct_plan_launch_grouped in order:
+   within a stage its workgroups take the stage's blocks in turn, and a grid-wide barrier (with
+   device-scope fences) separates consecutive stages.  Results equal ct_plan_launch_grouped's.
+   The plan must have been grouped with 256-thread stages (the default block size); the grid is at
+   most what the device keeps resident, capped by the widest stage and by `max_blocks` when it is
+   positive.  Asynchronous on `stream`; CT_E_INVALID for a plan that is not grouped (or grouped
+   with another block size), CT_E_HIP when the device cannot launch cooperatively. */
+ct_status ct_plan_launch_single(ct_plan *p, int32_t max_blocks, void *stream);
+
 /* --- kernel timing (tracing) ---------------------------------------------------------------- */
 
 /* Kernel kinds the library launches for a table. */

@@ -17,6 +17,7 @@
 // empty the pool, or when values come from a pool, the new actors are ranked by an exclusive scan
 // in index order (k_tile_count / k_tile_scan) and k_final hands out capacity and pool entries by
 // rank, so the k-th new key of the chunk is the k-th to be stored, as in the sequential replay.
+#include <hip/hip_cooperative_groups.h>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -2486,6 +2487,12 @@ __global__ __launch_bounds__(kBlock) void k_pool_push_front(PoolHeader* ph, int3
 // launch's entry list (first block of each step, ascending) and then runs exactly the range code
 // of the single-table kernel with the step's own block index and block count.
 // ---------------------------------------------------------------------------------------------
+// Stages of the grouped pipeline, in launch order within a level.
+enum GStage : int32_t {
+  gReset, gPro, gDedup, gFind, gInsert, gErase, gApply, gCount, gScan, gFinal, gFix, gStages,
+  gCopy = 100  // copy stage of merged operations (before the first and after the last level)
+};
+
 struct GStep {
   TableView v;
   const uint64_t* keys;
@@ -2510,39 +2517,38 @@ struct GLoc {
   int32_t step, lb, nblk;
 };
 
-// Step of this block: the last entry whose first block is <= blockIdx.x.  Uniform per block.
-__device__ __forceinline__ GLoc g_locate(const GEntry* __restrict__ e, int32_t n) {
-  const int32_t b = (int32_t)blockIdx.x;
+// Step of block b of a launch of nb blocks: the last entry whose first block is <= b.  Uniform per
+// block.
+__device__ __forceinline__ GLoc g_locate_at(const GEntry* __restrict__ e, int32_t n, int32_t b,
+                                            int32_t nb) {
   int32_t lo = 0, hi = n - 1;
   while (lo < hi) {
     const int32_t mid = (lo + hi + 1) >> 1;
     if (e[mid].first <= b) lo = mid;
     else hi = mid - 1;
   }
-  const int32_t end = lo + 1 < n ? e[lo + 1].first : (int32_t)gridDim.x;
+  const int32_t end = lo + 1 < n ? e[lo + 1].first : nb;
   return GLoc{e[lo].step, b - e[lo].first, end - e[lo].first};
 }
 
-__global__ __launch_bounds__(kBlock) void k_g_reset(const GStep* __restrict__ st,
-                                                    const GEntry* __restrict__ e, int32_t n) {
-  const GLoc L = g_locate(e, n);
+__device__ __forceinline__ GLoc g_locate(const GEntry* __restrict__ e, int32_t n) {
+  return g_locate_at(e, n, (int32_t)blockIdx.x, (int32_t)gridDim.x);
+}
+
+__device__ __forceinline__ void g_reset_body(const GStep* __restrict__ st, const GLoc L) {
   const TableView t = st[L.step].v;
   reset_range(t, (int64_t)L.lb * kBlock, (int64_t)t.nb * kSlots, (int64_t)L.nblk * kBlock,
               L.lb == 0, 0);
 }
 
-__global__ __launch_bounds__(kBlock) void k_g_prologue(const GStep* __restrict__ st,
-                                                       const GEntry* __restrict__ e, int32_t n) {
-  const GLoc L = g_locate(e, n);
+__device__ __forceinline__ void g_prologue_body(const GStep* __restrict__ st, const GLoc L) {
   const GStep& g = st[L.step];
   const TableView t = g.v;
   prologue_range(t, nullptr, g.db, g.q, (int64_t)L.lb * kBlock, prologue_units(g.db, g.q),
                  (int64_t)L.nblk * kBlock, L.lb == 0);
 }
 
-__global__ __launch_bounds__(kBlock) void k_g_dedup(const GStep* __restrict__ st,
-                                                    const GEntry* __restrict__ e, int32_t n) {
-  const GLoc L = g_locate(e, n);
+__device__ __forceinline__ void g_dedup_body(const GStep* __restrict__ st, const GLoc L) {
   const GStep& g = st[L.step];
   const TableView t = g.v;
   dedup_range(t, g.keys, nullptr, g.db - 1, (int64_t)L.lb * kBlock, g.q, (int64_t)L.nblk * kBlock);
@@ -2551,9 +2557,7 @@ __global__ __launch_bounds__(kBlock) void k_g_dedup(const GStep* __restrict__ st
 // The grouped find / insert / erase stages run with BS threads per block (the plan's block size):
 // the range code strides by the step's blocks times BS, 8 lanes per key group as always.
 template <int BS>
-__global__ __launch_bounds__(BS) void k_g_insert(const GStep* __restrict__ st,
-                                                 const GEntry* __restrict__ e, int32_t n) {
-  const GLoc L = g_locate(e, n);
+__device__ __forceinline__ void g_insert_body(const GStep* __restrict__ st, const GLoc L) {
   const GStep& g = st[L.step];
   const TableView t = g.v;
   const int64_t lo = (int64_t)L.lb * BS, step = (int64_t)L.nblk * BS;
@@ -2569,9 +2573,7 @@ __global__ __launch_bounds__(BS) void k_g_insert(const GStep* __restrict__ st,
 }
 
 template <int BS>
-__global__ __launch_bounds__(BS) void k_g_erase(const GStep* __restrict__ st,
-                                                const GEntry* __restrict__ e, int32_t n) {
-  const GLoc L = g_locate(e, n);
+__device__ __forceinline__ void g_erase_body(const GStep* __restrict__ st, const GLoc L) {
   const GStep& g = st[L.step];
   const TableView t = g.v;
   const int64_t del = erase_range<false>(t, g.keys, g.db - 1, g.flags, (int64_t)L.lb * BS,
@@ -2581,9 +2583,7 @@ __global__ __launch_bounds__(BS) void k_g_erase(const GStep* __restrict__ st,
 }
 
 template <int BS>
-__global__ __launch_bounds__(BS) void k_g_find(const GStep* __restrict__ st,
-                                               const GEntry* __restrict__ e, int32_t n) {
-  const GLoc L = g_locate(e, n);
+__device__ __forceinline__ void g_find_body(const GStep* __restrict__ st, const GLoc L) {
   const GStep& g = st[L.step];
   const TableView t = g.v;
   const int64_t lo = (int64_t)L.lb * BS, step = (int64_t)L.nblk * BS;
@@ -2592,16 +2592,12 @@ __global__ __launch_bounds__(BS) void k_g_find(const GStep* __restrict__ st,
   else find_range<0>(t, g.keys, nullptr, g.flags, lo, g.q, step);
 }
 
-__global__ __launch_bounds__(1024) void k_g_apply(const GStep* __restrict__ st,
-                                                  const GEntry* __restrict__ e, int32_t n) {
-  const GLoc L = g_locate(e, n);
+__device__ __forceinline__ void g_apply_body(const GStep* __restrict__ st, const GLoc L) {
   const TableView t = st[L.step].v;
   apply_count_block(t, st[L.step].gb);
 }
 
-__global__ __launch_bounds__(kBlock) void k_g_tile_count(const GStep* __restrict__ st,
-                                                         const GEntry* __restrict__ e, int32_t n) {
-  const GLoc L = g_locate(e, n);
+__device__ __forceinline__ void g_tile_count_body(const GStep* __restrict__ st, const GLoc L) {
   const GStep& g = st[L.step];
   const TableView t = g.v;
   if (t.hdr->fast) return;
@@ -2622,17 +2618,14 @@ __global__ __launch_bounds__(kBlock) void k_g_tile_count(const GStep* __restrict
   }
 }
 
-__global__ __launch_bounds__(1024) void k_g_tile_scan(const GStep* __restrict__ st,
-                                                      const GEntry* __restrict__ e, int32_t n) {
-  const GLoc L = g_locate(e, n);
+template <int NT>
+__device__ __forceinline__ void g_tile_scan_body(const GStep* __restrict__ st, const GLoc L) {
   const TableView t = st[L.step].v;
   if (t.hdr->fast) return;
-  scan_tiles_block<1024>(t, nullptr, st[L.step].ntiles, 0);
+  scan_tiles_block<NT>(t, nullptr, st[L.step].ntiles, 0);
 }
 
-__global__ __launch_bounds__(kBlock) void k_g_final(const GStep* __restrict__ st,
-                                                    const GEntry* __restrict__ e, int32_t n) {
-  const GLoc L = g_locate(e, n);
+__device__ __forceinline__ void g_final_body(const GStep* __restrict__ st, const GLoc L) {
   const GStep& g = st[L.step];
   const TableView t = g.v;
   if (g.vk == 1)
@@ -2651,9 +2644,7 @@ struct GCopy {
 };
 
 // Segment of this block's entry, copied by the entry's blocks in the widest aligned unit.
-__global__ __launch_bounds__(kBlock) void k_g_copy(const GCopy* __restrict__ segs,
-                                                   const GEntry* __restrict__ e, int32_t n) {
-  const GLoc L = g_locate(e, n);
+__device__ __forceinline__ void g_copy_body(const GCopy* __restrict__ segs, const GLoc L) {
   const GCopy g = segs[L.step];
   const uintptr_t a = reinterpret_cast<uintptr_t>(g.src) | reinterpret_cast<uintptr_t>(g.dst) |
                       (uintptr_t)g.bytes;
@@ -2674,12 +2665,106 @@ __global__ __launch_bounds__(kBlock) void k_g_copy(const GCopy* __restrict__ seg
   }
 }
 
-__global__ __launch_bounds__(kBlock) void k_g_fix(const GStep* __restrict__ st,
-                                                  const GEntry* __restrict__ e, int32_t n) {
-  const GLoc L = g_locate(e, n);
+__device__ __forceinline__ void g_fix_body(const GStep* __restrict__ st, const GLoc L) {
   const GStep& g = st[L.step];
   const TableView t = g.v;
   fix_range(t, g.flags, nullptr, (int64_t)L.lb * kBlock, (int64_t)L.nblk * kBlock);
+}
+
+// One launch per stage: block b of the launch runs the stage's body for its own step.
+__global__ __launch_bounds__(kBlock) void k_g_reset(const GStep* __restrict__ st,
+                                                    const GEntry* __restrict__ e, int32_t n) {
+  g_reset_body(st, g_locate(e, n));
+}
+__global__ __launch_bounds__(kBlock) void k_g_prologue(const GStep* __restrict__ st,
+                                                       const GEntry* __restrict__ e, int32_t n) {
+  g_prologue_body(st, g_locate(e, n));
+}
+__global__ __launch_bounds__(kBlock) void k_g_dedup(const GStep* __restrict__ st,
+                                                    const GEntry* __restrict__ e, int32_t n) {
+  g_dedup_body(st, g_locate(e, n));
+}
+template <int BS>
+__global__ __launch_bounds__(BS) void k_g_insert(const GStep* __restrict__ st,
+                                                 const GEntry* __restrict__ e, int32_t n) {
+  g_insert_body<BS>(st, g_locate(e, n));
+}
+template <int BS>
+__global__ __launch_bounds__(BS) void k_g_erase(const GStep* __restrict__ st,
+                                                const GEntry* __restrict__ e, int32_t n) {
+  g_erase_body<BS>(st, g_locate(e, n));
+}
+template <int BS>
+__global__ __launch_bounds__(BS) void k_g_find(const GStep* __restrict__ st,
+                                               const GEntry* __restrict__ e, int32_t n) {
+  g_find_body<BS>(st, g_locate(e, n));
+}
+__global__ __launch_bounds__(1024) void k_g_apply(const GStep* __restrict__ st,
+                                                  const GEntry* __restrict__ e, int32_t n) {
+  g_apply_body(st, g_locate(e, n));
+}
+__global__ __launch_bounds__(kBlock) void k_g_tile_count(const GStep* __restrict__ st,
+                                                         const GEntry* __restrict__ e, int32_t n) {
+  g_tile_count_body(st, g_locate(e, n));
+}
+__global__ __launch_bounds__(1024) void k_g_tile_scan(const GStep* __restrict__ st,
+                                                      const GEntry* __restrict__ e, int32_t n) {
+  g_tile_scan_body<1024>(st, g_locate(e, n));
+}
+__global__ __launch_bounds__(kBlock) void k_g_final(const GStep* __restrict__ st,
+                                                    const GEntry* __restrict__ e, int32_t n) {
+  g_final_body(st, g_locate(e, n));
+}
+__global__ __launch_bounds__(kBlock) void k_g_copy(const GCopy* __restrict__ segs,
+                                                   const GEntry* __restrict__ e, int32_t n) {
+  g_copy_body(segs, g_locate(e, n));
+}
+__global__ __launch_bounds__(kBlock) void k_g_fix(const GStep* __restrict__ st,
+                                                  const GEntry* __restrict__ e, int32_t n) {
+  g_fix_body(st, g_locate(e, n));
+}
+
+// The whole grouped schedule in one cooperative launch.  Every workgroup of the grid is resident
+// at once (the runtime refuses a cooperative launch that cannot be), so a grid-wide barrier
+// between stages cannot wait for a workgroup that never runs.  Stage by stage, the grid's blocks
+// take the stage's blocks in turn (block b runs b, b + grid, ...) with the same bodies as the
+// per-stage launches, 256 threads each, then meet at the barrier, whose device-scope fences make
+// the stage's stores visible to every XCD before the next stage reads them.  No workgroup waits
+// for another in any other way, and every workgroup reaches every barrier.
+struct GLaunchDev {
+  int32_t stage, n, blocks, pad;
+  int64_t entry_off;
+};
+
+__global__ __launch_bounds__(kBlock) void k_g_persistent(const GLaunchDev* __restrict__ ls,
+                                                         int32_t nl, const GStep* __restrict__ st,
+                                                         const GEntry* __restrict__ en,
+                                                         const GCopy* __restrict__ cp) {
+  cooperative_groups::grid_group grid = cooperative_groups::this_grid();
+  for (int32_t l = 0; l < nl; ++l) {
+    const GLaunchDev L = ls[l];
+    const GEntry* e = en + L.entry_off;
+    for (int32_t b = (int32_t)blockIdx.x; b < L.blocks; b += (int32_t)gridDim.x) {
+      const GLoc g = g_locate_at(e, L.n, b, L.blocks);
+      switch (L.stage) {
+        case gReset: g_reset_body(st, g); break;
+        case gPro: g_prologue_body(st, g); break;
+        case gDedup: g_dedup_body(st, g); break;
+        case gFind: g_find_body<kBlock>(st, g); break;
+        case gInsert: g_insert_body<kBlock>(st, g); break;
+        case gErase: g_erase_body<kBlock>(st, g); break;
+        case gApply: g_apply_body(st, g); break;
+        case gCount: g_tile_count_body(st, g); break;
+        case gScan: g_tile_scan_body<kBlock>(st, g); break;
+        case gFinal: g_final_body(st, g); break;
+        case gFix: g_fix_body(st, g); break;
+        case gCopy: g_copy_body(cp, g); break;
+        default: break;
+      }
+      __syncthreads();  // the next block's body reuses this workgroup's LDS
+    }
+    grid.sync();
+  }
 }
 
 }  // namespace
@@ -3724,6 +3809,8 @@ struct ct_plan {
   const void* gcopies = nullptr;   // device: GCopy[] of the merged operations' copy stages
   size_t grouped_ops = (size_t)-1;
   int gblock = kBlock;             // threads per block of its find / insert / erase stages
+  const void* glaunch_dev = nullptr;  // device: GLaunchDev[] for the single-launch form
+  int32_t gwidest = 1;             // most blocks of any one stage launch
 };
 
 namespace {
@@ -3767,10 +3854,6 @@ ct_status run_op(const PlanOp& o, hipStream_t s) {
   }
 }
 
-enum GStage : int32_t {
-  gReset, gPro, gDedup, gFind, gInsert, gErase, gApply, gCount, gScan, gFinal, gFix, gStages,
-  gCopy = 100  // copy stage of merged operations (before the first and after the last level)
-};
 
 // Copy-stage blocks for a segment: enough 256-thread blocks for 16-byte units, at most 2048.
 int copy_blocks(int64_t bytes) {
@@ -3807,7 +3890,8 @@ struct GroupForm {
   std::vector<GCopy> copies;
   std::vector<ct_group::Launch> launches;
   int64_t merge_bytes = 0;
-  int64_t steps_off = 0, entries_off = 0, copies_off = 0, merge_off = 0, total = 0;
+  int64_t steps_off = 0, entries_off = 0, copies_off = 0, launches_off = 0, merge_off = 0,
+          total = 0;
 };
 
 // Cut the plan into chunk-steps, assign each the per-table ordinal as its level, and lay out one
@@ -3957,7 +4041,12 @@ ct_status group_build(const ct_plan* p, int32_t options, uint8_t* base, GroupFor
     for (const GStep& g : F.steps)
       for (int stage = 0; stage < gStages; ++stage) nent += stage_blocks(stage, g) ? 1 : 0;
     F.copies_off = F.entries_off + align_up(nent * (int64_t)sizeof(GEntry));
-    F.merge_off = F.copies_off + align_up((int64_t)(F.copies.size() * sizeof(GCopy)));
+    // launch list for the single-launch form: at most a copy launch on each side of the levels
+    int32_t nlev_max = 0;
+    for (int32_t l : level) nlev_max = std::max(nlev_max, l + 1);
+    const int64_t max_launches = 2 + (int64_t)nlev_max * gStages;
+    F.launches_off = F.copies_off + align_up((int64_t)(F.copies.size() * sizeof(GCopy)));
+    F.merge_off = F.launches_off + align_up(max_launches * (int64_t)sizeof(GLaunchDev));
     F.total = std::max<int64_t>(kAlign, F.merge_off + F.merge_bytes);
   }
   // launches: copy in, the levels, copy out
@@ -4038,6 +4127,17 @@ ct_status ct_plan_group(ct_plan* p, int32_t options, void* d_buf, int64_t bytes)
   if (!F.copies.empty() && hipMemcpy(base + F.copies_off, F.copies.data(),
                                      F.copies.size() * sizeof(GCopy), hipMemcpyHostToDevice) != hipSuccess)
     return CT_E_HIP;
+  std::vector<GLaunchDev> ld;
+  int32_t widest = 1;
+  for (const ct_group::Launch& L : F.launches) {
+    ld.push_back(GLaunchDev{L.stage, L.n, L.blocks, 0, L.entry_off});
+    widest = std::max(widest, L.blocks);
+  }
+  if (!ld.empty() && hipMemcpy(base + F.launches_off, ld.data(), ld.size() * sizeof(GLaunchDev),
+                               hipMemcpyHostToDevice) != hipSuccess)
+    return CT_E_HIP;
+  p->glaunch_dev = base + F.launches_off;
+  p->gwidest = widest;
   p->glaunch = std::move(F.launches);
   p->gsteps = base + F.steps_off;
   p->gentries = base + F.entries_off;
@@ -4078,6 +4178,39 @@ ct_status ct_plan_launch_grouped(ct_plan* p, void* stream) {
     }
     if (launched() != CT_OK) return CT_E_HIP;
   }
+  return CT_OK;
+}
+
+ct_status ct_plan_launch_single(ct_plan* p, int32_t max_blocks, void* stream) {
+  if (!p || p->grouped_ops != p->ops.size() || p->gblock != kBlock || max_blocks < 0)
+    return CT_E_INVALID;
+  if (p->glaunch.empty()) return CT_OK;
+  int dev = 0, coop = 0, ncu = 0, per_cu = 0;
+  hipStream_t s = S(stream);
+  if (s) {
+    if (hipStreamGetDevice(s, &dev) != hipSuccess) return CT_E_HIP;
+  } else if (hipGetDevice(&dev) != hipSuccess) {
+    return CT_E_HIP;
+  }
+  if (hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev) != hipSuccess ||
+      hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_g_persistent, kBlock, 0) != hipSuccess)
+    return CT_E_HIP;
+  if (!coop || per_cu < 1 || ncu < 1) return CT_E_HIP;
+  // every workgroup must be resident at once: at most what the device holds, and no more than
+  // the widest stage can use
+  int64_t grid = std::min<int64_t>((int64_t)per_cu * ncu, p->gwidest);
+  if (max_blocks > 0) grid = std::min<int64_t>(grid, max_blocks);
+  grid = std::max<int64_t>(grid, 1);
+  const GLaunchDev* ls = static_cast<const GLaunchDev*>(p->glaunch_dev);
+  int32_t nl = (int32_t)p->glaunch.size();
+  const GStep* st = static_cast<const GStep*>(p->gsteps);
+  const GEntry* en = static_cast<const GEntry*>(p->gentries);
+  const GCopy* cp = static_cast<const GCopy*>(p->gcopies);
+  void* args[] = {&ls, &nl, &st, &en, &cp};
+  if (hipLaunchCooperativeKernel(reinterpret_cast<const void*>(k_g_persistent), dim3((unsigned)grid),
+                                 dim3(kBlock), args, 0, s) != hipSuccess)
+    return CT_E_HIP;
   return CT_OK;
 }
 

@@ -113,6 +113,7 @@ SIGNATURES = {
     "ct_plan_group": (C.c_int, [_P, _I32, _P, _I64]),
     "ct_plan_group_info": (C.c_int, [_P, _PI64, _PI64]),
     "ct_plan_launch_grouped": (C.c_int, [_P, _P]),
+    "ct_plan_launch_single": (C.c_int, [_P, _I32, _P]),
     "ct_plan_capture_grouped": (C.c_int, [_P, _P, C.POINTER(_P)]),
     "ct_graph_launch": (C.c_int, [_P, _P]),
     "ct_graph_destroy": (C.c_int, [_P]),
@@ -637,6 +638,12 @@ class Plan:
 
     def launch_grouped(self):
         _check(lib().ct_plan_launch_grouped(self._h, _stream(self.device)), "ct_plan_launch_grouped")
+
+    def launch_single(self, max_blocks: int = 0):
+        """The grouped form as one cooperative launch (grid barriers between stages); needs the
+        default 256-thread stages.  max_blocks > 0 caps the grid."""
+        _check(lib().ct_plan_launch_single(self._h, int(max_blocks), _stream(self.device)),
+               "ct_plan_launch_single")
 
     def capture_grouped(self, stream=None):
         s = stream or torch.cuda.Stream(self.device)

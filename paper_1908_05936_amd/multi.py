@@ -5,9 +5,11 @@ creates tables and device arrays, records the schedule into a plan, and measures
 
 Autotuner.  The knobs of a plan run are
   * lanes       -- 0: the grouped form (one launch per pipeline stage per level, covering every
-                   table); 1..8: side streams the tables are spread over, each operation running
-                   its own pipeline (operations on different tables overlap on the device; a
-                   table's operations keep their order),
+                   table); -1: the grouped form as one cooperative launch (ct_plan_launch_single:
+                   the stages separated by grid-wide barriers inside the kernel; 256-thread stages);
+                   1..8: side streams the tables are spread over, each operation running its own
+                   pipeline (operations on different tables overlap on the device; a table's
+                   operations keep their order),
   * merge       -- grouped form only: merge each table's runs of same-kind operations into one
                    operation over gathered copies (fewer levels and launches, more memory),
   * chunk       -- per-table insert/erase chunk (a larger chunk means fewer chained sub-operations
@@ -116,11 +118,12 @@ def time_fn(fn, reps=3, warmup=1):
 
 
 def runner(p: ct.Plan, lanes: int, merge: bool = False, block: int = 256):
-    """Callable running plan `p` once: grouped (lanes 0, built on first use) or on side streams."""
-    if lanes == 0:
+    """Callable running plan `p` once: grouped (lanes 0, built on first use), grouped as one
+    cooperative launch (lanes -1, 256-thread stages) or on side streams."""
+    if lanes <= 0:
         if getattr(p, "_gbuf", None) is None:
-            p.group(merge_runs=merge, block=block)
-        return p.launch_grouped
+            p.group(merge_runs=merge, block=block if lanes == 0 else 256)
+        return p.launch_grouped if lanes == 0 else p.launch_single
     return lambda: p.launch(lanes)
 
 
@@ -160,14 +163,16 @@ def tune(w: dict, dev, cache: str | None = None, reps: int = 3, log=print) -> di
         return t
 
     best_t = run(best)
-    space = [("lanes", [0, 1, 2, 4, 8]), ("chunk", [0, -1]), ("provision", [1.0, 1.25, 1.5]),
+    space = [("lanes", [0, -1, 1, 2, 4, 8]), ("chunk", [0, -1]), ("provision", [1.0, 1.25, 1.5]),
              ("merge", [False, True]), ("block", [128, 256, 512, 1024])]
     seen = {repr(sorted(best.items()))}
     for sweep in range(2):  # a second sweep revisits each knob at the others' new values
         improved = False
         for name, values in space:
-            if name in ("merge", "block") and best["lanes"] != 0:
-                continue   # knobs of the grouped form only
+            if name == "merge" and best["lanes"] > 0:
+                continue   # a knob of the grouped forms only
+            if name == "block" and best["lanes"] != 0:
+                continue   # the single launch runs 256-thread stages
             for v in values:
                 cfg = dict(best, **{name: v})
                 if repr(sorted(cfg.items())) in seen:
@@ -197,8 +202,8 @@ def measure(w: dict, dev, cfg: dict, reps: int = 5, graph_replays: int = 10) -> 
     t_plan = time_fn(runner(p, cfg["lanes"], cfg.get("merge", False), cfg.get("block", 256)),
                      reps=reps)
     s = torch.cuda.Stream(dev)
-    if cfg["lanes"] == 0:
-        p.capture_grouped(stream=s)
+    if cfg["lanes"] <= 0:
+        p.capture_grouped(stream=s)   # (the single launch is one submission already)
     else:
         p.capture(cfg["lanes"], stream=s)
 
@@ -215,8 +220,14 @@ def measure(w: dict, dev, cfg: dict, reps: int = 5, graph_replays: int = 10) -> 
     t_batch = time_fn(wl.per_batch, reps=max(1, reps // 2))
     n = wl.n_keys
     extra = {}
-    if cfg["lanes"] == 0:
+    if cfg["lanes"] <= 0:
         extra = dict(zip(("grouped_launches", "grouped_steps"), p.group_info()))
+    # the grouped form as one cooperative launch, whatever form was chosen
+    p1 = wl.plan()
+    p1.group(merge_runs=cfg.get("merge", False), block=256)
+    t_single = time_fn(p1.launch_single, reps=reps)
+    extra.update(single_launch_ms=t_single * 1e3, single_launch_Mkeys_s=wl.n_keys / t_single / 1e6)
+    del p1
     t_streams = time_fn(lambda: p.launch(4), reps=reps)
     return dict(extra, keys=n, ops=len(w["schedule"]), tables=len(w["tables"]),
                 streams4_ms=t_streams * 1e3,
