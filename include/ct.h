@@ -343,8 +343,11 @@ ct_status ct_table_dedup_skewed(ct_table *t, int32_t *h_skewed, void *stream);
    erase).
    CT_INSERT_AUTO (the default): speculative while the table's last chunk of the same operation
    stored (erase: removed) at least half of its keys, else resolve first; the table reports each
-   chunk through a word of pinned host memory that the host reads without synchronising.  Results
-   are identical on every path.  Host only: applies to calls enqueued afterwards. */
+   chunk through a word of pinned host memory that the host reads without synchronising.  A clear
+   starts a fresh history (the next chunks speculate).  Results are identical on every path.
+   Host only: applies to calls enqueued afterwards, and to grouped plans built afterwards
+   (ct_plan_group records each table's path; the grouped steps then decide on the device, from the
+   table's size and last chunks when the step starts, so replays decide afresh). */
 #define CT_INSERT_AUTO 0
 #define CT_INSERT_RESOLVE_FIRST 1
 #define CT_INSERT_SPECULATIVE 2

@@ -92,6 +92,9 @@ struct alignas(256) Header {
                            // index is a multiple of it is treated as lost to another key
   uint64_t closed_count;   // health scan: buckets without an empty slot
   uint64_t tomb_count;     //              tombstone slots
+  uint64_t fbd[2];         // the last insert (0) and erase (1) chunk: keys << 32 | keys stored
+                           // or removed (the device copy of the feedback words)
+  uint32_t spec;           // 1: the current chunk resolves repeated keys after its claims
 };
 static_assert(sizeof(Header) == 256, "the header fills one 256-byte line");
 

@@ -175,7 +175,14 @@ __device__ __forceinline__ void reset_range(const TableView& t, int64_t lo, int6
       h->err = 0;
       h->inject = 0;
     }
+    // an empty table starts a fresh history: its next insert and erase chunks speculate
+    h->fbd[0] = h->fbd[1] = 0;
+    if (t.fb) {
+      __hip_atomic_store(t.fb, (uint64_t)0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+      __hip_atomic_store(t.fb + 1, (uint64_t)0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    }
     h->fast = 0;
+    h->spec = 0;
     h->ndup = 0;
     h->nnew = 0;
     h->dump_count = 0;
@@ -216,6 +223,7 @@ __device__ __forceinline__ void chunk_header(const TableView& t, PoolHeader* poo
     fast = fast && pool->top >= q;
   }
   h->fast = fast ? 1u : 0u;
+  h->spec = 0u;
   h->dmode = dmode;
   h->dovf = 0;
   // binned chunks of a table whose keys recently overflowed the bins fold each tile's repeated
@@ -1087,9 +1095,10 @@ __device__ __forceinline__ int64_t apply_count_block(const TableView& t, int npa
 // Word 0 reports insert chunks (keys stored), word 1 erase chunks (keys removed).
 __device__ __forceinline__ void chunk_feedback(const TableView& t, int word, int64_t q,
                                                int64_t changed) {
-  if (!t.fb || q <= 0) return;
+  if (q <= 0) return;
   const uint64_t w = ((uint64_t)q << 32) | (uint64_t)(uint32_t)(changed < 0 ? 0 : changed);
-  __hip_atomic_store(t.fb + word, w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+  t.hdr->fbd[word] = w;
+  if (t.fb) __hip_atomic_store(t.fb + word, w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
 // fb_q > 0: the partials are the count changes of an insert (fb_word 0) or erase (fb_word 1)
@@ -1336,6 +1345,7 @@ __global__ void k_spec_prologue(TableView t, int64_t q, int insert) {
     h->ndup = 0;
     h->nnew = 0;
     h->fast = 1u;
+    h->spec = 1u;
     h->dmode = 0u;
     if (insert && h->size + (uint64_t)q > t.cap) h->err |= kErrInternal;
   }
@@ -1375,20 +1385,26 @@ __global__ __launch_bounds__(1024) void k_spec_sum(TableView t, int nblocks, int
 
 // Clears the dd entries (and, in the claimer direction, the lowest-index words) the resolution
 // uses; nothing when no element is listed.
-__global__ __launch_bounds__(kBlock) void k_spec_clear(TableView t, int64_t q) {
+// (The resolution stages take their block b of nb as arguments, so that the grouped plan can run
+// them per step; the single-table kernels pass blockIdx.x and gridDim.x.)
+__device__ __forceinline__ void spec_clear_range(const TableView& t, int64_t q, int64_t b, int64_t nb) {
   const uint32_t nd = t.hdr->ndup;
   if (nd == 0) return;
   const SpecPlan p = spec_plan(nd, q);
   const int64_t units = p.slots / 2;
   const uint4 ones = make_uint4(0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu);
-  for (int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x; j < units; j += (int64_t)gridDim.x * kBlock) {
+  for (int64_t j = b * kBlock + threadIdx.x; j < units; j += nb * kBlock) {
     reinterpret_cast<uint4*>(t.dd)[j] = ones;
     if (p.by_claimers && j < units / 2) reinterpret_cast<uint4*>(spec_low(t, p))[j] = ones;
   }
-  if (p.by_claimers && units == 1 && blockIdx.x == 0 && threadIdx.x == 0) {
+  if (p.by_claimers && units == 1 && b == 0 && threadIdx.x == 0) {
     spec_low(t, p)[0] = kNone;
     spec_low(t, p)[1] = kNone;
   }
+}
+
+__global__ __launch_bounds__(kBlock) void k_spec_clear(TableView t, int64_t q) {
+  spec_clear_range(t, q, blockIdx.x, gridDim.x);
 }
 
 // dd slot of `key` among entries (tag | chunk index); kNone when absent.
@@ -1414,8 +1430,8 @@ __device__ __forceinline__ uint32_t dd_find(const TableView& t, const uint64_t* 
 // when the held index is already lower).  Claimer direction: every claimer's key is distinct, so
 // each takes an empty entry with one CAS.  Out-of-band listed copies take an atomic min on their
 // header word in both directions.
-__global__ __launch_bounds__(kBlock) void k_spec_build(TableView t, const uint64_t* __restrict__ keys,
-                                                       int64_t q) {
+__device__ __forceinline__ void spec_build_range(const TableView& t, const uint64_t* __restrict__ keys,
+                                                 int64_t q, int64_t blk, int64_t nblk) {
   const uint32_t nd = t.hdr->ndup;  // written by k_spec_sum
   if (nd == 0) return;
   const SpecPlan p = spec_plan(nd, q);
@@ -1423,7 +1439,7 @@ __global__ __launch_bounds__(kBlock) void k_spec_build(TableView t, const uint64
   constexpr uint32_t kW = 2 * kBlock;
   __shared__ unsigned long long wk[kW];
   __shared__ uint32_t wmin[kW];
-  for (int64_t b0 = (int64_t)blockIdx.x * kBlock; b0 < q; b0 += (int64_t)gridDim.x * kBlock) {
+  for (int64_t b0 = blk * kBlock; b0 < q; b0 += nblk * kBlock) {
     const int64_t i = b0 + threadIdx.x;
     const uint8_t f = i < q ? t.flag[i] : kFlagNone;
     const uint64_t key = f != kFlagNone ? keys[i] : kEmpty;
@@ -1480,6 +1496,11 @@ __global__ __launch_bounds__(kBlock) void k_spec_build(TableView t, const uint64
   }
 }
 
+__global__ __launch_bounds__(kBlock) void k_spec_build(TableView t, const uint64_t* __restrict__ keys,
+                                                       int64_t q) {
+  spec_build_range(t, keys, q, blockIdx.x, gridDim.x);
+}
+
 // Slot of a key that is known to be stored (one lane alone, eight key loads per bucket).
 __device__ __forceinline__ uint64_t lane_slot_of(const TableView& t, uint64_t key) {
   const Seq q = probe_seq(t, key);
@@ -1524,9 +1545,10 @@ __device__ __forceinline__ void hand_over(const TableView& t, const void* __rest
 // (windows of 256 elements combine copies of one entry in LDS first; skipped when the word is
 // already lower).
 template <int VK, bool ERASE>
-__global__ __launch_bounds__(kBlock) void k_spec_probe(TableView t, const uint64_t* __restrict__ keys,
-                                                       const void* __restrict__ vals, int64_t q,
-                                                       uint8_t* __restrict__ status) {
+__device__ __forceinline__ void spec_probe_range(const TableView& t, const uint64_t* __restrict__ keys,
+                                                 const void* __restrict__ vals, int64_t q,
+                                                 uint8_t* __restrict__ status, int64_t blk,
+                                                 int64_t nblk) {
   const uint32_t nd = t.hdr->ndup;  // written by k_spec_sum
   if (nd == 0) return;
   const SpecPlan p = spec_plan(nd, q);
@@ -1534,7 +1556,7 @@ __global__ __launch_bounds__(kBlock) void k_spec_probe(TableView t, const uint64
   uint32_t* low = spec_low(t, p);
   constexpr uint32_t kW = 2 * kBlock;
   __shared__ uint32_t wh[kW], wmin[kW];
-  for (int64_t b0 = (int64_t)blockIdx.x * kBlock; b0 < q; b0 += (int64_t)gridDim.x * kBlock) {
+  for (int64_t b0 = blk * kBlock; b0 < q; b0 += nblk * kBlock) {
     const int64_t i = b0 + threadIdx.x;
     const uint8_t f = i < q ? t.flag[i] : kFlagNone;
     if (!p.by_claimers) {
@@ -1575,15 +1597,24 @@ __global__ __launch_bounds__(kBlock) void k_spec_probe(TableView t, const uint64
   }
 }
 
-// Swap (claimer direction): a claimer whose entry holds a lower listed index hands over.  Thread
-// 0 of block 0 inserts each out-of-band key for its lowest copy when it was absent.
 template <int VK, bool ERASE>
-__global__ __launch_bounds__(kBlock) void k_spec_swap(TableView t, const uint64_t* __restrict__ keys,
-                                                      const void* __restrict__ vals, int64_t q,
-                                                      uint8_t* __restrict__ status) {
+__global__ __launch_bounds__(kBlock) void k_spec_probe(TableView t, const uint64_t* __restrict__ keys,
+                                                       const void* __restrict__ vals, int64_t q,
+                                                       uint8_t* __restrict__ status) {
+  spec_probe_range<VK, ERASE>(t, keys, vals, q, status, blockIdx.x, gridDim.x);
+}
+
+// Swap (claimer direction): a claimer whose entry holds a lower listed index hands over.  Thread
+// 0 of the first block settles each out-of-band key on its lowest copy (an insert stores it when
+// it was absent, an erase removes it when it was there).
+template <int VK, bool ERASE>
+__device__ __forceinline__ void spec_swap_range(const TableView& t, const uint64_t* __restrict__ keys,
+                                                const void* __restrict__ vals, int64_t q,
+                                                uint8_t* __restrict__ status, int64_t blk,
+                                                int64_t nblk) {
   const uint32_t nd = t.hdr->ndup;  // written by k_spec_sum
   if (nd == 0) return;
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
+  if (blk == 0 && threadIdx.x == 0) {
     Header* h = t.hdr;
     for (int s = 0; s < 2; ++s) {
       const uint32_t m = h->spec_first[s];
@@ -1606,7 +1637,7 @@ __global__ __launch_bounds__(kBlock) void k_spec_swap(TableView t, const uint64_
   if (!p.by_claimers) return;
   const uint32_t dmask = p.slots - 1;
   const uint32_t* low = spec_low(t, p);
-  for (int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x; c < q; c += (int64_t)gridDim.x * kBlock) {
+  for (int64_t c = blk * kBlock + threadIdx.x; c < q; c += nblk * kBlock) {
     if (t.flag[c] != kFlagClaimed) continue;
     const uint64_t key = keys[c];
     uint32_t self = 0;
@@ -1618,6 +1649,13 @@ __global__ __launch_bounds__(kBlock) void k_spec_swap(TableView t, const uint64_
     const uint32_t m = low[h];
     if (m < (uint32_t)c) hand_over<VK, ERASE>(t, vals, status, key, (uint32_t)c, m);
   }
+}
+
+template <int VK, bool ERASE>
+__global__ __launch_bounds__(kBlock) void k_spec_swap(TableView t, const uint64_t* __restrict__ keys,
+                                                      const void* __restrict__ vals, int64_t q,
+                                                      uint8_t* __restrict__ status) {
+  spec_swap_range<VK, ERASE>(t, keys, vals, q, status, blockIdx.x, gridDim.x);
 }
 
 // Flagged count per tile of kTile elements.
@@ -2488,8 +2526,13 @@ __global__ __launch_bounds__(kBlock) void k_pool_push_front(PoolHeader* ph, int3
 // of the single-table kernel with the step's own block index and block count.
 // ---------------------------------------------------------------------------------------------
 // Stages of the grouped pipeline, in launch order within a level.
+// Plan operation kinds (the CT_OP_* values).
+enum : int32_t { kOpClear = 0, kOpInsert = 1, kOpFind = 2, kOpErase = 3 };
+
 enum GStage : int32_t {
-  gReset, gPro, gDedup, gFind, gInsert, gErase, gApply, gCount, gScan, gFinal, gFix, gStages,
+  gReset, gPro, gDedup, gFind, gInsert, gErase, gApply,
+  gSClear, gSBuild, gSProbe, gSSwap,  // resolution of speculative steps
+  gCount, gScan, gFinal, gFix, gStages,
   gCopy = 100  // copy stage of merged operations (before the first and after the last level)
 };
 
@@ -2505,7 +2548,9 @@ struct GStep {
   int32_t type;   // plan operation
   int32_t gb;     // blocks of the step's insert / erase / find stage
   int32_t ntiles; // rank-scan tiles
-  int32_t pad;
+  int32_t spath;  // insert or erase: 0 resolve repeated keys first; 1 speculate when the table's
+                  // last chunk of the kind changed at least half its keys; 2 speculate always
+                  // (an insert only when it cannot reach capacity)
 };
 
 struct GEntry {
@@ -2541,9 +2586,41 @@ __device__ __forceinline__ void g_reset_body(const GStep* __restrict__ st, const
               L.lb == 0, 0);
 }
 
+// Whether an insert or erase step speculates, decided on the device from the table's state when
+// the step starts, so that a plan replayed later decides afresh.  Every block of the prologue
+// stage computes it from words that no block of the stage writes, so all agree.
+__device__ __forceinline__ bool g_speculates(const GStep& g) {
+  if (g.spath == 0 || g.q <= 0 || (g.type != kOpInsert && g.type != kOpErase)) return false;
+  const Header* h = g.v.hdr;
+  const bool ins = g.type == kOpInsert;
+  if (ins && h->size + (uint64_t)g.q > g.v.cap) return false;   // FULL must be ranked
+  if (g.spath == 2) return true;
+  const uint64_t f = h->fbd[ins ? 0 : 1];
+  const uint64_t fq = f >> 32, changed = f & 0xFFFFFFFFull;
+  return fq == 0 || 2 * changed >= fq;
+}
+
+// Prologue: a speculative step needs only its header snapshot and zeroed listed counts (the dd
+// entries are cleared after the claims, and only when something is listed); otherwise the
+// dedup scratch is cleared and the header decides as for a single-table chunk.
 __device__ __forceinline__ void g_prologue_body(const GStep* __restrict__ st, const GLoc L) {
   const GStep& g = st[L.step];
   const TableView t = g.v;
+  if (g_speculates(g)) {
+    if (L.lb != 0) return;
+    if (threadIdx.x < kListStripes) list_stripes(t)[threadIdx.x * kListStripeWords] = 0;
+    if (threadIdx.x == 0) {
+      Header* h = t.hdr;
+      h->size0 = h->size;
+      h->spec_first[0] = h->spec_first[1] = kNone;
+      h->ndup = 0;
+      h->nnew = 0;
+      h->fast = 1u;
+      h->spec = 1u;
+      h->dmode = 0u;
+    }
+    return;
+  }
   prologue_range(t, nullptr, g.db, g.q, (int64_t)L.lb * kBlock, prologue_units(g.db, g.q),
                  (int64_t)L.nblk * kBlock, L.lb == 0);
 }
@@ -2551,7 +2628,21 @@ __device__ __forceinline__ void g_prologue_body(const GStep* __restrict__ st, co
 __device__ __forceinline__ void g_dedup_body(const GStep* __restrict__ st, const GLoc L) {
   const GStep& g = st[L.step];
   const TableView t = g.v;
+  if (t.hdr->spec) return;
   dedup_range(t, g.keys, nullptr, g.db - 1, (int64_t)L.lb * kBlock, g.q, (int64_t)L.nblk * kBlock);
+}
+
+// Block totals of a speculative insert or erase: the count change into the block's partial, the
+// listed elements onto one of the listed-count stripes.
+template <int BS>
+__device__ __forceinline__ void g_spec_counts(const TableView& t, uint2 c, int32_t lb, bool erase) {
+  const int64_t tot = block_sum<BS>((int64_t)c.x + ((int64_t)c.y << 32));
+  if (threadIdx.x == 0) {
+    const int64_t changed = tot & 0xFFFFFFFFll;
+    t.bcnt[lb] = erase ? -changed : changed;
+    const uint32_t nl = (uint32_t)(tot >> 32);
+    if (nl) aadd32(&list_stripes(t)[(lb % kListStripes) * kListStripeWords], nl);
+  }
 }
 
 // The grouped find / insert / erase stages run with BS threads per block (the plan's block size):
@@ -2561,6 +2652,14 @@ __device__ __forceinline__ void g_insert_body(const GStep* __restrict__ st, cons
   const GStep& g = st[L.step];
   const TableView t = g.v;
   const int64_t lo = (int64_t)L.lb * BS, step = (int64_t)L.nblk * BS;
+  if (t.hdr->spec) {
+    uint2 c;
+    if (g.vk == 1) c = insert_spec_range<1>(t, g.keys, g.vals, g.flags, lo, g.q, step);
+    else if (g.vk == 2) c = insert_spec_range<2>(t, g.keys, g.vals, g.flags, lo, g.q, step);
+    else c = insert_spec_range<0>(t, g.keys, nullptr, g.flags, lo, g.q, step);
+    g_spec_counts<BS>(t, c, L.lb, false);
+    return;
+  }
   int64_t ins;
   if (g.vk == 1)
     ins = insert_range<1, false>(t, g.keys, nullptr, g.vals, g.db - 1, g.flags, nullptr, lo, g.q, step);
@@ -2576,6 +2675,12 @@ template <int BS>
 __device__ __forceinline__ void g_erase_body(const GStep* __restrict__ st, const GLoc L) {
   const GStep& g = st[L.step];
   const TableView t = g.v;
+  if (t.hdr->spec) {
+    const uint2 c = erase_spec_range(t, g.keys, g.flags, (int64_t)L.lb * BS, g.q,
+                                     (int64_t)L.nblk * BS);
+    g_spec_counts<BS>(t, c, L.lb, true);
+    return;
+  }
   const int64_t del = erase_range<false>(t, g.keys, g.db - 1, g.flags, (int64_t)L.lb * BS,
                                          g.q, (int64_t)L.nblk * BS);
   const int64_t tot = block_sum<BS>(del);
@@ -2592,9 +2697,50 @@ __device__ __forceinline__ void g_find_body(const GStep* __restrict__ st, const 
   else find_range<0>(t, g.keys, nullptr, g.flags, lo, g.q, step);
 }
 
+// The count change into the live count and the feedback words; for a speculative step also the
+// listed total, which the resolution stages read.
 __device__ __forceinline__ void g_apply_body(const GStep* __restrict__ st, const GLoc L) {
-  const TableView t = st[L.step].v;
-  apply_count_block(t, st[L.step].gb);
+  const GStep& g = st[L.step];
+  const TableView t = g.v;
+  const int64_t change = apply_count_block(t, g.gb);
+  if (threadIdx.x == 0) {
+    const bool erase = g.type == kOpErase;
+    chunk_feedback(t, erase ? 1 : 0, g.q, erase ? -change : change);
+    if (t.hdr->spec) t.hdr->ndup = listed_total(t);
+  }
+}
+
+// Resolution of a speculative step (the single-table kernels' range code, per step).
+__device__ __forceinline__ void g_sclear_body(const GStep* __restrict__ st, const GLoc L) {
+  const GStep& g = st[L.step];
+  if (!g.v.hdr->spec) return;
+  spec_clear_range(g.v, g.q, L.lb, L.nblk);
+}
+
+__device__ __forceinline__ void g_sbuild_body(const GStep* __restrict__ st, const GLoc L) {
+  const GStep& g = st[L.step];
+  if (!g.v.hdr->spec) return;
+  spec_build_range(g.v, g.keys, g.q, L.lb, L.nblk);
+}
+
+template <bool SWAP>
+__device__ __forceinline__ void g_sfix_body(const GStep* __restrict__ st, const GLoc L) {
+  const GStep& g = st[L.step];
+  const TableView t = g.v;
+  if (!t.hdr->spec) return;
+  if (g.type == kOpErase) {
+    if (SWAP) spec_swap_range<0, true>(t, g.keys, nullptr, g.q, g.flags, L.lb, L.nblk);
+    else spec_probe_range<0, true>(t, g.keys, nullptr, g.q, g.flags, L.lb, L.nblk);
+  } else if (g.vk == 1) {
+    if (SWAP) spec_swap_range<1, false>(t, g.keys, g.vals, g.q, g.flags, L.lb, L.nblk);
+    else spec_probe_range<1, false>(t, g.keys, g.vals, g.q, g.flags, L.lb, L.nblk);
+  } else if (g.vk == 2) {
+    if (SWAP) spec_swap_range<2, false>(t, g.keys, g.vals, g.q, g.flags, L.lb, L.nblk);
+    else spec_probe_range<2, false>(t, g.keys, g.vals, g.q, g.flags, L.lb, L.nblk);
+  } else {
+    if (SWAP) spec_swap_range<0, false>(t, g.keys, nullptr, g.q, g.flags, L.lb, L.nblk);
+    else spec_probe_range<0, false>(t, g.keys, nullptr, g.q, g.flags, L.lb, L.nblk);
+  }
 }
 
 __device__ __forceinline__ void g_tile_count_body(const GStep* __restrict__ st, const GLoc L) {
@@ -2628,6 +2774,7 @@ __device__ __forceinline__ void g_tile_scan_body(const GStep* __restrict__ st, c
 __device__ __forceinline__ void g_final_body(const GStep* __restrict__ st, const GLoc L) {
   const GStep& g = st[L.step];
   const TableView t = g.v;
+  if (t.hdr->fast) return;   // nothing to rank: leave before any of the tile code
   if (g.vk == 1)
     final_tile<1, 0>(t, nullptr, nullptr, g.keys, g.vals, g.q, g.flags, nullptr, L.lb);
   else if (g.vk == 2)
@@ -2668,6 +2815,7 @@ __device__ __forceinline__ void g_copy_body(const GCopy* __restrict__ segs, cons
 __device__ __forceinline__ void g_fix_body(const GStep* __restrict__ st, const GLoc L) {
   const GStep& g = st[L.step];
   const TableView t = g.v;
+  if (t.hdr->spec) return;   // (ndup counts listed elements there, not repeated keys)
   fix_range(t, g.flags, nullptr, (int64_t)L.lb * kBlock, (int64_t)L.nblk * kBlock);
 }
 
@@ -2723,6 +2871,19 @@ __global__ __launch_bounds__(kBlock) void k_g_fix(const GStep* __restrict__ st,
                                                   const GEntry* __restrict__ e, int32_t n) {
   g_fix_body(st, g_locate(e, n));
 }
+__global__ __launch_bounds__(kBlock) void k_g_sclear(const GStep* __restrict__ st,
+                                                     const GEntry* __restrict__ e, int32_t n) {
+  g_sclear_body(st, g_locate(e, n));
+}
+__global__ __launch_bounds__(kBlock) void k_g_sbuild(const GStep* __restrict__ st,
+                                                     const GEntry* __restrict__ e, int32_t n) {
+  g_sbuild_body(st, g_locate(e, n));
+}
+template <bool SWAP>
+__global__ __launch_bounds__(kBlock) void k_g_sfix(const GStep* __restrict__ st,
+                                                   const GEntry* __restrict__ e, int32_t n) {
+  g_sfix_body<SWAP>(st, g_locate(e, n));
+}
 
 // The whole grouped schedule in one cooperative launch.  Every workgroup of the grid is resident
 // at once (the runtime refuses a cooperative launch that cannot be), so a grid-wide barrier
@@ -2758,6 +2919,10 @@ __global__ __launch_bounds__(kBlock) void k_g_persistent(const GLaunchDev* __res
         case gScan: g_tile_scan_body<kBlock>(st, g); break;
         case gFinal: g_final_body(st, g); break;
         case gFix: g_fix_body(st, g); break;
+        case gSClear: g_sclear_body(st, g); break;
+        case gSBuild: g_sbuild_body(st, g); break;
+        case gSProbe: g_sfix_body<false>(st, g); break;
+        case gSSwap: g_sfix_body<true>(st, g); break;
         case gCopy: g_copy_body(cp, g); break;
         default: break;
       }
@@ -3776,8 +3941,6 @@ ct_status ct_erase_release_batch(ct_table* t, ct_pool* p, const uint64_t* keys, 
 // order holds) and joined back at the end; each operation runs the same kernel pipeline as the
 // single-table call.  The whole fork/join sequence captures into one HIP graph.
 namespace {
-enum : int32_t { kOpClear = 0, kOpInsert = 1, kOpFind = 2, kOpErase = 3 };
-
 struct PlanOp {
   ct_table* t;
   int32_t type;
@@ -3863,21 +4026,38 @@ int copy_blocks(int64_t bytes) {
 
 bool inserts_or_erases(const GStep& g) { return g.type == kOpInsert || g.type == kOpErase; }
 
+// Blocks of a grouped stage whose blocks stride over n units of work and usually find little
+// or nothing to do (the resolution of a speculative step, the repeated-key outcomes, the
+// prologue's scratch clear): 8 units per thread, at most 1024 blocks per step.
+int spec_blocks(int64_t n) {
+  const int64_t b = (n + 8 * kBlock - 1) / (8 * kBlock);
+  return (int)std::max<int64_t>(1, std::min<int64_t>(b, 1024));
+}
+
+// Units of a chunk's scratch clear (as prologue_units on the device).
+int64_t prologue_units_host(uint32_t dslots, int64_t q) { return (int64_t)dslots / 2 + (q + 15) / 16; }
+
 // Blocks of step `g` in stage `stage` (0: the step has no such stage); the same grids as the
 // single-table pipeline.
 int stage_blocks(int stage, const GStep& g) {
   switch (stage) {
     case gReset: return g.type == kOpClear ? flat_blocks((int64_t)g.v.nb * kSlots) : 0;
-    case gPro: return inserts_or_erases(g) ? flat_blocks(g.db / 2) : 0;
+    case gPro: return inserts_or_erases(g) ? spec_blocks(prologue_units_host(g.db, g.q)) : 0;
     case gDedup: return inserts_or_erases(g) ? flat_blocks(g.q) : 0;
     case gFind: return g.type == kOpFind ? g.gb : 0;
     case gInsert: return g.type == kOpInsert ? g.gb : 0;
     case gErase: return g.type == kOpErase ? g.gb : 0;
     case gApply: return inserts_or_erases(g) ? 1 : 0;
+    // resolution of a speculative step: a few elements per thread when something is listed; the
+    // blocks leave at once otherwise
+    case gSClear: return inserts_or_erases(g) && g.spath ? spec_blocks((int64_t)g.db / 2) : 0;
+    case gSBuild:
+    case gSProbe:
+    case gSSwap: return inserts_or_erases(g) && g.spath ? spec_blocks(g.q) : 0;
     case gCount: return g.type == kOpInsert ? g.ntiles : 0;
     case gScan: return g.type == kOpInsert ? 1 : 0;
     case gFinal: return g.type == kOpInsert ? g.ntiles : 0;
-    case gFix: return g.type == kOpInsert && g.flags ? flat_blocks(g.q) : 0;
+    case gFix: return g.type == kOpInsert && g.flags ? spec_blocks(g.q) : 0;
   }
   return 0;
 }
@@ -4025,6 +4205,8 @@ ct_status group_build(const ct_plan* p, int32_t options, uint8_t* base, GroupFor
           g.vout = (o.type == kOpFind && o.vout) ? static_cast<uint8_t*>(o.vout) + c0 * vb : nullptr;
           g.flags = o.flags ? o.flags + c0 : nullptr;
           g.db = ie ? dedup_slots_for(q) : 0u;
+          g.spath = !ie || t->insert_path == CT_INSERT_RESOLVE_FIRST ? 0
+                    : t->insert_path == CT_INSERT_SPECULATIVE ? 2 : 1;
           g.gb = group_blocks((q + kSlots - 1) / kSlots, bs);
           g.ntiles = (int32_t)((q + kTile - 1) / kTile);
           F.steps.push_back(g);
@@ -4171,6 +4353,10 @@ ct_status ct_plan_launch_grouped(ct_plan* p, void* stream) {
       case gScan: k_g_tile_scan<<<L.blocks, 1024, 0, s>>>(st, e, L.n); break;
       case gFinal: k_g_final<<<L.blocks, kBlock, 0, s>>>(st, e, L.n); break;
       case gFix: k_g_fix<<<L.blocks, kBlock, 0, s>>>(st, e, L.n); break;
+      case gSClear: k_g_sclear<<<L.blocks, kBlock, 0, s>>>(st, e, L.n); break;
+      case gSBuild: k_g_sbuild<<<L.blocks, kBlock, 0, s>>>(st, e, L.n); break;
+      case gSProbe: k_g_sfix<false><<<L.blocks, kBlock, 0, s>>>(st, e, L.n); break;
+      case gSSwap: k_g_sfix<true><<<L.blocks, kBlock, 0, s>>>(st, e, L.n); break;
       case gCopy:
         k_g_copy<<<L.blocks, kBlock, 0, s>>>(static_cast<const GCopy*>(p->gcopies), e, L.n);
         break;

@@ -49,13 +49,15 @@ def expected(w):
 class Run:
     """GPU tables plus device inputs and outputs for every scheduled operation."""
 
-    def __init__(self, w, dev, chunk=0, provision=1.0):
+    def __init__(self, w, dev, chunk=0, provision=1.0, path=None):
         self.w = w
         self.tables = []
         for t in w["tables"]:
             nb = int(np.ceil(t["capacity"] * provision / 8)) if provision != 1.0 else 0
             self.tables.append(ct.Table(t["capacity"], ct.VAL_U32, ct.HASH_MIX64, bucket_count=nb,
                                         chunk=chunk, device=dev))
+            if path is not None:
+                self.tables[-1].set_insert_path(path)
         self.ops = []
         for ti, kind, keys, vals in w["schedule"]:
             k = g64(keys, dev)
@@ -184,6 +186,94 @@ def test_grouped_matches_oracle(dev, chunk, merge, block):
     r.check(exp)
 
 
+PATHS = [ct.INSERT_AUTO, ct.INSERT_SPECULATIVE, ct.INSERT_RESOLVE_FIRST]
+
+
+@pytest.mark.parametrize("path", PATHS)
+@pytest.mark.parametrize("chunk,merge,block", [(0, False, 256), (1024, True, 512)])
+def test_grouped_insert_paths(dev, path, chunk, merge, block):
+    """The grouped form with each insert path of the tables: speculative steps (decided on the
+    device when the step starts), steps that resolve repeated keys first, and the default's choice
+    from each table's previous chunk of the kind."""
+    w = small()
+    exp, tabs = expected(w)
+    r = Run(w, dev, chunk=chunk, path=path)
+    p = r.plan(dev)
+    p.group(merge_runs=merge, block=block)
+    for rep in range(2):      # the second run decides from the first run's feedback
+        r.scramble()
+        p.launch_grouped()
+        r.check(exp)
+        for t, o in zip(r.tables, tabs):
+            assert t.size() == o.size()
+            assert t.check() == 0
+
+
+def listing_schedule(seed=12, n_tables=10):
+    """Per table: fresh keys with repeats, then batches of mostly present keys with repeats (more
+    than half of a step listed: the claimer direction), batches of mostly new keys with a few
+    present copies (the listed direction), erases of present keys with repeats and absent keys,
+    and both out-of-band keys (all ones, all ones minus one) repeated inside batches."""
+    rng = np.random.default_rng(seed)
+    oob = np.array([~np.uint64(0), ~np.uint64(0) - np.uint64(1)], dtype=np.uint64)
+    tables, per = [], []
+    for t in range(n_tables):
+        cap = int(rng.integers(3000, 9000))
+        tables.append(dict(capacity=cap, entries=cap // 2, load_factor=0.5))
+        fresh = (np.arange(cap * 2, dtype=np.uint64) + np.uint64(t << 40)) * np.uint64(0x9E3779B97F4A7C15)
+        live = fresh[:cap // 3]
+        ops = []
+
+        def batch(keys):
+            keys = keys[rng.permutation(keys.size)]
+            return keys, rng.integers(0, 1 << 32, size=keys.size, dtype=np.uint64).astype(np.uint32)
+
+        k, v = batch(np.concatenate([live, live[rng.integers(0, live.size, live.size // 4)], oob]))
+        ops.append(("insert", k, v))
+        k, v = batch(np.concatenate([live[rng.integers(0, live.size, 1500)], fresh[cap // 3:cap // 3 + 300],
+                                     oob, oob]))
+        ops.append(("insert", k, v))
+        k, v = batch(np.concatenate([fresh[cap // 2:cap // 2 + 1200], live[rng.integers(0, live.size, 60)],
+                                     fresh[cap // 2:cap // 2 + 40]]))
+        ops.append(("insert", k, v))
+        ek = np.concatenate([live[rng.integers(0, live.size, 700)], fresh[cap + 10:cap + 200], oob[:1], oob[:1]])
+        ops.append(("erase", ek[rng.permutation(ek.size)], None))
+        k, v = batch(np.concatenate([live[rng.integers(0, live.size, 900)], oob]))
+        ops.append(("insert", k, v))
+        fk = np.concatenate([live, fresh[cap:cap + 500], oob])
+        ops.append(("find", fk, None))
+        per.append(ops)
+    sched = []
+    order = [(t, i) for i in range(6) for t in rng.permutation(n_tables)]
+    for t, i in order:
+        kind, k, v = per[t][i]
+        sched.append((int(t), kind, k, v))
+    return dict(tables=tables, schedule=sched)
+
+
+@pytest.mark.parametrize("path", PATHS)
+@pytest.mark.parametrize("merge", [False, True])
+def test_grouped_listed_copies_both_directions(dev, path, merge):
+    """Repeated and present keys in speculative steps: the resolution hands each key to its lowest
+    copy, in both directions, with out-of-band keys; checked over two graph replays."""
+    w = listing_schedule()
+    exp, tabs = expected(w)
+    r = Run(w, dev, chunk=2048, path=path)
+    p = r.plan(dev)
+    p.group(merge_runs=merge)
+    s = torch.cuda.Stream(dev)
+    p.capture_grouped(stream=s)
+    for rep in range(2):
+        r.scramble()
+        torch.cuda.synchronize()
+        p.replay(s)
+        s.synchronize()
+        r.check(exp)
+        for t, o in zip(r.tables, tabs):
+            assert t.size() == o.size()
+            assert t.check() == 0
+
+
 @pytest.mark.parametrize("merge", [False, True])
 def test_grouped_graph_replays_and_invalidation(dev, merge):
     w = small()
@@ -242,12 +332,15 @@ def mixed_kinds_schedule(seed=9, n_tables=12, n_ops=160):
     return tables, sched
 
 
+@pytest.mark.parametrize("path", PATHS)
 @pytest.mark.parametrize("chunk,merge", [(1024, False), (4096, False), (1024, True)])
-def test_grouped_mixed_value_kinds_and_capacity(dev, chunk, merge):
+def test_grouped_mixed_value_kinds_and_capacity(dev, chunk, merge, path):
     tables, sched = mixed_kinds_schedule()
     bits = {ct.VAL_NONE: 0, ct.VAL_U32: 32, ct.VAL_U64: 64}
     otabs = [oracle.OracleTable(t["capacity"], bits[t["kind"]]) for t in tables]
     gtabs = [ct.Table(t["capacity"], t["kind"], ct.HASH_MIX64, chunk=chunk, device=dev) for t in tables]
+    for g in gtabs:
+        g.set_insert_path(path)
     p = ct.Plan(device=dev)
     for g in gtabs:
         p.add(g, ct.OP_CLEAR)

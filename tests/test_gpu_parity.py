@@ -646,7 +646,12 @@ def test_auto_path_follows_the_last_chunk(dev):
     assert dedup_launches(a) == 1      # the last chunk stored every key: speculative (stores none)
     assert dedup_launches(a) == 5      # the last chunk stored none: repeated keys first
     assert dedup_launches(b) == 5      # still after a chunk that stored none (this one stores all)
-    assert dedup_launches(c) == 1      # speculative again
+    assert dedup_launches(c) == 1      # speculative again (stores all)
+    assert dedup_launches(c) == 1      # after a chunk that stored all (this one stores none)
+    assert dedup_launches(c) == 5      # the last chunk stored none
+    p.g.clear()                        # an empty table starts a fresh history
+    p.o.clear()
+    assert dedup_launches(c) == 1
     p.g.profiling(False)
     p.same_state()
 

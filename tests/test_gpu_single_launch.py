@@ -8,7 +8,7 @@ import torch
 import oracle
 from paper_1908_05936_amd import ct
 from paper_1908_05936_amd.workloads import multi_table
-from test_gpu_multi import Run, expected, g32, g64, mixed_kinds_schedule, small
+from test_gpu_multi import PATHS, Run, expected, g32, g64, listing_schedule, mixed_kinds_schedule, small
 
 pytestmark = pytest.mark.gpu
 
@@ -41,6 +41,25 @@ def test_single_launch_matches_oracle(dev, chunk, merge, max_blocks):
     r.scramble()
     p.launch_single(max_blocks)
     r.check(exp)
+
+
+@pytest.mark.parametrize("path", PATHS)
+@pytest.mark.parametrize("max_blocks", [0, 5])
+def test_single_launch_insert_paths(dev, path, max_blocks):
+    """Speculative steps and their resolution stages inside the one launch: repeated, present and
+    out-of-band keys, each table on the given insert path; two launches in a row."""
+    w = listing_schedule()
+    exp, tabs = expected(w)
+    r = Run(w, dev, chunk=2048, path=path)
+    p = r.plan(dev)
+    p.group(merge_runs=True)
+    for rep in range(2):
+        r.scramble()
+        p.launch_single(max_blocks)
+        r.check(exp)
+        for t, o in zip(r.tables, tabs):
+            assert t.size() == o.size()
+            assert t.check() == 0
 
 
 def test_single_launch_needs_256_thread_stages(dev):
