@@ -4231,6 +4231,26 @@ ct_status group_build(const ct_plan* p, int32_t options, uint8_t* base, GroupFor
     F.merge_off = F.launches_off + align_up(max_launches * (int64_t)sizeof(GLaunchDev));
     F.total = std::max<int64_t>(kAlign, F.merge_off + F.merge_bytes);
   }
+  // Keys per thread of the find / insert / erase stages, per level: a level with much work runs
+  // its steps with fewer, longer-running blocks (each block pays its step lookup and partial count
+  // once), as long as the level still offers about 2^20 threads; at most 16 keys per thread.
+  {
+    int32_t nl = 0;
+    for (int32_t l : level) nl = std::max(nl, l + 1);
+    std::vector<int64_t> keys_at(nl, 0);
+    auto probes = [](const GStep& g) {
+      return g.type == kOpInsert || g.type == kOpErase || g.type == kOpFind;
+    };
+    for (size_t i = 0; i < F.steps.size(); ++i)
+      if (probes(F.steps[i])) keys_at[level[i]] += F.steps[i].q;
+    for (size_t i = 0; i < F.steps.size(); ++i) {
+      GStep& g = F.steps[i];
+      if (!probes(g)) continue;
+      int64_t per = 1;
+      while (per < 16 && keys_at[level[i]] >= (per * 2) << 20) per *= 2;
+      g.gb = group_blocks((g.q + kSlots * per - 1) / (kSlots * per), bs);
+    }
+  }
   // launches: copy in, the levels, copy out
   F.entries.clear();
   F.launches.clear();
