@@ -312,13 +312,22 @@ class Table:
                                      n, _ptr(st), _stream(self.device)), "ct_insert_batch")
         return st
 
-    def find(self, keys: torch.Tensor, values: bool = True, found: bool = True, out=None):
+    def find(self, keys: torch.Tensor, values: bool = True, found: bool = True, out=None,
+             found_out=None):
+        """ct_find_batch: (values or None, found flags or None); `out` / `found_out` are written
+        in place when given (no allocation: the call can be captured into a HIP graph)."""
         n = keys.numel()
         _need(keys, torch.int64, None, "keys", self.device)
         v = None
         if values and self.value_kind != VAL_NONE:
+            if out is not None:
+                _need(out, self.value_dtype, n, "out", self.device)
             v = out if out is not None else torch.empty(n, dtype=self.value_dtype, device=self.device)
-        f = torch.empty(n, dtype=torch.uint8, device=self.device) if found else None
+        f = None
+        if found:
+            if found_out is not None:
+                _need(found_out, torch.uint8, n, "found_out", self.device)
+            f = found_out if found_out is not None else torch.empty(n, dtype=torch.uint8, device=self.device)
         _check(lib().ct_find_batch(self._h, _ptr(keys), n, _ptr(v), _ptr(f), _stream(self.device)),
                "ct_find_batch")
         return v, f

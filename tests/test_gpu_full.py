@@ -66,11 +66,12 @@ def test_large_table_full_size(dev):
     assert t.check() == 0
 
 
-@pytest.mark.parametrize("misses", ["compacted", "masked"])
+@pytest.mark.parametrize("misses", ["compacted", "masked", "graph"])
 def test_voxel_frames_full_size(dev, misses):
     """100 frames of find + insert_alloc of the misses on the full voxel workload, bit-exact
     against the oracle.  The misses reach the table either compacted on the host (the find's flags
-    select them) or through ct_insert_alloc_batch_masked with the find's flags as the mask."""
+    select them) or through ct_insert_alloc_batch_masked with the find's flags as the mask, called
+    directly or captured once into a HIP graph that every frame replays on a fixed input buffer."""
     print(f"voxel ({misses}): generating", flush=True)
     w = voxel_blocks(seed=2)
     nb = w["bucket_count"]
@@ -83,15 +84,39 @@ def test_voxel_frames_full_size(dev, misses):
     ev, es = o.insert_alloc(op, w["residents"])
     np.testing.assert_array_equal(st.cpu().numpy(), es)
     np.testing.assert_array_equal(v.cpu().numpy(), ev)
+    if misses == "graph":   # one capture over fixed buffers, replayed for every frame
+        n = w["frames"][0].size
+        assert all(q.size == n for q in w["frames"])
+        qbuf = torch.empty(n, dtype=torch.int64, device=dev)
+        fv = torch.empty(n, dtype=torch.int32, device=dev)
+        ff = torch.empty(n, dtype=torch.uint8, device=dev)
+        gv = torch.empty(n, dtype=torch.int32, device=dev)
+        gs = torch.empty(n, dtype=torch.uint8, device=dev)
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph, stream=torch.cuda.Stream(dev)):
+            t.find(qbuf, out=fv, found_out=ff)
+            t.insert_alloc_masked(gp, qbuf, ff, gv, gs)
+        torch.cuda.synchronize()
     for f, q in enumerate(w["frames"]):
         qd = g64(q, dev)
-        v, fd = t.find(qd)
+        if misses == "graph":
+            qbuf.copy_(qd)              # eager work and a synchronization between replays
+            torch.cuda.synchronize()
+            graph.replay()
+            torch.cuda.synchronize()
+            v, fd = fv, ff
+        else:
+            v, fd = t.find(qd)
         ev, ef = o.find(q)
         np.testing.assert_array_equal(fd.cpu().numpy(), ef)
         np.testing.assert_array_equal(v.cpu().numpy().view(np.uint32), ev)
         miss = q[ef == 0]
         ev, es = o.insert_alloc(op, miss)
-        if misses == "compacted":
+        if misses == "graph":
+            v, st = gv.cpu().numpy(), gs.cpu().numpy()
+            np.testing.assert_array_equal(st[ef == 0], es)
+            np.testing.assert_array_equal(v[ef == 0], ev)
+        elif misses == "compacted":
             v, st = t.insert_alloc(gp, g64(miss, dev))
             np.testing.assert_array_equal(st.cpu().numpy(), es)
             np.testing.assert_array_equal(v.cpu().numpy(), ev)
