@@ -2525,10 +2525,10 @@ __global__ __launch_bounds__(kBlock) void k_pool_push_front(PoolHeader* ph, int3
 // launch's entry list (first block of each step, ascending) and then runs exactly the range code
 // of the single-table kernel with the step's own block index and block count.
 // ---------------------------------------------------------------------------------------------
-// Stages of the grouped pipeline, in launch order within a level.
 // Plan operation kinds (the CT_OP_* values).
 enum : int32_t { kOpClear = 0, kOpInsert = 1, kOpFind = 2, kOpErase = 3 };
 
+// Stages of the grouped pipeline, in launch order within a level.
 enum GStage : int32_t {
   gReset, gPro, gDedup, gFind, gInsert, gErase, gApply,
   gSClear, gSBuild, gSProbe, gSSwap,  // resolution of speculative steps
@@ -4016,7 +4016,6 @@ ct_status run_op(const PlanOp& o, hipStream_t s) {
     }
   }
 }
-
 
 // Copy-stage blocks for a segment: enough 256-thread blocks for 16-byte units, at most 2048.
 int copy_blocks(int64_t bytes) {
