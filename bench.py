@@ -685,13 +685,15 @@ def main():
             kernels[name]["algorithmic_bytes_per_launch"] = alg / launches
     dominant = max(("k_find", "k_insert", "k_erase"), key=lambda k: kernels[k]["ms_per_step"])
     traffic = recorded_traffic()
-    tr = None
+    tr, rname = None, None
     if traffic and dominant in traffic.get("kernels", {}):
         tk = traffic["kernels"][dominant]
         tr = tk["fetch_bytes_per_launch"] + tk["write_bytes_per_launch"]
+        rname = tk.get("rocprof_name")
     dk = kernels[dominant]
     roof = {
-        "kernel": dominant,
+        "kernel": dominant,          # the library profiler's kernel kind
+        "rocprof_name": rname,       # the kernel of that kind in the committed profiles
         "bound": "hbm",
         "achieved": dk["achieved_GB_s"],
         "peak": HBM_PEAK_GBS,
