@@ -274,6 +274,82 @@ def test_grouped_listed_copies_both_directions(dev, path, merge):
             assert t.check() == 0
 
 
+@pytest.mark.parametrize("path", PATHS)
+@pytest.mark.parametrize("form", ["grouped", "merged", "single"])
+def test_grouped_empty_operations_and_mid_plan_clear(dev, path, form):
+    """Operations of zero keys (dropped when added), a clear in the middle of a table's schedule
+    (the table's later steps then decide their path afresh on the device), a table that is only
+    cleared, and repeated keys around the clear; every result equals the oracle's."""
+    rng = np.random.default_rng(77)
+    keys = (np.arange(1, 4001, dtype=np.uint64) * np.uint64(0x9E3779B97F4A7C15))
+    rep = keys[rng.integers(0, 4000, size=6000)]
+    caps = [5000, 3000, 100]
+    gt = [ct.Table(c, ct.VAL_U32, ct.HASH_MIX64, chunk=1024, device=dev) for c in caps]
+    for t in gt:
+        t.set_insert_path(path)
+    ot = [oracle.OracleTable(c, 32) for c in caps]
+    p = ct.Plan(device=dev)
+    outs = []
+    e64 = torch.empty(0, dtype=torch.int64, device=dev)
+
+    def op(ti, kind, k=None, v=None):
+        t, o = gt[ti], ot[ti]
+        if kind == "clear":
+            p.add(t, ct.OP_CLEAR)
+            o.clear()
+            return
+        if k is None:                       # zero keys: accepted and dropped
+            p.add(t, {"insert": ct.OP_INSERT, "find": ct.OP_FIND, "erase": ct.OP_ERASE}[kind],
+                  keys=e64, vals=torch.empty(0, dtype=torch.int32, device=dev) if kind == "insert" else None)
+            return
+        kd = g64(k, dev)
+        fl = torch.full((k.size,), 7, dtype=torch.uint8, device=dev)
+        vo = None
+        if kind == "insert":
+            p.add(t, ct.OP_INSERT, keys=kd, vals=g32(v, dev), flags_out=fl)
+            outs.append((fl, None, o.insert(k, v), None))
+        elif kind == "find":
+            vo = torch.empty(k.size, dtype=torch.int32, device=dev)
+            p.add(t, ct.OP_FIND, keys=kd, vals_out=vo, flags_out=fl)
+            ev, ef = o.find(k)
+            outs.append((fl, vo, ef, ev))
+        else:
+            p.add(t, ct.OP_ERASE, keys=kd, flags_out=fl)
+            outs.append((fl, None, o.erase(k), None))
+
+    vals = lambda n: rng.integers(0, 1 << 32, size=n, dtype=np.uint64).astype(np.uint32)
+    for ti in range(3):
+        op(ti, "clear")
+    op(0, "insert", rep[:3000], vals(3000))
+    op(0, "find")
+    op(1, "insert")
+    op(1, "insert", keys[:2500], vals(2500))
+    op(0, "clear")
+    op(0, "insert", rep[3000:], vals(3000))
+    op(2, "clear")
+    op(0, "erase")
+    op(0, "erase", rep[:1500])
+    op(1, "erase", keys[2000:3000])
+    op(1, "insert", rep[:2000], vals(2000))
+    op(0, "find", keys)
+    op(1, "find", keys)
+    op(2, "find", keys[:50])
+    if form == "single":
+        p.group(merge_runs=True)
+        p.launch_single()
+    else:
+        p.group(merge_runs=form == "merged")
+        p.launch_grouped()
+    torch.cuda.synchronize()
+    for fl, vo, ef, ev in outs:
+        np.testing.assert_array_equal(fl.cpu().numpy(), ef)
+        if vo is not None:
+            np.testing.assert_array_equal(vo.cpu().numpy().view(np.uint32), ev)
+    for t, o in zip(gt, ot):
+        assert t.size() == o.size()
+        assert t.check() == 0
+
+
 @pytest.mark.parametrize("merge", [False, True])
 def test_grouped_graph_replays_and_invalidation(dev, merge):
     w = small()
