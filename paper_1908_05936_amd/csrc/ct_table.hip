@@ -245,10 +245,15 @@ __device__ __forceinline__ void prologue_range(const TableView& t, PoolHeader* p
   if (header && threadIdx.x == 0) chunk_header(t, pool, q, 0u);
 }
 
+// zero_tiles: also zero the chunk's tile sums, for an insert kernel that counts its tiles itself.
 __global__ __launch_bounds__(kBlock) void k_prologue(TableView t, PoolHeader* pool,
-                                                     uint32_t dslots, int64_t q) {
+                                                     uint32_t dslots, int64_t q, int zero_tiles) {
   prologue_range(t, pool, dslots, q, (int64_t)blockIdx.x * blockDim.x, prologue_units(dslots, q),
                  (int64_t)gridDim.x * blockDim.x, blockIdx.x == 0);
+  if (zero_tiles)
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < (q + kTile - 1) / kTile;
+         j += (int64_t)gridDim.x * blockDim.x)
+      t.tsum[j] = 0;
 }
 
 // Lowest index per distinct key of the chunk.  The block takes 256 consecutive elements at a time
@@ -946,13 +951,25 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu((ALLOC |
                                                    const void* __restrict__ vals, int64_t q,
                                                    uint32_t dmask, uint8_t* __restrict__ status,
                                                    int32_t* __restrict__ vout,
-                                                   const uint8_t* __restrict__ skip) {
+                                                   const uint8_t* __restrict__ skip,
+                                                   int count_tiles) {
   const int64_t ins = insert_range<VK, ALLOC>(t, keys, skip, vals, dmask, status, vout,
                                               (int64_t)blockIdx.x * kBlock, q,
                                               (int64_t)gridDim.x * kBlock);
   // one partial per block, summed by k_apply_count: no same-address atomics across the grid
   const int64_t tot = block_sum(ins);
   if (threadIdx.x == 0) t.bcnt[blockIdx.x] = tot;
+  if (ALLOC && count_tiles) {
+    // the rank flags per tile (what k_tile_count computes): each pass of the block covers 256
+    // consecutive elements, all in one tile, and each thread re-reads the flag it wrote itself;
+    // the tile sums were zeroed by the chunk's prologue
+    for (int64_t b0 = (int64_t)blockIdx.x * kBlock; b0 < q; b0 += (int64_t)gridDim.x * kBlock) {
+      __syncthreads();  // block_sum's partials are reused
+      const int64_t i = b0 + threadIdx.x;
+      const int64_t c = block_sum((int64_t)(i < q ? t.flag[i] : 0));
+      if (threadIdx.x == 0 && c) aadd32(&t.tsum[b0 / kTile], (uint32_t)c);
+    }
+  }
 }
 
 // Host-side resizing (a table's capacity is fixed when it is created, Section 4; it grows by a
@@ -3162,7 +3179,7 @@ void dedup_chunk(ct_table* t, const TableView& v, PoolHeader* pool, const uint64
     launch(t, CT_KERNEL_DEDUP, s, [&] { k_bin_fallback_clear<<<flat_blocks(db / 2), kBlock, 0, s>>>(v, db); });
     launch(t, CT_KERNEL_DEDUP, s, [&] { k_bin_fallback_dedup<<<flat_blocks(q), kBlock, 0, s>>>(v, kc, q, db - 1); });
   } else {
-    launch(t, CT_KERNEL_PROLOGUE, s, [&] { k_prologue<<<flat_blocks(db / 2), kBlock, 0, s>>>(v, pool, db, q); });
+    launch(t, CT_KERNEL_PROLOGUE, s, [&] { k_prologue<<<flat_blocks(db / 2), kBlock, 0, s>>>(v, pool, db, q, 0); });
     launch(t, CT_KERNEL_DEDUP, s, [&] { k_dedup<<<flat_blocks(q), kBlock, 0, s>>>(v, kc, nullptr, q, db - 1); });
   }
 }
@@ -3222,7 +3239,7 @@ ct_status insert_chunks(ct_table* t, const TableView& v, int64_t chunk, const ui
       continue;
     }
     dedup_chunk(t, v, nullptr, kc, q, s);
-    launch(t, CT_KERNEL_INSERT, s, [&] { k_insert<VK, false><<<gb, kBlock, 0, s>>>(v, kc, vc, q, db - 1, sc, nullptr, nullptr); });
+    launch(t, CT_KERNEL_INSERT, s, [&] { k_insert<VK, false><<<gb, kBlock, 0, s>>>(v, kc, vc, q, db - 1, sc, nullptr, nullptr, 0); });
     // a chunk that may meet capacity stores more keys in its ranked pass: no report
     launch(t, CT_KERNEL_APPLY, s, [&] { k_apply_count<<<1, 1024, 0, s>>>(v, gb, surely_fast ? q : 0, 0); });
     if (!surely_fast) {
@@ -3883,14 +3900,16 @@ ct_status insert_alloc_chunks(ct_table* t, ct_pool* p, const uint64_t* keys, con
     int32_t* vc = vals_out ? vals_out + c0 : nullptr;
     const int gb = group_blocks((q + kSlots - 1) / kSlots);
     const int ntiles = (int)((q + kTile - 1) / kTile);
+    // a masked chunk's prologue also zeroes the tile sums, and its insert kernel counts the
+    // rank flags per tile itself: one launch fewer for the small chunks of a reconstruction frame
     if (mc) {
-      launch(t, CT_KERNEL_PROLOGUE, s, [&] { k_prologue<<<flat_blocks(db / 2), kBlock, 0, s>>>(t->v, p->hdr, db, q); });
+      launch(t, CT_KERNEL_PROLOGUE, s, [&] { k_prologue<<<flat_blocks(db / 2), kBlock, 0, s>>>(t->v, p->hdr, db, q, 1); });
       launch(t, CT_KERNEL_DEDUP, s, [&] { k_dedup<<<flat_blocks(q), kBlock, 0, s>>>(t->v, kc, mc, q, db - 1); });
     } else {
       dedup_chunk(t, t->v, p->hdr, kc, q, s);
     }
-    launch(t, CT_KERNEL_INSERT, s, [&] { k_insert<1, true><<<gb, kBlock, 0, s>>>(t->v, kc, nullptr, q, db - 1, sc, vc, mc); });
-    launch(t, CT_KERNEL_RANK, s, [&] { k_tile_count<<<ntiles, kBlock, 0, s>>>(t->v, q, 0); });
+    launch(t, CT_KERNEL_INSERT, s, [&] { k_insert<1, true><<<gb, kBlock, 0, s>>>(t->v, kc, nullptr, q, db - 1, sc, vc, mc, mc ? 1 : 0); });
+    if (!mc) launch(t, CT_KERNEL_RANK, s, [&] { k_tile_count<<<ntiles, kBlock, 0, s>>>(t->v, q, 0); });
     launch(t, CT_KERNEL_RANK, s, [&] { k_tile_scan<<<1, 1024, 0, s>>>(t->v, p->hdr, ntiles, 1); });
     launch(t, CT_KERNEL_FINAL, s, [&] { k_final<1, 1><<<ntiles, kBlock, 0, s>>>(t->v, p->hdr, p->stack, kc, nullptr, q, sc, vc); });
     if (sc || vc) launch(t, CT_KERNEL_FIX, s, [&] { k_fix<<<flat_blocks(q), kBlock, 0, s>>>(t->v, sc, vc); });
