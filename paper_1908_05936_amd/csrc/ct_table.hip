@@ -1698,6 +1698,36 @@ __global__ __launch_bounds__(kBlock) void k_tile_count(TableView t, int64_t q, i
 
 // One block of NT threads: exclusive scan of the tile counts, then the counter updates the ranks
 // imply.  mode 0: insert near capacity; 1: insert with pool values; 2: erase releasing to the pool.
+// A chunk's totals once its nnew new actors are ranked: the live count, the pool top and the
+// error bits (mode 0 insert near capacity, 1 insert with pool values, 2 erase releasing to the
+// pool).  One thread.
+__device__ __forceinline__ void rank_totals(const TableView& t, PoolHeader* pool, uint64_t nnew,
+                                            int mode) {
+  Header* h = t.hdr;
+  h->nnew = (uint32_t)nnew;
+  const uint64_t room = t.cap - h->size0;
+  if (mode == 0) {
+    const uint64_t ins = nnew < room ? nnew : room;
+    h->size = h->size0 + ins;
+    if (nnew > room) h->err |= kErrFull;
+  } else if (mode == 1) {
+    const uint64_t avail = (uint64_t)pool->top0;
+    const uint64_t lim = room < avail ? room : avail;
+    const uint64_t ins = nnew < lim ? nnew : lim;
+    h->size = h->size0 + ins;
+    pool->top = pool->top0 - (int64_t)ins;
+    if (nnew > lim) {
+      if (room <= avail) h->err |= kErrFull;
+      else h->err |= kErrPool;
+    }
+  } else {
+    const uint64_t room_p = (uint64_t)(pool->cap - pool->top0);
+    const uint64_t pushed = nnew < room_p ? nnew : room_p;
+    pool->top = pool->top0 + (int64_t)pushed;
+    if (nnew > room_p) pool->err |= kErrPool;
+  }
+}
+
 template <int NT>
 __device__ __forceinline__ void scan_tiles_block(const TableView& t, PoolHeader* pool, int ntiles,
                                                  int mode) {
@@ -1726,32 +1756,7 @@ __device__ __forceinline__ void scan_tiles_block(const TableView& t, PoolHeader*
     if (threadIdx.x == 0) carry += all;
     __syncthreads();
   }
-  if (threadIdx.x == 0) {
-    Header* h = t.hdr;
-    const uint64_t nnew = carry;
-    h->nnew = carry;
-    const uint64_t room = t.cap - h->size0;
-    if (mode == 0) {
-      const uint64_t ins = nnew < room ? nnew : room;
-      h->size = h->size0 + ins;
-      if (nnew > room) h->err |= kErrFull;
-    } else if (mode == 1) {
-      const uint64_t avail = (uint64_t)pool->top0;
-      const uint64_t lim = room < avail ? room : avail;
-      const uint64_t ins = nnew < lim ? nnew : lim;
-      h->size = h->size0 + ins;
-      pool->top = pool->top0 - (int64_t)ins;
-      if (nnew > lim) {
-        if (room <= avail) h->err |= kErrFull;
-        else h->err |= kErrPool;
-      }
-    } else {
-      const uint64_t room_p = (uint64_t)(pool->cap - pool->top0);
-      const uint64_t pushed = nnew < room_p ? nnew : room_p;
-      pool->top = pool->top0 + (int64_t)pushed;
-      if (nnew > room_p) pool->err |= kErrPool;
-    }
-  }
+  if (threadIdx.x == 0) rank_totals(t, pool, carry, mode);
   __syncthreads();
 }
 
@@ -1772,7 +1777,8 @@ __device__ __forceinline__ void final_tile(const TableView& t, PoolHeader* pool,
                                            const uint64_t* __restrict__ keys,
                                            const void* __restrict__ vals, int64_t q,
                                            uint8_t* __restrict__ status,
-                                           int32_t* __restrict__ vout, int64_t tile) {
+                                           int32_t* __restrict__ vout, int64_t tile,
+                                           int inline_tiles) {
   const bool fast = t.hdr->fast != 0;
   if (MODE == 0 && fast) return;
   __shared__ uint16_t list[kTile];
@@ -1791,7 +1797,30 @@ __device__ __forceinline__ void final_tile(const TableView& t, PoolHeader* pool,
   for (int k = 0; k < kTile / kBlock; ++k)
     if (f[k]) list[o++] = (uint16_t)(threadIdx.x * (kTile / kBlock) + k);
   __syncthreads();
-  const uint64_t rbase = t.tsum[tile];
+  // inline_tiles == 0: the tile sums hold the rank scan's exclusive prefixes.  inline_tiles = n > 0
+  // (small chunks, no scan launched): they hold the n tiles' counts; each block adds those before
+  // its tile, and the block of tile 0 also settles the chunk's totals as the scan would.
+  uint64_t rbase;
+  if (inline_tiles > 0) {
+    __shared__ uint64_t rb_shared;
+    uint64_t before = 0, all = 0;
+    for (int j = threadIdx.x; j < inline_tiles; j += kBlock) {
+      const uint64_t c = t.tsum[j];
+      all += c;
+      if (j < tile) before += c;
+    }
+    before = (uint64_t)block_sum((int64_t)before);
+    __syncthreads();  // block_sum's partials are reused
+    all = (uint64_t)block_sum((int64_t)all);
+    if (threadIdx.x == 0) {
+      rb_shared = before;
+      if (tile == 0) rank_totals(t, pool, all, MODE);
+    }
+    __syncthreads();
+    rbase = rb_shared;
+  } else {
+    rbase = t.tsum[tile];
+  }
   const Header* h = t.hdr;
   const uint64_t room = t.cap - h->size0;
   const int sub = threadIdx.x & 7;
@@ -1853,8 +1882,8 @@ __global__ __launch_bounds__(kBlock) void k_final(TableView t, PoolHeader* pool,
                                                   const uint64_t* __restrict__ keys,
                                                   const void* __restrict__ vals, int64_t q,
                                                   uint8_t* __restrict__ status,
-                                                  int32_t* __restrict__ vout) {
-  final_tile<VK, MODE>(t, pool, pstack, keys, vals, q, status, vout, blockIdx.x);
+                                                  int32_t* __restrict__ vout, int inline_tiles) {
+  final_tile<VK, MODE>(t, pool, pstack, keys, vals, q, status, vout, blockIdx.x, inline_tiles);
 }
 
 // Later copies of a key take the outcome of its first occurrence: PRESENT (or its value), unless
@@ -2793,11 +2822,11 @@ __device__ __forceinline__ void g_final_body(const GStep* __restrict__ st, const
   const TableView t = g.v;
   if (t.hdr->fast) return;   // nothing to rank: leave before any of the tile code
   if (g.vk == 1)
-    final_tile<1, 0>(t, nullptr, nullptr, g.keys, g.vals, g.q, g.flags, nullptr, L.lb);
+    final_tile<1, 0>(t, nullptr, nullptr, g.keys, g.vals, g.q, g.flags, nullptr, L.lb, 0);
   else if (g.vk == 2)
-    final_tile<2, 0>(t, nullptr, nullptr, g.keys, g.vals, g.q, g.flags, nullptr, L.lb);
+    final_tile<2, 0>(t, nullptr, nullptr, g.keys, g.vals, g.q, g.flags, nullptr, L.lb, 0);
   else
-    final_tile<0, 0>(t, nullptr, nullptr, g.keys, nullptr, g.q, g.flags, nullptr, L.lb);
+    final_tile<0, 0>(t, nullptr, nullptr, g.keys, nullptr, g.q, g.flags, nullptr, L.lb, 0);
 }
 
 // A byte range moved by the grouped plan's copy stages (operations merged into one step).
@@ -3145,6 +3174,11 @@ int group_blocks(int64_t n, int bs = kBlock) {
   return (int)std::max<int64_t>(1, std::min<int64_t>(b, kMaxGroupBlocks));
 }
 
+// Chunks of at most this many rank tiles skip the one-block rank scan: each ranked-completion
+// block sums the tile counts before its own tile (at most 256 loads), and the first settles the
+// chunk's totals.
+constexpr int kInlineRankTiles = 256;
+
 int flat_blocks(int64_t n) {
   const int64_t b = (n + kBlock - 1) / kBlock;
   return (int)std::max<int64_t>(1, std::min<int64_t>(b, 8192));
@@ -3244,8 +3278,9 @@ ct_status insert_chunks(ct_table* t, const TableView& v, int64_t chunk, const ui
     launch(t, CT_KERNEL_APPLY, s, [&] { k_apply_count<<<1, 1024, 0, s>>>(v, gb, surely_fast ? q : 0, 0); });
     if (!surely_fast) {
       launch(t, CT_KERNEL_RANK, s, [&] { k_tile_count<<<ntiles, kBlock, 0, s>>>(v, q, 1); });
-      launch(t, CT_KERNEL_RANK, s, [&] { k_tile_scan<<<1, 1024, 0, s>>>(v, nullptr, ntiles, 0); });
-      launch(t, CT_KERNEL_FINAL, s, [&] { k_final<VK, 0><<<ntiles, kBlock, 0, s>>>(v, nullptr, nullptr, kc, vc, q, sc, nullptr); });
+      const int inl = ntiles <= kInlineRankTiles ? ntiles : 0;
+      if (!inl) launch(t, CT_KERNEL_RANK, s, [&] { k_tile_scan<<<1, 1024, 0, s>>>(v, nullptr, ntiles, 0); });
+      launch(t, CT_KERNEL_FINAL, s, [&] { k_final<VK, 0><<<ntiles, kBlock, 0, s>>>(v, nullptr, nullptr, kc, vc, q, sc, nullptr, inl); });
     }
     if (sc) launch(t, CT_KERNEL_FIX, s, [&] { k_fix<<<flat_blocks(q), kBlock, 0, s>>>(v, sc, nullptr); });
     t->size_ub = std::min<uint64_t>(t->size_ub + (uint64_t)q, (uint64_t)t->desc.capacity);
@@ -3285,8 +3320,9 @@ ct_status erase_chunks(ct_table* t, ct_pool* p, const uint64_t* keys, int64_t n,
     launch(t, CT_KERNEL_APPLY, s, [&] { k_apply_count<<<1, 1024, 0, s>>>(t->v, gb, RELEASE ? 0 : q, 1); });
     if (RELEASE) {
       launch(t, CT_KERNEL_RANK, s, [&] { k_tile_count<<<ntiles, kBlock, 0, s>>>(t->v, q, 0); });
-      launch(t, CT_KERNEL_RANK, s, [&] { k_tile_scan<<<1, 1024, 0, s>>>(t->v, p->hdr, ntiles, 2); });
-      launch(t, CT_KERNEL_FINAL, s, [&] { k_final<0, 2><<<ntiles, kBlock, 0, s>>>(t->v, p->hdr, p->stack, kc, nullptr, q, nullptr, nullptr); });
+      const int inl = ntiles <= kInlineRankTiles ? ntiles : 0;
+      if (!inl) launch(t, CT_KERNEL_RANK, s, [&] { k_tile_scan<<<1, 1024, 0, s>>>(t->v, p->hdr, ntiles, 2); });
+      launch(t, CT_KERNEL_FINAL, s, [&] { k_final<0, 2><<<ntiles, kBlock, 0, s>>>(t->v, p->hdr, p->stack, kc, nullptr, q, nullptr, nullptr, inl); });
     }
     ct_status r = launched();
     if (r != CT_OK) return r;
@@ -3910,8 +3946,9 @@ ct_status insert_alloc_chunks(ct_table* t, ct_pool* p, const uint64_t* keys, con
     }
     launch(t, CT_KERNEL_INSERT, s, [&] { k_insert<1, true><<<gb, kBlock, 0, s>>>(t->v, kc, nullptr, q, db - 1, sc, vc, mc, mc ? 1 : 0); });
     if (!mc) launch(t, CT_KERNEL_RANK, s, [&] { k_tile_count<<<ntiles, kBlock, 0, s>>>(t->v, q, 0); });
-    launch(t, CT_KERNEL_RANK, s, [&] { k_tile_scan<<<1, 1024, 0, s>>>(t->v, p->hdr, ntiles, 1); });
-    launch(t, CT_KERNEL_FINAL, s, [&] { k_final<1, 1><<<ntiles, kBlock, 0, s>>>(t->v, p->hdr, p->stack, kc, nullptr, q, sc, vc); });
+    const int inl = ntiles <= kInlineRankTiles ? ntiles : 0;
+    if (!inl) launch(t, CT_KERNEL_RANK, s, [&] { k_tile_scan<<<1, 1024, 0, s>>>(t->v, p->hdr, ntiles, 1); });
+    launch(t, CT_KERNEL_FINAL, s, [&] { k_final<1, 1><<<ntiles, kBlock, 0, s>>>(t->v, p->hdr, p->stack, kc, nullptr, q, sc, vc, inl); });
     if (sc || vc) launch(t, CT_KERNEL_FIX, s, [&] { k_fix<<<flat_blocks(q), kBlock, 0, s>>>(t->v, sc, vc); });
     t->size_ub = std::min<uint64_t>(t->size_ub + (uint64_t)q, (uint64_t)t->desc.capacity);
     r = launched();
