@@ -457,6 +457,16 @@ def pool_ops(dev, keys, reps=3):
     return out
 
 
+def side_leg(name: str, fn) -> dict:
+    """Run one of the line's side measurements; a Python-level failure (a refused launch, say)
+    becomes an error entry instead of losing the whole line."""
+    try:
+        return fn()
+    except Exception as e:  # noqa: BLE001  (any failure of a side leg is reported, not raised)
+        log(f"[{name}] failed: {e!r}")
+        return {"error": repr(e)}
+
+
 def multi_table_leg(dev) -> dict:
     """The 256-table schedule (tables of 2^10..2^20 entries at load factors 0.5-0.9, a fill then a
     20/70/10 insert/find/erase mix of batches of 2^6..2^18 keys): the autotuner picks the execution
@@ -734,9 +744,9 @@ def main():
     line["insert_marginal_Mops_s"] = marginal_insert(dev, L, h, s)
     log(f"marginal insert of 2^20 fresh keys at load 0.8: {line['insert_marginal_Mops_s']:.0f} Mops/s")
     if not a.no_rehash:
-        line["rehash"] = rehash_leg(table, K_re, V_re)
+        line["rehash"] = side_leg("rehash", lambda: rehash_leg(table, K_re, V_re))
     if not a.no_mixed:
-        line["mixed_device_ops"] = mixed_device_leg(table, K_re, V_re)
+        line["mixed_device_ops"] = side_leg("mixed", lambda: mixed_device_leg(table, K_re, V_re))
     if not a.no_find_uniform:
         line["find_uniform_Mops_s"] = find_uniform(op_clear, op_fill, dev, K_fill, n_fill, n_find,
                                                    n_present_expected, L, h, s, vals_out, found)
@@ -758,18 +768,18 @@ def main():
                                                / ceil["R1_gather128_Mlines_s"])
         line["random_access"] = ceil
     if not a.no_pool:
-        line["pool"] = pool_ops(dev, K_fill[: min(n_fill, 1 << 24)])
+        line["pool"] = side_leg("pool", lambda: pool_ops(dev, K_fill[: min(n_fill, 1 << 24)]))
     if not a.no_voxel:
         from paper_1908_05936_amd import bench_voxel
-        line["voxel"] = bench_voxel.run(log=log)
-    if "voxel" in line and "random_access" in line:
+        line["voxel"] = side_leg("voxel", lambda: bench_voxel.run(log=log))
+    if "find_Mkeys_s" in line.get("voxel", {}) and "random_access" in line:
         # the voxel table is 2^21 buckets of 128 bytes: its find is compared with the gather
         # ceiling at that footprint (256 MiB, the last-level cache's size)
         r1 = line["random_access"]["by_footprint"]["256MiB"]["R1_Mlines_s"]
         line["voxel"]["find_R1_256MiB_Mlines_s"] = r1
         line["voxel"]["find_frac_of_R1_256MiB"] = line["voxel"]["find_Mkeys_s"] / r1
     if not a.no_multi:
-        line["multi_table"] = multi_table_leg(dev)
+        line["multi_table"] = side_leg("multi", lambda: multi_table_leg(dev))
     if serve_child is not None:
         del table, K_fill, V_fill, Q, E, K_re, V_re
         torch.cuda.empty_cache()

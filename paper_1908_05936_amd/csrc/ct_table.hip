@@ -4470,8 +4470,10 @@ ct_status ct_plan_launch_single(ct_plan* p, int32_t max_blocks, void* stream) {
   const GCopy* cp = static_cast<const GCopy*>(p->gcopies);
   void* args[] = {&ls, &nl, &st, &en, &cp};
   if (hipLaunchCooperativeKernel(reinterpret_cast<const void*>(k_g_persistent), dim3((unsigned)grid),
-                                 dim3(kBlock), args, 0, s) != hipSuccess)
+                                 dim3(kBlock), args, 0, s) != hipSuccess) {
+    (void)hipGetLastError();  // a refused launch must not fail the caller's next call
     return CT_E_HIP;
+  }
   return CT_OK;
 }
 

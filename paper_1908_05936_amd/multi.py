@@ -156,8 +156,14 @@ def tune(w: dict, dev, cache: str | None = None, reps: int = 3, log=print) -> di
             built[wk] = Workload(w, dev, chunk=cfg["chunk"], provision=cfg["provision"])
         wl = built[wk]
         p = wl.plan()
-        t = time_fn(runner(p, cfg["lanes"], cfg.get("merge", False), cfg.get("block", 256)),
-                    reps=reps)
+        try:
+            t = time_fn(runner(p, cfg["lanes"], cfg.get("merge", False), cfg.get("block", 256)),
+                        reps=reps)
+        except ct.CtError as e:
+            if cfg["lanes"] >= 0:
+                raise
+            t = float("inf")   # the device refused the cooperative launch: not a candidate
+            log(f"[tune] {cfg}: {e}")
         trials.append(dict(cfg, seconds=t))
         log(f"[tune] {cfg} -> {t * 1e3:.2f} ms")
         return t
@@ -225,8 +231,12 @@ def measure(w: dict, dev, cfg: dict, reps: int = 5, graph_replays: int = 10) -> 
     # the grouped form as one cooperative launch, whatever form was chosen
     p1 = wl.plan()
     p1.group(merge_runs=cfg.get("merge", False), block=256)
-    t_single = time_fn(p1.launch_single, reps=reps)
-    extra.update(single_launch_ms=t_single * 1e3, single_launch_Mkeys_s=wl.n_keys / t_single / 1e6)
+    try:
+        t_single = time_fn(p1.launch_single, reps=reps)
+        extra.update(single_launch_ms=t_single * 1e3,
+                     single_launch_Mkeys_s=wl.n_keys / t_single / 1e6)
+    except ct.CtError as e:
+        extra.update(single_launch_ms=None, single_launch_error=str(e))
     del p1
     t_streams = time_fn(lambda: p.launch(4), reps=reps)
     return dict(extra, keys=n, ops=len(w["schedule"]), tables=len(w["tables"]),
